@@ -1,0 +1,224 @@
+/*
+ * sparc_gpu.h -- C ABI of the MI355X (gfx950) CheFSI library.
+ *
+ * The library solves the Gamma-point, spin-unpolarised Kohn-Sham problem of
+ * Sec. 2 eq. (1) on a uniform periodic real-space grid (Sec. 2.1) with the
+ * Chebyshev-filtered subspace iteration (CheFSI) inside each SCF step
+ * (Sec. 2.1).  Every entry point below enqueues hand-written HIP kernels on
+ * the stream given at creation; nothing is computed on the host except
+ * geometry set-up at creation and a handful of scalars.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ *  - Grid: n[0] x n[1] x n[2] points on an orthorhombic cell L[0..2] (Bohr);
+ *    point (ix, iy, iz) sits at (ix*hx, iy*hy, iz*hz), h = L/n, and has flat
+ *    index p = ix + n[0]*(iy + n[1]*iz).  N_d = n[0]*n[1]*n[2].  Every axis
+ *    is periodic and must have at least 2*fd_half_order + 1 points.
+ *  - Blocks of orbitals ("X") are column-major N_d x ncol arrays with leading
+ *    dimension ldx >= N_d: orbital j occupies X[j*ldx .. j*ldx + N_d).  Their
+ *    element type is double for SPARC_FP64 and float for SPARC_FP32.
+ *  - Inner products carry the trapezoidal weight dV = hx*hy*hz (Sec. 2.1):
+ *    an orthonormal block satisfies dV * X^T X = I.
+ *  - Pointers named d_* are device addresses owned by the caller (allocated on
+ *    the device current at creation); the library never frees them.  Host
+ *    pointers are read during the call only.
+ *  - Calls are asynchronous on the context's stream unless stated otherwise.
+ *    A context is not reentrant: use one context per host thread.
+ *  - Arguments are validated on the host before anything is launched; a
+ *    rejected call returns SPARC_ERR_ARG and leaves every buffer untouched.
+ *    No exceptions cross the ABI and the library never exits the process.
+ *    After an error the context remains usable; sparc_gpu_last_error() gives
+ *    a message.
+ */
+#ifndef SPARC_GPU_H
+#define SPARC_GPU_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sparc_gpu_ctx_s* sparc_gpu_ctx;
+
+typedef enum {
+    SPARC_FP64 = 0, /* orbitals, stencil and subspace GEMMs in double      */
+    SPARC_FP32 = 1  /* orbitals, stencil and subspace GEMMs in float; the
+                       Cholesky factor, eigensolve, occupations, density
+                       accumulation, potential and mixing stay in double   */
+} sparc_prec;
+
+typedef enum {
+    SPARC_OK = 0,
+    SPARC_ERR_ARG = 1,        /* invalid argument (nothing was launched)   */
+    SPARC_ERR_HIP = 2,        /* a HIP runtime call failed                 */
+    SPARC_ERR_NOMEM = 3,      /* device allocation failed                  */
+    SPARC_ERR_NOT_SPD = 4,    /* Gram matrix not numerically positive
+                                 definite (rank-deficient block)           */
+    SPARC_ERR_EIG = 5,        /* subspace eigensolver did not converge     */
+    SPARC_ERR_FERMI = 6,      /* Fermi level bracket failed                */
+    SPARC_ERR_NOCONV = 7,     /* iteration limit reached                   */
+    SPARC_ERR_NONFINITE = 8   /* NaN/Inf met in a checked quantity         */
+} sparc_status;
+
+/*
+ * The system: a periodic cell of model atoms.  Each atom I carries a local
+ * pseudopotential V_I(r) = -Z_I erf(r/rc_loc_I)/r, represented through its
+ * Gaussian pseudocharge in the local real-space electrostatics of Sec. 2.1,
+ * and, if nl_lmax = 1, Kleinman-Bylander nonlocal projectors (Sec. 2.1,
+ * applied through their outer-product form):
+ *   chi_s  = N0 exp(-r^2/rc_nl^2),  chi_p{x,y,z} = N1 {x,y,z} exp(-r^2/rc_nl^2),
+ *   N0 = (2/(pi rc_nl^2))^(3/4),  N1 = (2/rc_nl) N0,  cut at r <= rcut_nl,
+ *   summed over periodic images, with energies gamma[I*2 + 0] (s) and
+ *   gamma[I*2 + 1] (p, shared by x, y, z).
+ * The struct and its arrays are copied by sparc_gpu_create().
+ */
+typedef struct {
+    int n[3];               /* grid points per axis                          */
+    double L[3];            /* cell lengths (Bohr)                           */
+    int fd_half_order;      /* n_o: 2*n_o-th order centred differences, 1..6  */
+    int n_atoms;
+    const double* pos;      /* [3*n_atoms] positions (Bohr)                  */
+    const double* Z;        /* [n_atoms] valence charges                     */
+    const double* rc_loc;   /* [n_atoms] local Gaussian widths (Bohr)        */
+    int nl_lmax;            /* -1: no nonlocal part; 1: s and p projectors   */
+    const double* gamma;    /* [2*n_atoms] projector energies (Ha); NULL if nl_lmax = -1 */
+    double rc_nl;           /* projector Gaussian width (Bohr)               */
+    double rcut_nl;         /* projector support radius (Bohr)               */
+    int n_states;           /* N_s: columns of the orbital block             */
+    double n_electrons;     /* N_e, 0 < N_e < 2*N_s                          */
+    double kT;              /* Fermi-Dirac smearing (Ha), > 0                */
+    double rho_floor;       /* density floor inside the LDA (e.g. 1e-14)     */
+    double sad_width;       /* width (Bohr) of the atomic model densities     */
+} sparc_gpu_system;
+
+/* Create a context on the current device: copies the system, builds the
+ * finite-difference coefficients, the pseudocharge b, the projector tables
+ * and the self/overlap energies.  hip_stream may be NULL (default stream).
+ * Synchronous.  Errors: SPARC_ERR_ARG (bad system), SPARC_ERR_NOMEM,
+ * SPARC_ERR_HIP. */
+sparc_status sparc_gpu_create(const sparc_gpu_system* sys, void* hip_stream, sparc_gpu_ctx* out);
+
+/* Free every device resource of the context (synchronises its stream). */
+sparc_status sparc_gpu_destroy(sparc_gpu_ctx ctx);
+
+/* Message describing the last error on this context ("" if none).  The
+ * string is owned by the context and valid until its next call. */
+const char* sparc_gpu_last_error(sparc_gpu_ctx ctx);
+
+/* Number of grid points N_d and the trapezoidal weight dV. */
+long sparc_gpu_grid_size(sparc_gpu_ctx ctx);
+double sparc_gpu_dV(sparc_gpu_ctx ctx);
+
+/* Set the effective potential V_eff (Sec. 2 eq. (1)) used by every H
+ * application: d_veff is N_d doubles, copied into the context. */
+sparc_status sparc_gpu_set_veff(sparc_gpu_ctx ctx, const double* d_veff);
+
+/* Y = H X  (Sec. 2 eq. (1), matrix-free per Sec. 2.1):
+ *   H x = -1/2 Delta_h x + V_eff x + sum_I sum_lm gamma_Il chi_Ilm (dV chi_Ilm^T x).
+ * d_X, d_Y: N_d x ncol blocks (ldx) of the given precision; they must not
+ * overlap.  1 <= ncol <= n_states. */
+sparc_status sparc_gpu_apply_H(sparc_gpu_ctx ctx, sparc_prec prec, const void* d_X, void* d_Y,
+                               int ncol, long ldx);
+
+/* Scaled Chebyshev filter of degree m >= 1 (the CheFSI filter named in
+ * Sec. 2.1): overwrites X with p_m(H) X where, on an eigenvector of H with
+ * eigenvalue lam, p_m(lam) = T_m((lam - c)/e) / T_m((a0 - c)/e),
+ * e = (b - a)/2, c = (b + a)/2.  Requires a0 < a < b.  d_work is caller
+ * scratch of the same shape and precision as X (contents destroyed). */
+sparc_status sparc_gpu_chebyshev_filter(sparc_gpu_ctx ctx, sparc_prec prec, void* d_X, void* d_work,
+                                        int ncol, long ldx, int degree, double a, double b, double a0);
+
+/* Orthonormalise and Rayleigh-Ritz (the subspace step of CheFSI, Sec. 2.1):
+ *   M = dV Y^T Y = R^T R (Cholesky, FP64), Hs = R^-T (dV Y^T H Y) R^-1,
+ *   Hs = Q diag(lam) Q^T (FP64 eigensolver, ascending), X <- Y R^-1 Q.
+ * Gram and projected-Hamiltonian products and the rotation run in the block's
+ * precision (FP32 MFMA with FP32 accumulation inside K-tiles, FP64 across
+ * them, for SPARC_FP32).  d_eig receives ncol doubles.  Synchronises the
+ * stream once to report SPARC_ERR_NOT_SPD / SPARC_ERR_EIG; on such an error X
+ * is left unchanged.  Uses context-owned workspace (one block). */
+sparc_status sparc_gpu_rayleigh_ritz(sparc_gpu_ctx ctx, sparc_prec prec, void* d_X, int ncol, long ldx,
+                                     double* d_eig);
+
+/* Electron density, Sec. 2 eq. (2): rho(p) = sum_j occ[j] X(p, j)^2,
+ * accumulated in FP64.  d_occ: ncol doubles; d_rho: N_d doubles. */
+sparc_status sparc_gpu_density(sparc_gpu_ctx ctx, sparc_prec prec, const void* d_X, int ncol, long ldx,
+                               const double* d_occ, double* d_rho);
+
+/* Fermi-Dirac occupations (Sec. 2: g_j = 2 f_j for the unpolarised case):
+ * bisection for mu on [lam_min - 40 kT, lam_max + 40 kT] until
+ * |sum g - N_e| < 1e-13.  d_eig, d_occ: ncol doubles; d_mu: 1 double (may
+ * be NULL).  Requires 0 < N_e <= 2 ncol. */
+sparc_status sparc_gpu_occupations(sparc_gpu_ctx ctx, const double* d_eig, int ncol, double* d_occ,
+                                   double* d_mu);
+
+/* Electrostatic and exchange-correlation potentials for density d_rho
+ * (Sec. 2.1): phi solves -Delta_h phi = 4 pi (rho + b - mean(rho + b)) with
+ * mean(phi) = 0 on the periodic grid; LDA (Slater exchange, PW92
+ * correlation).  Outputs (each N_d doubles, any may be NULL): phi, eps_xc,
+ * v_xc, V_eff = phi + v_xc.  Does not change the context's V_eff. */
+sparc_status sparc_gpu_potential(sparc_gpu_ctx ctx, const double* d_rho, double* d_phi, double* d_exc,
+                                 double* d_vxc, double* d_veff);
+
+/* Geometry-derived fields and constants: pseudocharge b (N_d doubles, may
+ * be NULL), Gaussian self energy E_self and the point-ion overlap correction
+ * E_c (host doubles, may be NULL).  Synchronous. */
+sparc_status sparc_gpu_pseudocharge(sparc_gpu_ctx ctx, double* d_b, double* e_self, double* e_c);
+
+/* Superposition-of-atomic-densities guess (Sec. 2.1): a normalised Gaussian of
+ * width sad_width carrying Z_I electrons per atom, rescaled so that
+ * dV sum rho = N_e.  d_rho: N_d doubles. */
+sparc_status sparc_gpu_sad_density(sparc_gpu_ctx ctx, double* d_rho);
+
+/* Bounds lo <= spec(H) <= hi of the current H (kinetic symbol bound,
+ * V_eff extrema, signed projector norms).  Synchronous. */
+sparc_status sparc_gpu_spectrum_bounds(sparc_gpu_ctx ctx, double* lo, double* hi);
+
+/* State carried across SCF iterations; every device buffer is caller-owned. */
+typedef struct {
+    double* d_rho_in;   /* in: rho_in of this iteration; out: mixed density   */
+    void* d_X;          /* in/out: N_d x n_states block (ldx, prec)          */
+    long ldx;
+    int prec;           /* sparc_prec of d_X                                 */
+    int cheb_degree;    /* m                                                  */
+    int n_first;        /* filter + RR passes in the first iteration (>= 1)  */
+    double mix_beta;    /* linear mixing factor, 0 < beta <= 1                */
+    int iter;           /* 0 on the first call; incremented by each call     */
+    double* d_eig;      /* out: n_states Ritz values (ascending)             */
+    double* d_occ;      /* out: n_states occupations                          */
+    double* d_rho_out;  /* optional out: N_d output density (may be NULL)    */
+    double bounds[3];   /* a, b, a0 of the last filter (in/out)              */
+} sparc_gpu_scf_state;
+
+/* What one SCF iteration reports (energies in Ha, times in ms of device
+ * time measured with HIP events on the context's stream). */
+typedef struct {
+    double free_energy;   /* Harris-Foulkes free energy at rho_in            */
+    double band, exc, vxc_dc, elec, self_energy, overlap, entropy; /* terms  */
+    double mu;            /* Fermi level                                     */
+    double residual;      /* ||rho_out - rho_in|| / ||rho_out||              */
+    double t_potential_ms, t_filter_ms, t_rr_ms, t_density_ms, t_total_ms;
+    int n_passes;         /* filter + RR passes performed                    */
+    int iter;             /* index of this iteration                         */
+} sparc_gpu_scf_report;
+
+/* One SCF iteration (Sec. 2.1): V_eff from rho_in (Poisson + LDA); on the
+ * first iteration a Rayleigh-Ritz of the starting block, then n_first passes
+ * (later iterations: one pass) of Chebyshev filter + Rayleigh-Ritz with
+ * a = largest and a0 = smallest Ritz value of the preceding step (a0 = lower
+ * spectrum bound before the first filter) and b = upper spectrum bound;
+ * occupations, rho_out (Sec. 2 eq. (2)), the free energy at rho_in, the
+ * residual, and linear mixing rho_in <- rho_in + beta (rho_out - rho_in).
+ * Synchronises once at the end to fill rep (may be NULL). */
+sparc_status sparc_gpu_scf_step(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st, sparc_gpu_scf_report* rep);
+
+/* After an SCF run in SPARC_FP32: promote st->d_X into the FP64 block d_X64
+ * (N_d x n_states, leading dimension ldx64), perform one FP64 Rayleigh-Ritz
+ * with V_eff from st->d_rho_in, then occupations, rho_out and the free
+ * energy at rho_in.  No mixing; st->iter unchanged.  Synchronises once. */
+sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st, double* d_X64, long ldx64,
+                                     sparc_gpu_scf_report* rep);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPARC_GPU_H */

@@ -1,0 +1,18 @@
+"""MI355X (gfx950) Chebyshev-filtered subspace iteration for real-space
+Kohn-Sham DFT.
+
+The compute path is the HIP library ``libsparc_gpu.so`` (sources in
+``csrc/``, C ABI in ``include/sparc_gpu.h``); this package only binds it.
+"""
+from ._lib import (  # noqa: F401
+    EXPORTED,
+    SPARC_FP32,
+    SPARC_FP64,
+    Context,
+    SCFReport,
+    SCFState,
+    SparcError,
+    load,
+    make_state,
+)
+from .driver import run_scf  # noqa: F401

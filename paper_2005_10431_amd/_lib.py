@@ -1,0 +1,311 @@
+"""ctypes binding of ``libsparc_gpu.so`` (declared in ``include/sparc_gpu.h``).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device buffers are torch tensors on the current HIP device; their
+raw addresses cross the C ABI.  Loading fails loudly when the shared library
+has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsparc_gpu.so")
+
+SPARC_FP64 = 0
+SPARC_FP32 = 1
+
+STATUS = {
+    0: "SPARC_OK",
+    1: "SPARC_ERR_ARG",
+    2: "SPARC_ERR_HIP",
+    3: "SPARC_ERR_NOMEM",
+    4: "SPARC_ERR_NOT_SPD",
+    5: "SPARC_ERR_EIG",
+    6: "SPARC_ERR_FERMI",
+    7: "SPARC_ERR_NOCONV",
+    8: "SPARC_ERR_NONFINITE",
+}
+
+EXPORTED = [
+    "sparc_gpu_create",
+    "sparc_gpu_destroy",
+    "sparc_gpu_last_error",
+    "sparc_gpu_grid_size",
+    "sparc_gpu_dV",
+    "sparc_gpu_set_veff",
+    "sparc_gpu_apply_H",
+    "sparc_gpu_chebyshev_filter",
+    "sparc_gpu_rayleigh_ritz",
+    "sparc_gpu_density",
+    "sparc_gpu_occupations",
+    "sparc_gpu_potential",
+    "sparc_gpu_pseudocharge",
+    "sparc_gpu_sad_density",
+    "sparc_gpu_spectrum_bounds",
+    "sparc_gpu_scf_step",
+    "sparc_gpu_final_rr_fp64",
+]
+
+
+class SparcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class System(C.Structure):
+    _fields_ = [
+        ("n", C.c_int * 3),
+        ("L", C.c_double * 3),
+        ("fd_half_order", C.c_int),
+        ("n_atoms", C.c_int),
+        ("pos", C.POINTER(C.c_double)),
+        ("Z", C.POINTER(C.c_double)),
+        ("rc_loc", C.POINTER(C.c_double)),
+        ("nl_lmax", C.c_int),
+        ("gamma", C.POINTER(C.c_double)),
+        ("rc_nl", C.c_double),
+        ("rcut_nl", C.c_double),
+        ("n_states", C.c_int),
+        ("n_electrons", C.c_double),
+        ("kT", C.c_double),
+        ("rho_floor", C.c_double),
+        ("sad_width", C.c_double),
+    ]
+
+
+class SCFState(C.Structure):
+    _fields_ = [
+        ("d_rho_in", C.c_void_p),
+        ("d_X", C.c_void_p),
+        ("ldx", C.c_long),
+        ("prec", C.c_int),
+        ("cheb_degree", C.c_int),
+        ("n_first", C.c_int),
+        ("mix_beta", C.c_double),
+        ("iter", C.c_int),
+        ("d_eig", C.c_void_p),
+        ("d_occ", C.c_void_p),
+        ("d_rho_out", C.c_void_p),
+        ("bounds", C.c_double * 3),
+    ]
+
+
+class SCFReport(C.Structure):
+    _fields_ = [
+        ("free_energy", C.c_double),
+        ("band", C.c_double),
+        ("exc", C.c_double),
+        ("vxc_dc", C.c_double),
+        ("elec", C.c_double),
+        ("self_energy", C.c_double),
+        ("overlap", C.c_double),
+        ("entropy", C.c_double),
+        ("mu", C.c_double),
+        ("residual", C.c_double),
+        ("t_potential_ms", C.c_double),
+        ("t_filter_ms", C.c_double),
+        ("t_rr_ms", C.c_double),
+        ("t_density_ms", C.c_double),
+        ("t_total_ms", C.c_double),
+        ("n_passes", C.c_int),
+        ("iter", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} not found: build it with `python -m paper_2005_10431_amd.build` "
+            "(there is no fallback implementation)")
+    lib = C.CDLL(path)
+    vp, i, l, d = C.c_void_p, C.c_int, C.c_long, C.c_double
+    sig = {
+        "sparc_gpu_create": ([C.POINTER(System), vp, C.POINTER(vp)], i),
+        "sparc_gpu_destroy": ([vp], i),
+        "sparc_gpu_last_error": ([vp], C.c_char_p),
+        "sparc_gpu_grid_size": ([vp], l),
+        "sparc_gpu_dV": ([vp], d),
+        "sparc_gpu_set_veff": ([vp, vp], i),
+        "sparc_gpu_apply_H": ([vp, i, vp, vp, i, l], i),
+        "sparc_gpu_chebyshev_filter": ([vp, i, vp, vp, i, l, i, d, d, d], i),
+        "sparc_gpu_rayleigh_ritz": ([vp, i, vp, i, l, vp], i),
+        "sparc_gpu_density": ([vp, i, vp, i, l, vp, vp], i),
+        "sparc_gpu_occupations": ([vp, vp, i, vp, vp], i),
+        "sparc_gpu_potential": ([vp, vp, vp, vp, vp, vp], i),
+        "sparc_gpu_pseudocharge": ([vp, vp, C.POINTER(d), C.POINTER(d)], i),
+        "sparc_gpu_sad_density": ([vp, vp], i),
+        "sparc_gpu_spectrum_bounds": ([vp, C.POINTER(d), C.POINTER(d)], i),
+        "sparc_gpu_scf_step": ([vp, C.POINTER(SCFState), C.POINTER(SCFReport)], i),
+        "sparc_gpu_final_rr_fp64": ([vp, C.POINTER(SCFState), vp, l, C.POINTER(SCFReport)], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    """Device address of a torch tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _prec_of(t):
+    import torch
+    if t.dtype == torch.float64:
+        return SPARC_FP64
+    if t.dtype == torch.float32:
+        return SPARC_FP32
+    raise TypeError(f"unsupported block dtype {t.dtype}")
+
+
+def _block(X):
+    """(ncol, ld) of a block stored as a torch tensor of shape (ncol, ld)."""
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("blocks are (ncol, ld) tensors with unit stride along the grid")
+    return X.shape[0], X.stride(0)
+
+
+class Context:
+    """One library context (``sparc_gpu_ctx``) for a ``workloads.System``."""
+
+    def __init__(self, system, stream=None):
+        import numpy as np
+        import torch
+        self.lib = load()
+        s = system
+        self._pos = np.ascontiguousarray(s.pos, dtype=np.float64).ravel()
+        self._Z = np.ascontiguousarray(s.Z, dtype=np.float64)
+        self._rc = np.ascontiguousarray(s.rc_loc, dtype=np.float64)
+        self._gamma = (np.ascontiguousarray(s.gamma, dtype=np.float64).ravel()
+                       if s.nl_lmax >= 0 and s.gamma is not None else None)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+        cs = System()
+        cs.n = (C.c_int * 3)(*[int(v) for v in s.n])
+        cs.L = (C.c_double * 3)(*[float(v) for v in s.L])
+        cs.fd_half_order = int(s.fd_half_order)
+        cs.n_atoms = int(s.n_atoms)
+        cs.pos = dp(self._pos)
+        cs.Z = dp(self._Z)
+        cs.rc_loc = dp(self._rc)
+        cs.nl_lmax = int(s.nl_lmax)
+        cs.gamma = dp(self._gamma)
+        cs.rc_nl = float(s.rc_nl)
+        cs.rcut_nl = float(s.rcut_nl)
+        cs.n_states = int(s.n_states)
+        cs.n_electrons = float(s.n_electrons)
+        cs.kT = float(s.kT)
+        cs.rho_floor = float(s.rho_floor)
+        cs.sad_width = float(s.sad_width)
+        self.system = s
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.sparc_gpu_create(C.byref(cs), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise SparcError(st, "sparc_gpu_create failed")
+        self.h = h
+        self.nd = int(self.lib.sparc_gpu_grid_size(h))
+        self.dV = float(self.lib.sparc_gpu_dV(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sparc_gpu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.sparc_gpu_last_error(self.h)
+            raise SparcError(st, msg.decode() if msg else "")
+
+    # ---- calls (same names as the C ABI) ----
+    def set_veff(self, veff):
+        self._check(self.lib.sparc_gpu_set_veff(self.h, _ptr(veff)))
+
+    def apply_H(self, X, Y):
+        ncol, ld = _block(X)
+        self._check(self.lib.sparc_gpu_apply_H(self.h, _prec_of(X), _ptr(X), _ptr(Y), ncol, ld))
+
+    def chebyshev_filter(self, X, work, degree, a, b, a0):
+        ncol, ld = _block(X)
+        self._check(self.lib.sparc_gpu_chebyshev_filter(self.h, _prec_of(X), _ptr(X), _ptr(work), ncol, ld,
+                                                        int(degree), float(a), float(b), float(a0)))
+
+    def rayleigh_ritz(self, X, eig):
+        ncol, ld = _block(X)
+        self._check(self.lib.sparc_gpu_rayleigh_ritz(self.h, _prec_of(X), _ptr(X), ncol, ld, _ptr(eig)))
+
+    def density(self, X, occ, rho):
+        ncol, ld = _block(X)
+        self._check(self.lib.sparc_gpu_density(self.h, _prec_of(X), _ptr(X), ncol, ld, _ptr(occ), _ptr(rho)))
+
+    def occupations(self, eig, occ, mu=None):
+        self._check(self.lib.sparc_gpu_occupations(self.h, _ptr(eig), int(eig.numel()), _ptr(occ), _ptr(mu)))
+
+    def potential(self, rho, phi=None, exc=None, vxc=None, veff=None):
+        self._check(self.lib.sparc_gpu_potential(self.h, _ptr(rho), _ptr(phi), _ptr(exc), _ptr(vxc), _ptr(veff)))
+
+    def pseudocharge(self, b=None):
+        es, ec = C.c_double(), C.c_double()
+        self._check(self.lib.sparc_gpu_pseudocharge(self.h, _ptr(b), C.byref(es), C.byref(ec)))
+        return es.value, ec.value
+
+    def sad_density(self, rho):
+        self._check(self.lib.sparc_gpu_sad_density(self.h, _ptr(rho)))
+
+    def spectrum_bounds(self):
+        lo, hi = C.c_double(), C.c_double()
+        self._check(self.lib.sparc_gpu_spectrum_bounds(self.h, C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def scf_step(self, state: SCFState) -> dict:
+        rep = SCFReport()
+        self._check(self.lib.sparc_gpu_scf_step(self.h, C.byref(state), C.byref(rep)))
+        return rep.as_dict()
+
+    def final_rr_fp64(self, state: SCFState, X64) -> dict:
+        rep = SCFReport()
+        ncol, ld = _block(X64)
+        self._check(self.lib.sparc_gpu_final_rr_fp64(self.h, C.byref(state), _ptr(X64), ld, C.byref(rep)))
+        return rep.as_dict()
+
+
+def make_state(rho_in, X, eig, occ, degree, n_first=4, beta=0.3, rho_out=None) -> SCFState:
+    st = SCFState()
+    st.d_rho_in = rho_in.data_ptr()
+    st.d_X = X.data_ptr()
+    st.ldx = X.stride(0)
+    st.prec = _prec_of(X)
+    st.cheb_degree = int(degree)
+    st.n_first = int(n_first)
+    st.mix_beta = float(beta)
+    st.iter = 0
+    st.d_eig = eig.data_ptr()
+    st.d_occ = occ.data_ptr()
+    st.d_rho_out = rho_out.data_ptr() if rho_out is not None else None
+    st.bounds = (C.c_double * 3)(0.0, 0.0, 0.0)
+    return st

@@ -1,0 +1,716 @@
+// Context creation, geometry tables and small public entry points.
+//
+// Geometry set-up (Sec. 2.1): uniform periodic grid, centred finite
+// differences, local real-space electrostatics with Gaussian pseudocharges,
+// and Kleinman-Bylander projector tables for the outer-product nonlocal
+// operator.  The host only enumerates which grid points (and periodic images)
+// fall inside each atom's cut-off; every field value is evaluated on the GPU.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace sg {
+
+sparc_status set_err(sparc_gpu_ctx c, sparc_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+sparc_status hip_err(sparc_gpu_ctx c, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return set_err(c, SPARC_ERR_NOMEM, m);
+    return set_err(c, SPARC_ERR_HIP, m);
+}
+
+static sparc_status grow(sparc_gpu_ctx c, void** p, size_t* have, size_t need) {
+    if (*have >= need) return SPARC_OK;
+    if (*p) {
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+        SG_HIP(c, hipFree(*p));
+        *p = nullptr;
+        *have = 0;
+    }
+    SG_HIP(c, hipMalloc(p, need));
+    *have = need;
+    return SPARC_OK;
+}
+
+sparc_status ensure_work(sparc_gpu_ctx c, size_t bytes) { return grow(c, &c->work, &c->work_bytes, bytes); }
+
+sparc_status ensure_gemm_part(sparc_gpu_ctx c, size_t elems) {
+    size_t have = c->gemm_part_elems * sizeof(double);
+    sparc_status s = grow(c, (void**)&c->gemm_part, &have, elems * sizeof(double));
+    c->gemm_part_elems = have / sizeof(double);
+    return s;
+}
+
+sparc_status ensure_small(sparc_gpu_ctx c, size_t elems) {
+    size_t have = c->small_elems * sizeof(double);
+    sparc_status s = grow(c, (void**)&c->small, &have, elems * sizeof(double));
+    c->small_elems = have / sizeof(double);
+    return s;
+}
+
+sparc_status ensure_red(sparc_gpu_ctx c, size_t elems) {
+    size_t have = c->red_elems * sizeof(double);
+    sparc_status s = grow(c, (void**)&c->red, &have, elems * sizeof(double));
+    c->red_elems = have / sizeof(double);
+    return s;
+}
+
+sparc_status ensure_fields(sparc_gpu_ctx c, int n) {
+    if (c->n_field >= n) return SPARC_OK;
+    size_t have = (size_t)c->n_field * c->nd * sizeof(double);
+    sparc_status s = grow(c, (void**)&c->field, &have, (size_t)n * c->nd * sizeof(double));
+    if (s == SPARC_OK) c->n_field = n;
+    return s;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// b(p) = -sum_I sum_images Z_I (pi rc_I^2)^-3/2 exp(-d^2/rc_I^2), d <= rmax_I
+// (or the analogous positive atomic densities when sign > 0).
+struct AtomImages {
+    double x, y, z;     // position
+    double amp;         // prefactor of the Gaussian
+    double inv_w2;      // 1 / width^2
+    double rmax2;       // squared cut-off
+    int n0[3], n1[3];   // image shift ranges per axis
+};
+
+__global__ void k_gaussian_field(const AtomImages* at, int n_atoms, int nx, int ny, int nz, double hx,
+                                 double hy, double hz, double Lx, double Ly, double Lz, double* out) {
+    long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long nd = (long)nx * ny * nz;
+    if (p >= nd) return;
+    int ix = (int)(p % nx);
+    int iy = (int)((p / nx) % ny);
+    int iz = (int)(p / ((long)nx * ny));
+    double px = ix * hx, py = iy * hy, pz = iz * hz;
+    double acc = 0.0;
+    for (int a = 0; a < n_atoms; ++a) {
+        AtomImages A = at[a];
+        for (int kz = A.n0[2]; kz <= A.n1[2]; ++kz) {
+            double dz = pz - A.z - kz * Lz;
+            for (int ky = A.n0[1]; ky <= A.n1[1]; ++ky) {
+                double dy = py - A.y - ky * Ly;
+                for (int kx = A.n0[0]; kx <= A.n1[0]; ++kx) {
+                    double dx = px - A.x - kx * Lx;
+                    double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 <= A.rmax2) acc += A.amp * exp(-r2 * A.inv_w2);
+                }
+            }
+        }
+    }
+    out[p] = acc;
+}
+
+// One block per atom: 1/2 dV sum over its (unwrapped) ball of b_I V_I, with
+// V_I(r) = -Z erf(r/rc)/r and its r -> 0 limit.  Partial per atom.
+__global__ void k_self_energy(const AtomImages* at, const double* Zs, const double* rcs, int n_atoms, double hx,
+                              double hy, double hz, double dV, double* part) {
+    int a = blockIdx.x;
+    AtomImages A = at[a];
+    double Z = Zs[a], rc = rcs[a];
+    double rmax = sqrt(A.rmax2);
+    int lo[3], hi[3];
+    double c[3] = {A.x, A.y, A.z}, h[3] = {hx, hy, hz};
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = (int)ceil((c[d] - rmax) / h[d]);
+        hi[d] = (int)floor((c[d] + rmax) / h[d]);
+    }
+    int nxb = hi[0] - lo[0] + 1, nyb = hi[1] - lo[1] + 1, nzb = hi[2] - lo[2] + 1;
+    long tot = (long)nxb * nyb * nzb;
+    double acc = 0.0;
+    const double pi = 3.14159265358979323846;
+    for (long t = threadIdx.x; t < tot; t += blockDim.x) {
+        int i = lo[0] + (int)(t % nxb);
+        int j = lo[1] + (int)((t / nxb) % nyb);
+        int k = lo[2] + (int)(t / ((long)nxb * nyb));
+        double dx = i * hx - A.x, dy = j * hy - A.y, dz = k * hz - A.z;
+        double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 > A.rmax2) continue;
+        double bI = A.amp * exp(-r2 * A.inv_w2);
+        double r = sqrt(r2);
+        double V = (r < 1e-12) ? -2.0 * Z / (sqrt(pi) * rc) : -Z * erf(r / rc) / r;
+        acc += bI * V;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[a] = 0.5 * dV * red[0];
+}
+
+// Overlap correction: thread per ordered pair (I, J), images with d < rmax.
+__global__ void k_overlap(const double* pos, const double* Z, const double* rc, int n_atoms, double Lx, double Ly,
+                          double Lz, double rmax, int nimx, int nimy, int nimz, double* part) {
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n_atoms * n_atoms) return;
+    int I = (int)(t / n_atoms), J = (int)(t % n_atoms);
+    double s = sqrt(rc[I] * rc[I] + rc[J] * rc[J]);
+    double acc = 0.0;
+    for (int a = -nimx; a <= nimx; ++a)
+        for (int b = -nimy; b <= nimy; ++b)
+            for (int cc = -nimz; cc <= nimz; ++cc) {
+                if (I == J && a == 0 && b == 0 && cc == 0) continue;
+                double dx = pos[3 * J] + a * Lx - pos[3 * I];
+                double dy = pos[3 * J + 1] + b * Ly - pos[3 * I + 1];
+                double dz = pos[3 * J + 2] + cc * Lz - pos[3 * I + 2];
+                double d = sqrt(dx * dx + dy * dy + dz * dz);
+                if (d < rmax) acc += 0.5 * Z[I] * Z[J] * erfc(d / s) / d;
+            }
+    part[t] = acc;
+}
+
+// Fixed-order sum of n values by one block (deterministic).
+__global__ void k_sum_serial(const double* v, long n, double* out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (long i = threadIdx.x; i < n; i += blockDim.x) acc += v[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// Projector values on each unique support point: sum over its periodic images
+// of chi_s = N0 e, chi_p = N1 {dx,dy,dz} e, e = exp(-r^2/rc^2).
+__global__ void k_projector_values(const int* img_off, const int* img_ijk, const int* sup_atom, const double* pos,
+                                   long n_sup, double hx, double hy, double hz, double inv_rc2, double N0, double N1,
+                                   double* chi) {
+    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sup) return;
+    int a = sup_atom[s];
+    double ax = pos[3 * a], ay = pos[3 * a + 1], az = pos[3 * a + 2];
+    double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    for (int e = img_off[s]; e < img_off[s + 1]; ++e) {
+        double dx = img_ijk[3 * e] * hx - ax;
+        double dy = img_ijk[3 * e + 1] * hy - ay;
+        double dz = img_ijk[3 * e + 2] * hz - az;
+        double ex = exp(-(dx * dx + dy * dy + dz * dz) * inv_rc2);
+        v0 += N0 * ex;
+        v1 += N1 * dx * ex;
+        v2 += N1 * dy * ex;
+        v3 += N1 * dz * ex;
+    }
+    chi[4 * s + 0] = v0;
+    chi[4 * s + 1] = v1;
+    chi[4 * s + 2] = v2;
+    chi[4 * s + 3] = v3;
+}
+
+__global__ void k_gather_chi(const int* pt_src, long n, const double* sup_chi, double* pt_chi, float* pt_chi32,
+                             float* sup_chi32) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int s = pt_src[e];
+    for (int k = 0; k < 4; ++k) {
+        double v = sup_chi[4 * (long)s + k];
+        pt_chi[4 * e + k] = v;
+        pt_chi32[4 * e + k] = (float)v;
+        sup_chi32[4 * e + k] = (float)sup_chi[4 * e + k];
+    }
+}
+
+// dV ||chi_lm||^2 per atom (one block per atom).
+__global__ void k_projector_norms(const long* sup_off, const double* chi, double dV, double* norms) {
+    int a = blockIdx.x;
+    __shared__ double red[4][256];
+    double acc[4] = {0, 0, 0, 0};
+    for (long s = sup_off[a] + threadIdx.x; s < sup_off[a + 1]; s += blockDim.x)
+        for (int k = 0; k < 4; ++k) acc[k] += chi[4 * s + k] * chi[4 * s + k];
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) norms[4 * a + threadIdx.x] = dV * red[threadIdx.x][0];
+}
+
+__global__ void k_scale(double* v, long n, const double* num, double target) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] *= target / *num;
+}
+
+// ------------------------------------------------------------------ host set-up
+
+static long factorial(int n) {
+    long r = 1;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+
+// Centred second-derivative weights of order 2 n_o:
+//   w_q = 2 (-1)^(q+1) (n_o!)^2 / (q^2 (n_o-q)! (n_o+q)!),  w_0 = -2 sum w_q.
+static void fd_weights(int n_o, double* w) {
+    double s = 0.0;
+    for (int q = 1; q <= n_o; ++q) {
+        double num = 2.0 * ((q % 2) ? 1.0 : -1.0) * (double)factorial(n_o) * (double)factorial(n_o);
+        double den = (double)q * q * (double)factorial(n_o - q) * (double)factorial(n_o + q);
+        w[q] = num / den;
+        s += w[q];
+    }
+    w[0] = -2.0 * s;
+    for (int q = n_o + 1; q <= kMaxHalfOrder; ++q) w[q] = 0.0;
+}
+
+static AtomImages make_images(const sparc_gpu_ctx c, int a, double amp, double width, double rmax) {
+    AtomImages A;
+    A.x = c->pos[3 * a];
+    A.y = c->pos[3 * a + 1];
+    A.z = c->pos[3 * a + 2];
+    A.amp = amp;
+    A.inv_w2 = 1.0 / (width * width);
+    A.rmax2 = rmax * rmax;
+    double P[3] = {A.x, A.y, A.z}, L[3] = {c->Lx, c->Ly, c->Lz};
+    for (int d = 0; d < 3; ++d) {
+        // shifts n with |x - P - n L| <= rmax for some x in [0, L)
+        A.n0[d] = (int)std::floor((0.0 - P[d] - rmax) / L[d]) - 1;
+        A.n1[d] = (int)std::ceil((L[d] - P[d] + rmax) / L[d]) + 1;
+    }
+    return A;
+}
+
+template <typename V>
+static sparc_status upload(sparc_gpu_ctx c, V** dst, const std::vector<V>& src) {
+    SG_HIP(c, hipMalloc((void**)dst, std::max<size_t>(1, src.size()) * sizeof(V)));
+    if (!src.empty())
+        SG_HIP(c, hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice, c->stream));
+    return SPARC_OK;
+}
+
+static sparc_status gaussian_field(sparc_gpu_ctx c, double sign, double* out, bool sad) {
+    std::vector<AtomImages> at(c->n_atoms);
+    const double pi = 3.14159265358979323846;
+    for (int a = 0; a < c->n_atoms; ++a) {
+        double w = sad ? c->sad_width : c->rc_loc[a];
+        double amp = sign * c->Z[a] * std::pow(pi * w * w, -1.5);
+        at[a] = make_images(c, a, amp, w, 8.0 * w);
+    }
+    AtomImages* d_at = nullptr;
+    sparc_status s = upload(c, &d_at, at);
+    if (s != SPARC_OK) return s;
+    k_gaussian_field<<<div_up(c->nd, 256), 256, 0, c->stream>>>(d_at, c->n_atoms, c->nx, c->ny, c->nz, c->hx, c->hy,
+                                                                 c->hz, c->Lx, c->Ly, c->Lz, out);
+    SG_CHECK_LAUNCH(c);
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    SG_HIP(c, hipFree(d_at));
+    return SPARC_OK;
+}
+
+// Real orthonormal eigenbasis of the periodic 1D stencil: columns are the
+// constant, cos/sin pairs and (N even) the alternating mode.  freq[k] is the
+// integer frequency of column k.
+static void fourier_basis(int N, std::vector<double>& U, std::vector<int>& freq) {
+    const double pi = 3.14159265358979323846;
+    U.assign((size_t)N * N, 0.0);
+    freq.assign(N, 0);
+    int col = 0;
+    for (int j = 0; j < N; ++j) U[j + (size_t)N * col] = 1.0 / std::sqrt((double)N);
+    freq[col++] = 0;
+    for (int k = 1; 2 * k < N; ++k) {
+        for (int j = 0; j < N; ++j) {
+            double th = 2.0 * pi * (double)k * (double)j / N;
+            U[j + (size_t)N * col] = std::sqrt(2.0 / N) * std::cos(th);
+            U[j + (size_t)N * (col + 1)] = std::sqrt(2.0 / N) * std::sin(th);
+        }
+        freq[col] = k;
+        freq[col + 1] = k;
+        col += 2;
+    }
+    if (N % 2 == 0) {
+        for (int j = 0; j < N; ++j) U[j + (size_t)N * col] = (j % 2 ? -1.0 : 1.0) / std::sqrt((double)N);
+        freq[col++] = N / 2;
+    }
+}
+
+static double symbol(const double* w, int n_o, double th) {
+    double s = w[0];
+    for (int q = 1; q <= n_o; ++q) s += 2.0 * w[q] * std::cos(q * th);
+    return s;
+}
+
+sparc_status build_tables(sparc_gpu_ctx c) {
+#pragma clang fp contract(off)
+    const double pi = 3.14159265358979323846;
+    // --- stencil coefficients of -1/2 Delta_h
+    fd_weights(c->n_o, c->w);
+    double ix2 = 1.0 / (c->hx * c->hx), iy2 = 1.0 / (c->hy * c->hy), iz2 = 1.0 / (c->hz * c->hz);
+    for (int q = 0; q <= kMaxHalfOrder; ++q) {
+        c->cf64.cx[q] = -0.5 * c->w[q] * ix2;
+        c->cf64.cy[q] = -0.5 * c->w[q] * iy2;
+        c->cf64.cz[q] = -0.5 * c->w[q] * iz2;
+        c->cf32.cx[q] = (float)c->cf64.cx[q];
+        c->cf32.cy[q] = (float)c->cf64.cy[q];
+        c->cf32.cz[q] = (float)c->cf64.cz[q];
+    }
+    c->cf64.c0 = -0.5 * c->w[0] * (ix2 + iy2 + iz2);
+    c->cf32.c0 = (float)c->cf64.c0;
+    double spi = std::fabs(symbol(c->w, c->n_o, pi));
+    c->kin_bound = 0.5 * spi * (ix2 + iy2 + iz2);
+
+    // --- device scalars and flags
+    SG_HIP(c, hipMalloc((void**)&c->scal, S_COUNT * sizeof(double)));
+    SG_HIP(c, hipMalloc((void**)&c->flags, F_COUNT * sizeof(int)));
+    SG_HIP(c, hipMemsetAsync(c->scal, 0, S_COUNT * sizeof(double), c->stream));
+    SG_HIP(c, hipMemsetAsync(c->flags, 0, F_COUNT * sizeof(int), c->stream));
+    SG_HIP(c, hipMalloc((void**)&c->veff, c->nd * sizeof(double)));
+    SG_HIP(c, hipMalloc((void**)&c->veff32, c->nd * sizeof(float)));
+    SG_HIP(c, hipMemsetAsync(c->veff, 0, c->nd * sizeof(double), c->stream));
+    SG_HIP(c, hipMemsetAsync(c->veff32, 0, c->nd * sizeof(float), c->stream));
+
+    // --- pseudocharge
+    SG_HIP(c, hipMalloc((void**)&c->b, c->nd * sizeof(double)));
+    sparc_status st = gaussian_field(c, -1.0, c->b, false);
+    if (st != SPARC_OK) return st;
+
+    // --- self energy and overlap correction
+    {
+        std::vector<AtomImages> at(c->n_atoms);
+        for (int a = 0; a < c->n_atoms; ++a) {
+            double rc = c->rc_loc[a];
+            at[a] = make_images(c, a, -c->Z[a] * std::pow(pi * rc * rc, -1.5), rc, 8.0 * rc);
+        }
+        AtomImages* d_at = nullptr;
+        double *d_Z = nullptr, *d_rc = nullptr, *d_pos = nullptr, *d_part = nullptr, *d_sum = nullptr;
+        if ((st = upload(c, &d_at, at)) != SPARC_OK) return st;
+        if ((st = upload(c, &d_Z, c->Z)) != SPARC_OK) return st;
+        if ((st = upload(c, &d_rc, c->rc_loc)) != SPARC_OK) return st;
+        if ((st = upload(c, &d_pos, c->pos)) != SPARC_OK) return st;
+        long npair = (long)c->n_atoms * c->n_atoms;
+        SG_HIP(c, hipMalloc((void**)&d_part, std::max<long>(npair, c->n_atoms) * sizeof(double)));
+        SG_HIP(c, hipMalloc((void**)&d_sum, 2 * sizeof(double)));
+        k_self_energy<<<c->n_atoms, 256, 0, c->stream>>>(d_at, d_Z, d_rc, c->n_atoms, c->hx, c->hy, c->hz, c->dV,
+                                                        d_part);
+        SG_CHECK_LAUNCH(c);
+        k_sum_serial<<<1, 256, 0, c->stream>>>(d_part, c->n_atoms, d_sum);
+        const double rmax = 10.0;
+        int nim[3] = {(int)std::ceil(rmax / c->Lx) + 1, (int)std::ceil(rmax / c->Ly) + 1,
+                      (int)std::ceil(rmax / c->Lz) + 1};
+        k_overlap<<<div_up(npair, 128), 128, 0, c->stream>>>(d_pos, d_Z, d_rc, c->n_atoms, c->Lx, c->Ly, c->Lz, rmax,
+                                                            nim[0], nim[1], nim[2], d_part);
+        SG_CHECK_LAUNCH(c);
+        k_sum_serial<<<1, 256, 0, c->stream>>>(d_part, npair, d_sum + 1);
+        double h2[2];
+        SG_HIP(c, hipMemcpyAsync(h2, d_sum, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+        c->e_self = h2[0];
+        c->e_c = h2[1];
+        hipFree(d_at);
+        hipFree(d_Z);
+        hipFree(d_rc);
+        hipFree(d_part);
+        hipFree(d_sum);
+        hipFree(d_pos);
+    }
+
+    // --- nonlocal projector tables
+    if (c->nl_lmax >= 1) {
+        sg::NonlocalTables& T = c->nl;
+        T.n_atoms = c->n_atoms;
+        std::vector<long> sup_off(c->n_atoms + 1, 0);
+        std::vector<int> sup_idx, sup_atom, img_off(1, 0), img_ijk;
+        const double rcut = c->rcut_nl, r2max = rcut * rcut;
+        const double h[3] = {c->hx, c->hy, c->hz};
+        const int n[3] = {c->nx, c->ny, c->nz};
+        for (int a = 0; a < c->n_atoms; ++a) {
+            const double* P = &c->pos[3 * a];
+            int lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = (int)std::ceil((P[d] - rcut) / h[d]);
+                hi[d] = (int)std::floor((P[d] + rcut) / h[d]);
+            }
+            // (flat index, unwrapped i, j, k) of every image point in the ball
+            std::vector<std::pair<long, std::array<int, 3>>> pts;
+            for (int k = lo[2]; k <= hi[2]; ++k) {
+                double dz = k * h[2] - P[2];
+                for (int j = lo[1]; j <= hi[1]; ++j) {
+                    double dy = j * h[1] - P[1];
+                    for (int i = lo[0]; i <= hi[0]; ++i) {
+                        double dx = i * h[0] - P[0];
+                        double r2 = dx * dx + dy * dy;
+                        r2 = r2 + dz * dz;
+                        if (r2 > r2max) continue;
+                        int wi = ((i % n[0]) + n[0]) % n[0];
+                        int wj = ((j % n[1]) + n[1]) % n[1];
+                        int wk = ((k % n[2]) + n[2]) % n[2];
+                        long flat = wi + (long)n[0] * (wj + (long)n[1] * wk);
+                        pts.push_back({flat, {i, j, k}});
+                    }
+                }
+            }
+            std::stable_sort(pts.begin(), pts.end(),
+                             [](const auto& A, const auto& B) { return A.first < B.first; });
+            long prev = -1;
+            for (auto& q : pts) {
+                if (q.first != prev) {
+                    if (prev >= 0) img_off.push_back((int)(img_ijk.size() / 3));
+                    sup_idx.push_back((int)q.first);
+                    sup_atom.push_back(a);
+                    prev = q.first;
+                }
+                img_ijk.push_back(q.second[0]);
+                img_ijk.push_back(q.second[1]);
+                img_ijk.push_back(q.second[2]);
+            }
+            if (prev >= 0) img_off.push_back((int)(img_ijk.size() / 3));
+            sup_off[a + 1] = (long)sup_idx.size();
+            T.max_per_atom = std::max<int>(T.max_per_atom, (int)(sup_off[a + 1] - sup_off[a]));
+        }
+        T.n_sup = (long)sup_idx.size();
+        // point-major inverse lists (entries per point in atom order)
+        std::vector<int> pt_off(c->nd + 1, 0), pt_atom(T.n_sup), pt_src(T.n_sup);
+        for (long s = 0; s < T.n_sup; ++s) pt_off[sup_idx[s] + 1]++;
+        for (long p = 0; p < c->nd; ++p) pt_off[p + 1] += pt_off[p];
+        {
+            std::vector<int> fill(pt_off.begin(), pt_off.end() - 1);
+            for (long s = 0; s < T.n_sup; ++s) {
+                int e = fill[sup_idx[s]]++;
+                pt_atom[e] = sup_atom[s];
+                pt_src[e] = (int)s;
+            }
+        }
+        std::vector<double> g4(4 * c->n_atoms);
+        for (int a = 0; a < c->n_atoms; ++a) {
+            g4[4 * a] = c->gamma[2 * a];
+            g4[4 * a + 1] = g4[4 * a + 2] = g4[4 * a + 3] = c->gamma[2 * a + 1];
+        }
+        int *d_img_off = nullptr, *d_img_ijk = nullptr, *d_sup_atom = nullptr, *d_pt_src = nullptr;
+        double* d_pos = nullptr;
+        if ((st = upload(c, &T.sup_off, sup_off)) != SPARC_OK) return st;
+        if ((st = upload(c, &T.sup_idx, sup_idx)) != SPARC_OK) return st;
+        if ((st = upload(c, &T.pt_off, pt_off)) != SPARC_OK) return st;
+        if ((st = upload(c, &T.pt_atom, pt_atom)) != SPARC_OK) return st;
+        if ((st = upload(c, &T.gamma4, g4)) != SPARC_OK) return st;
+        if ((st = upload(c, &d_img_off, img_off)) != SPARC_OK) return st;
+        if ((st = upload(c, &d_img_ijk, img_ijk)) != SPARC_OK) return st;
+        if ((st = upload(c, &d_sup_atom, sup_atom)) != SPARC_OK) return st;
+        if ((st = upload(c, &d_pt_src, pt_src)) != SPARC_OK) return st;
+        if ((st = upload(c, &d_pos, c->pos)) != SPARC_OK) return st;
+        long ns = std::max<long>(T.n_sup, 1);
+        SG_HIP(c, hipMalloc((void**)&T.sup_chi, 4 * ns * sizeof(double)));
+        SG_HIP(c, hipMalloc((void**)&T.sup_chi32, 4 * ns * sizeof(float)));
+        SG_HIP(c, hipMalloc((void**)&T.pt_chi, 4 * ns * sizeof(double)));
+        SG_HIP(c, hipMalloc((void**)&T.pt_chi32, 4 * ns * sizeof(float)));
+        double rc = c->rc_nl;
+        double N0 = std::pow(2.0 / (pi * rc * rc), 0.75);
+        double N1 = (2.0 / rc) * N0;
+        if (T.n_sup > 0) {
+            k_projector_values<<<div_up(T.n_sup, 256), 256, 0, c->stream>>>(
+                d_img_off, d_img_ijk, d_sup_atom, d_pos, T.n_sup, c->hx, c->hy, c->hz, 1.0 / (rc * rc), N0, N1,
+                T.sup_chi);
+            SG_CHECK_LAUNCH(c);
+            k_gather_chi<<<div_up(T.n_sup, 256), 256, 0, c->stream>>>(d_pt_src, T.n_sup, T.sup_chi, T.pt_chi,
+                                                                      T.pt_chi32, T.sup_chi32);
+            SG_CHECK_LAUNCH(c);
+        }
+        double* d_norms = nullptr;
+        SG_HIP(c, hipMalloc((void**)&d_norms, 4 * c->n_atoms * sizeof(double)));
+        k_projector_norms<<<c->n_atoms, 256, 0, c->stream>>>(T.sup_off, T.sup_chi, c->dV, d_norms);
+        SG_CHECK_LAUNCH(c);
+        std::vector<double> norms(4 * c->n_atoms);
+        SG_HIP(c, hipMemcpyAsync(norms.data(), d_norms, norms.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+        T.nl_hi = T.nl_lo = 0.0;
+        for (int a = 0; a < c->n_atoms; ++a)
+            for (int k = 0; k < 4; ++k) {
+                T.nl_hi += std::max(g4[4 * a + k], 0.0) * norms[4 * a + k];
+                T.nl_lo += std::min(g4[4 * a + k], 0.0) * norms[4 * a + k];
+            }
+        hipFree(d_norms);
+        hipFree(d_img_off);
+        hipFree(d_img_ijk);
+        hipFree(d_sup_atom);
+        hipFree(d_pt_src);
+        hipFree(d_pos);
+        SG_HIP(c, hipMalloc((void**)&c->D, std::max<size_t>(1, 4 * (size_t)c->n_atoms * c->n_states) * sizeof(double)));
+        SG_HIP(c, hipMalloc((void**)&c->D32, std::max<size_t>(1, 4 * (size_t)c->n_atoms * c->n_states) * sizeof(float)));
+    }
+
+    // --- Poisson eigenbases
+    {
+        std::vector<double> Ux, Uy, Uz;
+        std::vector<int> fx, fy, fz;
+        fourier_basis(c->nx, Ux, fx);
+        fourier_basis(c->ny, Uy, fy);
+        fourier_basis(c->nz, Uz, fz);
+        std::vector<double> inv(c->nd);
+        for (int k = 0; k < c->nz; ++k)
+            for (int j = 0; j < c->ny; ++j)
+                for (int i = 0; i < c->nx; ++i) {
+                    double lam = -symbol(c->w, c->n_o, 2.0 * pi * fx[i] / c->nx) * ix2 -
+                                 symbol(c->w, c->n_o, 2.0 * pi * fy[j] / c->ny) * iy2 -
+                                 symbol(c->w, c->n_o, 2.0 * pi * fz[k] / c->nz) * iz2;
+                    long p = i + (long)c->nx * (j + (long)c->ny * k);
+                    inv[p] = (i == 0 && j == 0 && k == 0) ? 0.0 : 4.0 * pi / lam;
+                }
+        if ((st = upload(c, &c->pois_ux, Ux)) != SPARC_OK) return st;
+        if ((st = upload(c, &c->pois_uy, Uy)) != SPARC_OK) return st;
+        if ((st = upload(c, &c->pois_uz, Uz)) != SPARC_OK) return st;
+        if ((st = upload(c, &c->pois_inv, inv)) != SPARC_OK) return st;
+    }
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    return SPARC_OK;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc_gpu_ctx* out) {
+    if (!out) return SPARC_ERR_ARG;
+    *out = nullptr;
+    if (!s) return SPARC_ERR_ARG;
+    const int mino = 2 * s->fd_half_order + 1;
+    if (s->fd_half_order < 1 || s->fd_half_order > kMaxHalfOrder) return SPARC_ERR_ARG;
+    for (int d = 0; d < 3; ++d) {
+        if (s->n[d] < mino || s->n[d] > 4096) return SPARC_ERR_ARG;
+        if (!(s->L[d] > 0.0) || !std::isfinite(s->L[d])) return SPARC_ERR_ARG;
+    }
+    if (s->n[0] > 1024 - 2 * kMaxHalfOrder) return SPARC_ERR_ARG;
+    if ((long)s->n[0] * s->n[1] * s->n[2] > (1L << 31) - 1) return SPARC_ERR_ARG;
+    if (s->n_atoms < 0 || (s->n_atoms > 0 && (!s->pos || !s->Z || !s->rc_loc))) return SPARC_ERR_ARG;
+    if (s->nl_lmax != -1 && s->nl_lmax != 1) return SPARC_ERR_ARG;
+    if (s->nl_lmax == 1 && (!s->gamma || !(s->rc_nl > 0) || !(s->rcut_nl > 0))) return SPARC_ERR_ARG;
+    if (s->n_states < 1) return SPARC_ERR_ARG;
+    if (!(s->n_electrons > 0.0) || s->n_electrons > 2.0 * s->n_states) return SPARC_ERR_ARG;
+    if (!(s->kT > 0.0)) return SPARC_ERR_ARG;
+    if (!(s->sad_width > 0.0)) return SPARC_ERR_ARG;
+    for (int a = 0; a < s->n_atoms; ++a) {
+        if (!(s->rc_loc[a] > 0.0) || !std::isfinite(s->Z[a])) return SPARC_ERR_ARG;
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(s->pos[3 * a + d])) return SPARC_ERR_ARG;
+    }
+
+    sparc_gpu_ctx c = new (std::nothrow) sparc_gpu_ctx_s();
+    if (!c) return SPARC_ERR_NOMEM;
+    c->nx = s->n[0];
+    c->ny = s->n[1];
+    c->nz = s->n[2];
+    c->nd = (long)c->nx * c->ny * c->nz;
+    c->Lx = s->L[0];
+    c->Ly = s->L[1];
+    c->Lz = s->L[2];
+    c->hx = c->Lx / c->nx;
+    c->hy = c->Ly / c->ny;
+    c->hz = c->Lz / c->nz;
+    c->dV = c->hx * c->hy * c->hz;
+    c->n_o = s->fd_half_order;
+    c->n_atoms = s->n_atoms;
+    c->pos.assign(s->pos, s->pos + 3 * s->n_atoms);
+    c->Z.assign(s->Z, s->Z + s->n_atoms);
+    c->rc_loc.assign(s->rc_loc, s->rc_loc + s->n_atoms);
+    c->nl_lmax = s->nl_lmax;
+    if (s->nl_lmax == 1) c->gamma.assign(s->gamma, s->gamma + 2 * s->n_atoms);
+    c->rc_nl = s->rc_nl;
+    c->rcut_nl = s->rcut_nl;
+    c->n_states = s->n_states;
+    c->n_electrons = s->n_electrons;
+    c->kT = s->kT;
+    c->rho_floor = s->rho_floor;
+    c->sad_width = s->sad_width;
+    c->stream = (hipStream_t)hip_stream;
+    for (int i = 0; i < 8; ++i) c->ev[i] = nullptr;
+
+    int dev = 0;
+    sparc_status st = SPARC_OK;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&c->prop, dev);
+    for (int i = 0; e == hipSuccess && i < 8; ++i) e = hipEventCreate(&c->ev[i]);
+    if (e != hipSuccess) {
+        st = hip_err(c, e, "device query");
+    } else {
+        st = build_tables(c);
+    }
+    if (st != SPARC_OK) {
+        sparc_gpu_destroy(c);
+        return st;
+    }
+    *out = c;
+    return SPARC_OK;
+}
+
+sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
+    if (!c) return SPARC_ERR_ARG;
+    hipStreamSynchronize(c->stream);
+    void* ptrs[] = {c->veff, c->veff32, c->b, c->pois_ux, c->pois_uy, c->pois_uz, c->pois_inv, c->work, c->D,
+                    c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,
+                    c->nl.sup_idx, c->nl.sup_chi, c->nl.sup_chi32, c->nl.pt_off, c->nl.pt_atom, c->nl.pt_chi,
+                    c->nl.pt_chi32, c->nl.gamma4};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    for (int i = 0; i < 8; ++i)
+        if (c->ev[i]) hipEventDestroy(c->ev[i]);
+    delete c;
+    return SPARC_OK;
+}
+
+const char* sparc_gpu_last_error(sparc_gpu_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+long sparc_gpu_grid_size(sparc_gpu_ctx c) { return c ? c->nd : 0; }
+
+double sparc_gpu_dV(sparc_gpu_ctx c) { return c ? c->dV : 0.0; }
+
+sparc_status sparc_gpu_set_veff(sparc_gpu_ctx c, const double* d_veff) {
+    if (!c) return SPARC_ERR_ARG;
+    if (!d_veff) return set_err(c, SPARC_ERR_ARG, "set_veff: null pointer");
+    c->err.clear();
+    return set_veff_impl(c, d_veff);
+}
+
+sparc_status sparc_gpu_pseudocharge(sparc_gpu_ctx c, double* d_b, double* e_self, double* e_c) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (d_b) SG_HIP(c, hipMemcpyAsync(d_b, c->b, c->nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (e_self) *e_self = c->e_self;
+    if (e_c) *e_c = c->e_c;
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    return SPARC_OK;
+}
+
+sparc_status sparc_gpu_sad_density(sparc_gpu_ctx c, double* d_rho) {
+    if (!c) return SPARC_ERR_ARG;
+    if (!d_rho) return set_err(c, SPARC_ERR_ARG, "sad_density: null pointer");
+    c->err.clear();
+    sparc_status st = gaussian_field(c, +1.0, d_rho, true);
+    if (st != SPARC_OK) return st;
+    k_sum_serial<<<1, 256, 0, c->stream>>>(d_rho, c->nd, c->scal + S_RED0);
+    SG_CHECK_LAUNCH(c);
+    k_scale<<<div_up(c->nd, 256), 256, 0, c->stream>>>(d_rho, c->nd, c->scal + S_RED0, c->n_electrons / c->dV);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+sparc_status sparc_gpu_spectrum_bounds(sparc_gpu_ctx c, double* lo, double* hi) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = bounds_impl(c);
+    if (st != SPARC_OK) return st;
+    double h2[2];
+    SG_HIP(c, hipMemcpyAsync(h2, c->scal + S_LO, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    if (lo) *lo = h2[0];
+    if (hi) *hi = h2[1];
+    return SPARC_OK;
+}
+
+}  // extern "C"
+

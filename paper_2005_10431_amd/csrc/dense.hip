@@ -1,0 +1,400 @@
+// FP64 subspace algebra of Rayleigh-Ritz (the N_s x N_s part of CheFSI,
+// Sec. 2.1; the paper notes its cubic cost limits scaling, Sec. 4):
+// Cholesky of the Gram matrix, inverse of its triangular factor, small
+// products, and a parallel cyclic Jacobi eigensolver.
+//
+// All matrices are N x N, column-major, leading dimension N, in device memory.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace sg {
+
+// Pivots at or below this fraction of their original diagonal entry mean a
+// numerically rank-deficient block (about 64 units of rounding).
+constexpr double kPivotRtol = 64.0 * 2.220446049250313e-16;
+
+// Right-looking Cholesky M = L L^T in place (lower triangle), one workgroup.
+// flag[0] is set on a non-positive (relative) pivot or a non-finite entry.
+__global__ __launch_bounds__(1024) void k_cholesky(double* M, int N, int* flag) {
+    extern __shared__ double dorig[];
+    __shared__ int bad;
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int i = t; i < N; i += nt) dorig[i] = M[i + (long)i * N];
+    if (t == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < N; ++j) {
+        if (t == 0) {
+            double d = M[j + (long)j * N];
+            if (!(d > kPivotRtol * dorig[j]) || !isfinite(d)) {
+                bad = 1;
+            } else {
+                M[j + (long)j * N] = sqrt(d);
+            }
+        }
+        __syncthreads();
+        if (bad) {
+            if (t == 0) flag[0] = 1;
+            return;
+        }
+        const double ljj = M[j + (long)j * N];
+        for (int i = j + 1 + t; i < N; i += nt) M[i + (long)j * N] /= ljj;
+        __syncthreads();
+        const int nr = N - j - 1;
+        const long tot = (long)nr * nr;
+        for (long f = t; f < tot; f += nt) {
+            int i = j + 1 + (int)(f % nr);
+            int k = j + 1 + (int)(f / nr);
+            if (k <= i) M[i + (long)k * N] -= M[i + (long)j * N] * M[k + (long)j * N];
+        }
+        __syncthreads();
+    }
+    // zero the strict upper triangle so that M holds exactly L
+    for (long f = t; f < (long)N * N; f += nt) {
+        int i = (int)(f % N), k = (int)(f / N);
+        if (k > i) M[f] = 0.0;
+    }
+}
+
+sparc_status dense_cholesky(sparc_gpu_ctx c, double* M, int N, int* flag) {
+    k_cholesky<<<1, 1024, N * sizeof(double), c->stream>>>(M, N, flag);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+__global__ void k_transpose(const double* A, double* B, int N) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)N * N) return;
+    int i = (int)(e % N), j = (int)(e / N);
+    B[j + (long)i * N] = A[e];
+}
+
+// Column j of L^-1 by forward substitution, one wave per column; Lt = L^T
+// (so that row i of L is contiguous).
+__global__ __launch_bounds__(64) void k_tri_inv_col(const double* __restrict__ Lt, double* __restrict__ Linv, int N) {
+    extern __shared__ double xs[];
+    const int j = blockIdx.x, lane = threadIdx.x;
+    for (int i = lane; i < N; i += 64) xs[i] = 0.0;
+    __syncthreads();
+    if (lane == 0) xs[j] = 1.0 / Lt[j + (long)j * N];
+    __syncthreads();
+    for (int i = j + 1; i < N; ++i) {
+        const double* li = Lt + (long)i * N;  // L[i][k] = Lt[k + i N]
+        double s = 0.0;
+        for (int k = j + lane; k < i; k += 64) s += li[k] * xs[k];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        s = __shfl(s, 0, 64);
+        if (lane == 0) xs[i] = -s / li[i];
+        __syncthreads();
+    }
+    for (int i = lane; i < N; i += 64) Linv[i + (long)j * N] = xs[i];
+}
+
+sparc_status dense_tri_inverse_lower(sparc_gpu_ctx c, const double* L, double* Linv, int N) {
+    // Linv doubles as scratch for L^T first
+    double* Lt = c->small + 8 * (size_t)N * N;
+    k_transpose<<<div_up((long)N * N, 256), 256, 0, c->stream>>>(L, Lt, N);
+    SG_CHECK_LAUNCH(c);
+    k_tri_inv_col<<<N, 64, N * sizeof(double), c->stream>>>(Lt, Linv, N);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+// C = op(A) op(B), 16x16 tiles through LDS.
+__global__ __launch_bounds__(256) void k_small_gemm(int N, const double* __restrict__ A, bool ta,
+                                                    const double* __restrict__ B, bool tb, double* __restrict__ C) {
+    __shared__ double sA[16][17], sB[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + tx;  // row of C
+    const int j = blockIdx.y * 16 + ty;  // column of C
+    double acc = 0.0;
+    for (int k0 = 0; k0 < N; k0 += 16) {
+        // sA[tx][ty] = op(A)[i][k0 + ty]; sB[tx][ty] = op(B)[k0 + tx][j]
+        int k = k0 + ty;
+        double va = 0.0;
+        if (i < N && k < N) va = ta ? A[k + (long)i * N] : A[i + (long)k * N];
+        int kb = k0 + tx;
+        double vb = 0.0;
+        if (j < N && kb < N) vb = tb ? B[j + (long)kb * N] : B[kb + (long)j * N];
+        sA[tx][ty] = va;
+        sB[tx][ty] = vb;
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) acc += sA[tx][kk] * sB[kk][ty];
+        __syncthreads();
+    }
+    if (i < N && j < N) C[i + (long)j * N] = acc;
+}
+
+sparc_status dense_gemm(sparc_gpu_ctx c, char ta, char tb, int N, const double* A, const double* B, double* C) {
+    dim3 grid(div_up(N, 16), div_up(N, 16));
+    k_small_gemm<<<grid, 256, 0, c->stream>>>(N, A, ta == 'T', B, tb == 'T', C);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+__global__ void k_symmetrize(double* A, int N) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)N * N) return;
+    int i = (int)(e % N), j = (int)(e / N);
+    if (i < j) {
+        double v = 0.5 * (A[i + (long)j * N] + A[j + (long)i * N]);
+        A[i + (long)j * N] = v;
+        A[j + (long)i * N] = v;
+    }
+}
+
+sparc_status dense_symmetrize(sparc_gpu_ctx c, double* A, int N) {
+    k_symmetrize<<<div_up((long)N * N, 256), 256, 0, c->stream>>>(A, N);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+// ---------------------------------------------------------------- Jacobi
+
+// Round-robin pairing of P (even) players over rounds r = 0..P-2: player
+// P-1 meets r; any other i meets (2r - i) mod (P-1).
+__device__ inline int partner(int i, int r, int P) {
+    if (i == P - 1) return r;
+    if (i == r) return P - 1;
+    int q = (2 * r - i) % (P - 1);
+    return q < 0 ? q + (P - 1) : q;
+}
+
+// Rotation (c, g) of index i in round r: column i of J has J_ii = c and
+// J_{p(i), i} = g; for the pair lo < hi, t = sgn(z)/(|z| + sqrt(1 + z^2)),
+// z = (a_hh - a_ll) / (2 a_lh), c = 1/sqrt(1 + t^2), s = t c, g = -s at lo
+// and +s at hi; this zeroes a_lh.
+__device__ inline void rotation(const double* A, int N, int i, int p, double& cc, double& g) {
+    cc = 1.0;
+    g = 0.0;
+    if (p >= N || p == i) return;
+    int lo = min(i, p), hi = max(i, p);
+    double all = A[lo + (long)lo * N], ahh = A[hi + (long)hi * N], alh = A[lo + (long)hi * N];
+    if (alh == 0.0) return;
+    double z = (ahh - all) / (2.0 * alh);
+    double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+    double cs = 1.0 / sqrt(1.0 + t * t);
+    double s = t * cs;
+    cc = cs;
+    g = (i == lo) ? -s : s;
+}
+
+// A' = J^T A J and V' = V J for one round of disjoint rotations.
+__global__ __launch_bounds__(256) void k_jacobi_round(const double* __restrict__ A, double* __restrict__ An,
+                                                      const double* __restrict__ V, double* __restrict__ Vn, int N,
+                                                      int P, int r) {
+    __shared__ double ci[16], gi[16], cj[16], gj[16];
+    __shared__ int pi[16], pj[16];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+    if (threadIdx.x < 16) {
+        int i = i0 + threadIdx.x;
+        if (i < N) {
+            int p = partner(i, r, P);
+            double cc, g;
+            rotation(A, N, i, p, cc, g);
+            ci[threadIdx.x] = cc;
+            gi[threadIdx.x] = g;
+            pi[threadIdx.x] = p < N ? p : i;
+        }
+    } else if (threadIdx.x < 32) {
+        int j = j0 + threadIdx.x - 16;
+        if (j < N) {
+            int p = partner(j, r, P);
+            double cc, g;
+            rotation(A, N, j, p, cc, g);
+            cj[threadIdx.x - 16] = cc;
+            gj[threadIdx.x - 16] = g;
+            pj[threadIdx.x - 16] = p < N ? p : j;
+        }
+    }
+    __syncthreads();
+    const int i = i0 + tx, j = j0 + ty;
+    if (i >= N || j >= N) return;
+    const double c_i = ci[tx], g_i = gi[tx], c_j = cj[ty], g_j = gj[ty];
+    const int p_i = pi[tx], p_j = pj[ty];
+    double v = c_i * c_j * A[i + (long)j * N] + c_i * g_j * A[i + (long)p_j * N] +
+               g_i * c_j * A[p_i + (long)j * N] + g_i * g_j * A[p_i + (long)p_j * N];
+    An[i + (long)j * N] = v;
+    // V' = V J: row i of V, column j
+    Vn[i + (long)j * N] = V[i + (long)j * N] * c_j + V[i + (long)p_j * N] * g_j;
+}
+
+__global__ void k_identity(double* V, int N) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)N * N) return;
+    V[e] = ((e % N) == (e / N)) ? 1.0 : 0.0;
+}
+
+// out[0] = sum_{i != j} A_ij^2, out[1] = sum A_ij^2 (one block, fixed order)
+__global__ void k_offnorm(const double* A, int N, double* out) {
+    __shared__ double s0[1024], s1[1024];
+    double a = 0.0, b = 0.0;
+    for (long e = threadIdx.x; e < (long)N * N; e += blockDim.x) {
+        double v = A[e] * A[e];
+        b += v;
+        if ((e % N) != (e / N)) a += v;
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            s0[threadIdx.x] += s0[threadIdx.x + s];
+            s1[threadIdx.x] += s1[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s0[0];
+        out[1] = s1[0];
+    }
+}
+
+// Ascending order of the diagonal (ties by index) and the matching columns.
+__global__ void k_sort_eig(const double* A, const double* V, int N, double* eig, double* Vs) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double di = A[i + (long)i * N];
+    int rank = 0;
+    for (int j = 0; j < N; ++j) {
+        double dj = A[j + (long)j * N];
+        if (dj < di || (dj == di && j < i)) ++rank;
+    }
+    eig[rank] = di;
+    for (int k = 0; k < N; ++k) Vs[k + (long)rank * N] = V[k + (long)i * N];
+}
+
+// A (destroyed), V: N x N; eig: N; work: 2 N^2 doubles.
+sparc_status dense_eigh(sparc_gpu_ctx c, double* A, int N, double* V, double* eig, double* work) {
+    const int P = N + (N & 1);
+    double* A2 = work;
+    double* V2 = work + (size_t)N * N;
+    k_identity<<<div_up((long)N * N, 256), 256, 0, c->stream>>>(V, N);
+    SG_CHECK_LAUNCH(c);
+    double* Acur = A;
+    double* Anext = A2;
+    double* Vcur = V;
+    double* Vnext = V2;
+    const int max_sweeps = 40;
+    bool converged = false;
+    // Off-diagonal mass at the rounding floor of the rotations (each element
+    // is recomputed with O(eps ||A||) error), so ask for (4 N eps)^2 ||A||_F^2.
+    const double ne = 4.0 * N * 2.220446049250313e-16;
+    const double tol = std::max(ne * ne, 1e-30);
+    double prev_off = -1.0;
+    dim3 grid(div_up(N, 16), div_up(N, 16));
+    double* d_norm = c->scal + S_EIG;
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+        k_offnorm<<<1, 1024, 0, c->stream>>>(Acur, N, d_norm);
+        SG_CHECK_LAUNCH(c);
+        double h[2];
+        SG_HIP(c, hipMemcpyAsync(h, d_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+        if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return set_err(c, SPARC_ERR_NONFINITE, "eigh: non-finite");
+        if (h[0] <= tol * h[1] || h[1] == 0.0) {
+            converged = true;
+            break;
+        }
+        // stagnation at the rounding floor also counts as converged
+        if (prev_off >= 0.0 && h[0] <= 1e-20 * h[1] && h[0] >= 0.25 * prev_off) {
+            converged = true;
+            break;
+        }
+        prev_off = h[0];
+        for (int r = 0; r < P - 1; ++r) {
+            k_jacobi_round<<<grid, 256, 0, c->stream>>>(Acur, Anext, Vcur, Vnext, N, P, r);
+            SG_CHECK_LAUNCH(c);
+            std::swap(Acur, Anext);
+            std::swap(Vcur, Vnext);
+        }
+    }
+    if (!converged) return set_err(c, SPARC_ERR_EIG, "Jacobi eigensolver did not converge");
+    // sorted result into eig and V (V may currently live in work)
+    double* Vs = (Vcur == V) ? V2 : V;
+    k_sort_eig<<<div_up(N, 128), 128, 0, c->stream>>>(Acur, Vcur, N, eig, Vs);
+    SG_CHECK_LAUNCH(c);
+    if (Vs != V) SG_HIP(c, hipMemcpyAsync(V, Vs, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return SPARC_OK;
+}
+
+// ---------------------------------------------------------------- Rayleigh-Ritz
+
+template <typename T>
+__global__ void k_copy_cols(const T* __restrict__ src, T* __restrict__ dst, long nd, int ncol, long ld) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i < nd && j < ncol) dst[i + (long)j * ld] = src[i + (long)j * ld];
+}
+
+// X <- Y R^-1 Q with dV Y^T Y = R^T R (R = L^T) and
+// R^-T (dV Y^T H Y) R^-1 = Q diag(eig) Q^T.  Workspace: c->work (one block)
+// and c->small (>= 12 N^2 doubles).
+template <typename T>
+sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* d_eig, bool check) {
+    sparc_status st;
+    const size_t blk = ((size_t)(N - 1) * ldx + c->nd) * sizeof(T);
+    if ((st = ensure_work(c, blk)) != SPARC_OK) return st;
+    if ((st = ensure_small(c, 12 * (size_t)N * N + 16)) != SPARC_OK) return st;
+    T* W = (T*)c->work;
+    const size_t NN = (size_t)N * N;
+    double* M = c->small;           // Gram, then L
+    double* Linv = M + NN;
+    double* K = M + 2 * NN;         // dV Y^T H Y
+    double* T1 = M + 3 * NN;
+    double* Hs = M + 4 * NN;
+    double* Vq = M + 5 * NN;
+    double* Rot = M + 6 * NN;
+    double* ework = M + 9 * NN;     // 2 NN (eigh), Lt lives at 8 NN
+    SG_HIP(c, hipMemsetAsync(c->flags + F_NOT_SPD, 0, sizeof(int), c->stream));
+    if ((st = gemm_tn<T>(c, N, N, c->nd, X, ldx, X, ldx, c->dV, M, N, true)) != SPARC_OK) return st;
+    if ((st = dense_cholesky(c, M, N, c->flags + F_NOT_SPD)) != SPARC_OK) return st;
+    if (check) {
+        int f = 0;
+        SG_HIP(c, hipMemcpyAsync(&f, c->flags + F_NOT_SPD, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+        if (f) return set_err(c, SPARC_ERR_NOT_SPD, "Gram matrix of the block is not positive definite");
+    }
+    if ((st = dense_tri_inverse_lower(c, M, Linv, N)) != SPARC_OK) return st;
+    // H Y into W
+    if ((st = launch_projection<T>(c, X, N, ldx)) != SPARC_OK) return st;
+    if ((st = launch_hsweep<T>(c, X, W, nullptr, N, ldx, 0, 0)) != SPARC_OK) return st;
+    if ((st = gemm_tn<T>(c, N, N, c->nd, X, ldx, W, ldx, c->dV, K, N, false)) != SPARC_OK) return st;
+    if ((st = dense_gemm(c, 'N', 'N', N, Linv, K, T1)) != SPARC_OK) return st;
+    if ((st = dense_gemm(c, 'N', 'T', N, T1, Linv, Hs)) != SPARC_OK) return st;
+    if ((st = dense_symmetrize(c, Hs, N)) != SPARC_OK) return st;
+    if ((st = dense_eigh(c, Hs, N, Vq, d_eig, ework)) != SPARC_OK) return st;
+    if ((st = dense_gemm(c, 'T', 'N', N, Linv, Vq, Rot)) != SPARC_OK) return st;
+    if ((st = gemm_nn<T>(c, c->nd, N, N, X, ldx, Rot, N, W, ldx)) != SPARC_OK) return st;
+    dim3 grid(div_up(c->nd, 256), N);
+    k_copy_cols<T><<<grid, 256, 0, c->stream>>>(W, X, c->nd, N, ldx);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+template sparc_status rayleigh_ritz_impl<double>(sparc_gpu_ctx, double*, int, long, double*, bool);
+template sparc_status rayleigh_ritz_impl<float>(sparc_gpu_ctx, float*, int, long, double*, bool);
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" sparc_status sparc_gpu_rayleigh_ritz(sparc_gpu_ctx c, sparc_prec prec, void* d_X, int ncol, long ldx,
+                                                double* d_eig) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (prec != SPARC_FP64 && prec != SPARC_FP32) return set_err(c, SPARC_ERR_ARG, "rayleigh_ritz: bad precision");
+    if (!d_X || !d_eig) return set_err(c, SPARC_ERR_ARG, "rayleigh_ritz: null pointer");
+    if (ncol < 1 || ncol > c->n_states) return set_err(c, SPARC_ERR_ARG, "rayleigh_ritz: ncol out of range");
+    if (ldx < c->nd) return set_err(c, SPARC_ERR_ARG, "rayleigh_ritz: ldx < N_d");
+    sparc_status st;
+    if (prec == SPARC_FP64)
+        st = rayleigh_ritz_impl<double>(c, (double*)d_X, ncol, ldx, d_eig, true);
+    else
+        st = rayleigh_ritz_impl<float>(c, (float*)d_X, ncol, ldx, d_eig, true);
+    if (st != SPARC_OK) return st;
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    return SPARC_OK;
+}

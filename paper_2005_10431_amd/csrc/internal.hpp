@@ -1,0 +1,187 @@
+// Internal declarations of the MI355X CheFSI library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sparc_gpu.h"
+
+namespace sg {
+
+constexpr int kMaxHalfOrder = 6;  // stencil half-width instantiated in the kernels
+
+// Finite-difference coefficients of H's kinetic part -1/2 Delta_h along each
+// axis: c*[q] multiplies f(p + q e_d) + f(p - q e_d); c0 multiplies f(p).
+template <typename T>
+struct StencilCoef {
+    T cx[kMaxHalfOrder + 1];
+    T cy[kMaxHalfOrder + 1];
+    T cz[kMaxHalfOrder + 1];
+    T c0;
+};
+
+// Nonlocal projector tables on the device.
+//  Atom-major (for projections):   atom a owns support entries
+//     s in [sup_off[a], sup_off[a+1]):  grid index sup_idx[s],
+//     values sup_chi[4*s + lm]  (lm = s, px, py, pz; images summed).
+//  Point-major (for the apply):    point p owns entries
+//     e in [pt_off[p], pt_off[p+1]):    atom pt_atom[e],
+//     values pt_chi[4*e + lm].
+struct NonlocalTables {
+    int n_atoms = 0;
+    long n_sup = 0;
+    long* sup_off = nullptr;   // n_atoms + 1
+    int* sup_idx = nullptr;    // n_sup
+    double* sup_chi = nullptr; // 4 n_sup
+    float* sup_chi32 = nullptr;
+    int* pt_off = nullptr;     // N_d + 1
+    int* pt_atom = nullptr;    // n_sup
+    double* pt_chi = nullptr;  // 4 n_sup
+    float* pt_chi32 = nullptr;
+    double* gamma4 = nullptr;  // 4 n_atoms: (g_s, g_p, g_p, g_p)
+    double nl_hi = 0.0, nl_lo = 0.0;  // signed spectral bound contributions
+    int max_per_atom = 0;
+};
+
+}  // namespace sg
+
+struct sparc_gpu_ctx_s {
+    // geometry
+    int nx = 0, ny = 0, nz = 0;
+    long nd = 0;
+    double hx = 0, hy = 0, hz = 0, dV = 0;
+    double Lx = 0, Ly = 0, Lz = 0;
+    int n_o = 6;
+    double w[sg::kMaxHalfOrder + 1] = {0};
+    sg::StencilCoef<double> cf64;
+    sg::StencilCoef<float> cf32;
+    double kin_bound = 0;    // upper bound of -1/2 Delta_h
+
+    // atoms
+    int n_atoms = 0;
+    std::vector<double> pos, Z, rc_loc, gamma;
+    int nl_lmax = -1;
+    double rc_nl = 0, rcut_nl = 0;
+    int n_states = 0;
+    double n_electrons = 0, kT = 0, rho_floor = 1e-14, sad_width = 1.0;
+
+    hipStream_t stream = nullptr;
+    hipDeviceProp_t prop;
+
+    // device fields
+    double* veff = nullptr;     // N_d
+    float* veff32 = nullptr;    // N_d
+    double* b = nullptr;        // pseudocharge, N_d
+    double e_self = 0, e_c = 0;
+    sg::NonlocalTables nl;
+
+    // Poisson: real orthonormal Fourier bases per axis and the operator's
+    // eigenvalues on the product basis
+    double* pois_ux = nullptr;  // nx*nx
+    double* pois_uy = nullptr;
+    double* pois_uz = nullptr;
+    double* pois_inv = nullptr; // N_d: 4 pi / eigenvalue of -Delta_h (0 for k = 0)
+
+    // workspace (lazily sized)
+    void* work = nullptr;       // one block of n_states columns (bytes below)
+    size_t work_bytes = 0;
+    double* D = nullptr;        // projector coefficients: 4 n_atoms x n_states
+    float* D32 = nullptr;
+    double* gemm_part = nullptr; // split-K partials
+    size_t gemm_part_elems = 0;
+    double* small = nullptr;    // dense subspace matrices
+    size_t small_elems = 0;
+    double* red = nullptr;      // reduction partials
+    size_t red_elems = 0;
+    double* scal = nullptr;     // device scalars (filter params, mu, ...)
+    int* flags = nullptr;       // device status flags
+    double* field = nullptr;    // grid scratch fields (several N_d)
+    int n_field = 0;
+
+    hipEvent_t ev[8];
+    std::string err;
+};
+
+namespace sg {
+
+// ---- error handling -----------------------------------------------------
+sparc_status set_err(sparc_gpu_ctx c, sparc_status s, const std::string& msg);
+sparc_status hip_err(sparc_gpu_ctx c, hipError_t e, const char* what);
+
+#define SG_HIP(ctx, call)                                             \
+    do {                                                              \
+        hipError_t _e = (call);                                       \
+        if (_e != hipSuccess) return ::sg::hip_err((ctx), _e, #call); \
+    } while (0)
+
+#define SG_CHECK_LAUNCH(ctx) SG_HIP(ctx, hipGetLastError())
+
+// ---- workspace ----------------------------------------------------------
+sparc_status ensure_work(sparc_gpu_ctx c, size_t bytes);
+sparc_status ensure_gemm_part(sparc_gpu_ctx c, size_t elems);
+sparc_status ensure_small(sparc_gpu_ctx c, size_t elems);
+sparc_status ensure_red(sparc_gpu_ctx c, size_t elems);
+sparc_status ensure_fields(sparc_gpu_ctx c, int n);
+
+// Device scalar slots in ctx->scal
+enum Scalar {
+    S_A = 0, S_B = 1, S_A0 = 2,      // filter bounds
+    S_LO = 4, S_HI = 5,              // spectrum bounds of the current H
+    S_RED0 = 8,                      // grid reductions (6 slots)
+    S_OCC = 16,                      // mu, entropy term, band energy
+    S_EIG = 22,                      // eigensolver norms (2 slots)
+    S_COUNT = 64
+};
+enum Flag {
+    F_NOT_SPD = 0, F_EIG_NOCONV = 1, F_FERMI = 2, F_NONFINITE = 3, F_JACOBI_DONE = 4,
+    F_COUNT = 16
+};
+
+// ---- kernels (launchers) -------------------------------------------------
+// H application / Chebyshev sweeps. mode: 0 out = H x; 1 first filter step;
+// 2 filter step `step` (>= 2) with xprev = X_{k-1} (may alias out).
+template <typename T>
+sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, int ncol, long ldx,
+                           int mode, int step);
+template <typename T>
+sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx);
+
+// C(MxN, col-major, ldc) = alpha * A^T B, A: K x M (lda), B: K x N (ldb),
+// T inputs, double output, deterministic split-K.
+template <typename T>
+sparc_status gemm_tn(sparc_gpu_ctx c, int M, int N, long K, const T* A, long lda, const T* B, long ldb,
+                     double alpha, double* C, int ldc, bool symmetric);
+// Out(K x N, ldo) = A (K x M, lda) * Bm (M x N, ldb; double, converted to T)
+template <typename T>
+sparc_status gemm_nn(sparc_gpu_ctx c, long K, int N, int M, const T* A, long lda, const double* Bm, int ldb,
+                     T* Out, long ldo);
+
+// Dense subspace algebra (FP64, N x N col-major)
+sparc_status dense_cholesky(sparc_gpu_ctx c, double* M, int N, int* flag);
+sparc_status dense_tri_inverse_lower(sparc_gpu_ctx c, const double* L, double* Linv, int N);
+sparc_status dense_gemm(sparc_gpu_ctx c, char ta, char tb, int N, const double* A, const double* B, double* C);
+sparc_status dense_symmetrize(sparc_gpu_ctx c, double* A, int N);
+sparc_status dense_eigh(sparc_gpu_ctx c, double* A, int N, double* V, double* eig, double* work);
+
+// RR core shared by the public entry point and the SCF step; eig on device
+template <typename T>
+sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int ncol, long ldx, double* d_eig, bool check);
+
+// Grid-field kernels
+sparc_status potential_impl(sparc_gpu_ctx c, const double* rho, double* phi, double* exc, double* vxc,
+                            double* veff);
+sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu);
+template <typename T>
+sparc_status density_impl(sparc_gpu_ctx c, const T* X, int ncol, long ldx, const double* occ, double* rho);
+sparc_status set_veff_impl(sparc_gpu_ctx c, const double* d_veff);
+sparc_status bounds_impl(sparc_gpu_ctx c);  // writes S_LO / S_HI on device
+
+// Build geometry tables (ctx.hip)
+sparc_status build_tables(sparc_gpu_ctx c);
+
+inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace sg

@@ -1,0 +1,531 @@
+// SCF iteration around CheFSI (Sec. 2.1): potential from the density,
+// filter + Rayleigh-Ritz passes, Fermi-Dirac occupations, density
+// (Sec. 2 eq. (2)), free energy, residual and linear mixing.
+//
+// Electrostatics: -Delta_h phi = 4 pi (rho + b - mean) on the periodic grid.
+// The discrete periodic Laplacian is separable and each 1D stencil is
+// diagonalised by a real orthonormal Fourier basis U_d, so
+//   phi = (U_z x U_y x U_x) diag(4 pi / lambda) (U_z x U_y x U_x)^T (rho + b)
+// with lambda the eigenvalues of -Delta_h and the constant mode dropped.  This
+// is the exact solution of the same linear system the paper's iterative
+// stencil solver (AAR) converges to; here it costs six small dense
+// transforms along the grid axes.
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace sg {
+
+template <typename T>
+sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m);
+
+// out = (I x M x I) in along `axis`, M = U^T (fwd) or U (bwd); U is n x n
+// column-major (column k = mode k).
+__global__ void k_axis_transform(const double* __restrict__ in, double* __restrict__ out,
+                                 const double* __restrict__ U, int nx, int ny, int nz, int axis, int fwd) {
+    long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long nd = (long)nx * ny * nz;
+    if (p >= nd) return;
+    int ix = (int)(p % nx);
+    int iy = (int)((p / nx) % ny);
+    int iz = (int)(p / ((long)nx * ny));
+    int n, m;
+    long stride, base;
+    if (axis == 0) {
+        n = nx;
+        m = ix;
+        stride = 1;
+        base = p - ix;
+    } else if (axis == 1) {
+        n = ny;
+        m = iy;
+        stride = nx;
+        base = p - (long)iy * nx;
+    } else {
+        n = nz;
+        m = iz;
+        stride = (long)nx * ny;
+        base = p - (long)iz * nx * ny;
+    }
+    double acc = 0.0;
+    if (fwd) {
+        const double* u = U + (long)m * n;  // column m of U = row m of U^T
+        for (int l = 0; l < n; ++l) acc += u[l] * in[base + l * stride];
+    } else {
+        for (int l = 0; l < n; ++l) acc += U[m + (long)l * n] * in[base + l * stride];
+    }
+    out[p] = acc;
+}
+
+__global__ void k_add(const double* a, const double* b, double* out, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + b[i];
+}
+
+__global__ void k_mul(double* a, const double* b, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] *= b[i];
+}
+
+// Unpolarised LDA: Slater exchange and the PW92 correlation fit.
+__device__ inline void lda_point(double rho, double floor_, double& exc, double& vxc) {
+    const double pi = 3.14159265358979323846;
+    double r = fmax(rho, floor_);
+    double ex = -0.75 * cbrt(3.0 * r / pi);
+    double vx = (4.0 / 3.0) * ex;
+    double rs = cbrt(3.0 / (4.0 * pi * r));
+    const double A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+    double srs = sqrt(rs);
+    double Q0 = -2.0 * A * (1.0 + a1 * rs);
+    double Q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
+    double dQ1 = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs);
+    double lg = log1p(1.0 / Q1);
+    double ec = Q0 * lg;
+    double dec = -2.0 * A * a1 * lg - Q0 * dQ1 / (Q1 * Q1 + Q1);
+    exc = ex + ec;
+    vxc = vx + ec - rs / 3.0 * dec;
+}
+
+__global__ void k_lda(const double* __restrict__ rho, const double* __restrict__ phi, double floor_,
+                      double* __restrict__ exc, double* __restrict__ vxc, double* __restrict__ veff,
+                      float* __restrict__ veff32, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double e, v;
+    lda_point(rho[i], floor_, e, v);
+    if (exc) exc[i] = e;
+    if (vxc) vxc[i] = v;
+    if (veff) {
+        double ve = phi[i] + v;
+        veff[i] = ve;
+        if (veff32) veff32[i] = (float)ve;
+    }
+}
+
+// phi, eps_xc, v_xc, V_eff for density rho.  Uses fields[0..1] as scratch;
+// phi may not be null inside (a field is substituted).
+sparc_status potential_impl(sparc_gpu_ctx c, const double* rho, double* phi, double* exc, double* vxc,
+                            double* veff) {
+    sparc_status st = ensure_fields(c, 6);
+    if (st != SPARC_OK) return st;
+    double* t0 = c->field;
+    double* t1 = c->field + c->nd;
+    double* ph = phi ? phi : c->field + 2 * c->nd;
+    const int nb = div_up(c->nd, 256);
+    k_add<<<nb, 256, 0, c->stream>>>(rho, c->b, t0, c->nd);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_ux, c->nx, c->ny, c->nz, 0, 1);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uy, c->nx, c->ny, c->nz, 1, 1);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uz, c->nx, c->ny, c->nz, 2, 1);
+    k_mul<<<nb, 256, 0, c->stream>>>(t1, c->pois_inv, c->nd);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uz, c->nx, c->ny, c->nz, 2, 0);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uy, c->nx, c->ny, c->nz, 1, 0);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, ph, c->pois_ux, c->nx, c->ny, c->nz, 0, 0);
+    float* v32 = (veff == c->veff) ? c->veff32 : nullptr;
+    k_lda<<<nb, 256, 0, c->stream>>>(rho, ph, c->rho_floor, exc, vxc, veff, v32, c->nd);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+// ------------------------------------------------------------ occupations
+
+__device__ inline double fermi(double lam, double mu, double kT) {
+    double x = (lam - mu) / kT;
+    if (x > 0.0) {
+        double e = exp(-x);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (1.0 + exp(x));
+}
+
+// One block: bisection for mu, then occupations and the entropy term
+// out[0] = mu, out[1] = 2 kT sum [f ln f + (1-f) ln(1-f)], out[2] = sum g lam.
+__global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ eig, int N, double ne, double kT,
+                                                     double* __restrict__ occ, double* __restrict__ out,
+                                                     int* __restrict__ flag) {
+    __shared__ double red[256];
+    __shared__ double s_lo, s_hi, s_mu;
+    __shared__ int s_done;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        s_lo = eig[0] - 40.0 * kT;
+        s_hi = eig[N - 1] + 40.0 * kT;
+        s_done = 0;
+        for (int i = 0; i < N; ++i) {
+            s_lo = fmin(s_lo, eig[i] - 40.0 * kT);
+            s_hi = fmax(s_hi, eig[i] + 40.0 * kT);
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < 500; ++it) {
+        double mu = 0.5 * (s_lo + s_hi);
+        double acc = 0.0;
+        for (int i = t; i < N; i += blockDim.x) acc += 2.0 * fermi(eig[i], mu, kT);
+        red[t] = acc;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (t < s) red[t] += red[t + s];
+            __syncthreads();
+        }
+        if (t == 0) {
+            double n = red[0];
+            s_mu = mu;
+            if (fabs(n - ne) < 1e-13) {
+                s_done = 1;
+            } else {
+                if (n < ne)
+                    s_lo = mu;
+                else
+                    s_hi = mu;
+                double mid = 0.5 * (s_lo + s_hi);
+                if (!(s_lo < mid && mid < s_hi)) s_done = 1;
+            }
+        }
+        __syncthreads();
+        if (s_done) break;
+    }
+    const double mu = s_mu;
+    double ent = 0.0, band = 0.0;
+    for (int i = t; i < N; i += blockDim.x) {
+        double f = fermi(eig[i], mu, kT);
+        occ[i] = 2.0 * f;
+        band += 2.0 * f * eig[i];
+        if (f > 0.0 && f < 1.0) ent += f * log(f) + (1.0 - f) * log(1.0 - f);
+    }
+    __syncthreads();
+    red[t] = ent;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    double ent_sum = red[0];
+    __syncthreads();
+    red[t] = band;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = mu;
+        out[1] = 2.0 * kT * ent_sum;
+        out[2] = red[0];
+        if (!s_done || !isfinite(mu)) flag[0] = 1;
+    }
+}
+
+sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu) {
+    k_occupations<<<1, 256, 0, c->stream>>>(eig, ncol, c->n_electrons, c->kT, occ, c->scal + S_OCC,
+                                           c->flags + F_FERMI);
+    SG_CHECK_LAUNCH(c);
+    if (mu) SG_HIP(c, hipMemcpyAsync(mu, c->scal + S_OCC, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return SPARC_OK;
+}
+
+// ------------------------------------------------------------ density
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_density(const T* __restrict__ X, int ncol, long ldx,
+                                                 const double* __restrict__ occ, double* __restrict__ rho, long nd) {
+    long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nd) return;
+    double acc = 0.0;
+    for (int j = 0; j < ncol; ++j) {
+        double v = (double)X[p + (long)j * ldx];
+        acc += occ[j] * v * v;
+    }
+    rho[p] = acc;
+}
+
+template <typename T>
+sparc_status density_impl(sparc_gpu_ctx c, const T* X, int ncol, long ldx, const double* occ, double* rho) {
+    k_density<T><<<div_up(c->nd, 256), 256, 0, c->stream>>>(X, ncol, ldx, occ, rho, c->nd);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+template sparc_status density_impl<double>(sparc_gpu_ctx, const double*, int, long, const double*, double*);
+template sparc_status density_impl<float>(sparc_gpu_ctx, const float*, int, long, const double*, double*);
+
+// ------------------------------------------------------------ energy + mixing
+
+constexpr int kRed = 6;  // rho exc, rho vxc, (b - rho) phi, |dr|^2, |rho_out|^2, sum rho_out
+
+// Per-block partial sums; optionally rho_in <- rho_in + beta (rho_out - rho_in).
+__global__ __launch_bounds__(256) void k_energy_mix(double* __restrict__ rho_in, const double* __restrict__ rho_out,
+                                                    const double* __restrict__ exc, const double* __restrict__ vxc,
+                                                    const double* __restrict__ phi, const double* __restrict__ b,
+                                                    long n, double beta, int do_mix, double* __restrict__ part) {
+    __shared__ double red[kRed][256];
+    const int t = threadIdx.x;
+    double s[kRed] = {0, 0, 0, 0, 0, 0};
+    for (long i = (long)blockIdx.x * blockDim.x + t; i < n; i += (long)gridDim.x * blockDim.x) {
+        double ri = rho_in[i], ro = rho_out[i];
+        s[0] += ri * exc[i];
+        s[1] += ri * vxc[i];
+        s[2] += (b[i] - ri) * phi[i];
+        double d = ro - ri;
+        s[3] += d * d;
+        s[4] += ro * ro;
+        s[5] += ro;
+        if (do_mix) rho_in[i] = ri + beta * d;
+    }
+    for (int k = 0; k < kRed; ++k) red[k][t] = s[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st)
+            for (int k = 0; k < kRed; ++k) red[k][t] += red[k][t + st];
+        __syncthreads();
+    }
+    if (t < kRed) part[(long)blockIdx.x * kRed + t] = red[t][0];
+}
+
+__global__ void k_energy_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+    int k = threadIdx.x;
+    if (k >= kRed) return;
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += part[(long)i * kRed + k];
+    out[k] = s;
+}
+
+// filter bounds from the latest Ritz values: a = max, a0 = min (or the lower
+// spectrum bound before the first filter); b = upper spectrum bound
+__global__ void k_bounds_from_eig(const double* eig, int N, double* scal, int first) {
+    scal[S_A] = eig[N - 1];
+    scal[S_A0] = first ? scal[S_LO] : eig[0];
+    scal[S_B] = scal[S_HI];
+}
+
+__global__ void k_set_ab(double* scal, double a, double a0) {
+    scal[S_A] = a;
+    scal[S_A0] = a0;
+    scal[S_B] = scal[S_HI];
+}
+
+__global__ void k_set_b(double* scal) { scal[S_B] = scal[S_HI]; }
+
+template <typename T>
+__global__ void k_promote(const T* __restrict__ src, double* __restrict__ dst, long nd, int ncol, long lds, long ldd) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i < nd) dst[i + (long)j * ldd] = (double)src[i + (long)j * lds];
+}
+
+struct Timer {
+    sparc_gpu_ctx c;
+    explicit Timer(sparc_gpu_ctx cc) : c(cc) {}
+    void mark(int i) { hipEventRecord(c->ev[i], c->stream); }
+    double ms(int a, int b) {
+        float v = 0.f;
+        hipEventElapsedTime(&v, c->ev[a], c->ev[b]);
+        return (double)v;
+    }
+};
+
+// Energy terms and residual at (rho_in, rho_out) into the report; mixes when
+// do_mix.  Fields: phi = f[2], exc = f[3], vxc = f[4].
+static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double* rho_out, double beta, int do_mix,
+                                  sparc_gpu_scf_report* rep, double* hscal) {
+    const int nblk = std::min(1024, div_up(c->nd, 256));
+    sparc_status st = ensure_red(c, (size_t)nblk * kRed);
+    if (st != SPARC_OK) return st;
+    const double* phi = c->field + 2 * c->nd;
+    const double* exc = c->field + 3 * c->nd;
+    const double* vxc = c->field + 4 * c->nd;
+    k_energy_mix<<<nblk, 256, 0, c->stream>>>(rho_in, rho_out, exc, vxc, phi, c->b, c->nd, beta, do_mix, c->red);
+    SG_CHECK_LAUNCH(c);
+    k_energy_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_RED0);
+    SG_CHECK_LAUNCH(c);
+    double hloc[S_COUNT];
+    double* h = hscal ? hscal : hloc;
+    int fl[F_COUNT];
+    SG_HIP(c, hipMemcpyAsync(h, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP(c, hipMemcpyAsync(fl, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    if (fl[F_FERMI]) return set_err(c, SPARC_ERR_FERMI, "Fermi level bisection failed");
+    const double* r = h + S_RED0;
+    const double dV = c->dV;
+    sparc_gpu_scf_report R;
+    std::memset(&R, 0, sizeof(R));
+    R.mu = h[S_OCC];
+    R.entropy = h[S_OCC + 1];
+    R.band = h[S_OCC + 2];
+    R.exc = dV * r[0];
+    R.vxc_dc = -dV * r[1];
+    R.elec = 0.5 * dV * r[2];
+    R.self_energy = -c->e_self;
+    R.overlap = c->e_c;
+    R.free_energy = R.band + R.exc + R.vxc_dc + R.elec + R.self_energy + R.overlap + R.entropy;
+    R.residual = (r[4] > 0.0) ? std::sqrt(r[3] / r[4]) : 0.0;
+    if (!std::isfinite(R.free_energy) || !std::isfinite(R.residual))
+        return set_err(c, SPARC_ERR_NONFINITE, "non-finite energy or residual");
+    if (rep) *rep = R;
+    return SPARC_OK;
+}
+
+template <typename T>
+static sparc_status scf_step_impl(sparc_gpu_ctx c, sparc_gpu_scf_state* s, sparc_gpu_scf_report* rep) {
+    sparc_status st;
+    const int N = c->n_states;
+    T* X = (T*)s->d_X;
+    if ((st = ensure_fields(c, 6)) != SPARC_OK) return st;
+    if ((st = ensure_work(c, ((size_t)(N - 1) * s->ldx + c->nd) * sizeof(T))) != SPARC_OK) return st;
+    double* phi = c->field + 2 * c->nd;
+    double* exc = c->field + 3 * c->nd;
+    double* vxc = c->field + 4 * c->nd;
+    double* rho_out = s->d_rho_out ? s->d_rho_out : c->field + 5 * c->nd;
+    SG_HIP(c, hipMemsetAsync(c->flags, 0, F_COUNT * sizeof(int), c->stream));
+    Timer tm(c);
+    tm.mark(0);
+    if ((st = potential_impl(c, s->d_rho_in, phi, exc, vxc, c->veff)) != SPARC_OK) return st;
+    if ((st = bounds_impl(c)) != SPARC_OK) return st;
+    tm.mark(1);
+    const bool first = s->iter == 0;
+    if (first) {
+        if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, s->d_eig, true)) != SPARC_OK) return st;
+        k_bounds_from_eig<<<1, 1, 0, c->stream>>>(s->d_eig, N, c->scal, 1);
+    } else {
+        k_set_ab<<<1, 1, 0, c->stream>>>(c->scal, s->bounds[0], s->bounds[2]);
+    }
+    SG_CHECK_LAUNCH(c);
+    const int npass = first ? s->n_first : 1;
+    double t_filter = 0.0, t_rr = 0.0;
+    for (int pass = 0; pass < npass; ++pass) {
+        tm.mark(2);
+        if ((st = filter_impl<T>(c, X, (T*)c->work, N, s->ldx, s->cheb_degree)) != SPARC_OK) return st;
+        tm.mark(3);
+        if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, s->d_eig, true)) != SPARC_OK) return st;
+        k_bounds_from_eig<<<1, 1, 0, c->stream>>>(s->d_eig, N, c->scal, 0);
+        SG_CHECK_LAUNCH(c);
+        tm.mark(4);
+        SG_HIP(c, hipEventSynchronize(c->ev[4]));
+        t_filter += tm.ms(2, 3);
+        t_rr += tm.ms(3, 4);
+    }
+    tm.mark(5);
+    if ((st = occupations_impl(c, s->d_eig, N, s->d_occ, nullptr)) != SPARC_OK) return st;
+    if ((st = density_impl<T>(c, X, N, s->ldx, s->d_occ, rho_out)) != SPARC_OK) return st;
+    tm.mark(6);
+    sparc_gpu_scf_report R;
+    double hs[S_COUNT];
+    if ((st = finish_energy(c, s->d_rho_in, rho_out, s->mix_beta, 1, &R, hs)) != SPARC_OK) return st;
+    tm.mark(7);
+    SG_HIP(c, hipEventSynchronize(c->ev[7]));
+    s->bounds[0] = hs[S_A];
+    s->bounds[1] = hs[S_B];
+    s->bounds[2] = hs[S_A0];
+    R.t_potential_ms = tm.ms(0, 1);
+    R.t_filter_ms = t_filter;
+    R.t_rr_ms = t_rr;
+    R.t_density_ms = tm.ms(5, 6);
+    R.t_total_ms = tm.ms(0, 7);
+    R.n_passes = npass;
+    R.iter = s->iter;
+    s->iter += 1;
+    if (rep) *rep = R;
+    return SPARC_OK;
+}
+
+static sparc_status check_state(sparc_gpu_ctx c, const sparc_gpu_scf_state* s) {
+    if (!s) return set_err(c, SPARC_ERR_ARG, "scf: null state");
+    if (!s->d_rho_in || !s->d_X || !s->d_eig || !s->d_occ) return set_err(c, SPARC_ERR_ARG, "scf: null buffer");
+    if (s->prec != SPARC_FP64 && s->prec != SPARC_FP32) return set_err(c, SPARC_ERR_ARG, "scf: bad precision");
+    if (s->ldx < c->nd) return set_err(c, SPARC_ERR_ARG, "scf: ldx < N_d");
+    if (s->cheb_degree < 1 || s->cheb_degree > 10000) return set_err(c, SPARC_ERR_ARG, "scf: bad degree");
+    if (s->n_first < 1 || s->n_first > 100) return set_err(c, SPARC_ERR_ARG, "scf: bad n_first");
+    if (!(s->mix_beta > 0.0 && s->mix_beta <= 1.0)) return set_err(c, SPARC_ERR_ARG, "scf: bad mix_beta");
+    if (s->iter < 0) return set_err(c, SPARC_ERR_ARG, "scf: negative iter");
+    if (s->iter > 0 && !(s->bounds[2] < s->bounds[0]))
+        return set_err(c, SPARC_ERR_ARG, "scf: bounds need a0 < a after the first iteration");
+    return SPARC_OK;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+sparc_status sparc_gpu_scf_step(sparc_gpu_ctx c, sparc_gpu_scf_state* s, sparc_gpu_scf_report* rep) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = check_state(c, s);
+    if (st != SPARC_OK) return st;
+    if (s->prec == SPARC_FP64) return scf_step_impl<double>(c, s, rep);
+    return scf_step_impl<float>(c, s, rep);
+}
+
+sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx c, sparc_gpu_scf_state* s, double* d_X64, long ldx64,
+                                     sparc_gpu_scf_report* rep) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = check_state(c, s);
+    if (st != SPARC_OK) return st;
+    if (!d_X64 || ldx64 < c->nd) return set_err(c, SPARC_ERR_ARG, "final_rr_fp64: bad FP64 block");
+    const int N = c->n_states;
+    if ((st = ensure_fields(c, 6)) != SPARC_OK) return st;
+    dim3 grid(div_up(c->nd, 256), N);
+    if (s->prec == SPARC_FP32)
+        k_promote<float><<<grid, 256, 0, c->stream>>>((const float*)s->d_X, d_X64, c->nd, N, s->ldx, ldx64);
+    else
+        k_promote<double><<<grid, 256, 0, c->stream>>>((const double*)s->d_X, d_X64, c->nd, N, s->ldx, ldx64);
+    SG_CHECK_LAUNCH(c);
+    SG_HIP(c, hipMemsetAsync(c->flags, 0, F_COUNT * sizeof(int), c->stream));
+    double* phi = c->field + 2 * c->nd;
+    double* exc = c->field + 3 * c->nd;
+    double* vxc = c->field + 4 * c->nd;
+    double* rho_out = s->d_rho_out ? s->d_rho_out : c->field + 5 * c->nd;
+    Timer tm(c);
+    tm.mark(0);
+    if ((st = potential_impl(c, s->d_rho_in, phi, exc, vxc, c->veff)) != SPARC_OK) return st;
+    tm.mark(1);
+    if ((st = rayleigh_ritz_impl<double>(c, d_X64, N, ldx64, s->d_eig, true)) != SPARC_OK) return st;
+    tm.mark(2);
+    if ((st = occupations_impl(c, s->d_eig, N, s->d_occ, nullptr)) != SPARC_OK) return st;
+    if ((st = density_impl<double>(c, d_X64, N, ldx64, s->d_occ, rho_out)) != SPARC_OK) return st;
+    tm.mark(3);
+    sparc_gpu_scf_report R;
+    if ((st = finish_energy(c, s->d_rho_in, rho_out, 0.0, 0, &R, nullptr)) != SPARC_OK) return st;
+    tm.mark(4);
+    SG_HIP(c, hipEventSynchronize(c->ev[4]));
+    R.t_potential_ms = tm.ms(0, 1);
+    R.t_rr_ms = tm.ms(1, 2);
+    R.t_density_ms = tm.ms(2, 3);
+    R.t_total_ms = tm.ms(0, 4);
+    R.n_passes = 0;
+    R.iter = s->iter;
+    if (rep) *rep = R;
+    return SPARC_OK;
+}
+
+sparc_status sparc_gpu_density(sparc_gpu_ctx c, sparc_prec prec, const void* d_X, int ncol, long ldx,
+                               const double* d_occ, double* d_rho) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (prec != SPARC_FP64 && prec != SPARC_FP32) return set_err(c, SPARC_ERR_ARG, "density: bad precision");
+    if (!d_X || !d_occ || !d_rho) return set_err(c, SPARC_ERR_ARG, "density: null pointer");
+    if (ncol < 1 || ncol > c->n_states) return set_err(c, SPARC_ERR_ARG, "density: ncol out of range");
+    if (ldx < c->nd) return set_err(c, SPARC_ERR_ARG, "density: ldx < N_d");
+    if (prec == SPARC_FP64) return density_impl<double>(c, (const double*)d_X, ncol, ldx, d_occ, d_rho);
+    return density_impl<float>(c, (const float*)d_X, ncol, ldx, d_occ, d_rho);
+}
+
+sparc_status sparc_gpu_occupations(sparc_gpu_ctx c, const double* d_eig, int ncol, double* d_occ, double* d_mu) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_eig || !d_occ) return set_err(c, SPARC_ERR_ARG, "occupations: null pointer");
+    if (ncol < 1 || ncol > c->n_states) return set_err(c, SPARC_ERR_ARG, "occupations: ncol out of range");
+    if (c->n_electrons > 2.0 * ncol) return set_err(c, SPARC_ERR_ARG, "occupations: N_e > 2 ncol");
+    return occupations_impl(c, d_eig, ncol, d_occ, d_mu);
+}
+
+sparc_status sparc_gpu_potential(sparc_gpu_ctx c, const double* d_rho, double* d_phi, double* d_exc, double* d_vxc,
+                                 double* d_veff) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_rho) return set_err(c, SPARC_ERR_ARG, "potential: null density");
+    if (d_veff == c->veff) return set_err(c, SPARC_ERR_ARG, "potential: output aliases the context");
+    return potential_impl(c, d_rho, d_phi, d_exc, d_vxc, d_veff);
+}
+
+}  // extern "C"

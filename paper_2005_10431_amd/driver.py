@@ -1,0 +1,55 @@
+"""Host-side SCF loop over ``sparc_gpu_scf_step`` (control flow only; each
+iteration runs entirely in the library's kernels)."""
+from __future__ import annotations
+
+import numpy as np
+
+from ._lib import SPARC_FP32, Context, make_state
+
+
+def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100, tol: float = 1e-10,
+            device: str = "cuda", final_fp64_rr: bool = True, ctx: Context = None, callback=None,
+            n_first: int = None, degree: int = None, beta: float = None):
+    """Run the SCF iteration on the GPU.
+
+    X0: (N_s, N_d) numpy array (random block, see ``workloads.initial_orbitals``);
+    rho0: (N_d,) numpy array or None for the atomic-density guess.
+    Returns a dict with the history of reports and the final device tensors."""
+    import torch
+    ctx = ctx or Context(system)
+    nd, ns = system.nd, system.n_states
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if X0 is None:
+        from workloads import initial_orbitals
+        X0 = initial_orbitals(nd, ns, system.seed)
+    X = torch.as_tensor(np.asarray(X0), dtype=dt).to(device).contiguous()
+    rho_in = torch.empty(nd, dtype=torch.float64, device=device)
+    if rho0 is None:
+        ctx.sad_density(rho_in)
+    else:
+        rho_in.copy_(torch.as_tensor(np.asarray(rho0), dtype=torch.float64))
+    eig = torch.empty(ns, dtype=torch.float64, device=device)
+    occ = torch.empty(ns, dtype=torch.float64, device=device)
+    rho_out = torch.empty(nd, dtype=torch.float64, device=device)
+    st = make_state(rho_in, X, eig, occ,
+                    degree if degree is not None else system.cheb_degree,
+                    n_first if n_first is not None else system.n_first,
+                    beta if beta is not None else system.mix_beta, rho_out)
+    hist = []
+    for _ in range(max_iter):
+        rep = ctx.scf_step(st)
+        rep["eig"] = eig.detach().cpu().numpy().copy()
+        hist.append(rep)
+        if callback is not None:
+            callback(rep)
+        if rep["residual"] < tol:
+            break
+    out = dict(history=hist, X=X, eig=eig, occ=occ, rho_in=rho_in, rho_out=rho_out, state=st, ctx=ctx)
+    if prec != "fp64" and final_fp64_rr:
+        X64 = torch.empty((ns, nd), dtype=torch.float64, device=device)
+        # one FP64 Rayleigh-Ritz at the (converged) input density
+        rep = ctx.final_rr_fp64(st, X64)
+        rep["eig"] = eig.detach().cpu().numpy().copy()
+        out["final"] = rep
+        out["X64"] = X64
+    return out

@@ -1,0 +1,278 @@
+"""GPU <-> oracle parity of every step of the hot path, through the C ABI.
+
+Tolerances (FP64): 1e-12 relative on one H.X, 1e-8 Ha on eigenvalues,
+1e-6 Ha/atom on the free energy.  FP32 blocks: relative errors of the order
+of single-precision rounding of the stencil sum (1e-5).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import atoms, chefsi, electrostatics, hamiltonian, scf, xc
+
+from gpu_helpers import (log, ragged_system, rel_err, require_gpu, small_images_system, to_dev, to_np)
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(system):
+    from paper_2005_10431_amd import Context
+    return Context(system)
+
+
+def _veff(system, seed=11, scale=0.5):
+    return np.random.default_rng(seed).uniform(-scale, scale, system.nd)
+
+
+@pytest.mark.parametrize("make", [ragged_system, small_images_system], ids=["ragged", "images"])
+def test_apply_H_fp64(make):
+    torch = require_gpu()
+    s = make()
+    log("apply_H fp64", s.n, s.L)
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s)
+    X = W.initial_orbitals(s.nd, 5, 1)
+    Yref = hamiltonian.apply_H(s, v, projs, X)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Yd = torch.zeros_like(Xd)
+    ctx.apply_H(Xd, Yd)
+    Y = to_np(Yd)
+    assert rel_err(Y, Yref) <= 1e-12
+    assert np.max(np.abs(Y - Yref)) <= 1e-12 * np.max(np.abs(Yref))
+
+
+def test_apply_H_fp64_padded_leading_dimension():
+    torch = require_gpu()
+    s = ragged_system()
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 12)
+    X = W.initial_orbitals(s.nd, 3, 2)
+    ld = s.nd + 37
+    Xp = np.zeros((3, ld))
+    Xp[:, :s.nd] = X
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, Xp)
+    Yd = torch.full_like(Xd, 7.0)
+    ctx.apply_H(Xd, Yd)
+    Y = to_np(Yd)
+    Yref = hamiltonian.apply_H(s, v, projs, X)
+    assert rel_err(Y[:, :s.nd], Yref) <= 1e-12
+    assert np.all(Y[:, s.nd:] == 7.0)          # padding untouched
+
+
+def test_apply_H_fp32():
+    torch = require_gpu()
+    s = ragged_system()
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s)
+    X = W.initial_orbitals(s.nd, 4, 3).astype(np.float32)
+    Yref = hamiltonian.apply_H(s, v, projs, X.astype(np.float64))
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Yd = torch.zeros_like(Xd)
+    ctx.apply_H(Xd, Yd)
+    assert rel_err(to_np(Yd).astype(np.float64), Yref) <= 2e-6
+
+
+def test_apply_H_cfg2_sampled_columns():
+    """Full config-2 block (72^3, 260 states, 108 atoms with s+p projectors)
+    in the launch configuration of the benchmark; the oracle recomputes three
+    columns one by one."""
+    torch = require_gpu()
+    s = W.config2(0)
+    log("apply_H cfg2 full block")
+    ctx = _ctx(s)
+    v = _veff(s, 21, 1.0)
+    X = W.initial_orbitals(s.nd, s.n_states, 0)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Yd = torch.zeros_like(Xd)
+    ctx.apply_H(Xd, Yd)
+    torch.cuda.synchronize()
+    projs = atoms.projectors(s)
+    for j in (0, 137, 259):
+        yref = hamiltonian.apply_H(s, v, projs, X[j:j + 1])[0]
+        y = to_np(Yd[j])
+        assert rel_err(y, yref) <= 1e-12, j
+
+
+@pytest.mark.parametrize("degree", [1, 7, 8])
+def test_chebyshev_filter_fp64(degree):
+    torch = require_gpu()
+    s = small_images_system()
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 13)
+    lo, hi = hamiltonian.spectrum_bounds(s, v, projs)
+    a, b, a0 = lo + 0.3 * (hi - lo), hi, lo
+    X = W.initial_orbitals(s.nd, 6, 4)
+    Yref = chefsi.chebyshev_filter(s, v, projs, X, degree, a, b, a0)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Wd = torch.zeros_like(Xd)
+    ctx.chebyshev_filter(Xd, Wd, degree, a, b, a0)
+    assert rel_err(to_np(Xd), Yref) <= 1e-11
+
+
+def test_chebyshev_filter_cfg2_sampled_columns():
+    """Degree-20 filter over the full config-2 block; the filter acts column
+    by column, so the oracle filters two columns alone."""
+    torch = require_gpu()
+    s = W.config2(0)
+    log("filter cfg2 full block")
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 22, 1.0)
+    lo, hi = hamiltonian.spectrum_bounds(s, v, projs)
+    a, b, a0 = lo + 0.05 * (hi - lo), hi, lo
+    X = W.initial_orbitals(s.nd, s.n_states, 1)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Wd = torch.empty_like(Xd)
+    ctx.chebyshev_filter(Xd, Wd, 20, a, b, a0)
+    torch.cuda.synchronize()
+    for j in (3, 258):
+        yref = chefsi.chebyshev_filter(s, v, projs, X[j:j + 1], 20, a, b, a0)[0]
+        assert rel_err(to_np(Xd[j]), yref) <= 1e-11, j
+
+
+def _projector(X, dV):
+    return dV * X.T @ X
+
+
+def test_rayleigh_ritz_fp64():
+    torch = require_gpu()
+    s = small_images_system(n_states=8)
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 14)
+    X = W.initial_orbitals(s.nd, 8, 5)
+    Xr, lam = chefsi.rayleigh_ritz(s, v, projs, X)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    eig = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ctx.rayleigh_ritz(Xd, eig)
+    Xg = to_np(Xd)
+    np.testing.assert_allclose(to_np(eig), lam, atol=1e-10)
+    O = s.dV * Xg @ Xg.T
+    assert np.max(np.abs(O - np.eye(8))) < 1e-12
+    # same Ritz subspace, column by column up to sign (eigenvalues are simple)
+    for j in range(8):
+        c = s.dV * float(Xg[j] @ Xr[j])
+        assert abs(abs(c) - 1.0) < 1e-9, j
+
+
+def test_rayleigh_ritz_fp32():
+    torch = require_gpu()
+    s = small_images_system(n_states=8)
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 14)
+    X = W.initial_orbitals(s.nd, 8, 5)
+    _, lam = chefsi.rayleigh_ritz(s, v, projs, X)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X, torch.float32)
+    eig = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ctx.rayleigh_ritz(Xd, eig)
+    np.testing.assert_allclose(to_np(eig), lam, atol=2e-4 * np.max(np.abs(lam)))
+    Xg = to_np(Xd).astype(np.float64)
+    assert np.max(np.abs(s.dV * Xg @ Xg.T - np.eye(8))) < 1e-5
+
+
+def test_rayleigh_ritz_rank_deficient_block():
+    from paper_2005_10431_amd import SparcError
+    torch = require_gpu()
+    s = small_images_system(n_states=4)
+    ctx = _ctx(s)
+    ctx.set_veff(to_dev(torch, _veff(s)))
+    X = W.initial_orbitals(s.nd, 4, 6)
+    X[3] = X[1]
+    Xd = to_dev(torch, X)
+    eig = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(SparcError) as ei:
+        ctx.rayleigh_ritz(Xd, eig)
+    assert ei.value.name == "SPARC_ERR_NOT_SPD"
+    np.testing.assert_array_equal(to_np(Xd), X)
+
+
+def test_occupations_and_density():
+    torch = require_gpu()
+    s = W.config1(0)
+    ctx = _ctx(s)
+    lam = np.sort(np.random.default_rng(8).uniform(-0.6, 0.3, s.n_states))
+    mu_ref, g_ref = scf.occupations(lam, s.n_electrons, s.kT)
+    eig = to_dev(torch, lam)
+    occ = torch.zeros_like(eig)
+    mu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.occupations(eig, occ, mu)
+    np.testing.assert_allclose(to_np(occ), g_ref, atol=1e-12)
+    assert abs(float(to_np(mu)[0]) - mu_ref) < 1e-10
+    X = W.initial_orbitals(s.nd, s.n_states, 7)
+    rho = torch.zeros(s.nd, dtype=torch.float64, device="cuda")
+    ctx.density(to_dev(torch, X), occ, rho)
+    assert rel_err(to_np(rho), scf.density(X, g_ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("make", [W.config1, small_images_system], ids=["cfg1", "images"])
+def test_pseudocharge_energies_and_sad(make):
+    torch = require_gpu()
+    s = make()
+    ctx = _ctx(s)
+    b = torch.zeros(s.nd, dtype=torch.float64, device="cuda")
+    es, ec = ctx.pseudocharge(b)
+    assert rel_err(to_np(b), atoms.pseudocharge(s)) <= 1e-13
+    assert abs(es - atoms.self_energy(s)) <= 1e-11 * abs(es)
+    assert abs(ec - atoms.overlap_correction(s)) <= 1e-12 * max(1.0, abs(ec))
+    rho = torch.zeros(s.nd, dtype=torch.float64, device="cuda")
+    ctx.sad_density(rho)
+    assert rel_err(to_np(rho), atoms.sad_density(s)) <= 1e-13
+
+
+def test_potential_matches_oracle():
+    torch = require_gpu()
+    s = W.config1(0)
+    ctx = _ctx(s)
+    st = scf.setup(s)
+    rho = atoms.sad_density(s)
+    phi, exc, vxc, veff = scf.potential(s, st, rho)
+    d = lambda: torch.zeros(s.nd, dtype=torch.float64, device="cuda")
+    P, E, V, VE = d(), d(), d(), d()
+    ctx.potential(to_dev(torch, rho), P, E, V, VE)
+    assert np.max(np.abs(to_np(P) - phi)) <= 1e-11 * max(1.0, np.max(np.abs(phi)))
+    assert rel_err(to_np(E), exc) <= 1e-13
+    assert rel_err(to_np(V), vxc) <= 1e-13
+    assert np.max(np.abs(to_np(VE) - veff)) <= 1e-11 * max(1.0, np.max(np.abs(veff)))
+
+
+def test_spectrum_bounds_match_oracle():
+    torch = require_gpu()
+    s = small_images_system()
+    ctx = _ctx(s)
+    v = _veff(s, 15)
+    ctx.set_veff(to_dev(torch, v))
+    lo, hi = ctx.spectrum_bounds()
+    lo_r, hi_r = hamiltonian.spectrum_bounds(s, v, atoms.projectors(s))
+    assert abs(lo - lo_r) < 1e-11 and abs(hi - hi_r) < 1e-10
+
+
+def test_argument_errors():
+    from paper_2005_10431_amd import SparcError
+    torch = require_gpu()
+    s = small_images_system(n_states=4)
+    ctx = _ctx(s)
+    X = torch.zeros((4, s.nd), dtype=torch.float64, device="cuda")
+    Y = torch.zeros_like(X)
+    with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
+        ctx.apply_H(X, X)                              # aliasing
+    with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
+        ctx.chebyshev_filter(X, Y, 5, 1.0, 2.0, 3.0)   # a0 >= a
+    big = torch.zeros((5, s.nd), dtype=torch.float64, device="cuda")
+    with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
+        ctx.apply_H(big, torch.zeros_like(big))        # ncol > n_states
+    short = torch.zeros((4, s.nd - 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
+        ctx.apply_H(short, torch.zeros_like(short))    # ldx < N_d
