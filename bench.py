@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the CheFSI hot path on one MI355X.
+
+Workload (default): the 108-atom / 72^3-grid / 260-state system with s+p
+nonlocal projectors, Chebyshev degree 20, FP64 (config 2 of the build's
+workload list).  A step is one SCF iteration after the first: potential
+(Poisson + LDA), one Chebyshev filter pass, Rayleigh-Ritz, occupations,
+density, energy and mixing, all on the GPU with inputs resident in HBM.
+
+Printed (one JSON line): filter HBM throughput in algorithmic GB/s
+(3 * s * N_d * N_s * m bytes per filter), time per SCF step, the roofline of
+the dominant kernel (the filter sweep), and the CPU oracle's filter rate on a
+bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+
+WORKLOADS = {
+    "cfg2": "cfg2: L=20 Bohr, 72^3 grid, 108 atoms (FCC 3^3, jitter 0.1), Z=4, s+p KB projectors, "
+            "260 states, Chebyshev degree 20",
+    "cfg4": "cfg4: L=34 Bohr, 120^3 grid, 500 atoms (FCC 5^3, jitter 0.1), Z=4, s+p KB projectors, "
+            "1200 states, Chebyshev degree 24",
+    "cfg1": "cfg1: L=8 Bohr, 24^3 grid, 8 atoms, Z=2, local only, 12 states, Chebyshev degree 12",
+}
+
+
+def traffic_record(kernel_key: str):
+    """HBM traffic per launch measured with rocprofv3 PMC counters, if the
+    recorded source hash still matches the current stencil source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel_key)
+    except Exception:
+        return None
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2005_10431_amd", "csrc", "stencil.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha") != h:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(system, ncols: int, degree: int, bounds):
+    """Time the CPU oracle's filter on `ncols` columns (single thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import atoms, chefsi
+
+    projs = atoms.projectors(system)
+    v = np.random.default_rng(123).uniform(-1.0, 1.0, system.nd)
+    X = W.initial_orbitals(system.nd, ncols, 99)
+    a, b, a0 = bounds
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        chefsi.chebyshev_filter(system, v, projs, X, degree, a, b, a0)
+        dt = time.perf_counter() - t0
+    bytes_ = 3 * 8 * system.nd * ncols * degree
+    return {
+        "value": bytes_ / dt / 1e9,
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"FP64 degree-{degree} Chebyshev filter of {ncols} of the {system.n_states} columns "
+                  f"({system.n[0]}^3 grid, same projectors), {dt:.1f} s, algorithmic bytes 3*8*N_d*ncols*m",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--cpu-cols", type=int, default=3, help="columns in the CPU oracle sample (0: skip)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-filter companion measurement")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2005_10431_amd import Context, make_state
+
+    system = {"cfg1": W.config1, "cfg2": W.config2, "cfg4": W.config4}[args.workload](0)
+    nd, ns, m = system.nd, system.n_states, system.cheb_degree
+
+    def run(prec, steps, warmup, profile):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        s = 8 if prec == "fp64" else 4
+        ctx = Context(system)
+        X = torch.as_tensor(W.initial_orbitals(nd, ns, 0)).to(dt).cuda()
+        rho = torch.empty(nd, dtype=torch.float64, device="cuda")
+        ctx.sad_density(rho)
+        eig = torch.empty(ns, dtype=torch.float64, device="cuda")
+        occ = torch.empty_like(eig)
+        st = make_state(rho, X, eig, occ, m, system.n_first, system.mix_beta)
+        first = ctx.scf_step(st)                      # iteration 0 (initial RR + n_first passes)
+        for _ in range(warmup):
+            ctx.scf_step(st)
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile(True)
+            for k in range(8):
+                ctx.profile_read(k)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = []
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            reps.append(ctx.scf_step(st))
+        e1.record()
+        torch.cuda.synchronize()
+        wall_ms = e0.elapsed_time(e1)
+        prof = {}
+        if profile:
+            for k, name in [(0, "sweep"), (1, "projection"), (2, "gemm_tn"), (3, "gemm_nn"), (4, "density"),
+                            (5, "sweep1"), (6, "apply")]:
+                ms, n = ctx.profile_read(k)
+                prof[name] = (ms, n)
+            ctx.profile(False)
+        filt_ms = sum(r["t_filter_ms"] for r in reps)
+        fbytes = 3 * s * nd * ns * m * steps
+        out = dict(
+            ms_per_step=wall_ms / steps,
+            filter_gbs=fbytes / (filt_ms * 1e-3) / 1e9,
+            t_filter_ms=float(np.median([r["t_filter_ms"] for r in reps])),
+            t_rr_ms=float(np.median([r["t_rr_ms"] for r in reps])),
+            t_potential_ms=float(np.median([r["t_potential_ms"] for r in reps])),
+            t_density_ms=float(np.median([r["t_density_ms"] for r in reps])),
+            free_energy_per_atom=reps[-1]["free_energy"] / system.n_atoms,
+            residual=reps[-1]["residual"],
+            first_iter_ms=first["t_total_ms"],
+            bounds=list(st.bounds),
+            prof=prof,
+            s=s,
+        )
+        ctx.close()
+        return out
+
+    res = run(args.prec, args.steps, args.warmup, True)
+    s = res["s"]
+    prof = res["prof"]
+    sw_ms, sw_n = prof["sweep"]
+    bytes_per_sweep = 3 * s * nd * ns
+    achieved = bytes_per_sweep / (sw_ms / sw_n * 1e-3) / 1e9 if sw_n else None
+    kernel_name = f"k_hsweep<{'double' if s == 8 else 'float'}, nonlocal, mode 2>"
+    traffic = traffic_record(f"{args.workload}_{args.prec}_sweep")
+    gt_ms, gt_n = prof["gemm_tn"]
+    gemm_flops = 2.0 * ns * ns * nd * gt_n   # two N_s x N_s products from K = N_d per RR (Gram counted full)
+    line = {
+        "metric": "CheFSI filter HBM GB/s + time/SCF step",
+        "value": res["filter_gbs"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if s == 8 else "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "grid": list(system.n), "n_states": ns,
+                   "n_atoms": system.n_atoms, "cheb_degree": m, "precision": args.prec},
+        "roofline": {
+            "kernel": kernel_name,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS if achieved else None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_per_sweep,
+            "avg_launch_ms": sw_ms / sw_n if sw_n else None,
+            "launches": sw_n,
+        },
+        "scf_step_breakdown_ms": {k: res[k] for k in ("t_potential_ms", "t_filter_ms", "t_rr_ms", "t_density_ms")},
+        "first_iteration_ms": res["first_iter_ms"],
+        "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
+        "gemm_tn_tflops": (gemm_flops / (gt_ms * 1e-3) / 1e12) if gt_ms else None,
+    }
+    if args.prec == "fp64" and not args.no_fp32:
+        r32 = run("fp32", max(2, args.steps // 2), 1, False)
+        line["fp32"] = {"filter_gbs": r32["filter_gbs"], "ms_per_step": r32["ms_per_step"],
+                        "scf_step_breakdown_ms": {k: r32[k] for k in ("t_potential_ms", "t_filter_ms",
+                                                                       "t_rr_ms", "t_density_ms")}}
+    if args.cpu_cols > 0:
+        line["cpu_baseline"] = cpu_baseline(system, args.cpu_cols, m, res["bounds"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

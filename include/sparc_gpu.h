@@ -13,7 +13,7 @@
  *  - Grid: n[0] x n[1] x n[2] points on an orthorhombic cell L[0..2] (Bohr);
  *    point (ix, iy, iz) sits at (ix*hx, iy*hy, iz*hz), h = L/n, and has flat
  *    index p = ix + n[0]*(iy + n[1]*iz).  N_d = n[0]*n[1]*n[2].  Every axis
- *    is periodic and must have at least 2*fd_half_order + 1 points.
+ *    is periodic and must have at least 13 points; n[0] <= 256.
  *  - Blocks of orbitals ("X") are column-major N_d x ncol arrays with leading
  *    dimension ldx >= N_d: orbital j occupies X[j*ldx .. j*ldx + N_d).  Their
  *    element type is double for SPARC_FP64 and float for SPARC_FP32.
@@ -216,6 +216,16 @@ sparc_status sparc_gpu_scf_step(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st, spar
  * energy at rho_in.  No mixing; st->iter unchanged.  Synchronises once. */
 sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st, double* d_X64, long ldx64,
                                      sparc_gpu_scf_report* rep);
+
+/* Kernel timing (tracing aid).  When enabled, every launch of the listed
+ * kernels is bracketed by HIP events on the context's stream.
+ * sparc_gpu_profile_read() synchronises, returns the summed device time (ms)
+ * and launch count since the last read for one kernel, and resets it.
+ * Kernel ids: 0 filter sweep of degree >= 2, 1 nonlocal projection,
+ * 2 Gram/projected-H GEMM, 3 rotation GEMM, 4 density, 5 first filter
+ * sweep, 6 plain H application. */
+sparc_status sparc_gpu_profile(sparc_gpu_ctx ctx, int enable);
+sparc_status sparc_gpu_profile_read(sparc_gpu_ctx ctx, int kernel_id, double* total_ms, long* launches);
 
 #ifdef __cplusplus
 }

@@ -46,6 +46,8 @@ EXPORTED = [
     "sparc_gpu_spectrum_bounds",
     "sparc_gpu_scf_step",
     "sparc_gpu_final_rr_fp64",
+    "sparc_gpu_profile",
+    "sparc_gpu_profile_read",
 ]
 
 
@@ -151,6 +153,8 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_spectrum_bounds": ([vp, C.POINTER(d), C.POINTER(d)], i),
         "sparc_gpu_scf_step": ([vp, C.POINTER(SCFState), C.POINTER(SCFReport)], i),
         "sparc_gpu_final_rr_fp64": ([vp, C.POINTER(SCFState), vp, l, C.POINTER(SCFReport)], i),
+        "sparc_gpu_profile": ([vp, i], i),
+        "sparc_gpu_profile_read": ([vp, i, C.POINTER(d), C.POINTER(l)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -286,6 +290,14 @@ class Context:
         rep = SCFReport()
         self._check(self.lib.sparc_gpu_scf_step(self.h, C.byref(state), C.byref(rep)))
         return rep.as_dict()
+
+    def profile(self, enable: bool):
+        self._check(self.lib.sparc_gpu_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, kernel_id: int):
+        ms, n = C.c_double(), C.c_long()
+        self._check(self.lib.sparc_gpu_profile_read(self.h, int(kernel_id), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def final_rr_fp64(self, state: SCFState, X64) -> dict:
         rep = SCFReport()

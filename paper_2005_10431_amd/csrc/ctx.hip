@@ -9,6 +9,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <numeric>
 
 #include "internal.hpp"
@@ -40,6 +41,41 @@ static sparc_status grow(sparc_gpu_ctx c, void** p, size_t* have, size_t need) {
 }
 
 sparc_status ensure_work(sparc_gpu_ctx c, size_t bytes) { return grow(c, &c->work, &c->work_bytes, bytes); }
+
+int prof_begin(sparc_gpu_ctx c, int kernel) {
+    if (!c->prof) return -1;
+    int slot = c->prof_used;
+    if (2 * (size_t)(slot + 1) > c->prof_pool.size()) {
+        for (int i = 0; i < 2; ++i) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            c->prof_pool.push_back(e);
+        }
+        c->prof_kernel.push_back(0);
+    }
+    c->prof_kernel[slot] = kernel;
+    c->prof_used++;
+    hipEventRecord(c->prof_pool[2 * slot], c->stream);
+    return slot;
+}
+
+void prof_end(sparc_gpu_ctx c, int slot) {
+    if (slot < 0) return;
+    hipEventRecord(c->prof_pool[2 * slot + 1], c->stream);
+}
+
+static sparc_status prof_flush(sparc_gpu_ctx c) {
+    if (c->prof_used == 0) return SPARC_OK;
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->prof_used; ++i) {
+        float ms = 0.f;
+        SG_HIP(c, hipEventElapsedTime(&ms, c->prof_pool[2 * i], c->prof_pool[2 * i + 1]));
+        c->prof_ms[c->prof_kernel[i]] += ms;
+        c->prof_n[c->prof_kernel[i]] += 1;
+    }
+    c->prof_used = 0;
+    return SPARC_OK;
+}
 
 sparc_status ensure_gemm_part(sparc_gpu_ctx c, size_t elems) {
     size_t have = c->gemm_part_elems * sizeof(double);
@@ -343,6 +379,88 @@ static double symbol(const double* w, int n_o, double th) {
     return s;
 }
 
+// Per-slab projector tables of the sweep kernel.  The grid is cut into
+// y-slabs of c->nl_ty rows.  A "candidate" of a slab is an (atom, periodic
+// image) pair whose support meets the slab; point p of the slab stores the
+// slab-local indices of its candidates as bytes of pe8[p] (0xFF pads).  For
+// each candidate the unwrapped x and z index ranges touched inside the slab
+// are recorded, so the sweep can tabulate the separable Gaussian factors.
+sparc_status build_slab_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent) {
+    sg::NonlocalTables& T = c->nl;
+    const int ty = c->nl_ty;
+    const int nslab = (c->ny + ty - 1) / ty;
+    std::vector<uint64_t> pe8(c->nd, ~0ull);
+    std::vector<std::vector<CandInfo>> cands(nslab);
+    int kmax = 0, xw = 0, zw = 0;
+    for (int sidx = 0; sidx < nslab; ++sidx) {
+        const int y0 = sidx * ty, tyn = std::min(ty, c->ny - y0);
+        std::vector<std::pair<uint32_t, int>> keys;  // packed word -> local index
+        auto& cl = cands[sidx];
+        for (int z = 0; z < c->nz; ++z)
+            for (int y = y0; y < y0 + tyn; ++y)
+                for (int x = 0; x < c->nx; ++x) {
+                    const long p = x + (long)c->nx * (y + (long)c->ny * z);
+                    int cnt = 0;
+                    uint64_t word = ~0ull;
+                    for (int e = c->pe_off_host[p]; e < c->pe_off_host[p + 1]; ++e) {
+                        const uint32_t w = ent[e];
+                        int k = -1;
+                        for (auto& kv : keys)
+                            if (kv.first == w) {
+                                k = kv.second;
+                                break;
+                            }
+                        const int sx = (int)((w >> 20) & 15u) - 8, sz = (int)(w >> 28) - 8;
+                        const int ix = x + sx * c->nx, iz = z + sz * c->nz;
+                        if (k < 0) {
+                            k = (int)cl.size();
+                            keys.push_back({w, k});
+                            CandInfo ci;
+                            ci.atom = (int)(w & 0xFFFFFu);
+                            ci.sx = sx;
+                            ci.sy = (int)((w >> 24) & 15u) - 8;
+                            ci.sz = sz;
+                            ci.ixlo = ci.ixhi = ix;
+                            ci.izlo = ci.izhi = iz;
+                            cl.push_back(ci);
+                        }
+                        CandInfo& ci = cl[k];
+                        ci.ixlo = std::min(ci.ixlo, ix);
+                        ci.ixhi = std::max(ci.ixhi, ix);
+                        ci.izlo = std::min(ci.izlo, iz);
+                        ci.izhi = std::max(ci.izhi, iz);
+                        if (k > 254 || cnt >= 7)
+                            return set_err(c, SPARC_ERR_ARG,
+                                           "projector overlap too dense for the sweep tables (> 254 images per slab "
+                                           "or > 7 projectors at one point)");
+                        word &= ~(0xFFull << (8 * cnt));
+                        word |= (uint64_t)k << (8 * cnt);
+                        ++cnt;
+                    }
+                    pe8[p] = word;
+                }
+        kmax = std::max(kmax, (int)cl.size());
+        for (auto& ci : cl) {
+            xw = std::max(xw, ci.ixhi - ci.ixlo + 1);
+            zw = std::max(zw, ci.izhi - ci.izlo + 1);
+        }
+    }
+    T.slab_kmax = std::max(kmax, 1);
+    T.slab_xw = std::max(xw, 1);
+    T.slab_zw = std::max(zw, 1);
+    std::vector<CandInfo> flat((size_t)nslab * T.slab_kmax);
+    std::vector<int> kcount(nslab);
+    for (int sidx = 0; sidx < nslab; ++sidx) {
+        kcount[sidx] = (int)cands[sidx].size();
+        for (size_t k = 0; k < cands[sidx].size(); ++k) flat[(size_t)sidx * T.slab_kmax + k] = cands[sidx][k];
+    }
+    sparc_status st;
+    if ((st = upload(c, &T.pe8, pe8)) != SPARC_OK) return st;
+    if ((st = upload(c, &T.slab_cand, flat)) != SPARC_OK) return st;
+    if ((st = upload(c, &T.slab_k, kcount)) != SPARC_OK) return st;
+    return SPARC_OK;
+}
+
 sparc_status build_tables(sparc_gpu_ctx c) {
 #pragma clang fp contract(off)
     const double pi = 3.14159265358979323846;
@@ -421,8 +539,11 @@ sparc_status build_tables(sparc_gpu_ctx c) {
     if (c->nl_lmax >= 1) {
         sg::NonlocalTables& T = c->nl;
         T.n_atoms = c->n_atoms;
+        if (c->n_atoms >= (1 << 20)) return set_err(c, SPARC_ERR_ARG, "too many atoms for the projector tables");
         std::vector<long> sup_off(c->n_atoms + 1, 0);
         std::vector<int> sup_idx, sup_atom, img_off(1, 0), img_ijk;
+        std::vector<std::pair<long, uint32_t>> img_pts;  // (flat point, packed atom/image)
+        bool image_overflow = false;
         const double rcut = c->rcut_nl, r2max = rcut * rcut;
         const double h[3] = {c->hx, c->hy, c->hz};
         const int n[3] = {c->nx, c->ny, c->nz};
@@ -435,6 +556,7 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             }
             // (flat index, unwrapped i, j, k) of every image point in the ball
             std::vector<std::pair<long, std::array<int, 3>>> pts;
+            auto fdiv = [](int v, int m) { return (v >= 0) ? v / m : -((-v + m - 1) / m); };
             for (int k = lo[2]; k <= hi[2]; ++k) {
                 double dz = k * h[2] - P[2];
                 for (int j = lo[1]; j <= hi[1]; ++j) {
@@ -449,6 +571,12 @@ sparc_status build_tables(sparc_gpu_ctx c) {
                         int wk = ((k % n[2]) + n[2]) % n[2];
                         long flat = wi + (long)n[0] * (wj + (long)n[1] * wk);
                         pts.push_back({flat, {i, j, k}});
+                        // image-level entry of the point: atom and image shifts
+                        int sx = fdiv(i, n[0]), sy = fdiv(j, n[1]), sz = fdiv(k, n[2]);
+                        if (sx < -8 || sx > 7 || sy < -8 || sy > 7 || sz < -8 || sz > 7) image_overflow = true;
+                        img_pts.push_back({flat, (uint32_t)a | ((uint32_t)((sx + 8) & 15) << 20) |
+                                                     ((uint32_t)((sy + 8) & 15) << 24) |
+                                                     ((uint32_t)((sz + 8) & 15) << 28)});
                     }
                 }
             }
@@ -471,6 +599,21 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             T.max_per_atom = std::max<int>(T.max_per_atom, (int)(sup_off[a + 1] - sup_off[a]));
         }
         T.n_sup = (long)sup_idx.size();
+        // image-level point-major entries, atom order within a point
+        {
+            if (image_overflow)
+                return set_err(c, SPARC_ERR_ARG, "projector support spans too many periodic images");
+            c->pe_off_host.assign(c->nd + 1, 0);
+            for (auto& q : img_pts) c->pe_off_host[q.first + 1]++;
+            for (long p = 0; p < c->nd; ++p) c->pe_off_host[p + 1] += c->pe_off_host[p];
+            std::vector<uint32_t> ent(img_pts.size());
+            std::vector<int> fill(c->pe_off_host.begin(), c->pe_off_host.end() - 1);
+            for (auto& q : img_pts) ent[fill[q.first]++] = q.second;
+            if ((st = upload(c, &T.pe_off, c->pe_off_host)) != SPARC_OK) return st;
+            if ((st = upload(c, &T.pe_ent, ent)) != SPARC_OK) return st;
+            T.n_pe = (long)ent.size();
+            if ((st = build_slab_tables(c, ent)) != SPARC_OK) return st;
+        }
         // point-major inverse lists (entries per point in atom order)
         std::vector<int> pt_off(c->nd + 1, 0), pt_atom(T.n_sup), pt_src(T.n_sup);
         for (long s = 0; s < T.n_sup; ++s) pt_off[sup_idx[s] + 1]++;
@@ -482,6 +625,27 @@ sparc_status build_tables(sparc_gpu_ctx c) {
                 pt_atom[e] = sup_atom[s];
                 pt_src[e] = (int)s;
             }
+        }
+        // Morton order of the atoms (10 bits per axis of the fractional position)
+        {
+            std::vector<std::pair<uint64_t, int>> key(c->n_atoms);
+            const double Ls[3] = {c->Lx, c->Ly, c->Lz};
+            for (int a = 0; a < c->n_atoms; ++a) {
+                uint64_t k = 0;
+                uint32_t q[3];
+                for (int d = 0; d < 3; ++d) {
+                    double f = c->pos[3 * a + d] / Ls[d];
+                    f = f - std::floor(f);
+                    q[d] = (uint32_t)std::min(1023.0, std::floor(f * 1024.0));
+                }
+                for (int bit = 9; bit >= 0; --bit)
+                    for (int d = 2; d >= 0; --d) k = (k << 1) | ((q[d] >> bit) & 1u);
+                key[a] = {k, a};
+            }
+            std::sort(key.begin(), key.end());
+            std::vector<int> order(c->n_atoms);
+            for (int a = 0; a < c->n_atoms; ++a) order[a] = key[a].second;
+            if ((st = upload(c, &T.atom_order, order)) != SPARC_OK) return st;
         }
         std::vector<double> g4(4 * c->n_atoms);
         for (int a = 0; a < c->n_atoms; ++a) {
@@ -541,6 +705,9 @@ sparc_status build_tables(sparc_gpu_ctx c) {
         SG_HIP(c, hipMalloc((void**)&c->D32, std::max<size_t>(1, 4 * (size_t)c->n_atoms * c->n_states) * sizeof(float)));
     }
 
+    // --- atom positions for the on-the-fly projector evaluation
+    if ((st = upload(c, &c->atom_pos, c->pos)) != SPARC_OK) return st;
+
     // --- Poisson eigenbases
     {
         std::vector<double> Ux, Uy, Uz;
@@ -585,7 +752,7 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
         if (s->n[d] < mino || s->n[d] > 4096) return SPARC_ERR_ARG;
         if (!(s->L[d] > 0.0) || !std::isfinite(s->L[d])) return SPARC_ERR_ARG;
     }
-    if (s->n[0] > 1024 - 2 * kMaxHalfOrder) return SPARC_ERR_ARG;
+    if (s->n[0] > 256) return SPARC_ERR_ARG;  // an x-row must fit one sweep workgroup
     if ((long)s->n[0] * s->n[1] * s->n[2] > (1L << 31) - 1) return SPARC_ERR_ARG;
     if (s->n_atoms < 0 || (s->n_atoms > 0 && (!s->pos || !s->Z || !s->rc_loc))) return SPARC_ERR_ARG;
     if (s->nl_lmax != -1 && s->nl_lmax != 1) return SPARC_ERR_ARG;
@@ -629,6 +796,8 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     c->sad_width = s->sad_width;
     c->stream = (hipStream_t)hip_stream;
     for (int i = 0; i < 8; ++i) c->ev[i] = nullptr;
+    if (const char* e = std::getenv("SPARC_GPU_SWEEP_SLAB_MAJOR")) c->sweep_slab_major = std::atoi(e) != 0;
+    c->nl_ty = choose_sweep_ty(c->nx, c->ny, 512);
 
     int dev = 0;
     sparc_status st = SPARC_OK;
@@ -654,16 +823,42 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
     void* ptrs[] = {c->veff, c->veff32, c->b, c->pois_ux, c->pois_uy, c->pois_uz, c->pois_inv, c->work, c->D,
                     c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,
                     c->nl.sup_idx, c->nl.sup_chi, c->nl.sup_chi32, c->nl.pt_off, c->nl.pt_atom, c->nl.pt_chi,
-                    c->nl.pt_chi32, c->nl.gamma4};
+                    c->nl.pt_chi32, c->nl.gamma4, c->nl.atom_order, c->nl.pe_off, c->nl.pe_ent, c->atom_pos,
+                    c->nl.pe8, c->nl.slab_cand, c->nl.slab_k};
     for (void* p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < 8; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
+    for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
     delete c;
     return SPARC_OK;
 }
 
 const char* sparc_gpu_last_error(sparc_gpu_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+sparc_status sparc_gpu_profile(sparc_gpu_ctx c, int enable) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!enable) {
+        sparc_status st = prof_flush(c);
+        if (st != SPARC_OK) return st;
+    }
+    c->prof = enable != 0;
+    return SPARC_OK;
+}
+
+sparc_status sparc_gpu_profile_read(sparc_gpu_ctx c, int kernel, double* total_ms, long* launches) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (kernel < 0 || kernel >= PK_COUNT) return set_err(c, SPARC_ERR_ARG, "profile_read: bad kernel id");
+    sparc_status st = prof_flush(c);
+    if (st != SPARC_OK) return st;
+    if (total_ms) *total_ms = c->prof_ms[kernel];
+    if (launches) *launches = c->prof_n[kernel];
+    c->prof_ms[kernel] = 0.0;
+    c->prof_n[kernel] = 0;
+    return SPARC_OK;
+}
 
 long sparc_gpu_grid_size(sparc_gpu_ctx c) { return c ? c->nd : 0; }
 

@@ -139,9 +139,11 @@ sparc_status gemm_tn(sparc_gpu_ctx c, int M, int N, long K, const T* A, long lda
     sparc_status st = ensure_gemm_part(c, (size_t)nsplit * M * N);
     if (st != SPARC_OK) return st;
     dim3 grid(tiles, nsplit);
+    const int slot = prof_begin(c, PK_GEMM_TN);
     k_gemm_tn_split<T><<<grid, 256, 0, c->stream>>>(M, N, K, kchunk, A, lda, B, ldb, c->gemm_part, tiles_m,
                                                   symmetric);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     k_gemm_reduce<<<div_up((long)M * N, 256), 256, 0, c->stream>>>(M, N, nsplit, c->gemm_part, alpha, C, ldc,
                                                                    symmetric);
     SG_CHECK_LAUNCH(c);
@@ -211,8 +213,10 @@ template <typename T>
 sparc_status gemm_nn(sparc_gpu_ctx c, long K, int N, int M, const T* A, long lda, const double* Bm, int ldb, T* Out,
                      long ldo) {
     dim3 grid(div_up(K, TB), div_up(N, TB));
+    const int slot = prof_begin(c, PK_GEMM_NN);
     k_gemm_nn<T><<<grid, 256, 0, c->stream>>>(K, N, M, A, lda, Bm, ldb, Out, ldo);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 

@@ -23,6 +23,13 @@ struct StencilCoef {
     T c0;
 };
 
+// An (atom, periodic image) pair whose projector support meets a slab, with
+// the unwrapped x and z index ranges it covers there.
+struct CandInfo {
+    int atom, sx, sy, sz;
+    int ixlo, ixhi, izlo, izhi;
+};
+
 // Nonlocal projector tables on the device.
 //  Atom-major (for projections):   atom a owns support entries
 //     s in [sup_off[a], sup_off[a+1]):  grid index sup_idx[s],
@@ -42,6 +49,19 @@ struct NonlocalTables {
     double* pt_chi = nullptr;  // 4 n_sup
     float* pt_chi32 = nullptr;
     double* gamma4 = nullptr;  // 4 n_atoms: (g_s, g_p, g_p, g_p)
+    int* atom_order = nullptr; // atoms in space-filling (Morton) order
+    // Image-level point-major entries for the sweep: point p owns entries
+    // [pe_off[p], pe_off[p+1]) of pe_ent, each packing the atom index
+    // (bits 0-19) and its periodic image shifts + 8 (bits 20-23 x, 24-27 y,
+    // 28-31 z); the projector values are evaluated on the fly.
+    int* pe_off = nullptr;
+    uint32_t* pe_ent = nullptr;
+    long n_pe = 0;
+    // per-slab candidate tables of the sweep (see build_slab_tables)
+    uint64_t* pe8 = nullptr;
+    CandInfo* slab_cand = nullptr;          // [n_slabs][slab_kmax]
+    int* slab_k = nullptr;                  // candidates per slab
+    int slab_kmax = 0, slab_xw = 0, slab_zw = 0;
     double nl_hi = 0.0, nl_lo = 0.0;  // signed spectral bound contributions
     int max_per_atom = 0;
 };
@@ -103,6 +123,19 @@ struct sparc_gpu_ctx_s {
 
     hipEvent_t ev[8];
     std::string err;
+    int sweep_slab_major = 0;   // block order of the sweep kernel
+    std::vector<int> pe_off_host;  // host copy of nl.pe_off (slab-plane maxima)
+    int emax_ty = -1, emax_val = 0;
+    int nl_ty = 6;                 // slab height of the nonlocal sweep
+    double* atom_pos = nullptr;    // 3 n_atoms
+
+    // kernel timing (sparc_gpu_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> prof_pool;        // 2 events per recorded launch
+    std::vector<int> prof_kernel;             // kernel id per recorded launch
+    int prof_used = 0;
+    double prof_ms[8] = {0};
+    long prof_n[8] = {0};
 };
 
 namespace sg {
@@ -179,8 +212,25 @@ sparc_status density_impl(sparc_gpu_ctx c, const T* X, int ncol, long ldx, const
 sparc_status set_veff_impl(sparc_gpu_ctx c, const double* d_veff);
 sparc_status bounds_impl(sparc_gpu_ctx c);  // writes S_LO / S_HI on device
 
+// Kernel timing: prof_begin returns a slot (or -1 when disabled), prof_end
+// records its closing event.
+enum ProfKernel {
+    PK_SWEEP = 0,    // filter step k >= 2 (reads X_k, X_{k-1}; writes X_{k+1})
+    PK_PROJ = 1,
+    PK_GEMM_TN = 2,
+    PK_GEMM_NN = 3,
+    PK_DENSITY = 4,
+    PK_SWEEP1 = 5,   // first filter step
+    PK_APPLY = 6,    // plain H application
+    PK_COUNT = 8
+};
+int prof_begin(sparc_gpu_ctx c, int kernel);
+void prof_end(sparc_gpu_ctx c, int slot);
+
 // Build geometry tables (ctx.hip)
 sparc_status build_tables(sparc_gpu_ctx c);
+sparc_status build_slab_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent);
+int choose_sweep_ty(int nx, int ny, int max_threads);
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 

@@ -240,8 +240,10 @@ __global__ __launch_bounds__(256) void k_density(const T* __restrict__ X, int nc
 
 template <typename T>
 sparc_status density_impl(sparc_gpu_ctx c, const T* X, int ncol, long ldx, const double* occ, double* rho) {
+    const int slot = prof_begin(c, PK_DENSITY);
     k_density<T><<<div_up(c->nd, 256), 256, 0, c->stream>>>(X, ncol, ldx, occ, rho, c->nd);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 template sparc_status density_impl<double>(sparc_gpu_ctx, const double*, int, long, const double*, double*);

@@ -15,6 +15,9 @@
 //  - z is marched with a register queue of 2*NO+1 planes per thread, so every
 //    point of X_k is fetched from HBM once per sweep (plus 2*NO wrap planes);
 //  - two LDS plane buffers alternate so one barrier per plane suffices.
+#include <cmath>
+#include <cstdlib>
+
 #include "internal.hpp"
 
 namespace sg {
@@ -29,14 +32,20 @@ struct SweepArgs {
     int ty, ntiles_y;
     StencilCoef<T> cf;
     const T* veff;
-    const int* pt_off;
-    const int* pt_atom;
-    const T* pt_chi;
+    // nonlocal part (per-slab candidate tables, see build_slab_tables)
+    const uint64_t* pe8;
+    const CandInfo* slab_cand;
+    const int* slab_k;
+    int kmax, xw;
+    const double* atom_pos;  // 3 n_atoms
+    T inv_rc2, N0, N1, hx, hy, hz;
     const T* D;       // gamma-scaled projections, column j at D + j*ldD
     int ldD;
     const double* params;  // a, b, a0 on the device
     int mode;              // 0: H x; 1: first filter step; 2: filter step `step`
     int step;
+    int ncol;
+    int slab_major;        // block order: slab-major instead of orbital-major
 };
 
 // Filter coefficients of step k of the scaled recurrence:
@@ -68,8 +77,165 @@ __device__ inline void filter_coefs(const double* params, int mode, int step, do
     beta = -sp * s;
 }
 
-template <typename T, bool NL>
-__global__ __launch_bounds__(1024) void k_hsweep(SweepArgs<T> a) {
+constexpr int RING = 2 * kMaxHalfOrder + 2;  // z-queue slots (one spare for prefetch)
+
+// Per-thread registers of the sweep: the z-queue ring (plane z lives in slot
+// z mod RING), the prefetched halo values of the next plane, and the next
+// plane's X_{k-1} and V_eff values.  Indices are compile-time after
+// unrolling, so everything stays in VGPRs.
+template <typename T, int HM>
+struct SweepRegs {
+    T q[RING];
+    T h[HM];             // next plane's halo values (this thread's share)
+    T xp[2];
+    T ve[2];
+    uint64_t pe8[2];     // own point's projector candidates (bytes, 0xFF pads)
+};
+
+template <typename T>
+struct SweepGeom {
+    const void* xc;
+    void* oc;
+    const void* pc;
+    long plane, pxy;
+    int nz, col, hn;
+    bool active;
+    int goff[3], loff[3], poff[3];
+    int lrow;  // LDS offset of this thread's own point
+    int W, nx, lx, ly, gy, t, nt;
+    // LDS tables of the slab's projector candidates (K of them):
+    T *cx, *cy, *cz;        // image-shifted atom centre
+    T *ds, *dpx, *dpy, *dpz; // this orbital's gamma-scaled projections
+    int* cxb;               // x index offset into the ex table
+    T* ex;                  // ex[k*xw + i]: exp(-dx^2/rc^2) over the candidate's x-range
+    T* ey;                  // ey[row*K + k]
+    T* ez;                  // ez[parity*K + k] for planes z+1 / z+2
+    T* ab;                  // ab[parity][row][k][2]: A, B of plane z / z+1
+    int K, y0, tyn, xw;
+};
+
+// A(row, k), B(row, k) of one plane z: the candidate's projector values on
+// the row factor as ex(x) * (A + B * dx) with
+//   A = ey ez (N0 D_s + N1 (dy D_py + dz D_pz)),  B = ey ez N1 D_px.
+template <typename T>
+__device__ __forceinline__ void sweep_ab(const SweepArgs<T>& a, const SweepGeom<T>& g, int z, int ezpar,
+                                         T* abz) {
+    const int n = g.tyn * g.K;
+    for (int j = g.t; j < n; j += g.nt) {
+        const int row = j / g.K, k = j - row * g.K;
+        const T eyz = g.ey[j] * g.ez[ezpar * g.K + k];
+        const T dy = (T)(g.y0 + row) * a.hy - g.cy[k];
+        const T dz = (T)z * a.hz - g.cz[k];
+        abz[2 * j] = eyz * (a.N0 * g.ds[k] + a.N1 * (dy * g.dpy[k] + dz * g.dpz[k]));
+        abz[2 * j + 1] = eyz * a.N1 * g.dpx[k];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void sweep_ez(const SweepArgs<T>& a, const SweepGeom<T>& g, int z, int ezpar) {
+    for (int k = g.t; k < g.K; k += g.nt) {
+        const T dz = (T)z * a.hz - g.cz[k];
+        g.ez[ezpar * g.K + k] = exp(-dz * dz * a.inv_rc2);
+    }
+}
+
+// One z-plane of the sweep at ring phase U (z = z0 + U).  On entry the LDS
+// buffer of parity U holds plane z (own rows with x-wrap padding, halo rows,
+// and the plane's projector entries), written during the previous step.
+//  1. barrier,
+//  2. issue the loads of plane z+1 (halo rows, projector entries, own
+//     X_{k-1}, V_eff and entry range; the plane index wraps so the loads are
+//     unconditional and the step is straight-line code),
+//  3. stencil + potential + nonlocal + recurrence for plane z, store,
+//  4. write plane z+1 into the other LDS buffer (its loads have had the
+//     whole compute phase to land),
+//  5. load plane z + NO + 2 into the ring slot freed by plane z - NO.
+// Threads without a point of the slab (ragged slab, padding to 64) load
+// valid clamped addresses and compute on them, but never store.
+template <int U, typename T, bool NL, int MODE, int HM>
+__device__ __forceinline__ void sweep_step(const SweepArgs<T>& a, SweepRegs<T, HM>& r, const SweepGeom<T>& g,
+                                           T* buf0, T* buf1, int z, T alpha, T cshift, T beta) {
+    constexpr int NO = kMaxHalfOrder;
+    constexpr int P = U & 1, PN = (U + 1) & 1;
+    constexpr int C = U % RING;
+    const T* __restrict__ xc = (const T*)g.xc;
+    __syncthreads();
+    const int z1 = (z + 1 == g.nz) ? 0 : z + 1;
+    const long zoff1 = (long)z1 * g.plane;
+#pragma unroll
+    for (int i = 0; i < HM; ++i) r.h[i] = xc[g.goff[i] + zoff1];
+    if (MODE == 2) r.xp[PN] = ((const T*)g.pc)[g.pxy + zoff1];
+    r.ve[PN] = a.veff[g.pxy + zoff1];
+    if (NL) r.pe8[PN] = a.pe8[g.pxy + zoff1];
+
+    T* buf = P ? buf1 : buf0;
+    const T* rp = buf + g.lrow;
+    const int W = g.W;
+    T lap = a.cf.c0 * r.q[C];
+#pragma unroll
+    for (int k = 1; k <= NO; ++k) lap += a.cf.cz[k] * (r.q[(U + k) % RING] + r.q[(U + RING - k) % RING]);
+#pragma unroll
+    for (int k = 1; k <= NO; ++k) lap += a.cf.cx[k] * (rp[k] + rp[-k]);
+#pragma unroll
+    for (int k = 1; k <= NO; ++k) lap += a.cf.cy[k] * (rp[k * W] + rp[-k * W]);
+    const long p = g.pxy + (long)z * g.plane;
+    T hv = lap + r.ve[P] * r.q[C];
+    if (NL) {
+        // sum over the projectors whose support holds this point of
+        // chi_s D_s + chi_p . D_p = ex(x) (A + B dx)   (see sweep_ab)
+        const T* abr = g.ab + (P * a.ty + (g.active ? g.ly : 0)) * 2 * g.K;
+        uint64_t w = g.active ? r.pe8[P] : ~0ull;
+        T nl = 0;
+        for (int j = 0; j < 7; ++j) {
+            const int k = (int)(w & 0xFFull);
+            if (k == 0xFF) break;
+            w >>= 8;
+            const T exv = g.ex[k * g.xw + (g.lx - g.cxb[k])];
+            const T dx = (T)g.lx * a.hx - g.cx[k];
+            nl += exv * (abr[2 * k] + abr[2 * k + 1] * dx);
+        }
+        hv += nl;
+    }
+    T o;
+    if (MODE == 0) {
+        o = hv;
+    } else {
+        o = alpha * (hv - cshift * r.q[C]);
+        if (MODE == 2) o += beta * r.xp[P];
+    }
+    if (g.active) ((T*)g.oc)[p] = o;
+
+    // plane z+1 into the other buffer
+    T* nbuf = P ? buf0 : buf1;
+    constexpr int CN = (U + 1) % RING;
+    if (g.active) {
+        nbuf[g.lrow] = r.q[CN];
+        if (g.lx < NO) nbuf[g.lrow + g.nx] = r.q[CN];
+        if (g.lx >= g.nx - NO) nbuf[g.lrow - g.nx] = r.q[CN];
+    }
+#pragma unroll
+    for (int i = 0; i < HM; ++i)
+        if (i < g.hn) {
+            nbuf[g.loff[i]] = r.h[i];
+            if (g.poff[i] >= 0) nbuf[g.poff[i]] = r.h[i];
+        }
+    if (NL) {
+        // tables of the next plane: A/B of z+1 (its ez was computed one step
+        // earlier), and ez of z+2
+        sweep_ab<T>(a, g, z1, PN, g.ab + PN * a.ty * 2 * g.K);
+        const int z2 = (z1 + 1 == g.nz) ? 0 : z1 + 1;
+        sweep_ez<T>(a, g, z2, P);
+    }
+    int zn = z + NO + 2;
+    zn = zn >= g.nz ? zn - g.nz : zn;
+    r.q[(U + NO + 2) % RING] = xc[g.pxy + (long)zn * g.plane];
+}
+
+// Workgroups of the nonlocal variant are capped at 512 threads so that its
+// extra live registers (entry prefetch, projector evaluation) fit without
+// spilling.
+template <typename T, bool NL, int MODE, int HM>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, NL ? 512 : 1024))) void k_hsweep(SweepArgs<T> a) {
     constexpr int NO = kMaxHalfOrder;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* buf0 = reinterpret_cast<T*>(smem_raw);
@@ -85,44 +251,102 @@ __global__ __launch_bounds__(1024) void k_hsweep(SweepArgs<T> a) {
     const int qn = nblk / 8, rn = nblk % 8;
     const int xcd = bid % 8, slot = bid / 8;
     const int logical = xcd * qn + min(xcd, rn) + slot;
-    const int col = logical / a.ntiles_y;
-    const int tile = logical - col * a.ntiles_y;
+    int col, tile;
+    if (a.slab_major) {
+        // all orbitals of one slab back to back: the slab's projector
+        // entries stay resident in the XCD's L2
+        tile = logical / a.ncol;
+        col = logical - tile * a.ncol;
+    } else {
+        col = logical / a.ntiles_y;
+        tile = logical - col * a.ntiles_y;
+    }
     const int y0 = tile * a.ty;
     const int tyn = min(a.ty, ny - y0);
 
     const int t = threadIdx.x;
     const int nt = blockDim.x;
     const int lx = t % nx, ly = t / nx;
-    const bool active = ly < tyn;
-    const long plane = (long)nx * ny;
-    const T* __restrict__ xc = a.x + (long)col * a.ldx;
-    T* oc = a.out + (long)col * a.ldx;
-    const T* pc = a.xprev ? a.xprev + (long)col * a.ldx : nullptr;
-    const long pxy = lx + (long)nx * (y0 + (active ? ly : 0));
 
-    double alpha_d, c_d, beta_d;
-    filter_coefs(a.params, a.mode, a.step, alpha_d, c_d, beta_d);
-    const T alpha = (T)alpha_d, cshift = (T)c_d, beta = (T)beta_d;
-
-    T q[2 * NO + 1];
-#pragma unroll
-    for (int j = 0; j <= 2 * NO; ++j) {
-        int zz = j - NO;
-        zz = zz < 0 ? zz + nz : zz;
-        q[j] = active ? xc[pxy + (long)zz * plane] : (T)0;
-    }
-
-    const int nhalo = 2 * NO * nx;
-    for (int z = 0; z < nz; ++z) {
-        T* buf = (z & 1) ? buf1 : buf0;
-        if (active) {
-            T* row = buf + (ly + NO) * W + NO;
-            row[lx] = q[NO];
-            if (lx < NO) row[lx + nx] = q[NO];
-            if (lx >= nx - NO) row[lx - nx] = q[NO];
+    SweepGeom<T> g;
+    g.active = ly < tyn;
+    g.plane = (long)nx * ny;
+    g.nz = nz;
+    g.col = col;
+    g.W = W;
+    g.nx = nx;
+    g.lx = lx;
+    g.gy = y0 + (g.active ? ly : 0);
+    g.ly = ly;
+    g.t = t;
+    g.nt = nt;
+    g.y0 = y0;
+    g.tyn = tyn;
+    if (NL) {
+        // LDS after the two plane buffers: candidate SoA (7 T + 1 int per
+        // candidate), ex, ey, ez (2 planes), A/B (2 planes)
+        const int KM = a.kmax;
+        T* tp = buf1 + R * W;
+        g.cx = tp;
+        g.cy = tp + KM;
+        g.cz = tp + 2 * KM;
+        g.ds = tp + 3 * KM;
+        g.dpx = tp + 4 * KM;
+        g.dpy = tp + 5 * KM;
+        g.dpz = tp + 6 * KM;
+        g.ex = tp + 7 * KM;
+        g.ey = g.ex + KM * a.xw;
+        g.ez = g.ey + a.ty * KM;
+        g.ab = g.ez + 2 * KM;
+        g.cxb = reinterpret_cast<int*>(g.ab + 4 * a.ty * KM);
+        g.xw = a.xw;
+        g.K = a.slab_k[tile];
+        const CandInfo* ci = a.slab_cand + (long)tile * KM;
+        const T* Dc = a.D + (long)col * a.ldD;
+        for (int k = t; k < g.K; k += nt) {
+            const CandInfo c = ci[k];
+            g.cx[k] = (T)(a.atom_pos[3 * c.atom] - (double)c.sx * (double)nx * (double)a.hx);
+            g.cy[k] = (T)(a.atom_pos[3 * c.atom + 1] - (double)c.sy * (double)ny * (double)a.hy);
+            g.cz[k] = (T)(a.atom_pos[3 * c.atom + 2] - (double)c.sz * (double)nz * (double)a.hz);
+            g.ds[k] = Dc[4 * c.atom];
+            g.dpx[k] = Dc[4 * c.atom + 1];
+            g.dpy[k] = Dc[4 * c.atom + 2];
+            g.dpz[k] = Dc[4 * c.atom + 3];
+            g.cxb[k] = c.ixlo - c.sx * nx;
         }
-        const T* zp = xc + (long)z * plane;
-        for (int e = t; e < nhalo; e += nt) {
+        __syncthreads();
+        for (int j = t; j < g.K * g.xw; j += nt) {
+            const int k = j / g.xw, i = j - k * g.xw;
+            const T dx = (T)(ci[k].ixlo + i) * a.hx - (T)a.atom_pos[3 * ci[k].atom];
+            g.ex[j] = exp(-dx * dx * a.inv_rc2);
+        }
+        for (int j = t; j < tyn * g.K; j += nt) {
+            const int row = j / g.K, k = j - row * g.K;
+            const T dy = (T)(y0 + row) * a.hy - g.cy[k];
+            g.ey[j] = exp(-dy * dy * a.inv_rc2);
+        }
+        sweep_ez<T>(a, g, 0, 0);
+        sweep_ez<T>(a, g, nz > 1 ? 1 : 0, 1);
+        __syncthreads();
+        sweep_ab<T>(a, g, 0, 0, g.ab);
+    }
+    const T* xc = a.x + (long)col * a.ldx;
+    g.xc = xc;
+    g.oc = a.out + (long)col * a.ldx;
+    g.pc = a.xprev ? a.xprev + (long)col * a.ldx : nullptr;
+    g.pxy = lx + (long)nx * (y0 + (g.active ? ly : 0));
+    g.lrow = (ly + NO) * W + NO + lx;
+    // halo rows: 2 NO rows of nx values per plane, spread over the threads
+    const int nhalo = 2 * NO * nx;
+    g.hn = 0;
+#pragma unroll
+    for (int i = 0; i < HM; ++i) {
+        const int e = t + i * nt;
+        g.goff[i] = 0;
+        g.loff[i] = 0;
+        g.poff[i] = -1;
+        if (e < nhalo) {
+            g.hn = i + 1;
             int hr = e / nx, hx = e - hr * nx;
             int lrow, gy;
             if (hr < NO) {
@@ -133,50 +357,49 @@ __global__ __launch_bounds__(1024) void k_hsweep(SweepArgs<T> a) {
                 gy = y0 + tyn + (hr - NO);
             }
             gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-            T v = zp[hx + (long)nx * gy];
-            T* row = buf + lrow * W + NO;
-            row[hx] = v;
-            if (hx < NO) row[hx + nx] = v;
-            if (hx >= nx - NO) row[hx - nx] = v;
-        }
-        __syncthreads();
-        if (active) {
-            const T* rp = buf + (ly + NO) * W + NO + lx;
-            T lap = a.cf.c0 * q[NO];
-#pragma unroll
-            for (int k = 1; k <= NO; ++k) {
-                lap += a.cf.cx[k] * (rp[k] + rp[-k]);
-                lap += a.cf.cy[k] * (rp[k * W] + rp[-k * W]);
-                lap += a.cf.cz[k] * (q[NO + k] + q[NO - k]);
-            }
-            const long p = pxy + (long)z * plane;
-            T hv = lap + a.veff[p] * q[NO];
-            if (NL) {
-                const int e0 = a.pt_off[p], e1 = a.pt_off[p + 1];
-                const T* Dc = a.D + (long)col * a.ldD;
-                for (int e = e0; e < e1; ++e) {
-                    const int at = 4 * a.pt_atom[e];
-                    const T* ch = a.pt_chi + 4 * (long)e;
-                    hv += ch[0] * Dc[at] + ch[1] * Dc[at + 1] + ch[2] * Dc[at + 2] + ch[3] * Dc[at + 3];
-                }
-            }
-            T o;
-            if (a.mode == 0) {
-                o = hv;
-            } else {
-                o = alpha * (hv - cshift * q[NO]);
-                if (a.mode == 2) o += beta * pc[p];
-            }
-            oc[p] = o;
-        }
-#pragma unroll
-        for (int j = 0; j < 2 * NO; ++j) q[j] = q[j + 1];
-        if (active) {
-            int zn = z + NO + 1;
-            zn = zn >= nz ? zn - nz : zn;
-            q[2 * NO] = xc[pxy + (long)zn * plane];
+            g.goff[i] = hx + nx * gy;
+            g.loff[i] = lrow * W + NO + hx;
+            if (hx < NO) g.poff[i] = g.loff[i] + nx;
+            if (hx >= nx - NO) g.poff[i] = g.loff[i] - nx;
         }
     }
+
+    double alpha_d, c_d, beta_d;
+    filter_coefs(a.params, MODE, a.step, alpha_d, c_d, beta_d);
+    const T alpha = (T)alpha_d, cshift = (T)c_d, beta = (T)beta_d;
+
+    SweepRegs<T, HM> r;
+    // ring: planes -NO .. NO+1 (slot = plane mod RING), plane 0 prefetches
+#pragma unroll
+    for (int j = -NO; j <= NO + 1; ++j) {
+        int zz = j < 0 ? j + nz : j;
+        r.q[(j + RING) % RING] = xc[g.pxy + (long)zz * g.plane];
+    }
+    r.xp[0] = (MODE == 2) ? ((const T*)g.pc)[g.pxy] : (T)0;
+    r.ve[0] = a.veff[g.pxy];
+    // plane 0 into LDS buffer 0
+    if (g.active) {
+        buf0[g.lrow] = r.q[0];
+        if (lx < NO) buf0[g.lrow + nx] = r.q[0];
+        if (lx >= nx - NO) buf0[g.lrow - nx] = r.q[0];
+    }
+#pragma unroll
+    for (int i = 0; i < HM; ++i)
+        if (i < g.hn) {
+            T v = xc[g.goff[i]];
+            buf0[g.loff[i]] = v;
+            if (g.poff[i] >= 0) buf0[g.poff[i]] = v;
+        }
+    if (NL) r.pe8[0] = a.pe8[g.pxy];
+
+#define SG_STEP(U)                                                                     \
+    if (z0 + U >= nz) break;                                                           \
+    sweep_step<U, T, NL, MODE, HM>(a, r, g, buf0, buf1, z0 + U, alpha, cshift, beta);
+    for (int z0 = 0; z0 < nz; z0 += RING) {
+        SG_STEP(0) SG_STEP(1) SG_STEP(2) SG_STEP(3) SG_STEP(4) SG_STEP(5) SG_STEP(6)
+        SG_STEP(7) SG_STEP(8) SG_STEP(9) SG_STEP(10) SG_STEP(11) SG_STEP(12) SG_STEP(13)
+    }
+#undef SG_STEP
 }
 
 // D(4a+lm, j) = gamma_lm * dV * sum_{s in support(a)} chi_lm(s) X(idx(s), j),
@@ -185,9 +408,19 @@ template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, long ldx, int ncol,
                                                     const long* __restrict__ sup_off, const int* __restrict__ sup_idx,
                                                     const double* __restrict__ chi, const double* __restrict__ g4,
-                                                    double dV, T* __restrict__ D, int ldD) {
-    const int a = blockIdx.x;
-    const int n0 = blockIdx.y * NB;
+                                                    double dV, T* __restrict__ D, int ldD,
+                                                    const int* __restrict__ atom_order, int n_atoms) {
+    // Block b runs on XCD b % 8.  Atoms are visited in a space-filling order
+    // and each XCD takes a contiguous range of it for one orbital chunk at a
+    // time, so overlapping supports of neighbouring atoms hit in that XCD's L2.
+    const int bid = blockIdx.x;
+    const int xcd = bid % 8, slot = bid / 8;
+    const int per = (n_atoms + 7) / 8;
+    const int rank = xcd * per + slot % per;
+    const int chunk = slot / per;
+    if (rank >= n_atoms || chunk * NB >= ncol) return;
+    const int a = atom_order[rank];
+    const int n0 = chunk * NB;
     const int nb = min(NB, ncol - n0);
     double acc[NB][4];
 #pragma unroll
@@ -230,8 +463,13 @@ __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, lon
     }
 }
 
-static int choose_ty(int nx, int ny) {
-    int maxty = std::max(1, std::min(16, 1024 / nx));
+int choose_sweep_ty(int nx, int ny, int max_threads) {
+    // tuning override: rows per y-slab
+    if (const char* e = std::getenv("SPARC_GPU_SWEEP_TY")) {
+        int v = std::atoi(e);
+        if (v >= 2 && v <= ny && ((v * nx + 63) / 64) * 64 <= max_threads) return v;
+    }
+    int maxty = std::max(1, std::min(16, max_threads / nx));
     maxty = std::min(maxty, ny);
     // prefer the largest divisor of ny not above maxty, unless it is small
     int best = 1;
@@ -278,17 +516,6 @@ float* D_of<float>(sparc_gpu_ctx c) {
 }
 
 template <typename T>
-static const T* ptchi_of(sparc_gpu_ctx c);
-template <>
-const double* ptchi_of<double>(sparc_gpu_ctx c) {
-    return c->nl.pt_chi;
-}
-template <>
-const float* ptchi_of<float>(sparc_gpu_ctx c) {
-    return c->nl.pt_chi32;
-}
-
-template <typename T>
 sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, int ncol, long ldx, int mode,
                            int step) {
     SweepArgs<T> a;
@@ -299,28 +526,73 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     a.nx = c->nx;
     a.ny = c->ny;
     a.nz = c->nz;
-    a.ty = choose_ty(c->nx, c->ny);
+    a.ty = choose_sweep_ty(c->nx, c->ny, 1024);
     a.ntiles_y = div_up(c->ny, a.ty);
     a.cf = coef<T>(c);
     a.veff = veff_of<T>(c);
-    const bool nl = c->nl_lmax >= 1 && c->nl.n_sup > 0;
-    a.pt_off = c->nl.pt_off;
-    a.pt_atom = c->nl.pt_atom;
-    a.pt_chi = ptchi_of<T>(c);
+    const bool nl = c->nl_lmax >= 1 && c->nl.n_pe > 0;
+    if (nl) {
+        a.ty = c->nl_ty;
+        a.ntiles_y = div_up(c->ny, a.ty);
+    }
+    a.pe8 = c->nl.pe8;
+    a.slab_cand = c->nl.slab_cand;
+    a.slab_k = c->nl.slab_k;
+    a.kmax = c->nl.slab_kmax;
+    a.xw = c->nl.slab_xw;
+    a.atom_pos = c->atom_pos;
+    {
+        const double pi = 3.14159265358979323846;
+        const double rc = c->rc_nl > 0 ? c->rc_nl : 1.0;
+        const double N0 = std::pow(2.0 / (pi * rc * rc), 0.75);
+        a.inv_rc2 = (T)(1.0 / (rc * rc));
+        a.N0 = (T)N0;
+        a.N1 = (T)((2.0 / rc) * N0);
+        a.hx = (T)c->hx;
+        a.hy = (T)c->hy;
+        a.hz = (T)c->hz;
+    }
     a.D = D_of<T>(c);
     a.ldD = 4 * c->n_atoms;
     a.params = c->scal + S_A;
     a.mode = mode;
     a.step = step;
+    a.ncol = ncol;
+    a.slab_major = c->sweep_slab_major;
     const int threads = div_up((long)c->nx * a.ty, 64) * 64;
-    const size_t shmem = 2 * (size_t)(a.ty + 2 * kMaxHalfOrder) * (c->nx + 2 * kMaxHalfOrder) * sizeof(T);
+    size_t shmem = 2 * (size_t)(a.ty + 2 * kMaxHalfOrder) * (c->nx + 2 * kMaxHalfOrder) * sizeof(T);
+    if (nl) {
+        const size_t KM = a.kmax;
+        shmem += (7 * KM + KM * a.xw + a.ty * KM + 2 * KM + 4 * a.ty * KM) * sizeof(T) + KM * sizeof(int);
+    }
+    if (shmem > 160 * 1024) return set_err(c, SPARC_ERR_ARG, "sweep workgroup needs more than 160 KB of LDS");
+    if (threads > (nl ? 512 : 1024)) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
     const long nblocks = (long)ncol * a.ntiles_y;
     if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "too many blocks");
-    if (nl)
-        k_hsweep<T, true><<<(int)nblocks, threads, shmem, c->stream>>>(a);
-    else
-        k_hsweep<T, false><<<(int)nblocks, threads, shmem, c->stream>>>(a);
+    const int hm = div_up(2L * kMaxHalfOrder * c->nx, threads);
+    if (hm > 3) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
+    const int slot = prof_begin(c, mode == 2 ? PK_SWEEP : (mode == 1 ? PK_SWEEP1 : PK_APPLY));
+    const dim3 g((unsigned)nblocks), b(threads);
+#define SG_LAUNCH_SWEEP(NLV, MV, HMV) k_hsweep<T, NLV, MV, HMV><<<g, b, shmem, c->stream>>>(a)
+#define SG_SWEEP_HM(NLV, MV)          \
+    do {                              \
+        if (hm == 1) SG_LAUNCH_SWEEP(NLV, MV, 1); \
+        else if (hm == 2) SG_LAUNCH_SWEEP(NLV, MV, 2); \
+        else SG_LAUNCH_SWEEP(NLV, MV, 3); \
+    } while (0)
+    if (nl) {
+        if (mode == 0) SG_SWEEP_HM(true, 0);
+        else if (mode == 1) SG_SWEEP_HM(true, 1);
+        else SG_SWEEP_HM(true, 2);
+    } else {
+        if (mode == 0) SG_SWEEP_HM(false, 0);
+        else if (mode == 1) SG_SWEEP_HM(false, 1);
+        else SG_SWEEP_HM(false, 2);
+    }
+#undef SG_SWEEP_HM
+#undef SG_LAUNCH_SWEEP
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 
@@ -328,10 +600,15 @@ template <typename T>
 sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) {
     if (c->nl_lmax < 1 || c->nl.n_sup == 0) return SPARC_OK;
     constexpr int NB = 8;
-    dim3 grid(c->n_atoms, div_up(ncol, NB));
+    const int per = (c->n_atoms + 7) / 8;
+    const int nchunks = div_up(ncol, NB);
+    dim3 grid(8 * per * nchunks);
+    const int slot = prof_begin(c, PK_PROJ);
     k_projection<T, NB><<<grid, 256, 0, c->stream>>>(x, ldx, ncol, c->nl.sup_off, c->nl.sup_idx, c->nl.sup_chi,
-                                                   c->nl.gamma4, c->dV, D_of<T>(c), 4 * c->n_atoms);
+                                                   c->nl.gamma4, c->dV, D_of<T>(c), 4 * c->n_atoms,
+                                                   c->nl.atom_order, c->n_atoms);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 
