@@ -124,7 +124,7 @@ def main():
         torch.cuda.synchronize()
         if profile:
             ctx.profile(True)
-            for k in range(8):
+            for k in range(16):
                 ctx.profile_read(k)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         reps = []
@@ -138,7 +138,9 @@ def main():
         prof = {}
         if profile:
             for k, name in [(0, "sweep"), (1, "projection"), (2, "gemm_tn"), (3, "gemm_nn"), (4, "density"),
-                            (5, "sweep1"), (6, "apply")]:
+                            (5, "sweep1"), (6, "apply"), (7, "cholesky"), (8, "tri_inverse"), (9, "eigensolver"),
+                            (10, "small_gemm"), (11, "copy"), (12, "eig_tridiag"), (13, "eig_bisect"),
+                            (14, "eig_invit"), (15, "eig_back")]:
                 ms, n = ctx.profile_read(k)
                 prof[name] = (ms, n)
             ctx.profile(False)

@@ -83,7 +83,7 @@ typedef struct {
     const double* gamma;    /* [2*n_atoms] projector energies (Ha); NULL if nl_lmax = -1 */
     double rc_nl;           /* projector Gaussian width (Bohr)               */
     double rcut_nl;         /* projector support radius (Bohr)               */
-    int n_states;           /* N_s: columns of the orbital block             */
+    int n_states;           /* N_s: columns of the orbital block, <= 4096    */
     double n_electrons;     /* N_e, 0 < N_e < 2*N_s                          */
     double kT;              /* Fermi-Dirac smearing (Ha), > 0                */
     double rho_floor;       /* density floor inside the LDA (e.g. 1e-14)     */
@@ -137,6 +137,14 @@ sparc_status sparc_gpu_chebyshev_filter(sparc_gpu_ctx ctx, sparc_prec prec, void
  * is left unchanged.  Uses context-owned workspace (one block). */
 sparc_status sparc_gpu_rayleigh_ritz(sparc_gpu_ctx ctx, sparc_prec prec, void* d_X, int ncol, long ldx,
                                      double* d_eig);
+
+/* Dense symmetric eigensolver used inside Rayleigh-Ritz (FP64): on the n x n
+ * column-major matrix d_A (destroyed; only the lower triangle is read)
+ * returns ascending eigenvalues d_eig (n) and orthonormal eigenvectors as
+ * the columns of d_V (n x n).  Householder tridiagonalisation, bisection and
+ * inverse iteration (or parallel Jacobi when SPARC_GPU_EIG=jacobi is set at
+ * context creation).  1 <= n <= 4096.  Synchronises the stream. */
+sparc_status sparc_gpu_subspace_eigh(sparc_gpu_ctx ctx, double* d_A, int n, double* d_V, double* d_eig);
 
 /* Electron density, Sec. 2 eq. (2): rho(p) = sum_j occ[j] X(p, j)^2,
  * accumulated in FP64.  d_occ: ncol doubles; d_rho: N_d doubles. */
@@ -223,7 +231,9 @@ sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st,
  * and launch count since the last read for one kernel, and resets it.
  * Kernel ids: 0 filter sweep of degree >= 2, 1 nonlocal projection,
  * 2 Gram/projected-H GEMM, 3 rotation GEMM, 4 density, 5 first filter
- * sweep, 6 plain H application. */
+ * sweep, 6 plain H application, 7 Cholesky, 8 triangular inverse,
+ * 9 subspace eigensolver (all its launches, host waits included),
+ * 10 small N_s x N_s products, 11 block copy-back; ids < 16. */
 sparc_status sparc_gpu_profile(sparc_gpu_ctx ctx, int enable);
 sparc_status sparc_gpu_profile_read(sparc_gpu_ctx ctx, int kernel_id, double* total_ms, long* launches);
 

@@ -38,6 +38,7 @@ EXPORTED = [
     "sparc_gpu_apply_H",
     "sparc_gpu_chebyshev_filter",
     "sparc_gpu_rayleigh_ritz",
+    "sparc_gpu_subspace_eigh",
     "sparc_gpu_density",
     "sparc_gpu_occupations",
     "sparc_gpu_potential",
@@ -145,6 +146,7 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_apply_H": ([vp, i, vp, vp, i, l], i),
         "sparc_gpu_chebyshev_filter": ([vp, i, vp, vp, i, l, i, d, d, d], i),
         "sparc_gpu_rayleigh_ritz": ([vp, i, vp, i, l, vp], i),
+        "sparc_gpu_subspace_eigh": ([vp, vp, i, vp, vp], i),
         "sparc_gpu_density": ([vp, i, vp, i, l, vp, vp], i),
         "sparc_gpu_occupations": ([vp, vp, i, vp, vp], i),
         "sparc_gpu_potential": ([vp, vp, vp, vp, vp, vp], i),
@@ -262,6 +264,11 @@ class Context:
     def rayleigh_ritz(self, X, eig):
         ncol, ld = _block(X)
         self._check(self.lib.sparc_gpu_rayleigh_ritz(self.h, _prec_of(X), _ptr(X), ncol, ld, _ptr(eig)))
+
+    def subspace_eigh(self, A, V, eig):
+        """A: (n, n) float64 device tensor (destroyed; symmetric)."""
+        n = A.shape[0]
+        self._check(self.lib.sparc_gpu_subspace_eigh(self.h, _ptr(A), int(n), _ptr(V), _ptr(eig)))
 
     def density(self, X, occ, rho):
         ncol, ld = _block(X)

@@ -612,7 +612,25 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             if ((st = upload(c, &T.pe_off, c->pe_off_host)) != SPARC_OK) return st;
             if ((st = upload(c, &T.pe_ent, ent)) != SPARC_OK) return st;
             T.n_pe = (long)ent.size();
-            if ((st = build_slab_tables(c, ent)) != SPARC_OK) return st;
+            // slab height: the largest (up to the 512-thread workgroup) whose
+            // FP64 sweep tables fit in LDS
+            for (int ty = c->nl_ty;; --ty) {
+                c->nl_ty = ty;
+                st = build_slab_tables(c, ent);
+                const size_t KM = c->nl.slab_kmax;
+                const size_t lds = (2 * (size_t)(ty + 2 * kMaxHalfOrder) * (c->nx + 2 * kMaxHalfOrder) + 7 * KM +
+                                    KM * c->nl.slab_xw + ty * KM + KM * c->nl.slab_zw + 4 * ty * KM) *
+                                       sizeof(double) +
+                                   2 * KM * sizeof(int);
+                if (st == SPARC_OK && lds <= 160 * 1024) break;
+                if (ty <= 2) return st != SPARC_OK ? st : set_err(c, SPARC_ERR_ARG, "projector tables exceed LDS");
+                for (void* p : {(void*)T.pe8, (void*)T.slab_cand, (void*)T.slab_k})
+                    if (p) hipFree(p);
+                T.pe8 = nullptr;
+                T.slab_cand = nullptr;
+                T.slab_k = nullptr;
+                c->err.clear();
+            }
         }
         // point-major inverse lists (entries per point in atom order)
         std::vector<int> pt_off(c->nd + 1, 0), pt_atom(T.n_sup), pt_src(T.n_sup);
@@ -757,7 +775,7 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     if (s->n_atoms < 0 || (s->n_atoms > 0 && (!s->pos || !s->Z || !s->rc_loc))) return SPARC_ERR_ARG;
     if (s->nl_lmax != -1 && s->nl_lmax != 1) return SPARC_ERR_ARG;
     if (s->nl_lmax == 1 && (!s->gamma || !(s->rc_nl > 0) || !(s->rcut_nl > 0))) return SPARC_ERR_ARG;
-    if (s->n_states < 1) return SPARC_ERR_ARG;
+    if (s->n_states < 1 || s->n_states > kEighMaxN) return SPARC_ERR_ARG;
     if (!(s->n_electrons > 0.0) || s->n_electrons > 2.0 * s->n_states) return SPARC_ERR_ARG;
     if (!(s->kT > 0.0)) return SPARC_ERR_ARG;
     if (!(s->sad_width > 0.0)) return SPARC_ERR_ARG;
@@ -798,6 +816,8 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     for (int i = 0; i < 8; ++i) c->ev[i] = nullptr;
     if (const char* e = std::getenv("SPARC_GPU_SWEEP_SLAB_MAJOR")) c->sweep_slab_major = std::atoi(e) != 0;
     c->nl_ty = choose_sweep_ty(c->nx, c->ny, 512);
+    if (const char* e = std::getenv("SPARC_GPU_DEBUG")) c->debug = std::atoi(e);
+    if (const char* e = std::getenv("SPARC_GPU_EIG")) c->eig_jacobi = std::string(e) == "jacobi";
 
     int dev = 0;
     sparc_status st = SPARC_OK;
@@ -830,6 +850,8 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
     for (int i = 0; i < 8; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
     for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
+    if (c->jac_exec) hipGraphExecDestroy(c->jac_exec);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
     return SPARC_OK;
 }

@@ -6,6 +6,7 @@
 // All matrices are N x N, column-major, leading dimension N, in device memory.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 
 #include "internal.hpp"
 
@@ -58,8 +59,10 @@ __global__ __launch_bounds__(1024) void k_cholesky(double* M, int N, int* flag) 
 }
 
 sparc_status dense_cholesky(sparc_gpu_ctx c, double* M, int N, int* flag) {
+    const int slot = prof_begin(c, PK_CHOL);
     k_cholesky<<<1, 1024, N * sizeof(double), c->stream>>>(M, N, flag);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 
@@ -94,10 +97,12 @@ __global__ __launch_bounds__(64) void k_tri_inv_col(const double* __restrict__ L
 sparc_status dense_tri_inverse_lower(sparc_gpu_ctx c, const double* L, double* Linv, int N) {
     // Linv doubles as scratch for L^T first
     double* Lt = c->small + 8 * (size_t)N * N;
+    const int slot = prof_begin(c, PK_TRINV);
     k_transpose<<<div_up((long)N * N, 256), 256, 0, c->stream>>>(L, Lt, N);
     SG_CHECK_LAUNCH(c);
     k_tri_inv_col<<<N, 64, N * sizeof(double), c->stream>>>(Lt, Linv, N);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 
@@ -129,8 +134,10 @@ __global__ __launch_bounds__(256) void k_small_gemm(int N, const double* __restr
 
 sparc_status dense_gemm(sparc_gpu_ctx c, char ta, char tb, int N, const double* A, const double* B, double* C) {
     dim3 grid(div_up(N, 16), div_up(N, 16));
+    const int slot = prof_begin(c, PK_SMALL);
     k_small_gemm<<<grid, 256, 0, c->stream>>>(N, A, ta == 'T', B, tb == 'T', C);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 
@@ -267,6 +274,51 @@ __global__ void k_sort_eig(const double* A, const double* V, int N, double* eig,
     for (int k = 0; k < N; ++k) Vs[k + (long)rank * N] = V[k + (long)i * N];
 }
 
+__global__ void k_copy2(const double* __restrict__ a2, double* __restrict__ a, const double* __restrict__ v2,
+                        double* __restrict__ v, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        a[i] = a2[i];
+        v[i] = v2[i];
+    }
+}
+
+// One Jacobi sweep (P-1 rounds ping-ponging between (A, V) and (A2, V2),
+// ending in (A, V)) as a HIP graph, captured once per matrix size and
+// buffer set on a private stream and replayed on the context's stream; the
+// sweep is hundreds of tiny launches, so this removes their launch cost.
+static sparc_status jacobi_sweep(sparc_gpu_ctx c, double* A, double* A2, double* V, double* V2, int N, int P) {
+    if (!c->jac_exec || c->jac_N != N || c->jac_A != A || c->jac_A2 != A2 || c->jac_V != V || c->jac_V2 != V2) {
+        if (c->jac_exec) {
+            hipGraphExecDestroy(c->jac_exec);
+            c->jac_exec = nullptr;
+        }
+        if (!c->cap_stream) SG_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        SG_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        dim3 grid(div_up(N, 16), div_up(N, 16));
+        double *Ac = A, *An = A2, *Vc = V, *Vn = V2;
+        for (int r = 0; r < P - 1; ++r) {
+            k_jacobi_round<<<grid, 256, 0, c->cap_stream>>>(Ac, An, Vc, Vn, N, P, r);
+            std::swap(Ac, An);
+            std::swap(Vc, Vn);
+        }
+        if (Ac != A) k_copy2<<<div_up((long)N * N, 256), 256, 0, c->cap_stream>>>(A2, A, V2, V, (long)N * N);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+        if (e != hipSuccess) return hip_err(c, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&c->jac_exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_err(c, e, "hipGraphInstantiate");
+        c->jac_N = N;
+        c->jac_A = A;
+        c->jac_A2 = A2;
+        c->jac_V = V;
+        c->jac_V2 = V2;
+    }
+    SG_HIP(c, hipGraphLaunch(c->jac_exec, c->stream));
+    return SPARC_OK;
+}
+
 // A (destroyed), V: N x N; eig: N; work: 2 N^2 doubles.
 sparc_status dense_eigh(sparc_gpu_ctx c, double* A, int N, double* V, double* eig, double* work) {
     const int P = N + (N & 1);
@@ -294,6 +346,7 @@ sparc_status dense_eigh(sparc_gpu_ctx c, double* A, int N, double* V, double* ei
         SG_HIP(c, hipMemcpyAsync(h, d_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         SG_HIP(c, hipStreamSynchronize(c->stream));
         if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return set_err(c, SPARC_ERR_NONFINITE, "eigh: non-finite");
+        if (c->debug) fprintf(stderr, "[sparc_gpu] eigh N=%d sweep %d off^2/norm^2 %.3e\n", N, sweep, h[0] / h[1]);
         if (h[0] <= tol * h[1] || h[1] == 0.0) {
             converged = true;
             break;
@@ -304,12 +357,8 @@ sparc_status dense_eigh(sparc_gpu_ctx c, double* A, int N, double* V, double* ei
             break;
         }
         prev_off = h[0];
-        for (int r = 0; r < P - 1; ++r) {
-            k_jacobi_round<<<grid, 256, 0, c->stream>>>(Acur, Anext, Vcur, Vnext, N, P, r);
-            SG_CHECK_LAUNCH(c);
-            std::swap(Acur, Anext);
-            std::swap(Vcur, Vnext);
-        }
+        sparc_status st = jacobi_sweep(c, Acur, Anext, Vcur, Vnext, N, P);
+        if (st != SPARC_OK) return st;
     }
     if (!converged) return set_err(c, SPARC_ERR_EIG, "Jacobi eigensolver did not converge");
     // sorted result into eig and V (V may currently live in work)
@@ -337,7 +386,7 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* 
     sparc_status st;
     const size_t blk = ((size_t)(N - 1) * ldx + c->nd) * sizeof(T);
     if ((st = ensure_work(c, blk)) != SPARC_OK) return st;
-    if ((st = ensure_small(c, 12 * (size_t)N * N + 16)) != SPARC_OK) return st;
+    if ((st = ensure_small(c, 9 * (size_t)N * N + eigh_work_doubles(N))) != SPARC_OK) return st;
     T* W = (T*)c->work;
     const size_t NN = (size_t)N * N;
     double* M = c->small;           // Gram, then L
@@ -347,7 +396,7 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* 
     double* Hs = M + 4 * NN;
     double* Vq = M + 5 * NN;
     double* Rot = M + 6 * NN;
-    double* ework = M + 9 * NN;     // 2 NN (eigh), Lt lives at 8 NN
+    double* ework = M + 9 * NN;     // eigensolver workspace; Lt lives at 8 NN
     SG_HIP(c, hipMemsetAsync(c->flags + F_NOT_SPD, 0, sizeof(int), c->stream));
     if ((st = gemm_tn<T>(c, N, N, c->nd, X, ldx, X, ldx, c->dV, M, N, true)) != SPARC_OK) return st;
     if ((st = dense_cholesky(c, M, N, c->flags + F_NOT_SPD)) != SPARC_OK) return st;
@@ -365,12 +414,19 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* 
     if ((st = dense_gemm(c, 'N', 'N', N, Linv, K, T1)) != SPARC_OK) return st;
     if ((st = dense_gemm(c, 'N', 'T', N, T1, Linv, Hs)) != SPARC_OK) return st;
     if ((st = dense_symmetrize(c, Hs, N)) != SPARC_OK) return st;
-    if ((st = dense_eigh(c, Hs, N, Vq, d_eig, ework)) != SPARC_OK) return st;
+    {
+        const int slot = prof_begin(c, PK_EIG);
+        st = c->eig_jacobi ? dense_eigh(c, Hs, N, Vq, d_eig, ework) : dense_eigh_tridiag(c, Hs, N, Vq, d_eig, ework);
+        prof_end(c, slot);
+        if (st != SPARC_OK) return st;
+    }
     if ((st = dense_gemm(c, 'T', 'N', N, Linv, Vq, Rot)) != SPARC_OK) return st;
     if ((st = gemm_nn<T>(c, c->nd, N, N, X, ldx, Rot, N, W, ldx)) != SPARC_OK) return st;
     dim3 grid(div_up(c->nd, 256), N);
+    const int slot = prof_begin(c, PK_COPY);
     k_copy_cols<T><<<grid, 256, 0, c->stream>>>(W, X, c->nd, N, ldx);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 
@@ -380,6 +436,20 @@ template sparc_status rayleigh_ritz_impl<float>(sparc_gpu_ctx, float*, int, long
 }  // namespace sg
 
 using namespace sg;
+
+extern "C" sparc_status sparc_gpu_subspace_eigh(sparc_gpu_ctx c, double* d_A, int n, double* d_V, double* d_eig) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_A || !d_V || !d_eig) return set_err(c, SPARC_ERR_ARG, "subspace_eigh: null pointer");
+    if (n < 1 || n > kEighMaxN) return set_err(c, SPARC_ERR_ARG, "subspace_eigh: n out of range");
+    sparc_status st = ensure_small(c, eigh_work_doubles(n));
+    if (st != SPARC_OK) return st;
+    double* work = c->small;
+    st = c->eig_jacobi ? dense_eigh(c, d_A, n, d_V, d_eig, work) : dense_eigh_tridiag(c, d_A, n, d_V, d_eig, work);
+    if (st != SPARC_OK) return st;
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    return SPARC_OK;
+}
 
 extern "C" sparc_status sparc_gpu_rayleigh_ritz(sparc_gpu_ctx c, sparc_prec prec, void* d_X, int ncol, long ldx,
                                                 double* d_eig) {

@@ -1,0 +1,457 @@
+// Dense symmetric eigensolver of the Rayleigh-Ritz step (FP64): Householder
+// reduction to tridiagonal form, eigenvalues by Sturm-sequence bisection,
+// eigenvectors by inverse iteration (re-orthogonalised inside clusters of
+// close eigenvalues), and back-transformation by the Householder
+// reflectors.  These are the textbook steps of a tridiagonal-based symmetric
+// eigensolver; the Ns x Ns problem is the part of CheFSI whose cubic cost the
+// paper names as its scaling limit (Sec. 4).
+//
+// All matrices are N x N column-major with leading dimension N.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace sg {
+
+constexpr double kEps = 2.220446049250313e-16;
+
+__device__ inline double block_sum(double v, double* red) {
+    // blockDim.x is a multiple of 64 and <= 1024
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];  // fixed order
+    return s;
+}
+
+// Householder tridiagonalisation (lower), one workgroup, of A - sigma I with
+// sigma = trace(A)/N (the shift keeps ||T|| at the spread of the spectrum,
+// which is what the cluster test of the inverse iteration measures against).
+// On exit d, e hold the tridiagonal matrix, column i of A below the
+// subdiagonal holds the reflector v_i (v_i[i+1] = 1 implicit), tau[i] its
+// factor, and shift[0] = sigma:
+//   H_i = I - tau_i v v^T,  Q = H_0 H_1 ... H_{N-3},  Q^T (A - sigma I) Q = T.
+// Each step reads and writes the trailing matrix once: the rank-2 update of
+// step i is fused with the product A v_{i+1} of step i+1 (the next reflector
+// comes from the updated column i+1, which is updated first).
+struct TrdLayout {
+    int rows, R, G, TPG;
+};
+
+__device__ inline TrdLayout trd_layout(int rows, int nt) {
+    TrdLayout L;
+    L.rows = rows;
+    L.R = ((rows + 63) / 64) * 64;
+    L.G = max(1, min(16, nt / max(L.R, 64)));
+    L.TPG = ((nt / L.G) / 64) * 64;
+    return L;
+}
+
+// Householder vector of x = A[j+1 .., j] (length N-j-1) into vn (indexed by
+// global row), returns tau, writes beta to *beta_out.  All threads call it.
+__device__ inline double trd_householder(double* A, int N, int j, double* vn, double* red, double* beta_out) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    const double* x = A + (long)j * N;
+    double s = 0.0;
+    for (int r = j + 2 + t; r < N; r += nt) s += x[r] * x[r];
+    const double xnorm2 = block_sum(s, red);
+    const double alpha = x[j + 1];
+    double tau = 0.0, beta = alpha;
+    if (xnorm2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        tau = (beta - alpha) / beta;
+    }
+    const double scal = (xnorm2 > 0.0) ? 1.0 / (alpha - beta) : 0.0;
+    for (int r = j + 1 + t; r < N; r += nt) vn[r] = (r == j + 1) ? 1.0 : x[r] * scal;
+    *beta_out = beta;
+    return tau;
+}
+
+// Trailing pass over rows/cols >= lo: optionally apply A -= v w^T + w v^T,
+// and accumulate acc[g] = sum_h A[g,h] vn[h] into part[] (G groups).
+template <bool UPDATE>
+__device__ inline void trd_pass(double* A, int N, int lo, const double* v, const double* w, const double* vn,
+                                double* part, TrdLayout L) {
+    const int t = threadIdx.x;
+    const int grp = t / L.TPG;
+    if (grp >= L.G) return;
+    const int lr0 = t - grp * L.TPG;
+    for (int lr = lr0; lr < L.rows; lr += L.TPG) {
+        const int g = lo + lr;
+        const double vg = UPDATE ? v[g] : 0.0, wg = UPDATE ? w[g] : 0.0;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int h = lo + grp;
+        const int G = L.G;
+        for (; h + 3 * G < N; h += 4 * G) {
+            double* p0 = A + g + (long)h * N;
+            double x0 = p0[0], x1 = p0[(long)G * N], x2 = p0[(long)2 * G * N], x3 = p0[(long)3 * G * N];
+            if (UPDATE) {
+                x0 -= vg * w[h] + wg * v[h];
+                x1 -= vg * w[h + G] + wg * v[h + G];
+                x2 -= vg * w[h + 2 * G] + wg * v[h + 2 * G];
+                x3 -= vg * w[h + 3 * G] + wg * v[h + 3 * G];
+                p0[0] = x0;
+                p0[(long)G * N] = x1;
+                p0[(long)2 * G * N] = x2;
+                p0[(long)3 * G * N] = x3;
+            }
+            a0 += x0 * vn[h];
+            a1 += x1 * vn[h + G];
+            a2 += x2 * vn[h + 2 * G];
+            a3 += x3 * vn[h + 3 * G];
+        }
+        for (; h < N; h += G) {
+            double* p0 = A + g + (long)h * N;
+            double x0 = p0[0];
+            if (UPDATE) {
+                x0 -= vg * w[h] + wg * v[h];
+                p0[0] = x0;
+            }
+            a0 += x0 * vn[h];
+        }
+        part[grp * L.R + lr] = (a0 + a1) + (a2 + a3);
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sytrd(double* A, int N, double* d, double* e, double* tau, double* shift) {
+    extern __shared__ double sh[];
+    double* v = sh;             // N: current reflector (global row index)
+    double* w = sh + N;         // N
+    double* vn = sh + 2 * N;    // N: next reflector
+    double* part = sh + 3 * N;  // <= 1024 + 16 * 64 partial sums
+    __shared__ double red[16];
+    __shared__ double s_beta;
+    const int t = threadIdx.x, nt = blockDim.x;
+    // shift by the mean of the diagonal
+    double tr = 0.0;
+    for (int i = t; i < N; i += nt) tr += A[i + (long)i * N];
+    const double sigma = block_sum(tr, red) / N;
+    __syncthreads();
+    for (int i = t; i < N; i += nt) A[i + (long)i * N] -= sigma;
+    if (t == 0) shift[0] = sigma;
+    __syncthreads();
+    if (N >= 3) {
+        double beta;
+        double tau_i = trd_householder(A, N, 0, v, red, &beta);
+        if (t == 0) {
+            d[0] = A[0];
+            e[0] = beta;
+            tau[0] = tau_i;
+        }
+        __syncthreads();
+        TrdLayout L = trd_layout(N - 1, nt);
+        trd_pass<false>(A, N, 1, v, w, v, part, L);
+        __syncthreads();
+        for (int i = 0; i + 2 < N; ++i) {
+            // p = tau A22 v from the partial sums, rows g >= i+1
+            const int lo = i + 1;
+            double pv = 0.0;
+            for (int lr = t; lr < L.rows; lr += nt) {
+                double acc = 0.0;
+                for (int q = 0; q < L.G; ++q) acc += part[q * L.R + lr];
+                const double p = tau_i * acc;
+                w[lo + lr] = p;
+                pv += p * v[lo + lr];
+            }
+            pv = block_sum(pv, red);
+            const double k2 = 0.5 * tau_i * pv;
+            for (int g = lo + t; g < N; g += nt) w[g] -= k2 * v[g];
+            __syncthreads();
+            // column i+1 (rows >= i+1) first: it yields the next reflector
+            {
+                const int h = i + 1;
+                double* col = A + (long)h * N;
+                const double vh = v[h], wh = w[h];
+                for (int g = h + t; g < N; g += nt) col[g] -= v[g] * wh + w[g] * vh;
+            }
+            __syncthreads();
+            // reflector i is stored below the subdiagonal of column i
+            {
+                double* x = A + (long)i * N;
+                for (int r = i + 2 + t; r < N; r += nt) x[r] = v[r];
+            }
+            const bool more = (i + 1) + 2 < N;
+            double tau_n = 0.0;
+            if (more) {
+                tau_n = trd_householder(A, N, i + 1, vn, red, &beta);
+                if (t == 0) {
+                    d[i + 1] = A[(i + 1) + (long)(i + 1) * N];
+                    e[i + 1] = beta;
+                    tau[i + 1] = tau_n;
+                }
+            } else {
+                for (int g = t; g < N; g += nt) vn[g] = 0.0;
+            }
+            __syncthreads();
+            L = trd_layout(N - (i + 2), nt);
+            trd_pass<true>(A, N, i + 2, v, w, vn, part, L);
+            __syncthreads();
+            if (!more) break;
+            double* tmp = v;
+            v = vn;
+            vn = tmp;
+            tau_i = tau_n;
+        }
+    }
+    if (t == 0) {
+        if (N >= 2) {
+            d[N - 2] = A[(N - 2) + (long)(N - 2) * N];
+            e[N - 2] = A[(N - 1) + (long)(N - 2) * N];
+            tau[N - 2] = 0.0;
+        }
+        d[N - 1] = A[(N - 1) + (long)(N - 1) * N];
+    }
+}
+
+// Number of eigenvalues of T smaller than x (Sturm count of the LDL^T
+// pivots of T - x I).
+__device__ inline int sturm_count(const double* d, const double* e2, int N, double x, double pivmin) {
+    int cnt = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+    for (int i = 1; i < N; ++i) {
+        q = d[i] - x - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// k-th smallest eigenvalue of T (workgroup k of 64 lanes): multisection of
+// the Gershgorin interval, 64 Sturm counts per round.  lam gets the
+// eigenvalue of T, eig the eigenvalue of A (T + shift).
+__global__ __launch_bounds__(64) void k_bisect(const double* d, const double* e, int N, const double* shift,
+                                               double* lam, double* eig) {
+    extern __shared__ double sh[];
+    double* sd = sh;
+    double* se2 = sh + N;
+    const int k = blockIdx.x, lane = threadIdx.x;
+    double lo = 1e300, hi = -1e300, emax2 = 0.0, tnorm = 0.0;
+    for (int i = lane; i < N; i += 64) {
+        const double di = d[i];
+        const double el = (i > 0) ? fabs(e[i - 1]) : 0.0, er = (i + 1 < N) ? fabs(e[i]) : 0.0;
+        sd[i] = di;
+        se2[i] = er * er;
+        lo = fmin(lo, di - el - er);
+        hi = fmax(hi, di + el + er);
+        tnorm = fmax(tnorm, fabs(di) + el + er);
+        emax2 = fmax(emax2, er * er);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+        tnorm = fmax(tnorm, __shfl_xor(tnorm, off, 64));
+        emax2 = fmax(emax2, __shfl_xor(emax2, off, 64));
+    }
+    __syncthreads();
+    const double pad = 2.0 * kEps * tnorm * N + 1e-300;
+    lo -= pad;
+    hi += pad;
+    const double pivmin = 1e-290 * fmax(1.0, emax2);
+    for (int it = 0; it < 64; ++it) {
+        if (!(hi - lo > 2.0 * kEps * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
+        const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
+        const bool above = (x > lo && x < hi) ? (sturm_count(sd, se2, N, x, pivmin) > k) : (x >= hi);
+        const unsigned long long m = __ballot(above);
+        // first lane whose point has more than k eigenvalues below it
+        const int j = m ? __ffsll((long long)m) - 1 : 64;
+        const double nlo = (j == 0) ? lo : __shfl(x, j - 1 < 0 ? 0 : j - 1, 64);
+        const double nhi = (j == 64) ? hi : __shfl(x, j > 63 ? 63 : j, 64);
+        if (!(nlo >= lo && nhi <= hi && nlo < nhi) || (nlo == lo && nhi == hi)) break;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane == 0) {
+        const double l = 0.5 * (lo + hi);
+        lam[k] = l;
+        eig[k] = l + shift[0];
+    }
+}
+
+// Inverse iteration for the eigenvectors of T, one thread per cluster of
+// close eigenvalues (consecutive indices whose gaps are below 1e-3 ||T||);
+// members of a cluster are shifted apart by a few ulps and Gram-Schmidt
+// orthogonalised against the earlier members at every step.  Scratch is
+// interleaved by thread (element i of thread c at i * nthr + c) so that a
+// wave's accesses coalesce; the vectors go to zt (row k = eigenvector k,
+// element i at i * N + k, i.e. zt is Z^T in column-major order).
+__global__ __launch_bounds__(64) void k_stein(const double* d, const double* e, const double* lam, int N,
+                                              const int* cl_start, const int* ncl, double* zt, double* work) {
+    const int nthr = gridDim.x * blockDim.x;
+    const int cl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= *ncl) return;
+    const int k0 = cl_start[cl], k1 = cl_start[cl + 1];
+    double* lo = work;                       // multiplier of L
+    double* rd = lo + (long)N * nthr;        // 1 / diagonal of U
+    double* u1 = rd + (long)N * nthr;        // first superdiagonal of U
+    double* u2 = u1 + (long)N * nthr;        // second superdiagonal of U (pivoting)
+    double* pv = u2 + (long)N * nthr;        // +1 where rows i, i+1 were interchanged
+#define SG_AT(arr, i) arr[(long)(i) * nthr + cl]
+#define SG_Z(i, k) zt[(long)(i) * N + (k)]
+    double tnorm = 0.0;
+    for (int i = 0; i < N; ++i)
+        tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0));
+    // floor keeps 1/tiny^2 finite for a (near-)zero T
+    const double tiny = kEps * fmax(tnorm, 1e-100);
+    const double sep = 10.0 * tiny;
+    double prev = -1e300;
+    for (int k = k0; k < k1; ++k) {
+        double x = lam[k];
+        if (k > k0 && x - prev < sep) x = prev + sep;
+        prev = x;
+        // LU with partial pivoting of T - x I
+        double a = d[0] - x, b = (N > 1) ? e[0] : 0.0;
+        for (int i = 0; i < N - 1; ++i) {
+            const double c = e[i];
+            const double dn = d[i + 1] - x;
+            const double bn = (i + 2 < N) ? e[i + 1] : 0.0;
+            if (fabs(a) >= fabs(c)) {
+                if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
+                const double l = c / a;
+                SG_AT(lo, i) = l;
+                SG_AT(rd, i) = 1.0 / a;
+                SG_AT(u1, i) = b;
+                SG_AT(u2, i) = 0.0;
+                SG_AT(pv, i) = 0.0;
+                a = dn - l * b;
+                b = bn;
+            } else {
+                const double l = a / c;
+                SG_AT(lo, i) = l;
+                SG_AT(rd, i) = 1.0 / c;
+                SG_AT(u1, i) = dn;
+                SG_AT(u2, i) = bn;
+                SG_AT(pv, i) = 1.0;
+                a = b - l * dn;
+                b = -l * bn;
+            }
+        }
+        if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
+        SG_AT(rd, N - 1) = 1.0 / a;
+        // start vector: a fixed, index-dependent pattern
+        for (int i = 0; i < N; ++i) SG_Z(i, k) = 1.0 + 0.1 * sin(1.3 * i + 0.7 * (k + 1));
+        for (int it = 0; it < 4; ++it) {
+            // forward: apply the row interchanges and L^{-1}
+            double cur = SG_Z(0, k);
+            for (int i = 0; i < N - 1; ++i) {
+                const double nxt = SG_Z(i + 1, k);
+                const double l = SG_AT(lo, i);
+                if (SG_AT(pv, i) != 0.0) {
+                    SG_Z(i, k) = nxt;
+                    cur = cur - l * nxt;
+                } else {
+                    SG_Z(i, k) = cur;
+                    cur = nxt - l * cur;
+                }
+            }
+            SG_Z(N - 1, k) = cur;
+            // backward: U^{-1}
+            double x1 = cur * SG_AT(rd, N - 1), x2 = 0.0;
+            SG_Z(N - 1, k) = x1;
+            for (int i = N - 2; i >= 0; --i) {
+                const double xi = (SG_Z(i, k) - SG_AT(u1, i) * x1 - SG_AT(u2, i) * x2) * SG_AT(rd, i);
+                SG_Z(i, k) = xi;
+                x2 = x1;
+                x1 = xi;
+            }
+            // orthogonalise against earlier members of the cluster, normalise
+            for (int j = k0; j < k; ++j) {
+                double s = 0.0;
+                for (int i = 0; i < N; ++i) s += SG_Z(i, j) * SG_Z(i, k);
+                for (int i = 0; i < N; ++i) SG_Z(i, k) -= s * SG_Z(i, j);
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < N; ++i) nrm += SG_Z(i, k) * SG_Z(i, k);
+            const double inv = (nrm > 0.0) ? 1.0 / sqrt(nrm) : 0.0;
+            for (int i = 0; i < N; ++i) SG_Z(i, k) *= inv;
+        }
+    }
+#undef SG_AT
+#undef SG_Z
+}
+
+// Clusters of consecutive eigenvalues of T with gaps below 1e-3 ||T||
+// (Gershgorin norm, floored as in the inverse iteration), computed by one
+// thread (N is small).
+__global__ void k_clusters(const double* d, const double* e, const double* lam, int N, int* cl_start, int* ncl) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double tnorm = 0.0;
+    for (int i = 0; i < N; ++i)
+        tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0));
+    const double gap = 1e-3 * fmax(tnorm, 1e-100);
+    int n = 0;
+    cl_start[n++] = 0;
+    for (int k = 1; k < N; ++k)
+        if (lam[k] - lam[k - 1] > gap) cl_start[n++] = k;
+    cl_start[n] = N;
+    *ncl = n;
+}
+
+// Z <- H_0 H_1 ... H_{N-3} Z^T (input zt = Z^T column-major), one wave per
+// output column; Z is written in column-major order.
+__global__ __launch_bounds__(256) void k_backtransform(const double* A, const double* tau, int N, const double* zt,
+                                                       double* Z) {
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= N) return;
+    double* zc = Z + (long)col * N;
+    // every element of the column is owned by one lane throughout
+    for (int r = lane; r < N; r += 64) zc[r] = zt[(long)r * N + col];
+    for (int i = N - 3; i >= 0; --i) {
+        const double ti = tau[i];
+        if (ti == 0.0) continue;
+        const double* vi = A + (long)i * N;   // v[r] at rows r = i+1.. (v[i+1] = 1)
+        const int r0 = ((i + 1) & ~63) + lane;
+        double s = 0.0;
+        for (int r = r0; r < N; r += 64)
+            if (r >= i + 1) s += ((r == i + 1) ? 1.0 : vi[r]) * zc[r];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        s *= ti;
+        for (int r = r0; r < N; r += 64)
+            if (r >= i + 1) zc[r] -= s * ((r == i + 1) ? 1.0 : vi[r]);
+    }
+}
+
+// A (destroyed) -> ascending eigenvalues eig and eigenvectors V (columns).
+// work: eigh_work_doubles(N) doubles.  N <= kEighMaxN (LDS of the
+// tridiagonalisation).
+sparc_status dense_eigh_tridiag(sparc_gpu_ctx c, double* A, int N, double* V, double* eig, double* work) {
+    double* d = work;
+    double* e = d + N;
+    double* tau = e + N;
+    double* lamw = tau + N;
+    double* shift = lamw + N;                // 1 (+7 pad)
+    int* cl = (int*)(shift + 8);             // N + 2 ints
+    int* ncl_d = cl + N + 1;
+    const int nthr = div_up(N, 64) * 64;     // threads of the inverse iteration
+    double* zt = shift + 8 + N + 2;          // N^2
+    double* stw = zt + (size_t)N * N;        // 5 N nthr
+    const int threads = std::min(1024, std::max(64, div_up(N, 64) * 64));
+    int slot = prof_begin(c, PK_EIG_TRD);
+    const size_t trd_lds = (3 * (size_t)N + std::max(1024, N + 64)) * sizeof(double);
+    k_sytrd<<<1, threads, trd_lds, c->stream>>>(A, N, d, e, tau, shift);
+    SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
+    slot = prof_begin(c, PK_EIG_BIS);
+    k_bisect<<<N, 64, 2 * N * sizeof(double), c->stream>>>(d, e, N, shift, lamw, eig);
+    SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
+    slot = prof_begin(c, PK_EIG_VEC);
+    k_clusters<<<1, 64, 0, c->stream>>>(d, e, lamw, N, cl, ncl_d);
+    SG_CHECK_LAUNCH(c);
+    k_stein<<<nthr / 64, 64, 0, c->stream>>>(d, e, lamw, N, cl, ncl_d, zt, stw);
+    SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
+    slot = prof_begin(c, PK_EIG_BACK);
+    k_backtransform<<<div_up(N, 4), 256, 0, c->stream>>>(A, tau, N, zt, V);
+    SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
+    return SPARC_OK;
+}
+
+}  // namespace sg

@@ -123,7 +123,15 @@ struct sparc_gpu_ctx_s {
 
     hipEvent_t ev[8];
     std::string err;
+
+    // captured Jacobi sweep (see dense.hip)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t jac_exec = nullptr;
+    int jac_N = 0;
+    double *jac_A = nullptr, *jac_A2 = nullptr, *jac_V = nullptr, *jac_V2 = nullptr;
     int sweep_slab_major = 0;   // block order of the sweep kernel
+    int debug = 0;              // SPARC_GPU_DEBUG: diagnostics on stderr
+    int eig_jacobi = 0;         // SPARC_GPU_EIG=jacobi: parallel Jacobi instead of tridiagonal
     std::vector<int> pe_off_host;  // host copy of nl.pe_off (slab-plane maxima)
     int emax_ty = -1, emax_val = 0;
     int nl_ty = 6;                 // slab height of the nonlocal sweep
@@ -134,8 +142,8 @@ struct sparc_gpu_ctx_s {
     std::vector<hipEvent_t> prof_pool;        // 2 events per recorded launch
     std::vector<int> prof_kernel;             // kernel id per recorded launch
     int prof_used = 0;
-    double prof_ms[8] = {0};
-    long prof_n[8] = {0};
+    double prof_ms[16] = {0};
+    long prof_n[16] = {0};
 };
 
 namespace sg {
@@ -198,6 +206,9 @@ sparc_status dense_tri_inverse_lower(sparc_gpu_ctx c, const double* L, double* L
 sparc_status dense_gemm(sparc_gpu_ctx c, char ta, char tb, int N, const double* A, const double* B, double* C);
 sparc_status dense_symmetrize(sparc_gpu_ctx c, double* A, int N);
 sparc_status dense_eigh(sparc_gpu_ctx c, double* A, int N, double* V, double* eig, double* work);
+sparc_status dense_eigh_tridiag(sparc_gpu_ctx c, double* A, int N, double* V, double* eig, double* work);
+constexpr int kEighMaxN = 4096;
+inline size_t eigh_work_doubles(int N) { return 6 * (size_t)N * N + 320 * (size_t)N + 64; }
 
 // RR core shared by the public entry point and the SCF step; eig on device
 template <typename T>
@@ -222,7 +233,16 @@ enum ProfKernel {
     PK_DENSITY = 4,
     PK_SWEEP1 = 5,   // first filter step
     PK_APPLY = 6,    // plain H application
-    PK_COUNT = 8
+    PK_CHOL = 7,     // Cholesky of the Gram matrix
+    PK_TRINV = 8,    // inverse of the Cholesky factor
+    PK_EIG = 9,      // subspace eigensolver (all its launches)
+    PK_SMALL = 10,   // N_s x N_s products
+    PK_COPY = 11,    // block copies
+    PK_EIG_TRD = 12, // eigensolver: tridiagonalisation
+    PK_EIG_BIS = 13, // eigensolver: eigenvalues of the tridiagonal matrix
+    PK_EIG_VEC = 14, // eigensolver: inverse iteration
+    PK_EIG_BACK = 15,// eigensolver: back-transformation
+    PK_COUNT = 16
 };
 int prof_begin(sparc_gpu_ctx c, int kernel);
 void prof_end(sparc_gpu_ctx c, int slot);

@@ -36,7 +36,7 @@ struct SweepArgs {
     const uint64_t* pe8;
     const CandInfo* slab_cand;
     const int* slab_k;
-    int kmax, xw;
+    int kmax, xw, zw;
     const double* atom_pos;  // 3 n_atoms
     T inv_rc2, N0, N1, hx, hy, hz;
     const T* D;       // gamma-scaled projections, column j at D + j*ldD
@@ -109,21 +109,24 @@ struct SweepGeom {
     int* cxb;               // x index offset into the ex table
     T* ex;                  // ex[k*xw + i]: exp(-dx^2/rc^2) over the candidate's x-range
     T* ey;                  // ey[row*K + k]
-    T* ez;                  // ez[parity*K + k] for planes z+1 / z+2
+    T* ez;                  // ez[k*zw + i]: exp(-dz^2/rc^2) over the candidate's z-range
+    int* czb;               // z index offset into the ez table
     T* ab;                  // ab[parity][row][k][2]: A, B of plane z / z+1
-    int K, y0, tyn, xw;
+    int K, y0, tyn, xw, zw;
 };
 
 // A(row, k), B(row, k) of one plane z: the candidate's projector values on
 // the row factor as ex(x) * (A + B * dx) with
 //   A = ey ez (N0 D_s + N1 (dy D_py + dz D_pz)),  B = ey ez N1 D_px.
 template <typename T>
-__device__ __forceinline__ void sweep_ab(const SweepArgs<T>& a, const SweepGeom<T>& g, int z, int ezpar,
-                                         T* abz) {
+__device__ __forceinline__ void sweep_ab(const SweepArgs<T>& a, const SweepGeom<T>& g, int z, T* abz) {
     const int n = g.tyn * g.K;
     for (int j = g.t; j < n; j += g.nt) {
         const int row = j / g.K, k = j - row * g.K;
-        const T eyz = g.ey[j] * g.ez[ezpar * g.K + k];
+        // planes outside the candidate's z-range never reach a point that
+        // lists it; clamp the table index there
+        const int iz = min(max(z - g.czb[k], 0), g.zw - 1);
+        const T eyz = g.ey[j] * g.ez[k * g.zw + iz];
         const T dy = (T)(g.y0 + row) * a.hy - g.cy[k];
         const T dz = (T)z * a.hz - g.cz[k];
         abz[2 * j] = eyz * (a.N0 * g.ds[k] + a.N1 * (dy * g.dpy[k] + dz * g.dpz[k]));
@@ -131,13 +134,7 @@ __device__ __forceinline__ void sweep_ab(const SweepArgs<T>& a, const SweepGeom<
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void sweep_ez(const SweepArgs<T>& a, const SweepGeom<T>& g, int z, int ezpar) {
-    for (int k = g.t; k < g.K; k += g.nt) {
-        const T dz = (T)z * a.hz - g.cz[k];
-        g.ez[ezpar * g.K + k] = exp(-dz * dz * a.inv_rc2);
-    }
-}
+
 
 // One z-plane of the sweep at ring phase U (z = z0 + U).  On entry the LDS
 // buffer of parity U holds plane z (own rows with x-wrap padding, halo rows,
@@ -219,13 +216,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& a, SweepRegs<T, H
             nbuf[g.loff[i]] = r.h[i];
             if (g.poff[i] >= 0) nbuf[g.poff[i]] = r.h[i];
         }
-    if (NL) {
-        // tables of the next plane: A/B of z+1 (its ez was computed one step
-        // earlier), and ez of z+2
-        sweep_ab<T>(a, g, z1, PN, g.ab + PN * a.ty * 2 * g.K);
-        const int z2 = (z1 + 1 == g.nz) ? 0 : z1 + 1;
-        sweep_ez<T>(a, g, z2, P);
-    }
+    if (NL) sweep_ab<T>(a, g, z1, g.ab + PN * a.ty * 2 * g.K);  // A/B of the next plane
     int zn = z + NO + 2;
     zn = zn >= g.nz ? zn - g.nz : zn;
     r.q[(U + NO + 2) % RING] = xc[g.pxy + (long)zn * g.plane];
@@ -297,9 +288,11 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, NL ? 512 : 1024))) void
         g.ex = tp + 7 * KM;
         g.ey = g.ex + KM * a.xw;
         g.ez = g.ey + a.ty * KM;
-        g.ab = g.ez + 2 * KM;
+        g.ab = g.ez + KM * a.zw;
         g.cxb = reinterpret_cast<int*>(g.ab + 4 * a.ty * KM);
+        g.czb = g.cxb + KM;
         g.xw = a.xw;
+        g.zw = a.zw;
         g.K = a.slab_k[tile];
         const CandInfo* ci = a.slab_cand + (long)tile * KM;
         const T* Dc = a.D + (long)col * a.ldD;
@@ -313,6 +306,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, NL ? 512 : 1024))) void
             g.dpy[k] = Dc[4 * c.atom + 2];
             g.dpz[k] = Dc[4 * c.atom + 3];
             g.cxb[k] = c.ixlo - c.sx * nx;
+            g.czb[k] = c.izlo - c.sz * nz;
         }
         __syncthreads();
         for (int j = t; j < g.K * g.xw; j += nt) {
@@ -325,10 +319,13 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, NL ? 512 : 1024))) void
             const T dy = (T)(y0 + row) * a.hy - g.cy[k];
             g.ey[j] = exp(-dy * dy * a.inv_rc2);
         }
-        sweep_ez<T>(a, g, 0, 0);
-        sweep_ez<T>(a, g, nz > 1 ? 1 : 0, 1);
+        for (int j = t; j < g.K * g.zw; j += nt) {
+            const int k = j / g.zw, i = j - k * g.zw;
+            const T dz = (T)(ci[k].izlo + i) * a.hz - (T)a.atom_pos[3 * ci[k].atom + 2];
+            g.ez[j] = exp(-dz * dz * a.inv_rc2);
+        }
         __syncthreads();
-        sweep_ab<T>(a, g, 0, 0, g.ab);
+        sweep_ab<T>(a, g, 0, g.ab);
     }
     const T* xc = a.x + (long)col * a.ldx;
     g.xc = xc;
@@ -540,6 +537,7 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     a.slab_k = c->nl.slab_k;
     a.kmax = c->nl.slab_kmax;
     a.xw = c->nl.slab_xw;
+    a.zw = c->nl.slab_zw;
     a.atom_pos = c->atom_pos;
     {
         const double pi = 3.14159265358979323846;
@@ -563,7 +561,7 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     size_t shmem = 2 * (size_t)(a.ty + 2 * kMaxHalfOrder) * (c->nx + 2 * kMaxHalfOrder) * sizeof(T);
     if (nl) {
         const size_t KM = a.kmax;
-        shmem += (7 * KM + KM * a.xw + a.ty * KM + 2 * KM + 4 * a.ty * KM) * sizeof(T) + KM * sizeof(int);
+        shmem += (7 * KM + KM * a.xw + a.ty * KM + KM * a.zw + 4 * a.ty * KM) * sizeof(T) + 2 * KM * sizeof(int);
     }
     if (shmem > 160 * 1024) return set_err(c, SPARC_ERR_ARG, "sweep workgroup needs more than 160 KB of LDS");
     if (threads > (nl ? 512 : 1024)) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
