@@ -63,6 +63,7 @@ class System:
     sad_width: float = 1.0           # Bohr, width of the atomic model densities
     cheb_degree: int = 12
     mix_beta: float = 0.3
+    kerker_q0: float = 0.0     # 0: plain linear mixing
     n_first: int = 4                 # filter passes in the first SCF iteration
     seed: int = 0
     meta: dict = field(default_factory=dict)
@@ -158,7 +159,9 @@ def config1(seed: int = 0, n: int = 24) -> System:
 def config2(seed: int = 0) -> System:
     """L = 20 Bohr cube, 72^3 grid, 108 atoms (FCC 3x3x3 conventional cells,
     jitter N(0, 0.1)), Z = 4, rc_loc = 1.0, s+p projectors with rc = 1.2 and
-    energies U[-1, 1] Ha, 260 states for 432 electrons, degree 20."""
+    energies U[-1, 1] Ha, 260 states for 432 electrons, degree 20.  Linear
+    mixing 0.3 with the Kerker-type residual preconditioner q0 = 1 / Bohr
+    (plain linear mixing sloshes at this cell size)."""
     rng = np.random.default_rng(seed)
     L = 20.0
     pos = fcc_jittered(L, 3, 0.1, rng)
@@ -166,7 +169,7 @@ def config2(seed: int = 0) -> System:
     return System(
         name="cfg2", n=(72, 72, 72), L=(L, L, L), pos=pos,
         Z=np.full(na, 4.0), rc_loc=np.full(na, 1.0),
-        n_states=260, n_electrons=432.0, kT=0.01, cheb_degree=20, mix_beta=0.3,
+        n_states=260, n_electrons=432.0, kT=0.01, cheb_degree=20, mix_beta=0.3, kerker_q0=1.0,
         nl_lmax=1, gamma=_gamma(na, 1, seed), rc_nl=1.2, rcut_nl=3.6, seed=seed,
     )
 
@@ -190,7 +193,7 @@ def config4(seed: int = 0) -> System:
     return System(
         name="cfg4", n=(120, 120, 120), L=(L, L, L), pos=pos,
         Z=np.full(na, 4.0), rc_loc=np.full(na, 1.0),
-        n_states=1200, n_electrons=2000.0, kT=0.01, cheb_degree=24, mix_beta=0.3,
+        n_states=1200, n_electrons=2000.0, kT=0.01, cheb_degree=24, mix_beta=0.3, kerker_q0=1.0,
         nl_lmax=1, gamma=_gamma(na, 1, seed), rc_nl=1.2, rcut_nl=3.6, seed=seed,
     )
 
@@ -231,6 +234,21 @@ def initial_orbitals(nd: int, ns: int, seed: int = 0, dtype=np.float64) -> np.nd
     the C ABI."""
     rng = np.random.default_rng([seed, 11])
     return rng.uniform(-0.5, 0.5, (ns, nd)).astype(dtype)
+
+
+def cnn_initial_weights(seed: int = 0) -> np.ndarray:
+    """Starting parameters of the 3 -> 16 -> 16 -> 1 warm-start network
+    (flat, float32; layout W1, b1, W2, b2, W3, b3 with W (out, in, 3, 3, 3)):
+    He-normal weights N(0, 2 / (27 in)), zero biases, the output layer scaled
+    by 0.1."""
+    rng = np.random.default_rng([seed, 13])
+    parts = []
+    for k, (ci, co) in enumerate(((3, 16), (16, 16), (16, 1))):
+        W = rng.standard_normal((co, ci, 3, 3, 3)) * np.sqrt(2.0 / (27 * ci))
+        if k == 2:
+            W *= 0.1
+        parts += [W.ravel(), np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
 
 
 CONFIG_NAMES = {
