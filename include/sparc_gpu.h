@@ -189,6 +189,12 @@ typedef struct {
     int cheb_degree;    /* m                                                  */
     int n_first;        /* filter + RR passes in the first iteration (>= 1)  */
     double mix_beta;    /* linear mixing factor, 0 < beta <= 1                */
+    double kerker_q0;   /* >= 0: mixing preconditioner wavenumber (1/Bohr);
+                           0 = plain linear mixing.  With q0 > 0 the residual
+                           is filtered by (-Lap_h)(-Lap_h + q0^2)^-1 before
+                           it is mixed (a Kerker-type preconditioner, in the
+                           spirit of the real-space preconditioner of
+                           Sec. 2.1).                                          */
     int iter;           /* 0 on the first call; incremented by each call     */
     double* d_eig;      /* out: n_states Ritz values (ascending)             */
     double* d_occ;      /* out: n_states occupations                          */

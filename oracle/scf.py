@@ -7,8 +7,12 @@ and mu fixed by sum_n g_n = N_e.
 Sec. 2.1: the ground state is the fixed point of the SCF iteration; the first
 iteration starts from a superposition of atomic densities and performs several
 CheFSI filtering passes, later iterations one.  The paper accelerates the
-iteration with restarted periodic Pulay mixing; the workloads here prescribe
-simple linear mixing  rho_in <- rho_in + beta (rho_out - rho_in).
+iteration with restarted periodic Pulay mixing and a real-space
+preconditioner; the workloads here prescribe simple linear mixing
+rho_in <- rho_in + beta (rho_out - rho_in), optionally with the residual
+filtered by the Kerker-type preconditioner P = (-Lap_h)(-Lap_h + q0^2)^-1
+(needed against charge sloshing in the larger cells; q0 = 0 is plain linear
+mixing).
 
 Energy: Harris-Foulkes free energy evaluated at the input density,
     F = sum_n g_n lam_n + dV sum rho_in eps_xc - dV sum rho_in v_xc
@@ -120,8 +124,24 @@ def energy_terms(sys, st: Setup, rho_in, phi, exc, vxc, lam, g):
     return t
 
 
-def mix(rho_in, rho_out, beta):
-    return rho_in + beta * (rho_out - rho_in)
+def kerker(sys, r: np.ndarray, q0: float) -> np.ndarray:
+    """P r with P = (-Lap_h)(-Lap_h + q0^2)^-1: the discrete Laplacian is
+    diagonal in the Fourier basis (eigenvalues S(k) <= 0 of the FD symbol),
+    so P scales each Fourier component by -S / (-S + q0^2); the constant
+    component is removed."""
+    nx, ny, nz = sys.n
+    lam = -electrostatics.fd_symbol_3d(sys)
+    rh = np.fft.fftn(r.reshape(nz, ny, nx))
+    rh *= lam / (lam + q0 * q0)
+    rh[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(rh)).reshape(-1)
+
+
+def mix(rho_in, rho_out, beta, sys=None, kerker_q0: float = 0.0):
+    d = rho_out - rho_in
+    if kerker_q0 > 0.0:
+        d = kerker(sys, d, kerker_q0)
+    return rho_in + beta * d
 
 
 @dataclass
@@ -182,7 +202,7 @@ def scf(sys, X0: np.ndarray, rho0: np.ndarray = None, max_iter: int = 50, tol: f
         if callback is not None:
             callback(rec)
         rho_prev = rho_in
-        rho_in = mix(rho_in, rho_out, beta)
+        rho_in = mix(rho_in, rho_out, beta, sys, getattr(sys, "kerker_q0", 0.0))
         if res < tol:
             break
     return SCFResult(X=X, lam=lam, g=g, mu=mu, rho_in=rho_prev, rho_out=rho_out, history=hist)

@@ -89,6 +89,7 @@ class SCFState(C.Structure):
         ("cheb_degree", C.c_int),
         ("n_first", C.c_int),
         ("mix_beta", C.c_double),
+        ("kerker_q0", C.c_double),
         ("iter", C.c_int),
         ("d_eig", C.c_void_p),
         ("d_occ", C.c_void_p),
@@ -313,7 +314,7 @@ class Context:
         return rep.as_dict()
 
 
-def make_state(rho_in, X, eig, occ, degree, n_first=4, beta=0.3, rho_out=None) -> SCFState:
+def make_state(rho_in, X, eig, occ, degree, n_first=4, beta=0.3, rho_out=None, kerker_q0=0.0) -> SCFState:
     st = SCFState()
     st.d_rho_in = rho_in.data_ptr()
     st.d_X = X.data_ptr()
@@ -322,6 +323,7 @@ def make_state(rho_in, X, eig, occ, degree, n_first=4, beta=0.3, rho_out=None) -
     st.cheb_degree = int(degree)
     st.n_first = int(n_first)
     st.mix_beta = float(beta)
+    st.kerker_q0 = float(kerker_q0)
     st.iter = 0
     st.d_eig = eig.data_ptr()
     st.d_occ = occ.data_ptr()

@@ -282,6 +282,26 @@ __global__ __launch_bounds__(256) void k_energy_mix(double* __restrict__ rho_in,
     if (t < kRed) part[(long)blockIdx.x * kRed + t] = red[t][0];
 }
 
+__global__ void k_residual(const double* a, const double* b, double* out, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] - b[i];
+}
+
+// Eigencomponent scaling of the mixing preconditioner: the Poisson table
+// holds 4 pi / lambda (0 for the constant mode), so
+// lambda / (lambda + q0^2) = 4 pi / (4 pi + q0^2 inv); the constant mode is
+// removed.
+__global__ void k_kerker(double* t, const double* inv, double q02, long n) {
+    const double fourpi = 12.566370614359172;
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) t[i] = (inv[i] == 0.0) ? 0.0 : t[i] * (fourpi / (fourpi + q02 * inv[i]));
+}
+
+__global__ void k_axpy(double* y, const double* x, double a, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+
 __global__ void k_energy_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
     int k = threadIdx.x;
     if (k >= kRed) return;
@@ -327,15 +347,34 @@ struct Timer {
 // Energy terms and residual at (rho_in, rho_out) into the report; mixes when
 // do_mix.  Fields: phi = f[2], exc = f[3], vxc = f[4].
 static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double* rho_out, double beta, int do_mix,
-                                  sparc_gpu_scf_report* rep, double* hscal) {
+                                  sparc_gpu_scf_report* rep, double* hscal, double kerker_q0 = 0.0) {
     const int nblk = std::min(1024, div_up(c->nd, 256));
     sparc_status st = ensure_red(c, (size_t)nblk * kRed);
     if (st != SPARC_OK) return st;
     const double* phi = c->field + 2 * c->nd;
     const double* exc = c->field + 3 * c->nd;
     const double* vxc = c->field + 4 * c->nd;
-    k_energy_mix<<<nblk, 256, 0, c->stream>>>(rho_in, rho_out, exc, vxc, phi, c->b, c->nd, beta, do_mix, c->red);
+    const bool kerker = do_mix && kerker_q0 > 0.0;
+    k_energy_mix<<<nblk, 256, 0, c->stream>>>(rho_in, rho_out, exc, vxc, phi, c->b, c->nd, beta, kerker ? 0 : do_mix,
+                                              c->red);
     SG_CHECK_LAUNCH(c);
+    if (kerker) {
+        // rho_in += beta P (rho_out - rho_in), P = (-Lap)(-Lap + q0^2)^-1 in
+        // the eigenbasis of the discrete Laplacian (fields 0, 1 are free)
+        double* t0 = c->field;
+        double* t1 = c->field + c->nd;
+        const int nb = div_up(c->nd, 256);
+        k_residual<<<nb, 256, 0, c->stream>>>(rho_out, rho_in, t0, c->nd);
+        k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_ux, c->nx, c->ny, c->nz, 0, 1);
+        k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uy, c->nx, c->ny, c->nz, 1, 1);
+        k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uz, c->nx, c->ny, c->nz, 2, 1);
+        k_kerker<<<nb, 256, 0, c->stream>>>(t1, c->pois_inv, kerker_q0 * kerker_q0, c->nd);
+        k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uz, c->nx, c->ny, c->nz, 2, 0);
+        k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uy, c->nx, c->ny, c->nz, 1, 0);
+        k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_ux, c->nx, c->ny, c->nz, 0, 0);
+        k_axpy<<<nb, 256, 0, c->stream>>>(rho_in, t0, beta, c->nd);
+        SG_CHECK_LAUNCH(c);
+    }
     k_energy_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_RED0);
     SG_CHECK_LAUNCH(c);
     double hloc[S_COUNT];
@@ -410,7 +449,7 @@ static sparc_status scf_step_impl(sparc_gpu_ctx c, sparc_gpu_scf_state* s, sparc
     tm.mark(6);
     sparc_gpu_scf_report R;
     double hs[S_COUNT];
-    if ((st = finish_energy(c, s->d_rho_in, rho_out, s->mix_beta, 1, &R, hs)) != SPARC_OK) return st;
+    if ((st = finish_energy(c, s->d_rho_in, rho_out, s->mix_beta, 1, &R, hs, s->kerker_q0)) != SPARC_OK) return st;
     tm.mark(7);
     SG_HIP(c, hipEventSynchronize(c->ev[7]));
     s->bounds[0] = hs[S_A];
@@ -436,6 +475,7 @@ static sparc_status check_state(sparc_gpu_ctx c, const sparc_gpu_scf_state* s) {
     if (s->cheb_degree < 1 || s->cheb_degree > 10000) return set_err(c, SPARC_ERR_ARG, "scf: bad degree");
     if (s->n_first < 1 || s->n_first > 100) return set_err(c, SPARC_ERR_ARG, "scf: bad n_first");
     if (!(s->mix_beta > 0.0 && s->mix_beta <= 1.0)) return set_err(c, SPARC_ERR_ARG, "scf: bad mix_beta");
+    if (!(s->kerker_q0 >= 0.0) || !std::isfinite(s->kerker_q0)) return set_err(c, SPARC_ERR_ARG, "scf: bad kerker_q0");
     if (s->iter < 0) return set_err(c, SPARC_ERR_ARG, "scf: negative iter");
     if (s->iter > 0 && !(s->bounds[2] < s->bounds[0]))
         return set_err(c, SPARC_ERR_ARG, "scf: bounds need a0 < a after the first iteration");

@@ -9,7 +9,7 @@ from ._lib import SPARC_FP32, Context, make_state
 
 def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100, tol: float = 1e-10,
             device: str = "cuda", final_fp64_rr: bool = True, ctx: Context = None, callback=None,
-            n_first: int = None, degree: int = None, beta: float = None):
+            n_first: int = None, degree: int = None, beta: float = None, kerker_q0: float = None):
     """Run the SCF iteration on the GPU.
 
     X0: (N_s, N_d) numpy array (random block, see ``workloads.initial_orbitals``);
@@ -34,7 +34,8 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
     st = make_state(rho_in, X, eig, occ,
                     degree if degree is not None else system.cheb_degree,
                     n_first if n_first is not None else system.n_first,
-                    beta if beta is not None else system.mix_beta, rho_out)
+                    beta if beta is not None else system.mix_beta, rho_out,
+                    kerker_q0 if kerker_q0 is not None else system.kerker_q0)
     hist = []
     for _ in range(max_iter):
         rep = ctx.scf_step(st)

@@ -1,0 +1,62 @@
+"""Writes the stored SCF reference values under tests/golden/ from the CPU
+oracle alone (no GPU code is imported).
+
+    python tests/golden/make_golden.py
+
+cfg1_scf.json: the 8-atom, 24^3 system (seed 0) iterated by the oracle's
+SCF (Sec. 2.1: Chebyshev-filtered subspace iteration with linear density
+mixing) from the seeded random block until the density residual is below
+1e-10: the free energy per atom and eigenvalues at the fixed point, the
+per-iteration trajectory of the first iterations, and the density at seeded
+sample points together with its integrals.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W  # noqa: E402
+from oracle import scf  # noqa: E402
+
+N_TRAJ = 12
+N_SAMPLES = 64
+
+
+def cfg1_scf():
+    s = W.config1(0)
+    X0 = W.initial_orbitals(s.nd, s.n_states, s.seed)
+    r = scf.scf(s, X0, max_iter=200, tol=1e-10)
+    dv = float(np.prod(s.h))
+    idx = np.sort(np.random.default_rng(2024).choice(s.nd, N_SAMPLES, replace=False))
+    last = r.history[-1]
+    return {
+        "system": "workloads.config1(0)",
+        "tol": 1e-10,
+        "n_iter": len(r.history),
+        "free_per_atom": last["free"] / s.n_atoms,
+        "terms": {k: last[k] for k in ("band", "exc", "vxc_dc", "elec", "self", "corr", "entropy", "free")},
+        "mu": float(r.mu),
+        "eig": [float(x) for x in r.lam],
+        "occ": [float(x) for x in r.g],
+        "residual": last["residual"],
+        "trajectory": [{"free_per_atom": h["free"] / s.n_atoms, "residual": h["residual"],
+                        "eig_min": float(h["lam"][0]), "eig_max": float(h["lam"][-1])}
+                       for h in r.history[:N_TRAJ]],
+        "rho_out_samples": {"index": [int(i) for i in idx], "value": [float(r.rho_out[i]) for i in idx]},
+        "rho_out_integrals": {"int_rho": float(dv * r.rho_out.sum()), "int_rho2": float(dv * (r.rho_out ** 2).sum())},
+    }
+
+
+def main():
+    out = os.path.join(HERE, "cfg1_scf.json")
+    with open(out, "w") as f:
+        json.dump(cfg1_scf(), f, indent=1)
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    main()

@@ -210,6 +210,33 @@ def test_poisson_solution_satisfies_stencil_equation():
     assert abs(phi.mean()) < 1e-13
 
 
+def test_kerker_preconditioner_solves_screened_stencil_equation():
+    """y = P r must satisfy (-Delta_h + q0^2) y = -Delta_h r, with Delta_h
+    applied by the real-space stencil (a different route from the Fourier
+    scaling); P removes the mean and tends to r - mean(r) as q0 -> 0."""
+    s = W.tiny_system(n=(13, 14, 15), L=(4.0, 4.3, 4.6))
+    r = np.random.default_rng(6).standard_normal(s.nd)
+    shape = (s.n[2], s.n[1], s.n[0])
+    for q0 in (0.5, 1.0, 2.5):
+        y = scf.kerker(s, r, q0)
+        lap_y = fd.laplacian(y.reshape(shape), s.h, 6).ravel()
+        lap_r = fd.laplacian(r.reshape(shape), s.h, 6).ravel()
+        np.testing.assert_allclose(-lap_y + q0 * q0 * y, -lap_r, atol=1e-10)
+        assert abs(y.mean()) < 1e-14
+    np.testing.assert_allclose(scf.kerker(s, r, 1e-7), r - r.mean(), atol=1e-10)
+
+
+def test_kerker_mixing_conserves_electrons():
+    s = W.tiny_system(n=(13, 14, 15), L=(4.0, 4.3, 4.6))
+    rng = np.random.default_rng(7)
+    rin = rng.uniform(0.1, 1.0, s.nd)
+    rout = rng.uniform(0.1, 1.0, s.nd)
+    rout *= rin.sum() / rout.sum()
+    new = scf.mix(rin, rout, 0.3, s, 1.0)
+    assert abs(new.sum() - rin.sum()) <= 1e-10 * rin.sum()
+    np.testing.assert_allclose(scf.mix(rin, rout, 0.3), rin + 0.3 * (rout - rin), rtol=0, atol=0)
+
+
 def test_poisson_plane_wave_continuum():
     s = W.config1(0)
     nx, ny, nz = s.n
