@@ -239,9 +239,52 @@ sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st,
  * 2 Gram/projected-H GEMM, 3 rotation GEMM, 4 density, 5 first filter
  * sweep, 6 plain H application, 7 Cholesky, 8 triangular inverse,
  * 9 subspace eigensolver (all its launches, host waits included),
- * 10 small N_s x N_s products, 11 block copy-back; ids < 16. */
+ * 10 small N_s x N_s products, 11 block copy-back, 12 tridiagonalisation,
+ * 13 tridiagonal eigenvalues, 14 inverse iteration, 15 back-transformation
+ * (12-15 are the phases inside 9); ids < 16. */
 sparc_status sparc_gpu_profile(sparc_gpu_ctx ctx, int enable);
 sparc_status sparc_gpu_profile_read(sparc_gpu_ctx ctx, int kernel_id, double* total_ms, long* launches);
+
+/* ---- Learned initial density (warm start of the SCF) ----------------------
+ * The SCF of Sec. 2.1 starts from a superposition of atomic densities; the
+ * warm start replaces that guess by the prediction of a small periodic
+ * convolutional network trained on converged densities of related
+ * geometries (machine-learning methods are a direction named in Sec. 5).
+ *
+ * Features: 3 channels f_c(x) = sum over atoms and periodic images within
+ * 6 w_c of exp(-|x - R_I - n L|^2 / (2 w_c^2)); d_feat is 3 x N_d float32,
+ * channel-major, grid order.  widths: 3 positive host doubles (Bohr). */
+sparc_status sparc_gpu_features(sparc_gpu_ctx ctx, const double* widths, float* d_feat);
+
+/* Network: a1 = relu(conv(W1, f) + b1) (3 -> 16), a2 = relu(conv(W2, a1) +
+ * b2) (16 -> 16), z = conv(W3, a2) + b3 (16 -> 1), 3x3x3 periodic
+ * cross-correlation; rho = N_e softplus(z) / (dV sum softplus(z)).
+ * d_w: SPARC_CNN_NPARAMS float32 in the order W1 (16,3,27), b1, W2 (16,16,27),
+ * b2, W3 (1,16,27), b3; tap k = 9 (dz+1) + 3 (dy+1) + (dx+1) for neighbour
+ * p + (dx, dy, dz).  d_act: caller scratch of 33 N_d float32 that keeps
+ * a1, a2, z for the backward pass.  d_rho: N_d float64 output. */
+#define SPARC_CNN_NPARAMS 8673
+sparc_status sparc_gpu_cnn_forward(sparc_gpu_ctx ctx, const float* d_w, const float* d_feat, float* d_act,
+                                   double* d_rho);
+
+/* Gradient of loss = mean_p (rho_p - target_p)^2 with respect to the
+ * parameters, from the forward pass's d_act and d_rho (same d_w, d_feat).
+ * d_grad: SPARC_CNN_NPARAMS float32 out; d_loss: one device double out (may
+ * be NULL).  Deterministic (fixed-order FP64 reductions). */
+sparc_status sparc_gpu_cnn_backward(sparc_gpu_ctx ctx, const float* d_w, const float* d_feat, const float* d_act,
+                                    const double* d_rho, const double* d_target, float* d_grad, double* d_loss);
+
+/* One Adam step (Kingma & Ba) on n float32 parameters with float32 moments
+ * d_m, d_v (start at zero); t >= 1 is the step count for bias correction. */
+sparc_status sparc_gpu_adam_step(sparc_gpu_ctx ctx, float* d_w, const float* d_grad, float* d_m, float* d_v, int n,
+                                 int t, double lr, double beta1, double beta2, double eps);
+
+/* Initial density for the SCF: the network's prediction with widths
+ * (0.5, 1.0, 2.0) Bohr, or the atomic-density guess (sparc_gpu_sad_density)
+ * when the prediction is not finite or dV sum |rho - rho_SAD| / N_e >
+ * max_l1.  *used_cnn (host, may be NULL) = 1 when the prediction was kept.
+ * Synchronises once. */
+sparc_status sparc_gpu_warm_start(sparc_gpu_ctx ctx, const float* d_w, double max_l1, double* d_rho, int* used_cnn);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,14 @@ EXPORTED = [
     "sparc_gpu_final_rr_fp64",
     "sparc_gpu_profile",
     "sparc_gpu_profile_read",
+    "sparc_gpu_features",
+    "sparc_gpu_cnn_forward",
+    "sparc_gpu_cnn_backward",
+    "sparc_gpu_adam_step",
+    "sparc_gpu_warm_start",
 ]
+
+CNN_NPARAMS = 8673
 
 
 class SparcError(RuntimeError):
@@ -158,6 +165,11 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_final_rr_fp64": ([vp, C.POINTER(SCFState), vp, l, C.POINTER(SCFReport)], i),
         "sparc_gpu_profile": ([vp, i], i),
         "sparc_gpu_profile_read": ([vp, i, C.POINTER(d), C.POINTER(l)], i),
+        "sparc_gpu_features": ([vp, C.POINTER(d), vp], i),
+        "sparc_gpu_cnn_forward": ([vp, vp, vp, vp, vp], i),
+        "sparc_gpu_cnn_backward": ([vp, vp, vp, vp, vp, vp, vp, vp], i),
+        "sparc_gpu_adam_step": ([vp, vp, vp, vp, vp, i, i, d, d, d, d], i),
+        "sparc_gpu_warm_start": ([vp, vp, d, vp, C.POINTER(i)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -306,6 +318,30 @@ class Context:
         ms, n = C.c_double(), C.c_long()
         self._check(self.lib.sparc_gpu_profile_read(self.h, int(kernel_id), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    # ---- learned initial density
+    def features(self, feat, widths=(0.5, 1.0, 2.0)):
+        """feat: (3, N_d) float32 device tensor."""
+        w = (C.c_double * 3)(*[float(x) for x in widths])
+        self._check(self.lib.sparc_gpu_features(self.h, w, _ptr(feat)))
+
+    def cnn_forward(self, w, feat, act, rho):
+        """w: (8673,) float32; feat: (3, N_d) float32; act: (33, N_d) float32
+        scratch; rho: (N_d,) float64 out."""
+        self._check(self.lib.sparc_gpu_cnn_forward(self.h, _ptr(w), _ptr(feat), _ptr(act), _ptr(rho)))
+
+    def cnn_backward(self, w, feat, act, rho, target, grad, loss=None):
+        self._check(self.lib.sparc_gpu_cnn_backward(self.h, _ptr(w), _ptr(feat), _ptr(act), _ptr(rho),
+                                                    _ptr(target), _ptr(grad), _ptr(loss)))
+
+    def adam_step(self, w, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.sparc_gpu_adam_step(self.h, _ptr(w), _ptr(grad), _ptr(m), _ptr(v), int(w.numel()),
+                                                 int(t), float(lr), float(beta1), float(beta2), float(eps)))
+
+    def warm_start(self, w, rho, max_l1=0.5) -> bool:
+        used = C.c_int(0)
+        self._check(self.lib.sparc_gpu_warm_start(self.h, _ptr(w), float(max_l1), _ptr(rho), C.byref(used)))
+        return bool(used.value)
 
     def final_rr_fp64(self, state: SCFState, X64) -> dict:
         rep = SCFReport()

@@ -1,0 +1,493 @@
+// Learned initial density for the SCF (the warm start that replaces the
+// superposition of atomic densities of Sec. 2.1 when it is close enough):
+// Gaussian atom features, a three-layer periodic 3x3x3 convolutional network
+// (3 -> 16 -> 16 -> 1 channels, ReLU, softplus output rescaled to N_e
+// electrons), its gradient for a mean-squared density loss, and Adam.
+//
+// Layouts: a field of C channels is C x N_d float32, channel-major, grid
+// order p = ix + nx (iy + ny iz).  Parameters are one flat float32 vector
+// W1 (16,3,27), b1 (16), W2 (16,16,27), b2 (16), W3 (1,16,27), b3 (1) with
+// tap index k = 9 (dz+1) + 3 (dy+1) + (dx+1) for the neighbour p + (dx,dy,dz):
+//   conv(W, u)[o, p] = b[o] + sum_i sum_k W[o, i, k] u[i, p + d(k)]
+// with periodic wrap.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace sg {
+
+namespace {
+
+constexpr int kT = 8;            // output tile edge
+constexpr int kH = kT + 2;       // input tile edge (one-point halo)
+constexpr int kTile = kT * kT * kT;
+constexpr int kHalo = kH * kH * kH;
+constexpr int kOff1 = 3 * 16 * 27;             // b1
+constexpr int kOff2 = kOff1 + 16;              // W2
+constexpr int kOff3 = kOff2 + 16 * 16 * 27;    // b2
+constexpr int kOff4 = kOff3 + 16;              // W3
+constexpr int kOff5 = kOff4 + 16 * 27;         // b3
+constexpr int kNParams = kOff5 + 1;
+static_assert(kNParams == 8673, "parameter count");
+
+struct Grid3 {
+    int nx, ny, nz, tx, ty, tz;   // grid and tile counts
+};
+
+__device__ inline int wrap(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Load the halo tile of C channels starting at grid point (x0-1, y0-1, z0-1).
+template <int C>
+__device__ inline void load_tile(float* tile, const float* __restrict__ u, long nd, const Grid3& g, int x0, int y0,
+                                 int z0) {
+    for (int q = threadIdx.x; q < C * kHalo; q += blockDim.x) {
+        const int c = q / kHalo, r = q - c * kHalo;
+        const int lz = r / (kH * kH), ly = (r / kH) % kH, lx = r % kH;
+        const int x = wrap(x0 + lx - 1, g.nx), y = wrap(y0 + ly - 1, g.ny), z = wrap(z0 + lz - 1, g.nz);
+        tile[q] = u[(long)c * nd + x + (long)g.nx * (y + (long)g.ny * z)];
+    }
+}
+
+__device__ inline void tile_origin(const Grid3& g, int& x0, int& y0, int& z0) {
+    int b = blockIdx.x;
+    const int bx = b % g.tx;
+    b /= g.tx;
+    const int by = b % g.ty;
+    const int bz = b / g.ty;
+    x0 = bx * kT;
+    y0 = by * kT;
+    z0 = bz * kT;
+}
+
+}  // namespace
+
+// MODE 0: out = act(conv(W, in) + b) with ReLU when RELU.
+// MODE 1: transposed: out[j, p] = mask[j, p] > 0 ? sum_o sum_k W[o, j, 26-k] in[o, p + d(k)] : 0
+//         (the input gradient of a forward layer with weights W (CO x CI),
+//          masked by that layer's ReLU input activation).
+template <int CI, int CO, int MODE, bool RELU>
+__global__ __launch_bounds__(512) void k_conv(const float* __restrict__ in, const float* __restrict__ W,
+                                              const float* __restrict__ bias, const float* __restrict__ mask,
+                                              float* __restrict__ out, Grid3 g) {
+    __shared__ float tile[CI * kHalo];
+    const long nd = (long)g.nx * g.ny * g.nz;
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    load_tile<CI>(tile, in, nd, g, x0, y0, z0);
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int lx = t % kT, ly = (t / kT) % kT, lz = t / (kT * kT);
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    float acc[CO];
+#pragma unroll
+    for (int o = 0; o < CO; ++o) acc[o] = (MODE == 0) ? bias[o] : 0.0f;
+    for (int i = 0; i < CI; ++i) {
+        const float* ti = tile + i * kHalo;
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+            const int dz = k / 9, dy = (k / 3) % 3, dx = k % 3;
+            const float v = ti[(lz + dz) * kH * kH + (ly + dy) * kH + (lx + dx)];
+#pragma unroll
+            for (int o = 0; o < CO; ++o) {
+                const float w = (MODE == 0) ? W[(o * CI + i) * 27 + k] : W[(i * CO + o) * 27 + (26 - k)];
+                acc[o] = fmaf(w, v, acc[o]);
+            }
+        }
+    }
+    const long p = x + (long)g.nx * (y + (long)g.ny * z);
+#pragma unroll
+    for (int o = 0; o < CO; ++o) {
+        float r = acc[o];
+        if (MODE == 0 && RELU) r = fmaxf(r, 0.0f);
+        if (MODE == 1) r = (mask[(long)o * nd + p] > 0.0f) ? r : 0.0f;
+        out[(long)o * nd + p] = r;
+    }
+}
+
+// Per-tile partial gradients of one layer: thread j < CI*27 owns the taps
+// (i = j / 27, k = j % 27) for every output channel, thread CI*27 + o owns
+// the bias of channel o.  part[tile][CO*CI*27 + CO] in the parameter order.
+template <int CI, int CO>
+__global__ __launch_bounds__(512) void k_wgrad(const float* __restrict__ u, const float* __restrict__ gr,
+                                               float* __restrict__ part, Grid3 g) {
+    extern __shared__ float lds_wg[];
+    float* ut = lds_wg;                 // CI * kHalo
+    float* gt = lds_wg + CI * kHalo;    // CO * kTile
+    const long nd = (long)g.nx * g.ny * g.nz;
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    load_tile<CI>(ut, u, nd, g, x0, y0, z0);
+    for (int q = threadIdx.x; q < CO * kTile; q += blockDim.x) {
+        const int o = q / kTile, r = q - o * kTile;
+        const int x = x0 + r % kT, y = y0 + (r / kT) % kT, z = z0 + r / (kT * kT);
+        gt[q] = (x < g.nx && y < g.ny && z < g.nz) ? gr[(long)o * nd + x + (long)g.nx * (y + (long)g.ny * z)] : 0.0f;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int np = CO * CI * 27 + CO;
+    float* pp = part + (long)blockIdx.x * np;
+    if (t < CI * 27) {
+        const int i = t / 27, k = t % 27;
+        const int dz = k / 9, dy = (k / 3) % 3, dx = k % 3;
+        const float* ui = ut + i * kHalo;
+        float acc[CO];
+#pragma unroll
+        for (int o = 0; o < CO; ++o) acc[o] = 0.0f;
+        for (int lz = 0; lz < kT; ++lz)
+            for (int ly = 0; ly < kT; ++ly)
+#pragma unroll 4
+                for (int lx = 0; lx < kT; ++lx) {
+                    const float v = ui[(lz + dz) * kH * kH + (ly + dy) * kH + (lx + dx)];
+                    const int r = (lz * kT + ly) * kT + lx;
+#pragma unroll
+                    for (int o = 0; o < CO; ++o) acc[o] = fmaf(gt[o * kTile + r], v, acc[o]);
+                }
+#pragma unroll
+        for (int o = 0; o < CO; ++o) pp[(o * CI + i) * 27 + k] = acc[o];
+    } else if (t < CI * 27 + CO) {
+        const int o = t - CI * 27;
+        float acc = 0.0f;
+        for (int r = 0; r < kTile; ++r) acc += gt[o * kTile + r];
+        pp[CO * CI * 27 + o] = acc;
+    }
+}
+
+// grad[off + j] = sum over tiles of part[tile][j] (FP64, fixed order).
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int ntiles, int np, float* __restrict__ grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    double s = 0.0;
+    for (int b = 0; b < ntiles; ++b) s += (double)part[(long)b * np + j];
+    grad[j] = (float)s;
+}
+
+__device__ inline double softplus_d(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
+__device__ inline double sigmoid_d(double z) { return 0.5 * (1.0 + tanh(0.5 * z)); }
+
+// Block partial sums (FP64) of up to 3 quantities; out[block * 3 + q].
+__device__ inline void block_reduce3(double a, double b, double c, double* out) {
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
+    red[0][t] = a;
+    red[1][t] = b;
+    red[2][t] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            red[0][t] += red[0][t + s];
+            red[1][t] += red[1][t + s];
+            red[2][t] += red[2][t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[blockIdx.x * 3 + 0] = red[0][0];
+        out[blockIdx.x * 3 + 1] = red[1][0];
+        out[blockIdx.x * 3 + 2] = red[2][0];
+    }
+}
+
+__global__ void k_reduce3_final(const double* part, int nblk, double* out) {
+    const int q = threadIdx.x;
+    if (q >= 3) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[b * 3 + q];
+    out[q] = s;
+}
+
+// sum of softplus(z)
+__global__ __launch_bounds__(256) void k_head_sum(const float* __restrict__ z, long n, double* part) {
+    double s = 0.0;
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x)
+        s += softplus_d((double)z[p]);
+    block_reduce3(s, 0.0, 0.0, part);
+}
+
+// rho = N_e softplus(z) / (dV S)
+__global__ void k_head_rho(const float* __restrict__ z, long n, const double* S, double scale,
+                           double* __restrict__ rho) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) rho[p] = scale * softplus_d((double)z[p]) / S[0];
+}
+
+// loss = sum (rho - t)^2 / n ; G = sum g s with g = 2 (rho - t) / n
+__global__ __launch_bounds__(256) void k_head_loss(const float* __restrict__ z, const double* __restrict__ rho,
+                                                   const double* __restrict__ tgt, long n, double* part) {
+    double l = 0.0, gs = 0.0;
+    const double inv = 1.0 / (double)n;
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) {
+        const double d = rho[p] - tgt[p];
+        l += d * d * inv;
+        gs += 2.0 * d * inv * softplus_d((double)z[p]);
+    }
+    block_reduce3(l, gs, 0.0, part);
+}
+
+// dz = (c g - (c / S) G) sigmoid(z),  c = N_e / (dV S)
+__global__ void k_head_dz(const float* __restrict__ z, const double* __restrict__ rho, const double* __restrict__ tgt,
+                          long n, const double* S, const double* LG, double ne_over_dv, float* __restrict__ dz) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double Sv = S[0];
+    const double cc = ne_over_dv / Sv;
+    const double g = 2.0 * (rho[p] - tgt[p]) / (double)n;
+    dz[p] = (float)((cc * g - cc / Sv * LG[1]) * sigmoid_d((double)z[p]));
+}
+
+// Gaussian features: channel c at p = sum over atoms and periodic images
+// within 6 w_c of exp(-r^2 / (2 w_c^2)).
+__global__ __launch_bounds__(256) void k_features(const double* __restrict__ pos, int na, double w0, double w1,
+                                                  double w2, int nx, int ny, int nz, double hx, double hy, double hz,
+                                                  double Lx, double Ly, double Lz, float* __restrict__ out) {
+    const long nd = (long)nx * ny * nz;
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nd) return;
+    const int ix = (int)(p % nx), iy = (int)((p / nx) % ny), iz = (int)(p / ((long)nx * ny));
+    const double X = ix * hx, Y = iy * hy, Z = iz * hz;
+    const double ws[3] = {w0, w1, w2};
+    for (int c = 0; c < 3; ++c) {
+        const double w = ws[c], rcut = 6.0 * w, rc2 = rcut * rcut, i2w2 = 1.0 / (2.0 * w * w);
+        const int Kx = (int)ceil((rcut + Lx) / Lx), Ky = (int)ceil((rcut + Ly) / Ly), Kz = (int)ceil((rcut + Lz) / Lz);
+        double acc = 0.0;
+        for (int a = 0; a < na; ++a) {
+            double Rx = fmod(pos[3 * a], Lx), Ry = fmod(pos[3 * a + 1], Ly), Rz = fmod(pos[3 * a + 2], Lz);
+            if (Rx < 0.0) Rx += Lx;
+            if (Ry < 0.0) Ry += Ly;
+            if (Rz < 0.0) Rz += Lz;
+            for (int i = -Kx; i <= Kx; ++i) {
+                const double dx = (X - Rx) - i * Lx;
+                if (fabs(dx) > rcut) continue;
+                for (int j = -Ky; j <= Ky; ++j) {
+                    const double dy = (Y - Ry) - j * Ly;
+                    if (fabs(dy) > rcut) continue;
+                    for (int k = -Kz; k <= Kz; ++k) {
+                        const double dz = (Z - Rz) - k * Lz;
+                        const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dz, dz), __dmul_rn(dy, dy)), __dmul_rn(dx, dx));
+                        if (r2 <= rc2) acc += exp(-r2 * i2w2);
+                    }
+                }
+            }
+        }
+        out[(long)c * nd + p] = (float)acc;
+    }
+}
+
+// Adam (Kingma & Ba) on float32 parameters, moments in float32, arithmetic
+// in FP64.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, double lr, double b1, double b2, double eps, double c1,
+                       double c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double gi = g[i];
+    const double mi = b1 * (double)m[i] + (1.0 - b1) * gi;
+    const double vi = b2 * (double)v[i] + (1.0 - b2) * gi * gi;
+    m[i] = (float)mi;
+    v[i] = (float)vi;
+    w[i] = (float)((double)w[i] - lr * (mi / c1) / (sqrt(vi / c2) + eps));
+}
+
+// dV sum |a - b| and the count of non-finite a (into part, then final).
+__global__ __launch_bounds__(256) void k_l1(const double* __restrict__ a, const double* __restrict__ b, long n,
+                                            double* part) {
+    double s = 0.0, bad = 0.0;
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) {
+        const double x = a[p];
+        if (!isfinite(x)) bad += 1.0;
+        else s += fabs(x - b[p]);
+    }
+    block_reduce3(s, bad, 0.0, part);
+}
+
+__global__ void k_copy_d(const double* a, double* b, long n) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) b[p] = a[p];
+}
+
+// ------------------------------------------------------------ host side
+
+static Grid3 grid3(sparc_gpu_ctx c) {
+    Grid3 g;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    g.tx = div_up(c->nx, kT);
+    g.ty = div_up(c->ny, kT);
+    g.tz = div_up(c->nz, kT);
+    return g;
+}
+
+static int ntiles(const Grid3& g) { return g.tx * g.ty * g.tz; }
+
+static sparc_status features_impl(sparc_gpu_ctx c, const double w[3], float* feat) {
+    for (int k = 0; k < 3; ++k)
+        if (!(w[k] > 0.0) || !std::isfinite(w[k])) return set_err(c, SPARC_ERR_ARG, "features: widths must be > 0");
+    if (c->n_atoms > 0 && !c->atom_pos) return set_err(c, SPARC_ERR_ARG, "features: no atoms");
+    k_features<<<div_up(c->nd, 256), 256, 0, c->stream>>>(c->atom_pos, c->n_atoms, w[0], w[1], w[2], c->nx, c->ny,
+                                                         c->nz, c->hx, c->hy, c->hz, c->Lx, c->Ly, c->Lz, feat);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+template <int CI, int CO>
+static size_t wgrad_lds() {
+    return (size_t)(CI * kHalo + CO * kTile) * sizeof(float);
+}
+
+// head scalars live in scal[S_CNN .. S_CNN+5]: S, -, -, loss, G, -
+static sparc_status forward_impl(sparc_gpu_ctx c, const float* w, const float* feat, float* act, double* rho) {
+    const Grid3 g = grid3(c);
+    const long nd = c->nd;
+    float* a1 = act;
+    float* a2 = act + 16 * nd;
+    float* z = act + 32 * nd;
+    const int nt = ntiles(g);
+    k_conv<3, 16, 0, true><<<nt, 512, 0, c->stream>>>(feat, w, w + kOff1, nullptr, a1, g);
+    k_conv<16, 16, 0, true><<<nt, 512, 0, c->stream>>>(a1, w + kOff2, w + kOff3, nullptr, a2, g);
+    k_conv<16, 1, 0, false><<<nt, 512, 0, c->stream>>>(a2, w + kOff4, w + kOff5, nullptr, z, g);
+    SG_CHECK_LAUNCH(c);
+    const int nblk = (int)std::min<long>(1024, div_up(nd, 256));
+    sparc_status st = ensure_red(c, 3 * (size_t)nblk);
+    if (st != SPARC_OK) return st;
+    k_head_sum<<<nblk, 256, 0, c->stream>>>(z, nd, c->red);
+    k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
+    k_head_rho<<<div_up(nd, 256), 256, 0, c->stream>>>(z, nd, c->scal + S_CNN, c->n_electrons / c->dV, rho);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+static sparc_status ensure_cnn(sparc_gpu_ctx c, size_t floats) {
+    return ensure_work(c, floats * sizeof(float));
+}
+
+static sparc_status backward_impl(sparc_gpu_ctx c, const float* w, const float* feat, const float* act,
+                                  const double* rho, const double* tgt, float* grad, double* loss) {
+    const Grid3 g = grid3(c);
+    const long nd = c->nd;
+    const float* a1 = act;
+    const float* a2 = act + 16 * nd;
+    const float* z = act + 32 * nd;
+    const int nt = ntiles(g);
+    const int np1 = 16 * 3 * 27 + 16, np2 = 16 * 16 * 27 + 16, np3 = 16 * 27 + 1;
+    // scratch: dz (nd), d2 (16 nd), d1 (16 nd), partials (nt * np2)
+    const size_t need = 33 * (size_t)nd + (size_t)nt * np2;
+    sparc_status st = ensure_cnn(c, need);
+    if (st != SPARC_OK) return st;
+    float* dz = (float*)c->work;
+    float* d2 = dz + nd;
+    float* d1 = d2 + 16 * nd;
+    float* part = d1 + 16 * nd;
+    const int nblk = (int)std::min<long>(1024, div_up(nd, 256));
+    if ((st = ensure_red(c, 3 * (size_t)nblk)) != SPARC_OK) return st;
+    // the forward's softplus sum is recomputed so that backward depends only
+    // on its arguments
+    k_head_sum<<<nblk, 256, 0, c->stream>>>(z, nd, c->red);
+    k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
+    k_head_loss<<<nblk, 256, 0, c->stream>>>(z, rho, tgt, nd, c->red);
+    k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN + 3);
+    k_head_dz<<<div_up(nd, 256), 256, 0, c->stream>>>(z, rho, tgt, nd, c->scal + S_CNN, c->scal + S_CNN + 3,
+                                                      c->n_electrons / c->dV, dz);
+    SG_CHECK_LAUNCH(c);
+    // layer 3
+    k_wgrad<16, 1><<<nt, 512, wgrad_lds<16, 1>(), c->stream>>>(a2, dz, part, g);
+    k_wgrad_reduce<<<div_up(np3, 256), 256, 0, c->stream>>>(part, nt, np3, grad + kOff4);
+    k_conv<1, 16, 1, false><<<nt, 512, 0, c->stream>>>(dz, w + kOff4, nullptr, a2, d2, g);
+    // layer 2
+    k_wgrad<16, 16><<<nt, 512, wgrad_lds<16, 16>(), c->stream>>>(a1, d2, part, g);
+    k_wgrad_reduce<<<div_up(np2, 256), 256, 0, c->stream>>>(part, nt, np2, grad + kOff2);
+    k_conv<16, 16, 1, false><<<nt, 512, 0, c->stream>>>(d2, w + kOff2, nullptr, a1, d1, g);
+    // layer 1
+    k_wgrad<3, 16><<<nt, 512, wgrad_lds<3, 16>(), c->stream>>>(feat, d1, part, g);
+    k_wgrad_reduce<<<div_up(np1, 256), 256, 0, c->stream>>>(part, nt, np1, grad);
+    SG_CHECK_LAUNCH(c);
+    if (loss)
+        SG_HIP(c, hipMemcpyAsync(loss, c->scal + S_CNN + 3, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return SPARC_OK;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+sparc_status sparc_gpu_features(sparc_gpu_ctx c, const double* widths, float* d_feat) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!widths || !d_feat) return set_err(c, SPARC_ERR_ARG, "features: null pointer");
+    return features_impl(c, widths, d_feat);
+}
+
+sparc_status sparc_gpu_cnn_forward(sparc_gpu_ctx c, const float* d_w, const float* d_feat, float* d_act,
+                                   double* d_rho) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_w || !d_feat || !d_act || !d_rho) return set_err(c, SPARC_ERR_ARG, "cnn_forward: null pointer");
+    return forward_impl(c, d_w, d_feat, d_act, d_rho);
+}
+
+sparc_status sparc_gpu_cnn_backward(sparc_gpu_ctx c, const float* d_w, const float* d_feat, const float* d_act,
+                                    const double* d_rho, const double* d_target, float* d_grad, double* d_loss) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_w || !d_feat || !d_act || !d_rho || !d_target || !d_grad)
+        return set_err(c, SPARC_ERR_ARG, "cnn_backward: null pointer");
+    return backward_impl(c, d_w, d_feat, d_act, d_rho, d_target, d_grad, d_loss);
+}
+
+sparc_status sparc_gpu_adam_step(sparc_gpu_ctx c, float* d_w, const float* d_grad, float* d_m, float* d_v, int n,
+                                 int t, double lr, double beta1, double beta2, double eps) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_w || !d_grad || !d_m || !d_v) return set_err(c, SPARC_ERR_ARG, "adam_step: null pointer");
+    if (n < 1 || t < 1) return set_err(c, SPARC_ERR_ARG, "adam_step: n and t must be >= 1");
+    if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return set_err(c, SPARC_ERR_ARG, "adam_step: bad hyper-parameters");
+    const double c1 = 1.0 - std::pow(beta1, t), c2 = 1.0 - std::pow(beta2, t);
+    k_adam<<<div_up(n, 256), 256, 0, c->stream>>>(d_w, d_grad, d_m, d_v, n, lr, beta1, beta2, eps, c1, c2);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+sparc_status sparc_gpu_warm_start(sparc_gpu_ctx c, const float* d_w, double max_l1, double* d_rho, int* used_cnn) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_w || !d_rho) return set_err(c, SPARC_ERR_ARG, "warm_start: null pointer");
+    if (!(max_l1 >= 0.0)) return set_err(c, SPARC_ERR_ARG, "warm_start: max_l1 must be >= 0");
+    const long nd = c->nd;
+    // scratch: features (3 nd) + activations (33 nd) floats, SAD in field 0
+    sparc_status st = ensure_cnn(c, 36 * (size_t)nd);
+    if (st != SPARC_OK) return st;
+    if ((st = ensure_fields(c, 6)) != SPARC_OK) return st;
+    float* feat = (float*)c->work;
+    float* act = feat + 3 * nd;
+    double* sad = c->field;
+    const double widths[3] = {0.5, 1.0, 2.0};
+    if ((st = features_impl(c, widths, feat)) != SPARC_OK) return st;
+    if ((st = forward_impl(c, d_w, feat, act, d_rho)) != SPARC_OK) return st;
+    if ((st = sparc_gpu_sad_density(c, sad)) != SPARC_OK) return st;
+    const int nblk = (int)std::min<long>(1024, div_up(nd, 256));
+    if ((st = ensure_red(c, 3 * (size_t)nblk)) != SPARC_OK) return st;
+    k_l1<<<nblk, 256, 0, c->stream>>>(d_rho, sad, nd, c->red);
+    k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
+    SG_CHECK_LAUNCH(c);
+    double h[3];
+    SG_HIP(c, hipMemcpyAsync(h, c->scal + S_CNN, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    const double l1 = c->dV * h[0] / c->n_electrons;
+    const bool ok = (h[1] == 0.0) && std::isfinite(l1) && l1 <= max_l1;
+    if (!ok) {
+        k_copy_d<<<div_up(nd, 256), 256, 0, c->stream>>>(sad, d_rho, nd);
+        SG_CHECK_LAUNCH(c);
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    if (used_cnn) *used_cnn = ok ? 1 : 0;
+    return SPARC_OK;
+}
+
+}  // extern "C"

@@ -174,6 +174,7 @@ enum Scalar {
     S_RED0 = 8,                      // grid reductions (6 slots)
     S_OCC = 16,                      // mu, entropy term, band energy
     S_EIG = 22,                      // eigensolver norms (2 slots)
+    S_CNN = 32,                      // warm-start network head sums (6 slots)
     S_COUNT = 64
 };
 enum Flag {

@@ -13,7 +13,8 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
     """Run the SCF iteration on the GPU.
 
     X0: (N_s, N_d) numpy array (random block, see ``workloads.initial_orbitals``);
-    rho0: (N_d,) numpy array or None for the atomic-density guess.
+    rho0: (N_d,) numpy array or float64 tensor, or None for the atomic-density
+    guess.
     Returns a dict with the history of reports and the final device tensors."""
     import torch
     ctx = ctx or Context(system)
@@ -27,7 +28,8 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
     if rho0 is None:
         ctx.sad_density(rho_in)
     else:
-        rho_in.copy_(torch.as_tensor(np.asarray(rho0), dtype=torch.float64))
+        src = rho0 if isinstance(rho0, torch.Tensor) else torch.as_tensor(np.asarray(rho0), dtype=torch.float64)
+        rho_in.copy_(src)
     eig = torch.empty(ns, dtype=torch.float64, device=device)
     occ = torch.empty(ns, dtype=torch.float64, device=device)
     rho_out = torch.empty(nd, dtype=torch.float64, device=device)

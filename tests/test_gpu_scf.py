@@ -128,16 +128,21 @@ def test_scf_cfg2_fixed_point():
     mu_o, g_o = scf.occupations(lam, s.n_electrons, s.kT)
     assert np.max(np.abs(g - g_o)) <= 1e-10
     # eigenpairs of the oracle's Hamiltonian at the GPU's input density
+    # fully occupied states are converged eigenvectors; the highest partly
+    # occupied state sits next to the filter's cut a, where one Chebyshev
+    # pass per SCF step damps unwanted components slowest, so its bar is
+    # looser
+    n_full = int(np.sum(g > 1.9))
     n_occ = int(np.sum(g > 1e-3))
-    cols = sorted(set([0, 1, n_occ // 2, n_occ - 1]))
+    cols = sorted(set([0, 1, n_full // 2, n_full - 1, n_occ - 1]))
     Xh = to_np(X[cols])
     HX = hamiltonian.apply_H(s, veff, st_o.projs, Xh)
     for j, c in enumerate(cols):
         r = np.linalg.norm(HX[j] - lam[c] * Xh[j]) / np.linalg.norm(Xh[j])
         nrm = s.dV * float(Xh[j] @ Xh[j])
-        log(f"  state {c}: lambda {lam[c]:.10f} residual {r:.2e} h^3|x|^2 {nrm:.15f}")
+        log(f"  state {c} (g = {g[c]:.3f}): lambda {lam[c]:.10f} residual {r:.2e} h^3|x|^2 {nrm:.15f}")
         assert abs(nrm - 1.0) <= 1e-10
-        assert r <= 1e-4
+        assert r <= (1e-6 if c < n_full else 1e-3)
     # density from the GPU's orbitals and occupations, by the oracle
     rho_o = np.zeros(nd)
     for c0 in range(0, ns, 32):
