@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+COPY_BYTES = 1 << 31
 
 WORKLOADS = {
     "cfg2": "cfg2: L=20 Bohr, 72^3 grid, 108 atoms (FCC 3^3, jitter 0.1), Z=4, s+p KB projectors, "
@@ -83,6 +84,83 @@ def cpu_baseline(system, ncols: int, degree: int, bounds):
     }
 
 
+def traffic_probe(system, prec):
+    """One degree-3 Chebyshev filter (one first sweep, two later sweeps) of
+    the full block, then an elementwise copy of COPY_BYTES bytes; each step is
+    announced on stdout before it runs."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2005_10431_amd import Context
+
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ctx = Context(system)
+    nd, ns = system.nd, system.n_states
+    v = torch.as_tensor(np.random.default_rng(7).uniform(-0.5, 0.5, nd)).cuda()
+    ctx.set_veff(v)
+    lo, hi = ctx.spectrum_bounds()
+    X = torch.as_tensor(W.initial_orbitals(nd, ns, 0)).to(dt).cuda()
+    Wk = torch.empty_like(X)
+    print(f"probe: filter degree 3, {ns} columns, {prec}", flush=True)
+    ctx.chebyshev_filter(X, Wk, 3, 0.5 * (lo + hi), hi, lo)
+    torch.cuda.synchronize()
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    print(f"probe: copy of {COPY_BYTES} bytes (read) + {COPY_BYTES} bytes (write)", flush=True)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print("probe: done", flush=True)
+
+
+def cnn_measure(steps: int = 10):
+    """Forward pass of the warm-start network on the 72^3 snapshot grid:
+    average time per forward and of its 16 -> 16 convolution, against the
+    FP32 vector peak (the convolutions are plain FMA work)."""
+    import torch
+
+    import workloads as W
+    from paper_2005_10431_amd import Context
+
+    s = W.config5_snapshot(200)
+    ctx = Context(s)
+    feat = torch.empty((3, s.nd), dtype=torch.float32, device="cuda")
+    ctx.features(feat)
+    w = torch.as_tensor(W.cnn_initial_weights(0)).cuda()
+    act = torch.empty((33, s.nd), dtype=torch.float32, device="cuda")
+    rho = torch.empty(s.nd, dtype=torch.float64, device="cuda")
+    tgt = rho.clone()
+    grad = torch.empty_like(w)
+    ctx.cnn_forward(w, feat, act, rho)
+    ctx.cnn_backward(w, feat, act, rho, tgt, grad)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for k in (16, 17, 18):
+        ctx.profile_read(k)
+    for _ in range(steps):
+        ctx.cnn_forward(w, feat, act, rho)
+        ctx.cnn_backward(w, feat, act, rho, tgt, grad)
+    torch.cuda.synchronize()
+    fwd_ms, n = ctx.profile_read(16)
+    c2_ms, n2 = ctx.profile_read(17)
+    bwd_ms, n3 = ctx.profile_read(18)
+    ctx.profile(False)
+    ctx.close()
+    flop_fwd = 2.0 * s.nd * 27 * (3 * 16 + 16 * 16 + 16 * 1)
+    flop_c2 = 2.0 * s.nd * 27 * 16 * 16
+    c2 = c2_ms / n2
+    return {
+        "workload": "warm-start network forward, 72^3 grid (3 -> 16 -> 16 -> 1 channels, 3x3x3 periodic), FP32",
+        "forward_ms": fwd_ms / n,
+        "backward_ms": bwd_ms / n3,
+        "forward_gflop": flop_fwd / 1e9,
+        "roofline": {"kernel": "k_conv<16, 16, forward, relu>", "bound": "alu",
+                     "achieved": flop_c2 / (c2 * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flop_c2 / (c2 * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, "avg_launch_ms": c2,
+                     "algorithmic_flop_per_launch": flop_c2},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,8 +168,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--cpu-cols", type=int, default=3, help="columns in the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-cols", type=int, default=40, help="columns in the CPU oracle sample (0: skip)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-filter companion measurement")
+    ap.add_argument("--no-cnn", action="store_true", help="skip the warm-start network measurement")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run only one degree-3 filter of the workload and a plain copy of known size "
+                         "(the program profiled with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -107,6 +189,9 @@ def main():
 
     system = {"cfg1": W.config1, "cfg2": W.config2, "cfg4": W.config4}[args.workload](0)
     nd, ns, m = system.nd, system.n_states, system.cheb_degree
+    if args.traffic_probe:
+        traffic_probe(system, args.prec)
+        return
 
     def run(prec, steps, warmup, profile):
         dt = torch.float64 if prec == "fp64" else torch.float32
@@ -210,6 +295,8 @@ def main():
         line["fp32"] = {"filter_gbs": r32["filter_gbs"], "ms_per_step": r32["ms_per_step"],
                         "scf_step_breakdown_ms": {k: r32[k] for k in ("t_potential_ms", "t_filter_ms",
                                                                        "t_rr_ms", "t_density_ms")}}
+    if not args.no_cnn:
+        line["warm_start_cnn"] = cnn_measure()
     if args.cpu_cols > 0:
         line["cpu_baseline"] = cpu_baseline(system, args.cpu_cols, m, res["bounds"])
     print(json.dumps(line), flush=True)

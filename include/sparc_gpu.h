@@ -241,7 +241,8 @@ sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st,
  * 9 subspace eigensolver (all its launches, host waits included),
  * 10 small N_s x N_s products, 11 block copy-back, 12 tridiagonalisation,
  * 13 tridiagonal eigenvalues, 14 inverse iteration, 15 back-transformation
- * (12-15 are the phases inside 9); ids < 16. */
+ * (12-15 are the phases inside 9), 16 warm-start network forward,
+ * 17 its 16 -> 16 convolution, 18 network gradient; ids < 32. */
 sparc_status sparc_gpu_profile(sparc_gpu_ctx ctx, int enable);
 sparc_status sparc_gpu_profile_read(sparc_gpu_ctx ctx, int kernel_id, double* total_ms, long* launches);
 

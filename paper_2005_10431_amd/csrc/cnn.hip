@@ -347,8 +347,11 @@ static sparc_status forward_impl(sparc_gpu_ctx c, const float* w, const float* f
     float* a2 = act + 16 * nd;
     float* z = act + 32 * nd;
     const int nt = ntiles(g);
+    const int slot = prof_begin(c, PK_CNN_FWD);
     k_conv<3, 16, 0, true><<<nt, 512, 0, c->stream>>>(feat, w, w + kOff1, nullptr, a1, g);
+    const int slot2 = prof_begin(c, PK_CNN_CONV2);
     k_conv<16, 16, 0, true><<<nt, 512, 0, c->stream>>>(a1, w + kOff2, w + kOff3, nullptr, a2, g);
+    prof_end(c, slot2);
     k_conv<16, 1, 0, false><<<nt, 512, 0, c->stream>>>(a2, w + kOff4, w + kOff5, nullptr, z, g);
     SG_CHECK_LAUNCH(c);
     const int nblk = (int)std::min<long>(1024, div_up(nd, 256));
@@ -358,6 +361,7 @@ static sparc_status forward_impl(sparc_gpu_ctx c, const float* w, const float* f
     k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
     k_head_rho<<<div_up(nd, 256), 256, 0, c->stream>>>(z, nd, c->scal + S_CNN, c->n_electrons / c->dV, rho);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     return SPARC_OK;
 }
 
@@ -384,6 +388,7 @@ static sparc_status backward_impl(sparc_gpu_ctx c, const float* w, const float* 
     float* part = d1 + 16 * nd;
     const int nblk = (int)std::min<long>(1024, div_up(nd, 256));
     if ((st = ensure_red(c, 3 * (size_t)nblk)) != SPARC_OK) return st;
+    const int slot = prof_begin(c, PK_CNN_BWD);
     // the forward's softplus sum is recomputed so that backward depends only
     // on its arguments
     k_head_sum<<<nblk, 256, 0, c->stream>>>(z, nd, c->red);
@@ -405,6 +410,7 @@ static sparc_status backward_impl(sparc_gpu_ctx c, const float* w, const float* 
     k_wgrad<3, 16><<<nt, 512, wgrad_lds<3, 16>(), c->stream>>>(feat, d1, part, g);
     k_wgrad_reduce<<<div_up(np1, 256), 256, 0, c->stream>>>(part, nt, np1, grad);
     SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
     if (loss)
         SG_HIP(c, hipMemcpyAsync(loss, c->scal + S_CNN + 3, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     return SPARC_OK;

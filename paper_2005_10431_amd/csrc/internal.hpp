@@ -142,8 +142,8 @@ struct sparc_gpu_ctx_s {
     std::vector<hipEvent_t> prof_pool;        // 2 events per recorded launch
     std::vector<int> prof_kernel;             // kernel id per recorded launch
     int prof_used = 0;
-    double prof_ms[16] = {0};
-    long prof_n[16] = {0};
+    double prof_ms[32] = {0};   // indexed by sg::ProfKernel
+    long prof_n[32] = {0};
 };
 
 namespace sg {
@@ -243,8 +243,12 @@ enum ProfKernel {
     PK_EIG_BIS = 13, // eigensolver: eigenvalues of the tridiagonal matrix
     PK_EIG_VEC = 14, // eigensolver: inverse iteration
     PK_EIG_BACK = 15,// eigensolver: back-transformation
-    PK_COUNT = 16
+    PK_CNN_FWD = 16, // warm-start network forward (all launches)
+    PK_CNN_CONV2 = 17,  // its 16 -> 16 convolution
+    PK_CNN_BWD = 18, // network gradient (all launches)
+    PK_COUNT = 32    // size of the per-context timing tables
 };
+static_assert(PK_COUNT == sizeof(sparc_gpu_ctx_s::prof_n) / sizeof(long), "timing table size");
 int prof_begin(sparc_gpu_ctx c, int kernel);
 void prof_end(sparc_gpu_ctx c, int slot);
 
