@@ -543,6 +543,9 @@ sparc_status build_tables(sparc_gpu_ctx c) {
         std::vector<long> sup_off(c->n_atoms + 1, 0);
         std::vector<int> sup_idx, sup_atom, img_off(1, 0), img_ijk;
         std::vector<std::pair<long, uint32_t>> img_pts;  // (flat point, packed atom/image)
+        std::vector<long> ip_off(c->n_atoms + 1, 0);
+        std::vector<int> ip_idx, box_lo(3 * (size_t)c->n_atoms);
+        std::vector<uint32_t> ip_box;
         bool image_overflow = false;
         const double rcut = c->rcut_nl, r2max = rcut * rcut;
         const double h[3] = {c->hx, c->hy, c->hz};
@@ -582,6 +585,16 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             }
             std::stable_sort(pts.begin(), pts.end(),
                              [](const auto& A, const auto& B) { return A.first < B.first; });
+            for (int d = 0; d < 3; ++d) {
+                box_lo[3 * a + d] = lo[d];
+                T.box_ext = std::max(T.box_ext, hi[d] - lo[d] + 1);
+            }
+            for (auto& q : pts) {
+                ip_idx.push_back((int)q.first);
+                ip_box.push_back((uint32_t)(q.second[0] - lo[0]) | ((uint32_t)(q.second[1] - lo[1]) << 8) |
+                                 ((uint32_t)(q.second[2] - lo[2]) << 16));
+            }
+            ip_off[a + 1] = (long)ip_idx.size();
             long prev = -1;
             for (auto& q : pts) {
                 if (q.first != prev) {
@@ -618,10 +631,8 @@ sparc_status build_tables(sparc_gpu_ctx c) {
                 c->nl_ty = ty;
                 st = build_slab_tables(c, ent);
                 const size_t KM = c->nl.slab_kmax;
-                const size_t lds = (2 * (size_t)(ty + 2 * kMaxHalfOrder) * (c->nx + 2 * kMaxHalfOrder) + 7 * KM +
-                                    KM * c->nl.slab_xw + ty * KM + KM * c->nl.slab_zw + 4 * ty * KM) *
-                                       sizeof(double) +
-                                   2 * KM * sizeof(int);
+                const size_t lds =
+                    nl_sweep_lds_bytes(ty, c->nx, KM, c->nl.slab_xw, c->nl.slab_zw, sizeof(double));
                 if (st == SPARC_OK && lds <= 160 * 1024) break;
                 if (ty <= 2) return st != SPARC_OK ? st : set_err(c, SPARC_ERR_ARG, "projector tables exceed LDS");
                 for (void* p : {(void*)T.pe8, (void*)T.slab_cand, (void*)T.slab_k})
@@ -672,6 +683,11 @@ sparc_status build_tables(sparc_gpu_ctx c) {
         }
         int *d_img_off = nullptr, *d_img_ijk = nullptr, *d_sup_atom = nullptr, *d_pt_src = nullptr;
         double* d_pos = nullptr;
+        if (T.box_ext > 255) return set_err(c, SPARC_ERR_ARG, "projector support box wider than 255 points");
+        if ((st = upload(c, &T.ip_off, ip_off)) != SPARC_OK) return st;
+        if ((st = upload(c, &T.ip_idx, ip_idx)) != SPARC_OK) return st;
+        if ((st = upload(c, &T.ip_box, ip_box)) != SPARC_OK) return st;
+        if ((st = upload(c, &T.box_lo, box_lo)) != SPARC_OK) return st;
         if ((st = upload(c, &T.sup_off, sup_off)) != SPARC_OK) return st;
         if ((st = upload(c, &T.sup_idx, sup_idx)) != SPARC_OK) return st;
         if ((st = upload(c, &T.pt_off, pt_off)) != SPARC_OK) return st;
@@ -844,7 +860,8 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
                     c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,
                     c->nl.sup_idx, c->nl.sup_chi, c->nl.sup_chi32, c->nl.pt_off, c->nl.pt_atom, c->nl.pt_chi,
                     c->nl.pt_chi32, c->nl.gamma4, c->nl.atom_order, c->nl.pe_off, c->nl.pe_ent, c->atom_pos,
-                    c->nl.pe8, c->nl.slab_cand, c->nl.slab_k};
+                    c->nl.pe8, c->nl.slab_cand, c->nl.slab_k, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box,
+                    c->nl.box_lo};
     for (void* p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < 8; ++i)

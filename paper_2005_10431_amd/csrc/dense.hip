@@ -16,38 +16,100 @@ namespace sg {
 // numerically rank-deficient block (about 64 units of rounding).
 constexpr double kPivotRtol = 64.0 * 2.220446049250313e-16;
 
-// Right-looking Cholesky M = L L^T in place (lower triangle), one workgroup.
-// flag[0] is set on a non-positive (relative) pivot or a non-finite entry.
-__global__ __launch_bounds__(1024) void k_cholesky(double* M, int N, int* flag) {
-    extern __shared__ double dorig[];
+// Blocked Cholesky M = L L^T in place (lower triangle), one workgroup.
+// Panels of jb columns are loaded into LDS, factored there column by column
+// (left-looking inside the panel), written back, and the trailing lower
+// triangle receives one rank-jb update per panel (each element read and
+// written once per panel).  flag[0] is set on a non-positive (relative)
+// pivot or a non-finite entry.
+__global__ __launch_bounds__(1024) void k_cholesky(double* M, int N, int jbmax, int* flag) {
+    extern __shared__ double sh[];
+    double* dorig = sh;            // N original diagonal entries
+    double* P = sh + N;            // panel: (N - j0) rows x jb columns, row-major
     __shared__ int bad;
+    __shared__ double piv;
     const int t = threadIdx.x, nt = blockDim.x;
     for (int i = t; i < N; i += nt) dorig[i] = M[i + (long)i * N];
     if (t == 0) bad = 0;
     __syncthreads();
-    for (int j = 0; j < N; ++j) {
-        if (t == 0) {
-            double d = M[j + (long)j * N];
-            if (!(d > kPivotRtol * dorig[j]) || !isfinite(d)) {
-                bad = 1;
-            } else {
-                M[j + (long)j * N] = sqrt(d);
+    for (int j0 = 0; j0 < N; j0 += jbmax) {
+        const int jb = min(jbmax, N - j0);
+        const int nr = N - j0;
+        for (int q = t; q < nr * jb; q += nt) {
+            const int r = q / jb, p = q - r * jb;
+            P[q] = M[(j0 + r) + (long)(j0 + p) * N];
+        }
+        __syncthreads();
+        for (int p = 0; p < jb; ++p) {
+            // column p of the panel minus the earlier panel columns
+            for (int r = p + t; r < nr; r += nt) {
+                double v = P[r * jb + p];
+                for (int q = 0; q < p; ++q) v -= P[r * jb + q] * P[p * jb + q];
+                P[r * jb + p] = v;
             }
+            __syncthreads();
+            if (t == 0) {
+                const double d = P[p * jb + p];
+                if (!(d > kPivotRtol * dorig[j0 + p]) || !isfinite(d)) {
+                    bad = 1;
+                } else {
+                    piv = sqrt(d);
+                }
+            }
+            __syncthreads();
+            if (bad) {
+                if (t == 0) flag[0] = 1;
+                return;
+            }
+            const double ljj = piv, inv = 1.0 / ljj;
+            for (int r = p + t; r < nr; r += nt) P[r * jb + p] = (r == p) ? ljj : P[r * jb + p] * inv;
+            __syncthreads();
         }
-        __syncthreads();
-        if (bad) {
-            if (t == 0) flag[0] = 1;
-            return;
+        for (int q = t; q < nr * jb; q += nt) {
+            const int r = q / jb, p = q - r * jb;
+            M[(j0 + r) + (long)(j0 + p) * N] = P[q];
         }
-        const double ljj = M[j + (long)j * N];
-        for (int i = j + 1 + t; i < N; i += nt) M[i + (long)j * N] /= ljj;
-        __syncthreads();
-        const int nr = N - j - 1;
-        const long tot = (long)nr * nr;
-        for (long f = t; f < tot; f += nt) {
-            int i = j + 1 + (int)(f % nr);
-            int k = j + 1 + (int)(f / nr);
-            if (k <= i) M[i + (long)k * N] -= M[i + (long)j * N] * M[k + (long)j * N];
+        // trailing update of the lower triangle: rows i >= k >= j0 + jb
+        const int k0 = j0 + jb;
+        const int m = N - k0;
+        if (m > 0) {
+            const int R = ((m + 63) / 64) * 64;
+            const int G = max(1, min(16, nt / R));
+            const int TPG = ((nt / G) / 64) * 64;
+            const int grp = t / TPG, lr0 = t - grp * TPG;
+            if (grp < G) {
+                for (int lr = lr0; lr < m; lr += TPG) {
+                    const int i = k0 + lr;
+                    const double* Pi = P + (i - j0) * jb;
+                    int k = k0 + grp;
+                    for (; k + 3 * G <= i; k += 4 * G) {
+                        double* a0 = M + i + (long)k * N;
+                        double x0 = a0[0], x1 = a0[(long)G * N], x2 = a0[(long)2 * G * N], x3 = a0[(long)3 * G * N];
+                        const double* P0 = P + (k - j0) * jb;
+                        const double* P1 = P0 + G * jb;
+                        const double* P2 = P1 + G * jb;
+                        const double* P3 = P2 + G * jb;
+                        for (int q = 0; q < jb; ++q) {
+                            const double pi = Pi[q];
+                            x0 -= pi * P0[q];
+                            x1 -= pi * P1[q];
+                            x2 -= pi * P2[q];
+                            x3 -= pi * P3[q];
+                        }
+                        a0[0] = x0;
+                        a0[(long)G * N] = x1;
+                        a0[(long)2 * G * N] = x2;
+                        a0[(long)3 * G * N] = x3;
+                    }
+                    for (; k <= i; k += G) {
+                        double* a0 = M + i + (long)k * N;
+                        double x0 = a0[0];
+                        const double* P0 = P + (k - j0) * jb;
+                        for (int q = 0; q < jb; ++q) x0 -= Pi[q] * P0[q];
+                        a0[0] = x0;
+                    }
+                }
+            }
         }
         __syncthreads();
     }
@@ -60,7 +122,10 @@ __global__ __launch_bounds__(1024) void k_cholesky(double* M, int N, int* flag) 
 
 sparc_status dense_cholesky(sparc_gpu_ctx c, double* M, int N, int* flag) {
     const int slot = prof_begin(c, PK_CHOL);
-    k_cholesky<<<1, 1024, N * sizeof(double), c->stream>>>(M, N, flag);
+    // panel width: the panel (N x jb) and the original diagonal fit in LDS
+    const int jb = std::max(1, std::min(16, (int)((120 * 1024) / (8 * (size_t)N))));
+    const size_t lds = ((size_t)N + (size_t)N * jb) * sizeof(double);
+    k_cholesky<<<1, 1024, lds, c->stream>>>(M, N, jb, flag);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
     return SPARC_OK;

@@ -9,6 +9,8 @@
 // All matrices are N x N column-major with leading dimension N.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -273,6 +275,14 @@ __global__ __launch_bounds__(64) void k_bisect(const double* d, const double* e,
     }
 }
 
+// Start vector of inverse iteration for eigenvalue k: a fixed,
+// index-dependent pattern in [0.5, 1.5) (a low-discrepancy sequence; any
+// vector with a component along the wanted eigenvector works).
+__device__ inline double start_value(int i, int k) {
+    const double u = i * 0.6180339887498949 + (k + 1) * 0.7548776662466927;
+    return 0.5 + (u - floor(u));
+}
+
 // Inverse iteration for the eigenvectors of T, one thread per cluster of
 // close eigenvalues (consecutive indices whose gaps are below 1e-3 ||T||);
 // members of a cluster are shifted apart by a few ulps and Gram-Schmidt
@@ -304,7 +314,7 @@ __global__ __launch_bounds__(64) void k_stein(const double* d, const double* e, 
         double x = lam[k];
         if (k > k0 && x - prev < sep) x = prev + sep;
         prev = x;
-        // LU with partial pivoting of T - x I
+        // LU with partial pivoting of T - x I (one reciprocal per pivot)
         double a = d[0] - x, b = (N > 1) ? e[0] : 0.0;
         for (int i = 0; i < N - 1; ++i) {
             const double c = e[i];
@@ -312,18 +322,20 @@ __global__ __launch_bounds__(64) void k_stein(const double* d, const double* e, 
             const double bn = (i + 2 < N) ? e[i + 1] : 0.0;
             if (fabs(a) >= fabs(c)) {
                 if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
-                const double l = c / a;
+                const double r = 1.0 / a;
+                const double l = c * r;
                 SG_AT(lo, i) = l;
-                SG_AT(rd, i) = 1.0 / a;
+                SG_AT(rd, i) = r;
                 SG_AT(u1, i) = b;
                 SG_AT(u2, i) = 0.0;
                 SG_AT(pv, i) = 0.0;
                 a = dn - l * b;
                 b = bn;
             } else {
-                const double l = a / c;
+                const double r = 1.0 / c;
+                const double l = a * r;
                 SG_AT(lo, i) = l;
-                SG_AT(rd, i) = 1.0 / c;
+                SG_AT(rd, i) = r;
                 SG_AT(u1, i) = dn;
                 SG_AT(u2, i) = bn;
                 SG_AT(pv, i) = 1.0;
@@ -333,12 +345,33 @@ __global__ __launch_bounds__(64) void k_stein(const double* d, const double* e, 
         }
         if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
         SG_AT(rd, N - 1) = 1.0 / a;
-        // start vector: a fixed, index-dependent pattern
-        for (int i = 0; i < N; ++i) SG_Z(i, k) = 1.0 + 0.1 * sin(1.3 * i + 0.7 * (k + 1));
+        for (int i = 0; i < N; ++i) SG_Z(i, k) = start_value(i, k);
         for (int it = 0; it < 4; ++it) {
-            // forward: apply the row interchanges and L^{-1}
+            // forward: apply the row interchanges and L^{-1}; the operands of
+            // CH steps are loaded before the chain that consumes them
+            constexpr int CH = 8;
             double cur = SG_Z(0, k);
-            for (int i = 0; i < N - 1; ++i) {
+            int i = 0;
+            for (; i + CH <= N - 1; i += CH) {
+                double nz[CH], l[CH], pq[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    nz[u] = SG_Z(i + u + 1, k);
+                    l[u] = SG_AT(lo, i + u);
+                    pq[u] = SG_AT(pv, i + u);
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    if (pq[u] != 0.0) {
+                        SG_Z(i + u, k) = nz[u];
+                        cur = cur - l[u] * nz[u];
+                    } else {
+                        SG_Z(i + u, k) = cur;
+                        cur = nz[u] - l[u] * cur;
+                    }
+                }
+            }
+            for (; i < N - 1; ++i) {
                 const double nxt = SG_Z(i + 1, k);
                 const double l = SG_AT(lo, i);
                 if (SG_AT(pv, i) != 0.0) {
@@ -349,11 +382,28 @@ __global__ __launch_bounds__(64) void k_stein(const double* d, const double* e, 
                     cur = nxt - l * cur;
                 }
             }
-            SG_Z(N - 1, k) = cur;
             // backward: U^{-1}
             double x1 = cur * SG_AT(rd, N - 1), x2 = 0.0;
             SG_Z(N - 1, k) = x1;
-            for (int i = N - 2; i >= 0; --i) {
+            i = N - 2;
+            for (; i - (CH - 1) >= 0; i -= CH) {
+                double zv[CH], a1[CH], a2[CH], r[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    zv[u] = SG_Z(i - u, k);
+                    a1[u] = SG_AT(u1, i - u);
+                    a2[u] = SG_AT(u2, i - u);
+                    r[u] = SG_AT(rd, i - u);
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const double xi = (zv[u] - a1[u] * x1 - a2[u] * x2) * r[u];
+                    SG_Z(i - u, k) = xi;
+                    x2 = x1;
+                    x1 = xi;
+                }
+            }
+            for (; i >= 0; --i) {
                 const double xi = (SG_Z(i, k) - SG_AT(u1, i) * x1 - SG_AT(u2, i) * x2) * SG_AT(rd, i);
                 SG_Z(i, k) = xi;
                 x2 = x1;
@@ -375,19 +425,134 @@ __global__ __launch_bounds__(64) void k_stein(const double* d, const double* e, 
 #undef SG_Z
 }
 
-// Clusters of consecutive eigenvalues of T with gaps below 1e-3 ||T||
-// (Gershgorin norm, floored as in the inverse iteration), computed by one
-// thread (N is small).
-__global__ void k_clusters(const double* d, const double* e, const double* lam, int N, int* cl_start, int* ncl) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Same inverse iteration with every thread's factors and vector in LDS
+// (tpw threads per workgroup, element i of lane l at i * tpw + l; d and e
+// shared).  Used when 6 N tpw + 2 N doubles fit in LDS.
+__global__ __launch_bounds__(64) void k_stein_lds(const double* d, const double* e, const double* lam, int N,
+                                                  const int* cl_start, const int* ncl, double* zt, int tpw) {
+    extern __shared__ double sh[];
+    double* sd = sh;                        // N
+    double* se = sh + N;                    // N
+    double* lo = se + N;                    // multiplier of L
+    double* rd = lo + (long)N * tpw;        // 1 / diagonal of U
+    double* u1 = rd + (long)N * tpw;        // first superdiagonal of U
+    double* u2 = u1 + (long)N * tpw;        // second superdiagonal of U (pivoting)
+    double* pv = u2 + (long)N * tpw;        // +1 where rows i, i+1 were interchanged
+    double* z = pv + (long)N * tpw;         // the vector being iterated
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        sd[i] = d[i];
+        se[i] = (i + 1 < N) ? e[i] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x;
+    const int cl = blockIdx.x * tpw + lane;
+    if (lane >= tpw || cl >= *ncl) return;  // no barrier below
+#define SG_L(arr, i) arr[(long)(i) * tpw + lane]
+    const int k0 = cl_start[cl], k1 = cl_start[cl + 1];
     double tnorm = 0.0;
     for (int i = 0; i < N; ++i)
-        tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0));
+        tnorm = fmax(tnorm, fabs(sd[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0) + (i + 1 < N ? fabs(se[i]) : 0.0));
+    const double tiny = kEps * fmax(tnorm, 1e-100);
+    const double sep = 10.0 * tiny;
+    double prev = -1e300;
+    for (int k = k0; k < k1; ++k) {
+        double x = lam[k];
+        if (k > k0 && x - prev < sep) x = prev + sep;
+        prev = x;
+        double a = sd[0] - x, b = (N > 1) ? se[0] : 0.0;
+        for (int i = 0; i < N - 1; ++i) {
+            const double c = se[i];
+            const double dn = sd[i + 1] - x;
+            const double bn = se[i + 1];
+            if (fabs(a) >= fabs(c)) {
+                if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
+                const double r = 1.0 / a;
+                const double l = c * r;
+                SG_L(lo, i) = l;
+                SG_L(rd, i) = r;
+                SG_L(u1, i) = b;
+                SG_L(u2, i) = 0.0;
+                SG_L(pv, i) = 0.0;
+                a = dn - l * b;
+                b = bn;
+            } else {
+                const double r = 1.0 / c;
+                const double l = a * r;
+                SG_L(lo, i) = l;
+                SG_L(rd, i) = r;
+                SG_L(u1, i) = dn;
+                SG_L(u2, i) = bn;
+                SG_L(pv, i) = 1.0;
+                a = b - l * dn;
+                b = -l * bn;
+            }
+        }
+        if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
+        SG_L(rd, N - 1) = 1.0 / a;
+        for (int i = 0; i < N; ++i) SG_L(z, i) = start_value(i, k);
+        for (int it = 0; it < 4; ++it) {
+            double cur = SG_L(z, 0);
+            for (int i = 0; i < N - 1; ++i) {
+                const double nxt = SG_L(z, i + 1);
+                const double l = SG_L(lo, i);
+                if (SG_L(pv, i) != 0.0) {
+                    SG_L(z, i) = nxt;
+                    cur = cur - l * nxt;
+                } else {
+                    SG_L(z, i) = cur;
+                    cur = nxt - l * cur;
+                }
+            }
+            double x1 = cur * SG_L(rd, N - 1), x2 = 0.0;
+            SG_L(z, N - 1) = x1;
+            for (int i = N - 2; i >= 0; --i) {
+                const double xi = (SG_L(z, i) - SG_L(u1, i) * x1 - SG_L(u2, i) * x2) * SG_L(rd, i);
+                SG_L(z, i) = xi;
+                x2 = x1;
+                x1 = xi;
+            }
+            // orthogonalise against the earlier members of the cluster
+            // (already written to zt by this thread), normalise
+            for (int j = k0; j < k; ++j) {
+                double s = 0.0;
+                for (int i = 0; i < N; ++i) s += zt[(long)i * N + j] * SG_L(z, i);
+                for (int i = 0; i < N; ++i) SG_L(z, i) -= s * zt[(long)i * N + j];
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < N; ++i) nrm += SG_L(z, i) * SG_L(z, i);
+            const double inv = (nrm > 0.0) ? 1.0 / sqrt(nrm) : 0.0;
+            for (int i = 0; i < N; ++i) SG_L(z, i) *= inv;
+        }
+        for (int i = 0; i < N; ++i) zt[(long)i * N + k] = SG_L(z, i);
+    }
+#undef SG_L
+}
+
+// Clusters of consecutive eigenvalues of T with gaps below 1e-3 ||T||
+// (Gershgorin norm, floored as in the inverse iteration); one workgroup:
+// the norm by a block reduction, the gap flags in LDS, the compaction by
+// one thread over LDS.
+__global__ __launch_bounds__(256) void k_clusters(const double* d, const double* e, const double* lam, int N,
+                                                  int* cl_start, int* ncl) {
+    extern __shared__ double shc[];
+    double* sl = shc;                              // N eigenvalues
+    __shared__ double red[4];
+    const int t = threadIdx.x;
+    double tn = 0.0;
+    for (int i = t; i < N; i += blockDim.x) {
+        tn = fmax(tn, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0));
+        sl[i] = lam[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) tn = fmax(tn, __shfl_xor(tn, off, 64));
+    if ((t & 63) == 0) red[t >> 6] = tn;
+    __syncthreads();
+    if (t != 0) return;
+    const double tnorm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     const double gap = 1e-3 * fmax(tnorm, 1e-100);
     int n = 0;
     cl_start[n++] = 0;
     for (int k = 1; k < N; ++k)
-        if (lam[k] - lam[k - 1] > gap) cl_start[n++] = k;
+        if (sl[k] - sl[k - 1] > gap) cl_start[n++] = k;
     cl_start[n] = N;
     *ncl = n;
 }
@@ -442,10 +607,34 @@ sparc_status dense_eigh_tridiag(sparc_gpu_ctx c, double* A, int N, double* V, do
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
     slot = prof_begin(c, PK_EIG_VEC);
-    k_clusters<<<1, 64, 0, c->stream>>>(d, e, lamw, N, cl, ncl_d);
+    k_clusters<<<1, 256, N * sizeof(double), c->stream>>>(d, e, lamw, N, cl, ncl_d);
     SG_CHECK_LAUNCH(c);
-    k_stein<<<nthr / 64, 64, 0, c->stream>>>(d, e, lamw, N, cl, ncl_d, zt, stw);
+    {
+        // threads per workgroup whose LU factors and vector fit in LDS
+        const long lds_doubles = (150L * 1024) / 8;
+        const int tpw = (int)std::min<long>(64, (lds_doubles - 2L * N) / (6L * N));
+        if (tpw >= 1) {
+            const size_t lds = (2 * (size_t)N + 6 * (size_t)N * tpw) * sizeof(double);
+            k_stein_lds<<<div_up(N, tpw), 64, lds, c->stream>>>(d, e, lamw, N, cl, ncl_d, zt, tpw);
+        } else {
+            k_stein<<<nthr / 64, 64, 0, c->stream>>>(d, e, lamw, N, cl, ncl_d, zt, stw);
+        }
+    }
     SG_CHECK_LAUNCH(c);
+    if (c->debug) {
+        std::vector<int> h(N + 2);
+        SG_HIP(c, hipMemcpyAsync(h.data(), cl, (N + 2) * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+        const int n = h[N + 1];
+        int mx = 0, multi = 0;
+        for (int q = 0; q < n; ++q) {
+            const int sz = h[q + 1] - h[q];
+            mx = std::max(mx, sz);
+            multi += sz > 1 ? sz : 0;
+        }
+        fprintf(stderr, "[sparc_gpu] eigh N=%d clusters %d, largest %d, states in clusters of >1: %d\n", N, n, mx,
+                multi);
+    }
     prof_end(c, slot);
     slot = prof_begin(c, PK_EIG_BACK);
     k_backtransform<<<div_up(N, 4), 256, 0, c->stream>>>(A, tau, N, zt, V);

@@ -64,6 +64,15 @@ struct NonlocalTables {
     int slab_kmax = 0, slab_xw = 0, slab_zw = 0;
     double nl_hi = 0.0, nl_lo = 0.0;  // signed spectral bound contributions
     int max_per_atom = 0;
+    // image points of each atom's ball for the projection, in grid order:
+    // flat index and the packed position in the atom's bounding box
+    // (bits 0-7 x, 8-15 y, 16-23 z, relative to box_lo); the projector
+    // values are products of per-axis Gaussian tables
+    long* ip_off = nullptr;     // n_atoms + 1
+    int* ip_idx = nullptr;
+    uint32_t* ip_box = nullptr;
+    int* box_lo = nullptr;      // 3 n_atoms (unwrapped grid index of the box corner)
+    int box_ext = 0;            // largest box edge (points)
 };
 
 }  // namespace sg
@@ -249,6 +258,15 @@ enum ProfKernel {
     PK_COUNT = 32    // size of the per-context timing tables
 };
 static_assert(PK_COUNT == sizeof(sparc_gpu_ctx_s::prof_n) / sizeof(long), "timing table size");
+// LDS of one nonlocal sweep workgroup: two padded plane buffers, then the
+// slab's candidate tables (delta, cz; ex, ez over the candidate's x/z range;
+// z-independent factors F (3 per row and candidate); A'/B' for two planes;
+// cxb, czb as ints).
+inline size_t nl_sweep_lds_bytes(int ty, int nx, size_t KM, int xw, int zw, size_t tsize) {
+    return (2 * (size_t)(ty + 2 * kMaxHalfOrder) * (nx + 2 * kMaxHalfOrder) + 2 * KM + KM * (size_t)xw +
+            KM * (size_t)zw + 7 * (size_t)ty * KM) * tsize + 2 * KM * sizeof(int);
+}
+
 int prof_begin(sparc_gpu_ctx c, int kernel);
 void prof_end(sparc_gpu_ctx c, int slot);
 

@@ -104,33 +104,43 @@ struct SweepGeom {
     int lrow;  // LDS offset of this thread's own point
     int W, nx, lx, ly, gy, t, nt;
     // LDS tables of the slab's projector candidates (K of them):
-    T *cx, *cy, *cz;        // image-shifted atom centre
-    T *ds, *dpx, *dpy, *dpz; // this orbital's gamma-scaled projections
-    int* cxb;               // x index offset into the ex table
+    T* delta;               // x offset of the candidate's first ex entry from its centre
+    T* cz;                  // image-shifted z centre
+    int* cxb;               // x index of the candidate's first ex entry (grid row coordinates)
     T* ex;                  // ex[k*xw + i]: exp(-dx^2/rc^2) over the candidate's x-range
-    T* ey;                  // ey[row*K + k]
     T* ez;                  // ez[k*zw + i]: exp(-dz^2/rc^2) over the candidate's z-range
     int* czb;               // z index offset into the ez table
-    T* ab;                  // ab[parity][row][k][2]: A, B of plane z / z+1
+    T* F;                   // F[(row*K + k)*3 + {0,1,2}]: z-independent factors (see sweep_ab)
+    T* ab;                  // ab[parity][row][k][2]: A', B' of plane z / z+1
     int K, y0, tyn, xw, zw;
+    int abk0, abdk;  // candidate of this thread's first sweep_ab pair, and its step per nt pairs
 };
 
-// A(row, k), B(row, k) of one plane z: the candidate's projector values on
-// the row factor as ex(x) * (A + B * dx) with
-//   A = ey ez (N0 D_s + N1 (dy D_py + dz D_pz)),  B = ey ez N1 D_px.
+// A'(row, k), B'(row, k) of one plane z.  The candidate's contribution at
+// a point of the row is ex(x) (A + B dx) with
+//   A = ey ez (N0 D_s + N1 (dy D_py + dz D_pz)),  B = ey ez N1 D_px;
+// the z-independent factors F0 = ey (N0 D_s + N1 dy D_py), F1 = ey N1 D_pz,
+// F2 = ey N1 D_px are tabulated once per workgroup, so A = ez (F0 + F1 dz),
+// B = ez F2.  With dx = delta_k + hx i (i the point's index in the ex table)
+// the apply needs A' = A + B delta_k and B' = B hx.
 template <typename T>
 __device__ __forceinline__ void sweep_ab(const SweepArgs<T>& a, const SweepGeom<T>& g, int z, T* abz) {
     const int n = g.tyn * g.K;
+    const T zh = (T)z * a.hz;
+    int k = g.abk0;  // candidate of pair j = row * K + k
     for (int j = g.t; j < n; j += g.nt) {
-        const int row = j / g.K, k = j - row * g.K;
         // planes outside the candidate's z-range never reach a point that
         // lists it; clamp the table index there
         const int iz = min(max(z - g.czb[k], 0), g.zw - 1);
-        const T eyz = g.ey[j] * g.ez[k * g.zw + iz];
-        const T dy = (T)(g.y0 + row) * a.hy - g.cy[k];
-        const T dz = (T)z * a.hz - g.cz[k];
-        abz[2 * j] = eyz * (a.N0 * g.ds[k] + a.N1 * (dy * g.dpy[k] + dz * g.dpz[k]));
-        abz[2 * j + 1] = eyz * a.N1 * g.dpx[k];
+        const T E = g.ez[k * g.zw + iz];
+        const T dz = zh - g.cz[k];
+        const T* F = g.F + 3 * j;
+        const T A = E * (F[0] + F[1] * dz);
+        const T B = E * F[2];
+        abz[2 * j] = A + B * g.delta[k];
+        abz[2 * j + 1] = B * a.hx;
+        k += g.abdk;  // abdk = nt mod K
+        if (k >= g.K) k -= g.K;
     }
 }
 
@@ -187,9 +197,8 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& a, SweepRegs<T, H
             const int k = (int)(w & 0xFFull);
             if (k == 0xFF) break;
             w >>= 8;
-            const T exv = g.ex[k * g.xw + (g.lx - g.cxb[k])];
-            const T dx = (T)g.lx * a.hx - g.cx[k];
-            nl += exv * (abr[2 * k] + abr[2 * k + 1] * dx);
+            const int i = g.lx - g.cxb[k];
+            nl += g.ex[k * g.xw + i] * (abr[2 * k] + abr[2 * k + 1] * (T)i);
         }
         hv += nl;
     }
@@ -274,55 +283,53 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, NL ? 512 : 1024))) void
     g.y0 = y0;
     g.tyn = tyn;
     if (NL) {
-        // LDS after the two plane buffers: candidate SoA (7 T + 1 int per
-        // candidate), ex, ey, ez (2 planes), A/B (2 planes)
+        // LDS after the two plane buffers (layout of nl_sweep_lds_bytes):
+        // delta, cz (K T each), ex (K xw), ez (K zw), F (3 ty K), A'/B'
+        // (2 planes x 2 ty K), cxb, czb (K int each)
         const int KM = a.kmax;
         T* tp = buf1 + R * W;
-        g.cx = tp;
-        g.cy = tp + KM;
-        g.cz = tp + 2 * KM;
-        g.ds = tp + 3 * KM;
-        g.dpx = tp + 4 * KM;
-        g.dpy = tp + 5 * KM;
-        g.dpz = tp + 6 * KM;
-        g.ex = tp + 7 * KM;
-        g.ey = g.ex + KM * a.xw;
-        g.ez = g.ey + a.ty * KM;
-        g.ab = g.ez + KM * a.zw;
+        g.delta = tp;
+        g.cz = tp + KM;
+        g.ex = tp + 2 * KM;
+        g.ez = g.ex + KM * a.xw;
+        g.F = g.ez + KM * a.zw;
+        g.ab = g.F + 3 * a.ty * KM;
         g.cxb = reinterpret_cast<int*>(g.ab + 4 * a.ty * KM);
         g.czb = g.cxb + KM;
         g.xw = a.xw;
         g.zw = a.zw;
         g.K = a.slab_k[tile];
+        g.abk0 = g.K > 0 ? t % g.K : 0;
+        g.abdk = g.K > 0 ? nt % g.K : 0;
         const CandInfo* ci = a.slab_cand + (long)tile * KM;
         const T* Dc = a.D + (long)col * a.ldD;
         for (int k = t; k < g.K; k += nt) {
             const CandInfo c = ci[k];
-            g.cx[k] = (T)(a.atom_pos[3 * c.atom] - (double)c.sx * (double)nx * (double)a.hx);
-            g.cy[k] = (T)(a.atom_pos[3 * c.atom + 1] - (double)c.sy * (double)ny * (double)a.hy);
+            g.delta[k] = (T)((double)c.ixlo * (double)a.hx - a.atom_pos[3 * c.atom]);
             g.cz[k] = (T)(a.atom_pos[3 * c.atom + 2] - (double)c.sz * (double)nz * (double)a.hz);
-            g.ds[k] = Dc[4 * c.atom];
-            g.dpx[k] = Dc[4 * c.atom + 1];
-            g.dpy[k] = Dc[4 * c.atom + 2];
-            g.dpz[k] = Dc[4 * c.atom + 3];
             g.cxb[k] = c.ixlo - c.sx * nx;
             g.czb[k] = c.izlo - c.sz * nz;
         }
-        __syncthreads();
         for (int j = t; j < g.K * g.xw; j += nt) {
             const int k = j / g.xw, i = j - k * g.xw;
             const T dx = (T)(ci[k].ixlo + i) * a.hx - (T)a.atom_pos[3 * ci[k].atom];
             g.ex[j] = exp(-dx * dx * a.inv_rc2);
         }
-        for (int j = t; j < tyn * g.K; j += nt) {
-            const int row = j / g.K, k = j - row * g.K;
-            const T dy = (T)(y0 + row) * a.hy - g.cy[k];
-            g.ey[j] = exp(-dy * dy * a.inv_rc2);
-        }
         for (int j = t; j < g.K * g.zw; j += nt) {
             const int k = j / g.zw, i = j - k * g.zw;
             const T dz = (T)(ci[k].izlo + i) * a.hz - (T)a.atom_pos[3 * ci[k].atom + 2];
             g.ez[j] = exp(-dz * dz * a.inv_rc2);
+        }
+        for (int j = t; j < tyn * g.K; j += nt) {
+            const int row = j / g.K, k = j - row * g.K;
+            const CandInfo c = ci[k];
+            const T cy = (T)(a.atom_pos[3 * c.atom + 1] - (double)c.sy * (double)ny * (double)a.hy);
+            const T dy = (T)(y0 + row) * a.hy - cy;
+            const T ey = exp(-dy * dy * a.inv_rc2);
+            const T* Dk = Dc + 4 * c.atom;
+            g.F[3 * j] = ey * (a.N0 * Dk[0] + a.N1 * dy * Dk[2]);
+            g.F[3 * j + 1] = ey * a.N1 * Dk[3];
+            g.F[3 * j + 2] = ey * a.N1 * Dk[1];
         }
         __syncthreads();
         sweep_ab<T>(a, g, 0, g.ab);
@@ -399,17 +406,23 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, NL ? 512 : 1024))) void
 #undef SG_STEP
 }
 
-// D(4a+lm, j) = gamma_lm * dV * sum_{s in support(a)} chi_lm(s) X(idx(s), j),
-// accumulated in double in a fixed order (deterministic).
+// D(4a+lm, j) = gamma_lm * dV * sum over the image points p of atom a's
+// ball of chi_lm(p) X(idx(p), j), accumulated in double in a fixed order
+// (deterministic).  chi_s = N0 e, chi_p = N1 {dx, dy, dz} e with
+// e = ex(x) ey(y) ez(z) from per-axis tables of the atom's bounding box,
+// evaluated in LDS (no per-point projector table is read).
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, long ldx, int ncol,
-                                                    const long* __restrict__ sup_off, const int* __restrict__ sup_idx,
-                                                    const double* __restrict__ chi, const double* __restrict__ g4,
-                                                    double dV, T* __restrict__ D, int ldD,
-                                                    const int* __restrict__ atom_order, int n_atoms) {
+                                                    const long* __restrict__ ip_off, const int* __restrict__ ip_idx,
+                                                    const uint32_t* __restrict__ ip_box, const int* __restrict__ box_lo,
+                                                    int ext, const double* __restrict__ pos, double hx, double hy,
+                                                    double hz, double inv_rc2, double N0, double N1,
+                                                    const double* __restrict__ g4, double dV, T* __restrict__ D,
+                                                    int ldD, const int* __restrict__ atom_order, int n_atoms) {
     // Block b runs on XCD b % 8.  Atoms are visited in a space-filling order
     // and each XCD takes a contiguous range of it for one orbital chunk at a
     // time, so overlapping supports of neighbouring atoms hit in that XCD's L2.
+    extern __shared__ double ptab[];  // e and d tables: ex, ey, ez, dx, dy, dz (ext each)
     const int bid = blockIdx.x;
     const int xcd = bid % 8, slot = bid / 8;
     const int per = (n_atoms + 7) / 8;
@@ -417,6 +430,20 @@ __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, lon
     const int chunk = slot / per;
     if (rank >= n_atoms || chunk * NB >= ncol) return;
     const int a = atom_order[rank];
+    for (int q = threadIdx.x; q < 3 * ext; q += blockDim.x) {
+        const int d = q / ext, i = q - d * ext;
+        const double h = d == 0 ? hx : (d == 1 ? hy : hz);
+        const double dv = (double)(box_lo[3 * a + d] + i) * h - pos[3 * a + d];
+        ptab[q] = exp(-dv * dv * inv_rc2);
+        ptab[3 * ext + q] = dv;
+    }
+    __syncthreads();
+    const double* ex = ptab;
+    const double* ey = ptab + ext;
+    const double* ez = ptab + 2 * ext;
+    const double* dxt = ptab + 3 * ext;
+    const double* dyt = ptab + 4 * ext;
+    const double* dzt = ptab + 5 * ext;
     const int n0 = chunk * NB;
     const int nb = min(NB, ncol - n0);
     double acc[NB][4];
@@ -424,10 +451,13 @@ __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, lon
     for (int n = 0; n < NB; ++n)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[n][k] = 0.0;
-    const long s0 = sup_off[a], s1 = sup_off[a + 1];
+    const long s0 = ip_off[a], s1 = ip_off[a + 1];
     for (long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-        const long idx = sup_idx[s];
-        const double c0 = chi[4 * s], c1 = chi[4 * s + 1], c2 = chi[4 * s + 2], c3 = chi[4 * s + 3];
+        const long idx = ip_idx[s];
+        const uint32_t b = ip_box[s];
+        const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
+        const double e = ex[bx] * ey[by] * ez[bz];
+        const double c0 = N0 * e, c1 = N1 * dxt[bx] * e, c2 = N1 * dyt[by] * e, c3 = N1 * dzt[bz] * e;
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
             if (n < nb) {
@@ -559,10 +589,7 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     a.slab_major = c->sweep_slab_major;
     const int threads = div_up((long)c->nx * a.ty, 64) * 64;
     size_t shmem = 2 * (size_t)(a.ty + 2 * kMaxHalfOrder) * (c->nx + 2 * kMaxHalfOrder) * sizeof(T);
-    if (nl) {
-        const size_t KM = a.kmax;
-        shmem += (7 * KM + KM * a.xw + a.ty * KM + KM * a.zw + 4 * a.ty * KM) * sizeof(T) + 2 * KM * sizeof(int);
-    }
+    if (nl) shmem = nl_sweep_lds_bytes(a.ty, c->nx, a.kmax, a.xw, a.zw, sizeof(T));
     if (shmem > 160 * 1024) return set_err(c, SPARC_ERR_ARG, "sweep workgroup needs more than 160 KB of LDS");
     if (threads > (nl ? 512 : 1024)) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
     const long nblocks = (long)ncol * a.ntiles_y;
@@ -602,9 +629,13 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) 
     const int nchunks = div_up(ncol, NB);
     dim3 grid(8 * per * nchunks);
     const int slot = prof_begin(c, PK_PROJ);
-    k_projection<T, NB><<<grid, 256, 0, c->stream>>>(x, ldx, ncol, c->nl.sup_off, c->nl.sup_idx, c->nl.sup_chi,
-                                                   c->nl.gamma4, c->dV, D_of<T>(c), 4 * c->n_atoms,
-                                                   c->nl.atom_order, c->n_atoms);
+    const double pi = 3.14159265358979323846;
+    const double rc = c->rc_nl;
+    const double N0 = std::pow(2.0 / (pi * rc * rc), 0.75), N1 = (2.0 / rc) * N0;
+    const int ext = c->nl.box_ext;
+    k_projection<T, NB><<<grid, 256, 6 * ext * sizeof(double), c->stream>>>(
+        x, ldx, ncol, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo, ext, c->atom_pos, c->hx, c->hy, c->hz,
+        1.0 / (rc * rc), N0, N1, c->nl.gamma4, c->dV, D_of<T>(c), 4 * c->n_atoms, c->nl.atom_order, c->n_atoms);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
     return SPARC_OK;
