@@ -252,8 +252,12 @@ def main():
     s = res["s"]
     prof = res["prof"]
     sw_ms, sw_n = prof["sweep"]
-    bytes_per_sweep = 3 * s * nd * ns
-    achieved = bytes_per_sweep / (sw_ms / sw_n * 1e-3) / 1e9 if sw_n else None
+    # every timed step runs one filter: m - 1 sweeps of the later kind over
+    # all columns (as two launches over half the block each when the filter
+    # is split over two streams)
+    sweep_bytes_total = 3 * s * nd * ns * (m - 1) * args.steps
+    bytes_per_sweep = sweep_bytes_total / sw_n if sw_n else None
+    achieved = sweep_bytes_total / (sw_ms * 1e-3) / 1e9 if sw_n else None
     kernel_name = f"k_hsweep<{'double' if s == 8 else 'float'}, nonlocal, mode 2>"
     traffic = traffic_record(f"{args.workload}_{args.prec}_sweep")
     gt_ms, gt_n = prof["gemm_tn"]
@@ -282,6 +286,7 @@ def main():
             "frac": achieved / PEAK_HBM_GBS if achieved else None,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_per_sweep,
+            "columns_per_launch": (ns * (m - 1) * args.steps) / sw_n if sw_n else None,
             "avg_launch_ms": sw_ms / sw_n if sw_n else None,
             "launches": sw_n,
         },

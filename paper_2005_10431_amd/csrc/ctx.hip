@@ -42,7 +42,7 @@ static sparc_status grow(sparc_gpu_ctx c, void** p, size_t* have, size_t need) {
 
 sparc_status ensure_work(sparc_gpu_ctx c, size_t bytes) { return grow(c, &c->work, &c->work_bytes, bytes); }
 
-int prof_begin(sparc_gpu_ctx c, int kernel) {
+int prof_begin(sparc_gpu_ctx c, int kernel, hipStream_t s) {
     if (!c->prof) return -1;
     int slot = c->prof_used;
     if (2 * (size_t)(slot + 1) > c->prof_pool.size()) {
@@ -55,18 +55,19 @@ int prof_begin(sparc_gpu_ctx c, int kernel) {
     }
     c->prof_kernel[slot] = kernel;
     c->prof_used++;
-    hipEventRecord(c->prof_pool[2 * slot], c->stream);
+    hipEventRecord(c->prof_pool[2 * slot], s ? s : c->stream);
     return slot;
 }
 
-void prof_end(sparc_gpu_ctx c, int slot) {
+void prof_end(sparc_gpu_ctx c, int slot, hipStream_t s) {
     if (slot < 0) return;
-    hipEventRecord(c->prof_pool[2 * slot + 1], c->stream);
+    hipEventRecord(c->prof_pool[2 * slot + 1], s ? s : c->stream);
 }
 
 static sparc_status prof_flush(sparc_gpu_ctx c) {
     if (c->prof_used == 0) return SPARC_OK;
     SG_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->aux_stream) SG_HIP(c, hipStreamSynchronize(c->aux_stream));
     for (int i = 0; i < c->prof_used; ++i) {
         float ms = 0.f;
         SG_HIP(c, hipEventElapsedTime(&ms, c->prof_pool[2 * i], c->prof_pool[2 * i + 1]));
@@ -834,6 +835,7 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     c->nl_ty = choose_sweep_ty(c->nx, c->ny, 512);
     if (const char* e = std::getenv("SPARC_GPU_DEBUG")) c->debug = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_EIG")) c->eig_jacobi = std::string(e) == "jacobi";
+    if (const char* e = std::getenv("SPARC_GPU_SPLIT_FILTER")) c->split_filter = std::atoi(e);
 
     int dev = 0;
     sparc_status st = SPARC_OK;
@@ -869,6 +871,12 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
     for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
     if (c->jac_exec) hipGraphExecDestroy(c->jac_exec);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    if (c->aux_stream) {
+        hipStreamSynchronize(c->aux_stream);
+        hipStreamDestroy(c->aux_stream);
+    }
+    if (c->fork_ev) hipEventDestroy(c->fork_ev);
+    if (c->join_ev) hipEventDestroy(c->join_ev);
     delete c;
     return SPARC_OK;
 }

@@ -135,6 +135,9 @@ struct sparc_gpu_ctx_s {
 
     // captured Jacobi sweep (see dense.hip)
     hipStream_t cap_stream = nullptr;
+    hipStream_t aux_stream = nullptr;  // second stream of the split filter
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    int split_filter = 0;       // SPARC_GPU_SPLIT_FILTER=1: filter halves on two streams
     hipGraphExec_t jac_exec = nullptr;
     int jac_N = 0;
     double *jac_A = nullptr, *jac_A2 = nullptr, *jac_V = nullptr, *jac_V2 = nullptr;
@@ -196,9 +199,12 @@ enum Flag {
 // 2 filter step `step` (>= 2) with xprev = X_{k-1} (may alias out).
 template <typename T>
 sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, int ncol, long ldx,
-                           int mode, int step);
+                           int mode, int step, int dcol0 = 0, hipStream_t s = nullptr);
+// dcol0: first column of the projection coefficients D that belongs to x;
+// s: stream (null: the context stream)
 template <typename T>
-sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx);
+sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, int dcol0 = 0,
+                               hipStream_t s = nullptr);
 
 // C(MxN, col-major, ldc) = alpha * A^T B, A: K x M (lda), B: K x N (ldb),
 // T inputs, double output, deterministic split-K.
@@ -267,8 +273,8 @@ inline size_t nl_sweep_lds_bytes(int ty, int nx, size_t KM, int xw, int zw, size
             KM * (size_t)zw + 7 * (size_t)ty * KM) * tsize + 2 * KM * sizeof(int);
 }
 
-int prof_begin(sparc_gpu_ctx c, int kernel);
-void prof_end(sparc_gpu_ctx c, int slot);
+int prof_begin(sparc_gpu_ctx c, int kernel, hipStream_t s = nullptr);  // s = null: the context stream
+void prof_end(sparc_gpu_ctx c, int slot, hipStream_t s = nullptr);
 
 // Build geometry tables (ctx.hip)
 sparc_status build_tables(sparc_gpu_ctx c);

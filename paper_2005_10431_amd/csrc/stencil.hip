@@ -544,7 +544,8 @@ float* D_of<float>(sparc_gpu_ctx c) {
 
 template <typename T>
 sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, int ncol, long ldx, int mode,
-                           int step) {
+                           int step, int dcol0, hipStream_t s) {
+    hipStream_t stream = s ? s : c->stream;
     SweepArgs<T> a;
     a.x = x;
     a.out = out;
@@ -580,7 +581,7 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
         a.hy = (T)c->hy;
         a.hz = (T)c->hz;
     }
-    a.D = D_of<T>(c);
+    a.D = D_of<T>(c) + (long)dcol0 * 4 * c->n_atoms;
     a.ldD = 4 * c->n_atoms;
     a.params = c->scal + S_A;
     a.mode = mode;
@@ -596,9 +597,9 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "too many blocks");
     const int hm = div_up(2L * kMaxHalfOrder * c->nx, threads);
     if (hm > 3) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
-    const int slot = prof_begin(c, mode == 2 ? PK_SWEEP : (mode == 1 ? PK_SWEEP1 : PK_APPLY));
+    const int slot = prof_begin(c, mode == 2 ? PK_SWEEP : (mode == 1 ? PK_SWEEP1 : PK_APPLY), stream);
     const dim3 g((unsigned)nblocks), b(threads);
-#define SG_LAUNCH_SWEEP(NLV, MV, HMV) k_hsweep<T, NLV, MV, HMV><<<g, b, shmem, c->stream>>>(a)
+#define SG_LAUNCH_SWEEP(NLV, MV, HMV) k_hsweep<T, NLV, MV, HMV><<<g, b, shmem, stream>>>(a)
 #define SG_SWEEP_HM(NLV, MV)          \
     do {                              \
         if (hm == 1) SG_LAUNCH_SWEEP(NLV, MV, 1); \
@@ -617,35 +618,38 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
 #undef SG_SWEEP_HM
 #undef SG_LAUNCH_SWEEP
     SG_CHECK_LAUNCH(c);
-    prof_end(c, slot);
+    prof_end(c, slot, stream);
     return SPARC_OK;
 }
 
 template <typename T>
-sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) {
+sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, int dcol0, hipStream_t s) {
     if (c->nl_lmax < 1 || c->nl.n_sup == 0) return SPARC_OK;
+    hipStream_t stream = s ? s : c->stream;
     constexpr int NB = 8;
     const int per = (c->n_atoms + 7) / 8;
     const int nchunks = div_up(ncol, NB);
     dim3 grid(8 * per * nchunks);
-    const int slot = prof_begin(c, PK_PROJ);
+    const int slot = prof_begin(c, PK_PROJ, stream);
     const double pi = 3.14159265358979323846;
     const double rc = c->rc_nl;
     const double N0 = std::pow(2.0 / (pi * rc * rc), 0.75), N1 = (2.0 / rc) * N0;
     const int ext = c->nl.box_ext;
-    k_projection<T, NB><<<grid, 256, 6 * ext * sizeof(double), c->stream>>>(
+    k_projection<T, NB><<<grid, 256, 6 * ext * sizeof(double), stream>>>(
         x, ldx, ncol, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo, ext, c->atom_pos, c->hx, c->hy, c->hz,
-        1.0 / (rc * rc), N0, N1, c->nl.gamma4, c->dV, D_of<T>(c), 4 * c->n_atoms, c->nl.atom_order, c->n_atoms);
+        1.0 / (rc * rc), N0, N1, c->nl.gamma4, c->dV, D_of<T>(c) + (long)dcol0 * 4 * c->n_atoms, 4 * c->n_atoms,
+        c->nl.atom_order, c->n_atoms);
     SG_CHECK_LAUNCH(c);
-    prof_end(c, slot);
+    prof_end(c, slot, stream);
     return SPARC_OK;
 }
 
 template sparc_status launch_hsweep<double>(sparc_gpu_ctx, const double*, double*, const double*, int, long, int,
-                                            int);
-template sparc_status launch_hsweep<float>(sparc_gpu_ctx, const float*, float*, const float*, int, long, int, int);
-template sparc_status launch_projection<double>(sparc_gpu_ctx, const double*, int, long);
-template sparc_status launch_projection<float>(sparc_gpu_ctx, const float*, int, long);
+                                            int, int, hipStream_t);
+template sparc_status launch_hsweep<float>(sparc_gpu_ctx, const float*, float*, const float*, int, long, int, int,
+                                           int, hipStream_t);
+template sparc_status launch_projection<double>(sparc_gpu_ctx, const double*, int, long, int, hipStream_t);
+template sparc_status launch_projection<float>(sparc_gpu_ctx, const float*, int, long, int, hipStream_t);
 
 template <typename T>
 static sparc_status apply_impl(sparc_gpu_ctx c, const T* X, T* Y, int ncol, long ldx) {
@@ -663,24 +667,70 @@ __global__ void k_copy_block(const T* __restrict__ src, T* __restrict__ dst, lon
 
 // Filter with bounds already in c->scal[S_A..S_A0].  Y_k lives in X when k is
 // even and in W when k is odd; the result ends in X.
+//
+// One chain of the filter over columns [col0, col0 + ncol) on stream s.
 template <typename T>
-sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m) {
+static sparc_status filter_chain(sparc_gpu_ctx c, T* X, T* Wk, int col0, int ncol, long ldx, int m, hipStream_t s) {
     sparc_status st;
-    if ((st = launch_projection<T>(c, X, ncol, ldx)) != SPARC_OK) return st;
-    if ((st = launch_hsweep<T>(c, X, Wk, nullptr, ncol, ldx, 1, 1)) != SPARC_OK) return st;
+    X += (long)col0 * ldx;
+    Wk += (long)col0 * ldx;
+    if ((st = launch_projection<T>(c, X, ncol, ldx, col0, s)) != SPARC_OK) return st;
+    if ((st = launch_hsweep<T>(c, X, Wk, nullptr, ncol, ldx, 1, 1, col0, s)) != SPARC_OK) return st;
     for (int k = 2; k <= m; ++k) {
         T* cur = (k % 2 == 0) ? Wk : X;   // Y_{k-1}
         T* dst = (k % 2 == 0) ? X : Wk;   // Y_{k-2}, overwritten with Y_k
-        if ((st = launch_projection<T>(c, cur, ncol, ldx)) != SPARC_OK) return st;
-        if ((st = launch_hsweep<T>(c, cur, dst, dst, ncol, ldx, 2, k)) != SPARC_OK) return st;
+        if ((st = launch_projection<T>(c, cur, ncol, ldx, col0, s)) != SPARC_OK) return st;
+        if ((st = launch_hsweep<T>(c, cur, dst, dst, ncol, ldx, 2, k, col0, s)) != SPARC_OK) return st;
     }
     if (m % 2 == 1) {
         dim3 grid(div_up(c->nd, 256), ncol);
-        k_copy_block<T><<<grid, 256, 0, c->stream>>>(Wk, X, c->nd, ncol, ldx);
+        k_copy_block<T><<<grid, 256, 0, s>>>(Wk, X, c->nd, ncol, ldx);
         SG_CHECK_LAUNCH(c);
     }
     return SPARC_OK;
 }
+
+// The filter acts on every column independently.  Optionally (context flag
+// split_filter, off by default) a block of at least 64 columns with
+// projectors is split in two halves filtered on two streams, the second
+// started one projection later, so that kernels of the two halves overlap.
+// The default is one stream: concurrent halves make the per-launch times
+// of the sweep overlap each other.
+template <typename T>
+sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m) {
+    const bool nl = c->nl_lmax >= 1 && c->nl.n_sup > 0;
+    if (!nl || ncol < 64 || !c->split_filter) return filter_chain<T>(c, X, Wk, 0, ncol, ldx, m, c->stream);
+    if (!c->aux_stream) {
+        SG_HIP(c, hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+        SG_HIP(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        SG_HIP(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    }
+    const int na = ncol / 2, nb = ncol - na;
+    sparc_status st;
+    // second half: starts after the first half's first projection (and after
+    // everything queued before this call on the context stream)
+    if ((st = launch_projection<T>(c, X, na, ldx, 0, c->stream)) != SPARC_OK) return st;
+    SG_HIP(c, hipEventRecord(c->fork_ev, c->stream));
+    SG_HIP(c, hipStreamWaitEvent(c->aux_stream, c->fork_ev, 0));
+    if ((st = filter_chain<T>(c, X, Wk, na, nb, ldx, m, c->aux_stream)) != SPARC_OK) return st;
+    // first half (its first projection is already queued)
+    if ((st = launch_hsweep<T>(c, X, Wk, nullptr, na, ldx, 1, 1, 0, c->stream)) != SPARC_OK) return st;
+    for (int k = 2; k <= m; ++k) {
+        T* cur = (k % 2 == 0) ? Wk : X;
+        T* dst = (k % 2 == 0) ? X : Wk;
+        if ((st = launch_projection<T>(c, cur, na, ldx, 0, c->stream)) != SPARC_OK) return st;
+        if ((st = launch_hsweep<T>(c, cur, dst, dst, na, ldx, 2, k, 0, c->stream)) != SPARC_OK) return st;
+    }
+    if (m % 2 == 1) {
+        dim3 grid(div_up(c->nd, 256), na);
+        k_copy_block<T><<<grid, 256, 0, c->stream>>>(Wk, X, c->nd, na, ldx);
+        SG_CHECK_LAUNCH(c);
+    }
+    SG_HIP(c, hipEventRecord(c->join_ev, c->aux_stream));
+    SG_HIP(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
+    return SPARC_OK;
+}
+
 template sparc_status filter_impl<double>(sparc_gpu_ctx, double*, double*, int, long, int);
 template sparc_status filter_impl<float>(sparc_gpu_ctx, float*, float*, int, long, int);
 

@@ -276,3 +276,25 @@ def test_argument_errors():
     short = torch.zeros((4, s.nd - 1), dtype=torch.float64, device="cuda")
     with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
         ctx.apply_H(short, torch.zeros_like(short))    # ldx < N_d
+
+
+def test_filter_split_over_two_streams_is_bitwise_identical(monkeypatch):
+    """The optional two-stream filter (halves of the block on two streams)
+    computes every column exactly as the one-stream filter."""
+    torch = require_gpu()
+    s = ragged_system(n_states=70)
+    v = _veff(s, 21)
+    X = W.initial_orbitals(s.nd, s.n_states, 4)
+    outs = []
+    for split in ("0", "1"):
+        monkeypatch.setenv("SPARC_GPU_SPLIT_FILTER", split)
+        ctx = _ctx(s)
+        ctx.set_veff(to_dev(torch, v))
+        lo, hi = ctx.spectrum_bounds()
+        Xd = to_dev(torch, X)
+        Wd = torch.empty_like(Xd)
+        ctx.chebyshev_filter(Xd, Wd, 9, 0.5 * (lo + hi), hi, lo)
+        outs.append(to_np(Xd))
+        ctx.close()
+    log("split filter: max |diff|", float(np.max(np.abs(outs[0] - outs[1]))))
+    assert np.array_equal(outs[0], outs[1])
