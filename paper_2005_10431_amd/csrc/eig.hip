@@ -163,29 +163,55 @@ __global__ __launch_bounds__(1024) void k_sytrd(double* A, int N, double* d, dou
             const double k2 = 0.5 * tau_i * pv;
             for (int g = lo + t; g < N; g += nt) w[g] -= k2 * v[g];
             __syncthreads();
-            // column i+1 (rows >= i+1) first: it yields the next reflector
-            {
-                const int h = i + 1;
-                double* col = A + (long)h * N;
-                const double vh = v[h], wh = w[h];
-                for (int g = h + t; g < N; g += nt) col[g] -= v[g] * wh + w[g] * vh;
-            }
-            __syncthreads();
             // reflector i is stored below the subdiagonal of column i
             {
                 double* x = A + (long)i * N;
                 for (int r = i + 2 + t; r < N; r += nt) x[r] = v[r];
             }
             const bool more = (i + 1) + 2 < N;
+            const int h = i + 1;
+            double* col = A + (long)h * N;
+            const double vh = v[h], wh = w[h];
             double tau_n = 0.0;
             if (more) {
-                tau_n = trd_householder(A, N, i + 1, vn, red, &beta);
+                // column i+1 (rows >= i+1) is updated in registers and yields
+                // the next reflector directly: its diagonal is d[i+1], row
+                // i+2 is alpha, rows >= i+3 the rest of x
+                double cv[4];  // N <= 4 nt
+                double ss = 0.0;
+                int q = 0;
+                for (int g = h + t; g < N; g += nt, ++q) {
+                    const double val = col[g] - (v[g] * wh + w[g] * vh);
+                    cv[q] = val;
+                    if (g == h) d[h] = val;
+                    if (g == h + 1) s_beta = val;  // alpha, read after the reduction's barriers
+                    if (g >= h + 2) ss += val * val;
+                }
+                const double xnorm2 = block_sum(ss, red);
+                const double alpha = s_beta;
+                double bn = alpha;
+                if (xnorm2 > 0.0) {
+                    bn = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+                    tau_n = (bn - alpha) / bn;
+                }
+                const double scal = (xnorm2 > 0.0) ? 1.0 / (alpha - bn) : 0.0;
+                q = 0;
+                for (int g = h + t; g < N; g += nt, ++q) {
+                    if (g == h + 1) {
+                        vn[g] = 1.0;
+                    } else if (g >= h + 2) {
+                        const double vv = cv[q] * scal;
+                        vn[g] = vv;
+                        col[g] = vv;
+                    }
+                }
                 if (t == 0) {
-                    d[i + 1] = A[(i + 1) + (long)(i + 1) * N];
-                    e[i + 1] = beta;
-                    tau[i + 1] = tau_n;
+                    e[h] = bn;
+                    tau[h] = tau_n;
                 }
             } else {
+                // last step: the updated column gives the final d and e
+                for (int g = h + t; g < N; g += nt) col[g] -= v[g] * wh + w[g] * vh;
                 for (int g = t; g < N; g += nt) vn[g] = 0.0;
             }
             __syncthreads();

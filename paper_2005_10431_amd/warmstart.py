@@ -22,12 +22,12 @@ import time
 import numpy as np
 
 
-def converge(system, rho0=None, tol=1e-10, max_iter=300, ctx=None):
+def converge(system, rho0=None, tol=1e-10, max_iter=300, ctx=None, n_first=None):
     """FP64 GPU SCF; returns (history, rho_fixed_point (device), ctx)."""
     from .driver import run_scf
     import workloads as W
     X0 = W.initial_orbitals(system.nd, system.n_states, system.seed)
-    out = run_scf(system, X0, rho0=rho0, prec="fp64", max_iter=max_iter, tol=tol, ctx=ctx)
+    out = run_scf(system, X0, rho0=rho0, prec="fp64", max_iter=max_iter, tol=tol, ctx=ctx, n_first=n_first)
     return out["history"], out["rho_out"], out["ctx"]
 
 
@@ -100,12 +100,20 @@ def train(data, epochs=20, lr=1e-3, seed=0, log=print):
     return w, curve, time.perf_counter() - t0
 
 
-def evaluate(w, data, max_l1=0.5, eps=1e-6, log=print):
+def evaluate(w, data, max_l1=0.5, eps=1e-6, log=print, n_first=None):
+    """SCF from the network's density against SCF from the atomic guess, both
+    with `n_first` filter passes in the first iteration (the system's value
+    when None)."""
     import torch
     from ._lib import Context
     rows = []
     for d in data:
         s = d["system"]
+        if n_first is not None and n_first != s.n_first:
+            hist_sad, _, ctx0 = converge(s, tol=1e-9, n_first=n_first)
+            ctx0.close()
+        else:
+            hist_sad = d["hist"]
         ctx = Context(s)
         rho0 = torch.empty(s.nd, dtype=torch.float64, device="cuda")
         used = ctx.warm_start(w, rho0, max_l1=max_l1)
@@ -116,13 +124,13 @@ def evaluate(w, data, max_l1=0.5, eps=1e-6, log=print):
         ctx.warm_start(w, pred, max_l1=float("inf"))
         l1_sad = float((sad - d["target"]).abs().sum()) * s.dV / s.n_electrons
         l1_cnn = float((pred - d["target"]).abs().sum()) * s.dV / s.n_electrons
-        hist_cnn, _, _ = converge(s, rho0=rho0, tol=1e-9, ctx=ctx)
+        hist_cnn, _, _ = converge(s, rho0=rho0, tol=1e-9, ctx=ctx, n_first=n_first)
         torch.cuda.synchronize()
         ctx.close()
-        k_sad = iterations_to(d["hist"], d["f_ref"], s.n_atoms, eps)
+        k_sad = iterations_to(hist_sad, d["f_ref"], s.n_atoms, eps)
         k_cnn = iterations_to(hist_cnn, d["f_ref"], s.n_atoms, eps)
         rows.append(dict(seed=d["seed"], used_cnn=used, iters_sad=k_sad, iters_cnn=k_cnn,
-                         ms_sad=time_to(d["hist"], k_sad), ms_cnn=time_to(hist_cnn, k_cnn),
+                         ms_sad=time_to(hist_sad, k_sad), ms_cnn=time_to(hist_cnn, k_cnn),
                          f_diff=abs(hist_cnn[-1]["free_energy"] - d["f_ref"]) / s.n_atoms,
                          l1_sad=l1_sad, l1_cnn=l1_cnn))
         log(f"  test snapshot {d['seed']}: SAD {k_sad} its, warm start {k_cnn} its (CNN used: {used}); "
@@ -137,6 +145,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--grid", type=int, default=72)
+    ap.add_argument("--eval-first", type=int, nargs="+", default=[None],
+                    help="first-iteration filter passes of the evaluation runs (default: the system's)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -149,24 +159,30 @@ def main(argv=None):
     log(f"test data: snapshots 200..{200 + args.test - 1}")
     test_set = make_dataset(range(200, 200 + args.test), n=args.grid, log=log)
     w, curve, t_train = train(train_set, epochs=args.epochs, lr=args.lr, log=log)
-    rows = evaluate(w, test_set, log=log)
-    k_sad = [r["iters_sad"] for r in rows if r["iters_sad"]]
-    k_cnn = [r["iters_cnn"] for r in rows if r["iters_cnn"]]
-    ms_sad = [r["ms_sad"] for r in rows if r["ms_sad"]]
-    ms_cnn = [r["ms_cnn"] for r in rows if r["ms_cnn"]]
+    evals = []
+    for nf in args.eval_first:
+        log(f"evaluation with {nf if nf is not None else 'default'} first-iteration passes")
+        rows = evaluate(w, test_set, log=log, n_first=nf)
+        k_sad = [r["iters_sad"] for r in rows if r["iters_sad"]]
+        k_cnn = [r["iters_cnn"] for r in rows if r["iters_cnn"]]
+        ms_sad = [r["ms_sad"] for r in rows if r["ms_sad"]]
+        ms_cnn = [r["ms_cnn"] for r in rows if r["ms_cnn"]]
+        ev = dict(
+            n_first=nf if nf is not None else test_set[0]["system"].n_first,
+            mean_iters_sad=float(np.mean(k_sad)), mean_iters_cnn=float(np.mean(k_cnn)),
+            mean_ms_sad=float(np.mean(ms_sad)), mean_ms_cnn=float(np.mean(ms_cnn)),
+            cnn_used=int(sum(r["used_cnn"] for r in rows)),
+            mean_l1_sad=float(np.mean([r["l1_sad"] for r in rows])),
+            mean_l1_cnn=float(np.mean([r["l1_cnn"] for r in rows])),
+            max_f_diff=float(max(r["f_diff"] for r in rows)), rows=rows)
+        log(json.dumps({k: v for k, v in ev.items() if k != "rows"}))
+        evals.append(ev)
     summary = dict(
         workload=f"cfg1 cell and physics on a {args.grid}^3 grid, snapshots N(0, 0.15 Bohr)",
         n_train=args.train, n_test=args.test, epochs=args.epochs, lr=args.lr,
-        loss_curve=curve, train_seconds=t_train,
-        mean_iters_sad=float(np.mean(k_sad)), mean_iters_cnn=float(np.mean(k_cnn)),
-        mean_ms_sad=float(np.mean(ms_sad)), mean_ms_cnn=float(np.mean(ms_cnn)),
-        cnn_used=int(sum(r["used_cnn"] for r in rows)),
-        mean_l1_sad=float(np.mean([r["l1_sad"] for r in rows])),
-        mean_l1_cnn=float(np.mean([r["l1_cnn"] for r in rows])),
-        max_f_diff=float(max(r["f_diff"] for r in rows)),
-        total_seconds=time.perf_counter() - t0, rows=rows,
+        loss_curve=curve, train_seconds=t_train, evaluations=evals,
+        total_seconds=time.perf_counter() - t0,
     )
-    log(json.dumps({k: v for k, v in summary.items() if k not in ("rows", "loss_curve")}))
     if args.out:
         with open(args.out, "w") as f:
             json.dump(summary, f, indent=1)
