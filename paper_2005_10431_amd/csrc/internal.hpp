@@ -138,6 +138,7 @@ struct sparc_gpu_ctx_s {
     hipStream_t aux_stream = nullptr;  // second stream of the split filter
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int split_filter = 0;       // SPARC_GPU_SPLIT_FILTER=1: filter halves on two streams
+    int proj_nb = 4;            // SPARC_GPU_PROJ_NB: orbitals per projection workgroup (2, 4, 8)
     hipGraphExec_t jac_exec = nullptr;
     int jac_N = 0;
     double *jac_A = nullptr, *jac_A2 = nullptr, *jac_V = nullptr, *jac_V2 = nullptr;

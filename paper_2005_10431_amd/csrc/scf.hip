@@ -302,12 +302,20 @@ __global__ void k_axpy(double* y, const double* x, double a, long n) {
     if (i < n) y[i] += a * x[i];
 }
 
-__global__ void k_energy_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
-    int k = threadIdx.x;
-    if (k >= kRed) return;
+// out[q] = sum over blocks of part[i][q]: block q, fixed-order tree.
+__global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ part, int nblk,
+                                                      double* __restrict__ out) {
+    __shared__ double red[256];
+    const int q = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
-    for (int i = 0; i < nblk; ++i) s += part[(long)i * kRed + k];
-    out[k] = s;
+    for (int i = t; i < nblk; i += blockDim.x) s += part[(long)i * kRed + q];
+    red[t] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) red[t] += red[t + st];
+        __syncthreads();
+    }
+    if (t == 0) out[q] = red[0];
 }
 
 // filter bounds from the latest Ritz values: a = max, a0 = min (or the lower
@@ -375,7 +383,7 @@ static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double*
         k_axpy<<<nb, 256, 0, c->stream>>>(rho_in, t0, beta, c->nd);
         SG_CHECK_LAUNCH(c);
     }
-    k_energy_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_RED0);
+    k_energy_final<<<kRed, 256, 0, c->stream>>>(c->red, nblk, c->scal + S_RED0);
     SG_CHECK_LAUNCH(c);
     double hloc[S_COUNT];
     double* h = hscal ? hscal : hloc;

@@ -452,16 +452,31 @@ __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, lon
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[n][k] = 0.0;
     const long s0 = ip_off[a], s1 = ip_off[a + 1];
-    for (long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-        const long idx = ip_idx[s];
-        const uint32_t b = ip_box[s];
-        const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
-        const double e = ex[bx] * ey[by] * ez[bz];
-        const double c0 = N0 * e, c1 = N1 * dxt[bx] * e, c2 = N1 * dyt[by] * e, c3 = N1 * dzt[bz] * e;
+    // two support points per iteration: both index loads, then both sets of
+    // orbital loads, are in flight before either is used
+    const long st = blockDim.x;
+    for (long s = s0 + threadIdx.x; s < s1; s += 2 * st) {
+        const bool two = s + st < s1;
+        const long idx0 = ip_idx[s];
+        const uint32_t b0 = ip_box[s];
+        const long idx1 = two ? ip_idx[s + st] : idx0;
+        const uint32_t b1 = two ? ip_box[s + st] : b0;
+        double v0[NB], v1[NB];
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
-            if (n < nb) {
-                double v = (double)x[idx + (long)(n0 + n) * ldx];
+            v0[n] = (n < nb) ? (double)x[idx0 + (long)(n0 + n) * ldx] : 0.0;
+            v1[n] = (n < nb && two) ? (double)x[idx1 + (long)(n0 + n) * ldx] : 0.0;
+        }
+        const uint32_t bb[2] = {b0, b1};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint32_t b = bb[u];
+            const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
+            const double e = ex[bx] * ey[by] * ez[bz];
+            const double c0 = N0 * e, c1 = N1 * dxt[bx] * e, c2 = N1 * dyt[by] * e, c3 = N1 * dzt[bz] * e;
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const double v = u == 0 ? v0[n] : v1[n];
                 acc[n][0] += c0 * v;
                 acc[n][1] += c1 * v;
                 acc[n][2] += c2 * v;
@@ -626,19 +641,26 @@ template <typename T>
 sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, int dcol0, hipStream_t s) {
     if (c->nl_lmax < 1 || c->nl.n_sup == 0) return SPARC_OK;
     hipStream_t stream = s ? s : c->stream;
-    constexpr int NB = 8;
     const int per = (c->n_atoms + 7) / 8;
-    const int nchunks = div_up(ncol, NB);
-    dim3 grid(8 * per * nchunks);
     const int slot = prof_begin(c, PK_PROJ, stream);
     const double pi = 3.14159265358979323846;
     const double rc = c->rc_nl;
     const double N0 = std::pow(2.0 / (pi * rc * rc), 0.75), N1 = (2.0 / rc) * N0;
     const int ext = c->nl.box_ext;
-    k_projection<T, NB><<<grid, 256, 6 * ext * sizeof(double), stream>>>(
-        x, ldx, ncol, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo, ext, c->atom_pos, c->hx, c->hy, c->hz,
-        1.0 / (rc * rc), N0, N1, c->nl.gamma4, c->dV, D_of<T>(c) + (long)dcol0 * 4 * c->n_atoms, 4 * c->n_atoms,
-        c->nl.atom_order, c->n_atoms);
+    T* Dd = D_of<T>(c) + (long)dcol0 * 4 * c->n_atoms;
+#define SG_PROJ(NBV)                                                                                               \
+    k_projection<T, NBV><<<dim3(8 * per * div_up(ncol, NBV)), 256, 6 * ext * sizeof(double), stream>>>(            \
+        x, ldx, ncol, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo, ext, c->atom_pos, c->hx, c->hy, c->hz, \
+        1.0 / (rc * rc), N0, N1, c->nl.gamma4, c->dV, Dd, 4 * c->n_atoms, c->nl.atom_order, c->n_atoms)
+    // columns per workgroup (tuning override SPARC_GPU_PROJ_NB = 2, 4 or 8):
+    // fewer accumulators per thread keep more waves in flight for the gather
+    if (c->proj_nb == 2)
+        SG_PROJ(2);
+    else if (c->proj_nb == 8)
+        SG_PROJ(8);
+    else
+        SG_PROJ(4);
+#undef SG_PROJ
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot, stream);
     return SPARC_OK;
@@ -760,14 +782,39 @@ sparc_status set_veff_impl(sparc_gpu_ctx c, const double* d_veff) {
 }
 
 // lo = min V_eff + nl_lo, hi = kin + max V_eff + nl_hi
-__global__ void k_bounds(const double* v, long n, double kin, double nl_lo, double nl_hi, double* out_lo,
-                         double* out_hi) {
-    __shared__ double smin[1024], smax[1024];
+// Extrema of V_eff: per-block partials (part[2 b], part[2 b + 1]), then one
+// block combines them into the spectrum bounds.
+__global__ __launch_bounds__(256) void k_minmax_part(const double* v, long n, double* part) {
+    __shared__ double smin[256], smax[256];
     double mn = 1e300, mx = -1e300;
-    for (long i = threadIdx.x; i < n; i += blockDim.x) {
-        double x = v[i];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double x = v[i];
         mn = fmin(mn, x);
         mx = fmax(mx, x);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = smin[0];
+        part[2 * blockIdx.x + 1] = smax[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bounds(const double* part, int nblk, double kin, double nl_lo,
+                                                double nl_hi, double* out_lo, double* out_hi) {
+    __shared__ double smin[256], smax[256];
+    double mn = 1e300, mx = -1e300;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        mn = fmin(mn, part[2 * b]);
+        mx = fmax(mx, part[2 * b + 1]);
     }
     smin[threadIdx.x] = mn;
     smax[threadIdx.x] = mx;
@@ -786,8 +833,12 @@ __global__ void k_bounds(const double* v, long n, double kin, double nl_lo, doub
 }
 
 sparc_status bounds_impl(sparc_gpu_ctx c) {
-    k_bounds<<<1, 1024, 0, c->stream>>>(c->veff, c->nd, c->kin_bound, c->nl.nl_lo, c->nl.nl_hi, c->scal + S_LO,
-                                       c->scal + S_HI);
+    const int nblk = (int)std::min<long>(512, div_up(c->nd, 256));
+    sparc_status st = ensure_red(c, 2 * (size_t)nblk);
+    if (st != SPARC_OK) return st;
+    k_minmax_part<<<nblk, 256, 0, c->stream>>>(c->veff, c->nd, c->red);
+    k_bounds<<<1, 256, 0, c->stream>>>(c->red, nblk, c->kin_bound, c->nl.nl_lo, c->nl.nl_hi, c->scal + S_LO,
+                                      c->scal + S_HI);
     SG_CHECK_LAUNCH(c);
     return SPARC_OK;
 }
