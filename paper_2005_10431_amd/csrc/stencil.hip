@@ -452,31 +452,16 @@ __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, lon
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[n][k] = 0.0;
     const long s0 = ip_off[a], s1 = ip_off[a + 1];
-    // two support points per iteration: both index loads, then both sets of
-    // orbital loads, are in flight before either is used
-    const long st = blockDim.x;
-    for (long s = s0 + threadIdx.x; s < s1; s += 2 * st) {
-        const bool two = s + st < s1;
-        const long idx0 = ip_idx[s];
-        const uint32_t b0 = ip_box[s];
-        const long idx1 = two ? ip_idx[s + st] : idx0;
-        const uint32_t b1 = two ? ip_box[s + st] : b0;
-        double v0[NB], v1[NB];
+    for (long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+        const long idx = ip_idx[s];
+        const uint32_t b = ip_box[s];
+        const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
+        const double e = ex[bx] * ey[by] * ez[bz];
+        const double c0 = N0 * e, c1 = N1 * dxt[bx] * e, c2 = N1 * dyt[by] * e, c3 = N1 * dzt[bz] * e;
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
-            v0[n] = (n < nb) ? (double)x[idx0 + (long)(n0 + n) * ldx] : 0.0;
-            v1[n] = (n < nb && two) ? (double)x[idx1 + (long)(n0 + n) * ldx] : 0.0;
-        }
-        const uint32_t bb[2] = {b0, b1};
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const uint32_t b = bb[u];
-            const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
-            const double e = ex[bx] * ey[by] * ez[bz];
-            const double c0 = N0 * e, c1 = N1 * dxt[bx] * e, c2 = N1 * dyt[by] * e, c3 = N1 * dzt[bz] * e;
-#pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                const double v = u == 0 ? v0[n] : v1[n];
+            if (n < nb) {
+                double v = (double)x[idx + (long)(n0 + n) * ldx];
                 acc[n][0] += c0 * v;
                 acc[n][1] += c1 * v;
                 acc[n][2] += c2 * v;
