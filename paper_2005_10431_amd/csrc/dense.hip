@@ -475,7 +475,8 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* 
     // H Y into W
     if ((st = launch_projection<T>(c, X, N, ldx)) != SPARC_OK) return st;
     if ((st = launch_hsweep<T>(c, X, W, nullptr, N, ldx, 0, 0)) != SPARC_OK) return st;
-    if ((st = gemm_tn<T>(c, N, N, c->nd, X, ldx, W, ldx, c->dV, K, N, false)) != SPARC_OK) return st;
+    // dV Y^T (H Y) is symmetric (H is): its upper tiles are computed and mirrored
+    if ((st = gemm_tn<T>(c, N, N, c->nd, X, ldx, W, ldx, c->dV, K, N, true)) != SPARC_OK) return st;
     if ((st = dense_gemm(c, 'N', 'N', N, Linv, K, T1)) != SPARC_OK) return st;
     if ((st = dense_gemm(c, 'N', 'T', N, T1, Linv, Hs)) != SPARC_OK) return st;
     if ((st = dense_symmetrize(c, Hs, N)) != SPARC_OK) return st;

@@ -22,12 +22,13 @@ import time
 import numpy as np
 
 
-def converge(system, rho0=None, tol=1e-10, max_iter=300, ctx=None, n_first=None):
+def converge(system, rho0=None, tol=1e-10, max_iter=300, ctx=None, n_first=None, degree=None):
     """FP64 GPU SCF; returns (history, rho_fixed_point (device), ctx)."""
     from .driver import run_scf
     import workloads as W
     X0 = W.initial_orbitals(system.nd, system.n_states, system.seed)
-    out = run_scf(system, X0, rho0=rho0, prec="fp64", max_iter=max_iter, tol=tol, ctx=ctx, n_first=n_first)
+    out = run_scf(system, X0, rho0=rho0, prec="fp64", max_iter=max_iter, tol=tol, ctx=ctx, n_first=n_first,
+                  degree=degree)
     return out["history"], out["rho_out"], out["ctx"]
 
 
@@ -100,17 +101,17 @@ def train(data, epochs=20, lr=1e-3, seed=0, log=print):
     return w, curve, time.perf_counter() - t0
 
 
-def evaluate(w, data, max_l1=0.5, eps=1e-6, log=print, n_first=None):
+def evaluate(w, data, max_l1=0.5, eps=1e-6, log=print, n_first=None, degree=None):
     """SCF from the network's density against SCF from the atomic guess, both
-    with `n_first` filter passes in the first iteration (the system's value
-    when None)."""
+    with `n_first` filter passes in the first iteration and Chebyshev degree
+    `degree` (the system's values when None)."""
     import torch
     from ._lib import Context
     rows = []
     for d in data:
         s = d["system"]
-        if n_first is not None and n_first != s.n_first:
-            hist_sad, _, ctx0 = converge(s, tol=1e-9, n_first=n_first)
+        if (n_first is not None and n_first != s.n_first) or (degree is not None and degree != s.cheb_degree):
+            hist_sad, _, ctx0 = converge(s, tol=1e-9, n_first=n_first, degree=degree)
             ctx0.close()
         else:
             hist_sad = d["hist"]
@@ -124,7 +125,7 @@ def evaluate(w, data, max_l1=0.5, eps=1e-6, log=print, n_first=None):
         ctx.warm_start(w, pred, max_l1=float("inf"))
         l1_sad = float((sad - d["target"]).abs().sum()) * s.dV / s.n_electrons
         l1_cnn = float((pred - d["target"]).abs().sum()) * s.dV / s.n_electrons
-        hist_cnn, _, _ = converge(s, rho0=rho0, tol=1e-9, ctx=ctx, n_first=n_first)
+        hist_cnn, _, _ = converge(s, rho0=rho0, tol=1e-9, ctx=ctx, n_first=n_first, degree=degree)
         torch.cuda.synchronize()
         ctx.close()
         k_sad = iterations_to(hist_sad, d["f_ref"], s.n_atoms, eps)
@@ -147,6 +148,8 @@ def main(argv=None):
     ap.add_argument("--grid", type=int, default=72)
     ap.add_argument("--eval-first", type=int, nargs="+", default=[None],
                     help="first-iteration filter passes of the evaluation runs (default: the system's)")
+    ap.add_argument("--eval-degree", type=int, default=None,
+                    help="Chebyshev degree of the evaluation runs (default: the system's)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -162,13 +165,14 @@ def main(argv=None):
     evals = []
     for nf in args.eval_first:
         log(f"evaluation with {nf if nf is not None else 'default'} first-iteration passes")
-        rows = evaluate(w, test_set, log=log, n_first=nf)
+        rows = evaluate(w, test_set, log=log, n_first=nf, degree=args.eval_degree)
         k_sad = [r["iters_sad"] for r in rows if r["iters_sad"]]
         k_cnn = [r["iters_cnn"] for r in rows if r["iters_cnn"]]
         ms_sad = [r["ms_sad"] for r in rows if r["ms_sad"]]
         ms_cnn = [r["ms_cnn"] for r in rows if r["ms_cnn"]]
         ev = dict(
             n_first=nf if nf is not None else test_set[0]["system"].n_first,
+            degree=args.eval_degree if args.eval_degree is not None else test_set[0]["system"].cheb_degree,
             mean_iters_sad=float(np.mean(k_sad)), mean_iters_cnn=float(np.mean(k_cnn)),
             mean_ms_sad=float(np.mean(ms_sad)), mean_ms_cnn=float(np.mean(ms_cnn)),
             cnn_used=int(sum(r["used_cnn"] for r in rows)),
