@@ -310,7 +310,7 @@ __device__ inline double start_value(int i, int k) {
 }
 
 // Inverse iteration for the eigenvectors of T, one thread per cluster of
-// close eigenvalues (consecutive indices whose gaps are below 1e-3 ||T||);
+// close eigenvalues (consecutive indices whose gaps are below 1e-5 ||T||);
 // members of a cluster are shifted apart by a few ulps and Gram-Schmidt
 // orthogonalised against the earlier members at every step.  Scratch is
 // interleaved by thread (element i of thread c at i * nthr + c) so that a
@@ -554,10 +554,13 @@ __global__ __launch_bounds__(64) void k_stein_lds(const double* d, const double*
 #undef SG_L
 }
 
-// Clusters of consecutive eigenvalues of T with gaps below 1e-3 ||T||
-// (Gershgorin norm, floored as in the inverse iteration); one workgroup:
-// the norm by a block reduction, the gap flags in LDS, the compaction by
-// one thread over LDS.
+// Clusters of consecutive eigenvalues of T with gaps below 1e-5 ||T||
+// (Gershgorin norm, floored as in the inverse iteration).  Eigenvectors of
+// different clusters come out orthogonal to about eps ||T|| / gap <= 2e-11
+// without re-orthogonalisation; a wider threshold chains the closely spaced
+// Ritz values of large subspaces into long clusters that one thread
+// orthogonalises serially.  One workgroup: the norm by a block reduction,
+// the compaction by one thread over the eigenvalues in LDS.
 __global__ __launch_bounds__(256) void k_clusters(const double* d, const double* e, const double* lam, int N,
                                                   int* cl_start, int* ncl) {
     extern __shared__ double shc[];
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(256) void k_clusters(const double* d, const double*
     __syncthreads();
     if (t != 0) return;
     const double tnorm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    const double gap = 1e-3 * fmax(tnorm, 1e-100);
+    const double gap = 1e-5 * fmax(tnorm, 1e-100);
     int n = 0;
     cl_start[n++] = 0;
     for (int k = 1; k < N; ++k)

@@ -100,7 +100,7 @@ struct SweepGeom {
     long plane, pxy;
     int nz, col, hn;
     bool active;
-    int goff[3], loff[3], poff[3];
+    int goff[6], loff[6], poff[6];  // per halo value of this thread (HM <= 6 used)
     int lrow;  // LDS offset of this thread's own point
     int W, nx, lx, ly, gy, t, nt;
     // LDS tables of the slab's projector candidates (K of them):
@@ -596,7 +596,7 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     const long nblocks = (long)ncol * a.ntiles_y;
     if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "too many blocks");
     const int hm = div_up(2L * kMaxHalfOrder * c->nx, threads);
-    if (hm > 3) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
+    if (hm > (nl ? 6 : 3)) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
     const int slot = prof_begin(c, mode == 2 ? PK_SWEEP : (mode == 1 ? PK_SWEEP1 : PK_APPLY), stream);
     const dim3 g((unsigned)nblocks), b(threads);
 #define SG_LAUNCH_SWEEP(NLV, MV, HMV) k_hsweep<T, NLV, MV, HMV><<<g, b, shmem, stream>>>(a)
@@ -606,15 +606,25 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
         else if (hm == 2) SG_LAUNCH_SWEEP(NLV, MV, 2); \
         else SG_LAUNCH_SWEEP(NLV, MV, 3); \
     } while (0)
+    // the nonlocal variant's slab can be as low as 2 rows on wide grids
+    // (its candidate tables share the LDS), hence up to 6 halo values
+#define SG_SWEEP_HM_NL(MV)            \
+    do {                              \
+        if (hm <= 3) SG_SWEEP_HM(true, MV); \
+        else if (hm == 4) SG_LAUNCH_SWEEP(true, MV, 4); \
+        else if (hm == 5) SG_LAUNCH_SWEEP(true, MV, 5); \
+        else SG_LAUNCH_SWEEP(true, MV, 6); \
+    } while (0)
     if (nl) {
-        if (mode == 0) SG_SWEEP_HM(true, 0);
-        else if (mode == 1) SG_SWEEP_HM(true, 1);
-        else SG_SWEEP_HM(true, 2);
+        if (mode == 0) SG_SWEEP_HM_NL(0);
+        else if (mode == 1) SG_SWEEP_HM_NL(1);
+        else SG_SWEEP_HM_NL(2);
     } else {
         if (mode == 0) SG_SWEEP_HM(false, 0);
         else if (mode == 1) SG_SWEEP_HM(false, 1);
         else SG_SWEEP_HM(false, 2);
     }
+#undef SG_SWEEP_HM_NL
 #undef SG_SWEEP_HM
 #undef SG_LAUNCH_SWEEP
     SG_CHECK_LAUNCH(c);

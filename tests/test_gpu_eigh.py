@@ -6,8 +6,8 @@ Eigenvalues must agree to 1e-12 ||A||; eigenvectors are checked through the
 residual ||A V - V diag(lam)|| and the orthogonality ||V^T V - I||, which hold
 whatever basis the solver picks inside a degenerate eigenspace.  The
 orthogonality bound between eigenvectors of different clusters of an
-inverse-iteration solver is eps ||A|| / gap with gap >= 1e-3 ||A||, so the
-bound below is 1e-11.
+inverse-iteration solver is eps ||A|| / gap with gap >= 1e-5 ||A|| (the
+cluster threshold), about 2e-11; the bound below is 5e-11.
 """
 import numpy as np
 import pytest
@@ -81,4 +81,4 @@ def test_subspace_eigh(case):
     assert np.all(np.diff(lam) >= 0.0)
     assert eerr <= 1e-12
     assert res <= 1e-11
-    assert orth <= 1e-11
+    assert orth <= 5e-11

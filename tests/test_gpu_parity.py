@@ -298,3 +298,21 @@ def test_filter_split_over_two_streams_is_bitwise_identical(monkeypatch):
         ctx.close()
     log("split filter: max |diff|", float(np.max(np.abs(outs[0] - outs[1]))))
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_apply_H_wide_grid_many_halo_values():
+    """200 x 14 x 13 grid: the nonlocal sweep's slab shrinks to 2 rows and
+    each thread carries 6 halo values per plane."""
+    torch = require_gpu()
+    s = W.tiny_system(n=(200, 14, 13), L=(30.0, 4.2, 3.9), n_atoms=4, seed=9)
+    log("apply_H wide grid", s.n)
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 23)
+    X = W.initial_orbitals(s.nd, 5, 3)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Yd = torch.zeros_like(Xd)
+    ctx.apply_H(Xd, Yd)
+    Yref = hamiltonian.apply_H(s, v, projs, X)
+    assert rel_err(to_np(Yd), Yref) <= 1e-12

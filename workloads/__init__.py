@@ -251,6 +251,16 @@ def cnn_initial_weights(seed: int = 0) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+def initial_orbitals_rows(nd: int, ns: int, seed: int = 0, rows: int = 16):
+    """The rows of ``initial_orbitals(nd, ns, seed)`` in consecutive chunks of
+    at most ``rows`` (same generator stream, so the values are identical),
+    for blocks too large to build on the host at once.  Yields (row0, array)."""
+    rng = np.random.default_rng([seed, 11])
+    for r0 in range(0, ns, rows):
+        k = min(rows, ns - r0)
+        yield r0, rng.uniform(-0.5, 0.5, (k, nd))
+
+
 CONFIG_NAMES = {
     "cfg1": config1,
     "cfg2": config2,
