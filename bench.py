@@ -113,6 +113,46 @@ def traffic_probe(system, prec):
     print("probe: done", flush=True)
 
 
+def fp32_accuracy(system, tol64=1e-7, tol32=1e-6, max_iter=200):
+    """The FP32 form against FP64 on the same workload and seed: both SCFs to
+    convergence (FP32 followed by one FP64 Rayleigh-Ritz), then the free
+    energy per atom, occupied eigenvalues and density compared."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2005_10431_amd.driver import run_scf
+
+    X0 = W.initial_orbitals(system.nd, system.n_states, system.seed)
+    t0 = time.perf_counter()
+    r64 = run_scf(system, X0, prec="fp64", max_iter=max_iter, tol=tol64)
+    r32 = run_scf(system, X0, prec="fp32", max_iter=max_iter, tol=tol32, final_fp64_rr=True)
+    torch.cuda.synchronize()
+    f64 = r64["history"][-1]["free_energy"] / system.n_atoms
+    f32 = r32["final"]["free_energy"] / system.n_atoms
+    occ = r64["occ"].cpu().numpy()
+    dl = np.abs(r32["final"]["eig"] - r64["eig"].cpu().numpy())
+    rho64 = r64["rho_out"].cpu().numpy()
+    rho32 = r32["rho_out"].cpu().numpy()
+    out = {
+        "free_energy_per_atom_fp64": f64,
+        "abs_diff_per_atom": abs(f32 - f64),
+        # fully occupied states, and the partly occupied ones at the Fermi
+        # level (which sit next to the filter cut, where the subspace
+        # converges slowest, and carry little weight in F and rho)
+        "max_abs_dlambda_full": float(np.max(dl[occ > 1.9])),
+        "max_abs_dlambda_partial": float(np.max(dl[(occ > 1e-6) & (occ <= 1.9)])) if np.any((occ > 1e-6) & (occ <= 1.9)) else 0.0,
+        "density_l1_per_electron": float(system.dV * np.sum(np.abs(rho32 - rho64)) / system.n_electrons),
+        "iterations": {"fp64": len(r64["history"]), "fp32": len(r32["history"])},
+        "residual_tol": {"fp64": tol64, "fp32": tol32},
+        "target_abs_diff_per_atom": 1e-5,
+        "seconds": time.perf_counter() - t0,
+    }
+    for r in (r64, r32):
+        r["ctx"].close()
+    return out
+
+
 def cnn_measure(steps: int = 10):
     """Forward pass of the warm-start network on the 72^3 snapshot grid:
     average time per forward and of its 16 -> 16 convolution, against the
@@ -171,6 +211,8 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=40, help="columns in the CPU oracle sample (0: skip)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-filter companion measurement")
     ap.add_argument("--no-cnn", action="store_true", help="skip the warm-start network measurement")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the converged FP32-vs-FP64 comparison on the workload")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only one degree-3 filter of the workload and a plain copy of known size "
                          "(the program profiled with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
@@ -300,6 +342,8 @@ def main():
         line["fp32"] = {"filter_gbs": r32["filter_gbs"], "ms_per_step": r32["ms_per_step"],
                         "scf_step_breakdown_ms": {k: r32[k] for k in ("t_potential_ms", "t_filter_ms",
                                                                        "t_rr_ms", "t_density_ms")}}
+    if args.prec == "fp64" and not args.no_fp32 and not args.no_accuracy:
+        line["fp32"]["accuracy_vs_fp64"] = fp32_accuracy(system)
     if not args.no_cnn:
         line["warm_start_cnn"] = cnn_measure()
     if args.cpu_cols > 0:
