@@ -247,19 +247,6 @@ __global__ void k_projector_values(const int* img_off, const int* img_ijk, const
     chi[4 * s + 3] = v3;
 }
 
-__global__ void k_gather_chi(const int* pt_src, long n, const double* sup_chi, double* pt_chi, float* pt_chi32,
-                             float* sup_chi32) {
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    int s = pt_src[e];
-    for (int k = 0; k < 4; ++k) {
-        double v = sup_chi[4 * (long)s + k];
-        pt_chi[4 * e + k] = v;
-        pt_chi32[4 * e + k] = (float)v;
-        sup_chi32[4 * e + k] = (float)sup_chi[4 * e + k];
-    }
-}
-
 // dV ||chi_lm||^2 per atom (one block per atom).
 __global__ void k_projector_norms(const long* sup_off, const double* chi, double dV, double* norms) {
     int a = blockIdx.x;
@@ -623,8 +610,6 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             std::vector<uint32_t> ent(img_pts.size());
             std::vector<int> fill(c->pe_off_host.begin(), c->pe_off_host.end() - 1);
             for (auto& q : img_pts) ent[fill[q.first]++] = q.second;
-            if ((st = upload(c, &T.pe_off, c->pe_off_host)) != SPARC_OK) return st;
-            if ((st = upload(c, &T.pe_ent, ent)) != SPARC_OK) return st;
             T.n_pe = (long)ent.size();
             // slab height: the largest (up to the 512-thread workgroup) whose
             // FP64 sweep tables fit in LDS
@@ -642,18 +627,6 @@ sparc_status build_tables(sparc_gpu_ctx c) {
                 T.slab_cand = nullptr;
                 T.slab_k = nullptr;
                 c->err.clear();
-            }
-        }
-        // point-major inverse lists (entries per point in atom order)
-        std::vector<int> pt_off(c->nd + 1, 0), pt_atom(T.n_sup), pt_src(T.n_sup);
-        for (long s = 0; s < T.n_sup; ++s) pt_off[sup_idx[s] + 1]++;
-        for (long p = 0; p < c->nd; ++p) pt_off[p + 1] += pt_off[p];
-        {
-            std::vector<int> fill(pt_off.begin(), pt_off.end() - 1);
-            for (long s = 0; s < T.n_sup; ++s) {
-                int e = fill[sup_idx[s]]++;
-                pt_atom[e] = sup_atom[s];
-                pt_src[e] = (int)s;
             }
         }
         // Morton order of the atoms (10 bits per axis of the fractional position)
@@ -682,7 +655,7 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             g4[4 * a] = c->gamma[2 * a];
             g4[4 * a + 1] = g4[4 * a + 2] = g4[4 * a + 3] = c->gamma[2 * a + 1];
         }
-        int *d_img_off = nullptr, *d_img_ijk = nullptr, *d_sup_atom = nullptr, *d_pt_src = nullptr;
+        int *d_img_off = nullptr, *d_img_ijk = nullptr, *d_sup_atom = nullptr;
         double* d_pos = nullptr;
         if (T.box_ext > 255) return set_err(c, SPARC_ERR_ARG, "projector support box wider than 255 points");
         if ((st = upload(c, &T.ip_off, ip_off)) != SPARC_OK) return st;
@@ -690,20 +663,13 @@ sparc_status build_tables(sparc_gpu_ctx c) {
         if ((st = upload(c, &T.ip_box, ip_box)) != SPARC_OK) return st;
         if ((st = upload(c, &T.box_lo, box_lo)) != SPARC_OK) return st;
         if ((st = upload(c, &T.sup_off, sup_off)) != SPARC_OK) return st;
-        if ((st = upload(c, &T.sup_idx, sup_idx)) != SPARC_OK) return st;
-        if ((st = upload(c, &T.pt_off, pt_off)) != SPARC_OK) return st;
-        if ((st = upload(c, &T.pt_atom, pt_atom)) != SPARC_OK) return st;
         if ((st = upload(c, &T.gamma4, g4)) != SPARC_OK) return st;
         if ((st = upload(c, &d_img_off, img_off)) != SPARC_OK) return st;
         if ((st = upload(c, &d_img_ijk, img_ijk)) != SPARC_OK) return st;
         if ((st = upload(c, &d_sup_atom, sup_atom)) != SPARC_OK) return st;
-        if ((st = upload(c, &d_pt_src, pt_src)) != SPARC_OK) return st;
         if ((st = upload(c, &d_pos, c->pos)) != SPARC_OK) return st;
         long ns = std::max<long>(T.n_sup, 1);
         SG_HIP(c, hipMalloc((void**)&T.sup_chi, 4 * ns * sizeof(double)));
-        SG_HIP(c, hipMalloc((void**)&T.sup_chi32, 4 * ns * sizeof(float)));
-        SG_HIP(c, hipMalloc((void**)&T.pt_chi, 4 * ns * sizeof(double)));
-        SG_HIP(c, hipMalloc((void**)&T.pt_chi32, 4 * ns * sizeof(float)));
         double rc = c->rc_nl;
         double N0 = std::pow(2.0 / (pi * rc * rc), 0.75);
         double N1 = (2.0 / rc) * N0;
@@ -711,9 +677,6 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             k_projector_values<<<div_up(T.n_sup, 256), 256, 0, c->stream>>>(
                 d_img_off, d_img_ijk, d_sup_atom, d_pos, T.n_sup, c->hx, c->hy, c->hz, 1.0 / (rc * rc), N0, N1,
                 T.sup_chi);
-            SG_CHECK_LAUNCH(c);
-            k_gather_chi<<<div_up(T.n_sup, 256), 256, 0, c->stream>>>(d_pt_src, T.n_sup, T.sup_chi, T.pt_chi,
-                                                                      T.pt_chi32, T.sup_chi32);
             SG_CHECK_LAUNCH(c);
         }
         double* d_norms = nullptr;
@@ -734,7 +697,6 @@ sparc_status build_tables(sparc_gpu_ctx c) {
         hipFree(d_img_off);
         hipFree(d_img_ijk);
         hipFree(d_sup_atom);
-        hipFree(d_pt_src);
         hipFree(d_pos);
         SG_HIP(c, hipMalloc((void**)&c->D, std::max<size_t>(1, 4 * (size_t)c->n_atoms * c->n_states) * sizeof(double)));
         SG_HIP(c, hipMalloc((void**)&c->D32, std::max<size_t>(1, 4 * (size_t)c->n_atoms * c->n_states) * sizeof(float)));
@@ -837,6 +799,8 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     if (const char* e = std::getenv("SPARC_GPU_EIG")) c->eig_jacobi = std::string(e) == "jacobi";
     if (const char* e = std::getenv("SPARC_GPU_SPLIT_FILTER")) c->split_filter = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_PROJ_NB")) c->proj_nb = std::atoi(e);
+    if (const char* e = std::getenv("SPARC_GPU_GEMM_TILE")) c->gemm_tile = std::atoi(e);
+    if (const char* e = std::getenv("SPARC_GPU_GEMM_NN_COLS")) c->gemm_nn_cols = std::atoi(e);
 
     int dev = 0;
     sparc_status st = SPARC_OK;
@@ -861,10 +825,8 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
     hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->veff, c->veff32, c->b, c->pois_ux, c->pois_uy, c->pois_uz, c->pois_inv, c->work, c->D,
                     c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,
-                    c->nl.sup_idx, c->nl.sup_chi, c->nl.sup_chi32, c->nl.pt_off, c->nl.pt_atom, c->nl.pt_chi,
-                    c->nl.pt_chi32, c->nl.gamma4, c->nl.atom_order, c->nl.pe_off, c->nl.pe_ent, c->atom_pos,
-                    c->nl.pe8, c->nl.slab_cand, c->nl.slab_k, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box,
-                    c->nl.box_lo};
+                    c->nl.sup_chi, c->nl.gamma4, c->nl.atom_order, c->atom_pos, c->nl.pe8, c->nl.slab_cand,
+                    c->nl.slab_k, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo};
     for (void* p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < 8; ++i)

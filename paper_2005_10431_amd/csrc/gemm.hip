@@ -196,6 +196,9 @@ sparc_status gemm_tn(sparc_gpu_ctx c, int M, int N, long K, const T* A, long lda
     const int mx = std::max(M, N);
     if (mx <= 32) return gemm_tn_launch<T, 1>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
     if (mx <= 64) return gemm_tn_launch<T, 2>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
+    // 160-wide tiles (one wave per SIMD) or 128-wide (two per SIMD); tuning
+    // override SPARC_GPU_GEMM_TILE = 128 | 160
+    if (c->gemm_tile == 128) return gemm_tn_launch<T, 4>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
     return gemm_tn_launch<T, 5>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
 }
 
@@ -290,7 +293,10 @@ sparc_status gemm_nn(sparc_gpu_ctx c, long K, int N, int M, const T* A, long lda
                      long ldo) {
     if (N <= 32) return gemm_nn_launch<T, 1>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
     if (N <= 96) return gemm_nn_launch<T, 3>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
-    return gemm_nn_launch<T, 9>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
+    // 160-column tiles (two waves per SIMD) or 288-column (one per SIMD,
+    // fewer passes over A); tuning override SPARC_GPU_GEMM_NN_COLS = 160 | 288
+    if (c->gemm_nn_cols == 288) return gemm_nn_launch<T, 9>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
+    return gemm_nn_launch<T, 5>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
 }
 
 template sparc_status gemm_tn<double>(sparc_gpu_ctx, int, int, long, const double*, long, const double*, long, double,

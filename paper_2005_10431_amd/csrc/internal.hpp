@@ -31,31 +31,20 @@ struct CandInfo {
 };
 
 // Nonlocal projector tables on the device.
-//  Atom-major (for projections):   atom a owns support entries
-//     s in [sup_off[a], sup_off[a+1]):  grid index sup_idx[s],
-//     values sup_chi[4*s + lm]  (lm = s, px, py, pz; images summed).
-//  Point-major (for the apply):    point p owns entries
-//     e in [pt_off[p], pt_off[p+1]):    atom pt_atom[e],
-//     values pt_chi[4*e + lm].
+//  - projection: the image points of each atom's ball (ip_*), with the
+//    projector values evaluated from per-axis Gaussian tables;
+//  - apply (inside the sweep): per-slab candidate (atom, image) lists and a
+//    per-point word of candidate indices (pe8, slab_*);
+//  - spectral bound: projector values per unique support point (sup_*).
 struct NonlocalTables {
     int n_atoms = 0;
     long n_sup = 0;
-    long* sup_off = nullptr;   // n_atoms + 1
-    int* sup_idx = nullptr;    // n_sup
-    double* sup_chi = nullptr; // 4 n_sup
-    float* sup_chi32 = nullptr;
-    int* pt_off = nullptr;     // N_d + 1
-    int* pt_atom = nullptr;    // n_sup
-    double* pt_chi = nullptr;  // 4 n_sup
-    float* pt_chi32 = nullptr;
+    long* sup_off = nullptr;   // n_atoms + 1: each atom's unique support points
+    double* sup_chi = nullptr; // 4 n_sup projector values (summed over images; for the spectral bound)
     double* gamma4 = nullptr;  // 4 n_atoms: (g_s, g_p, g_p, g_p)
     int* atom_order = nullptr; // atoms in space-filling (Morton) order
-    // Image-level point-major entries for the sweep: point p owns entries
-    // [pe_off[p], pe_off[p+1]) of pe_ent, each packing the atom index
-    // (bits 0-19) and its periodic image shifts + 8 (bits 20-23 x, 24-27 y,
-    // 28-31 z); the projector values are evaluated on the fly.
-    int* pe_off = nullptr;
-    uint32_t* pe_ent = nullptr;
+    // number of image-level (point, atom, image) entries; the sweep's
+    // per-slab tables are built from them on the host
     long n_pe = 0;
     // per-slab candidate tables of the sweep (see build_slab_tables)
     uint64_t* pe8 = nullptr;
@@ -139,14 +128,15 @@ struct sparc_gpu_ctx_s {
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int split_filter = 0;       // SPARC_GPU_SPLIT_FILTER=1: filter halves on two streams
     int proj_nb = 4;            // SPARC_GPU_PROJ_NB: orbitals per projection workgroup (2, 4, 8)
+    int gemm_tile = 160;        // SPARC_GPU_GEMM_TILE: Gram/projected-H tile edge (128, 160)
+    int gemm_nn_cols = 160;     // SPARC_GPU_GEMM_NN_COLS: rotation tile width (160, 288)
     hipGraphExec_t jac_exec = nullptr;
     int jac_N = 0;
     double *jac_A = nullptr, *jac_A2 = nullptr, *jac_V = nullptr, *jac_V2 = nullptr;
     int sweep_slab_major = 0;   // block order of the sweep kernel
     int debug = 0;              // SPARC_GPU_DEBUG: diagnostics on stderr
     int eig_jacobi = 0;         // SPARC_GPU_EIG=jacobi: parallel Jacobi instead of tridiagonal
-    std::vector<int> pe_off_host;  // host copy of nl.pe_off (slab-plane maxima)
-    int emax_ty = -1, emax_val = 0;
+    std::vector<int> pe_off_host;  // point offsets of the image-level entries (host)
     int nl_ty = 6;                 // slab height of the nonlocal sweep
     double* atom_pos = nullptr;    // 3 n_atoms
 
