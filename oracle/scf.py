@@ -144,6 +144,48 @@ def mix(rho_in, rho_out, beta, sys=None, kerker_q0: float = 0.0):
     return rho_in + beta * d
 
 
+class PeriodicPulay:
+    """Periodic Pulay mixing (the SCF accelerator of Sec. 2.1): with
+    x_k = rho_in and f_k = rho_out - rho_in, keep the last `m` differences
+    dX = x_j - x_{j-1}, dF = f_j - f_{j-1}.  Every `period`-th iteration
+    (k + 1 divisible by `period`, once there is history) take the
+    least-squares combination
+        gamma = argmin || f_k - dF gamma ||,
+        x_bar = x_k - dX gamma,   f_bar = f_k - dF gamma,
+        x_{k+1} = x_bar + beta P f_bar;
+    otherwise the linear step x_{k+1} = x_k + beta P f_k.  P is the optional
+    Kerker-type preconditioner (identity when q0 = 0)."""
+
+    def __init__(self, m: int, period: int, beta: float, sys=None, kerker_q0: float = 0.0):
+        self.m, self.period, self.beta = m, period, beta
+        self.sys, self.q0 = sys, kerker_q0
+        self.dX, self.dF = [], []
+        self.x_prev = self.f_prev = None
+        self.k = 0
+
+    def _precondition(self, f):
+        return kerker(self.sys, f, self.q0) if self.q0 > 0.0 else f
+
+    def step(self, x, f):
+        if self.x_prev is not None and self.m > 0:
+            self.dX.append(x - self.x_prev)
+            self.dF.append(f - self.f_prev)
+            if len(self.dX) > self.m:
+                self.dX.pop(0)
+                self.dF.pop(0)
+        self.x_prev, self.f_prev = x.copy(), f.copy()
+        pulay = self.m > 0 and len(self.dF) > 0 and (self.k + 1) % self.period == 0
+        self.k += 1
+        if not pulay:
+            return x + self.beta * self._precondition(f)
+        F = np.stack(self.dF, axis=1)
+        Xd = np.stack(self.dX, axis=1)
+        gamma = np.linalg.solve(F.T @ F, F.T @ f)
+        xb = x - Xd @ gamma
+        fb = f - F @ gamma
+        return xb + self.beta * self._precondition(fb)
+
+
 @dataclass
 class SCFResult:
     X: np.ndarray
@@ -169,7 +211,8 @@ def scf(sys, X0: np.ndarray, rho0: np.ndarray = None, max_iter: int = 50, tol: f
          filter(X, m, a, hi, a0) -> Rayleigh-Ritz, after each of which
          a = max Ritz value and a0 = min Ritz value.
       4. Occupations, rho_out, Harris-Foulkes free energy at rho_in,
-         residual ||rho_out - rho_in|| / ||rho_out||, linear mixing.
+         residual ||rho_out - rho_in|| / ||rho_out||, then linear mixing, or
+         periodic Pulay mixing when ``sys.pulay_history`` > 0.
     Stops after the iteration whose residual is below ``tol``.
     Parity unpinned: away from the fixed point only GPU <-> oracle agreement
     is checked."""
@@ -180,6 +223,9 @@ def scf(sys, X0: np.ndarray, rho0: np.ndarray = None, max_iter: int = 50, tol: f
     rho_in = atoms.sad_density(sys) if rho0 is None else rho0.copy()
     X = X0.copy()
     a = a0 = None
+    pulay = None
+    if getattr(sys, "pulay_history", 0) > 0:
+        pulay = PeriodicPulay(sys.pulay_history, sys.pulay_period, beta, sys, getattr(sys, "kerker_q0", 0.0))
     hist = []
     res = None
     for it in range(max_iter):
@@ -202,7 +248,10 @@ def scf(sys, X0: np.ndarray, rho0: np.ndarray = None, max_iter: int = 50, tol: f
         if callback is not None:
             callback(rec)
         rho_prev = rho_in
-        rho_in = mix(rho_in, rho_out, beta, sys, getattr(sys, "kerker_q0", 0.0))
+        if pulay is not None:
+            rho_in = pulay.step(rho_in, rho_out - rho_in)
+        else:
+            rho_in = mix(rho_in, rho_out, beta, sys, getattr(sys, "kerker_q0", 0.0))
         if res < tol:
             break
     return SCFResult(X=X, lam=lam, g=g, mu=mu, rho_in=rho_prev, rho_out=rho_out, history=hist)

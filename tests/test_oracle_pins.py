@@ -409,3 +409,56 @@ def test_scf_fixed_point_independent_of_start():
     fa, fb = ra.history[-1]["free"], rb.history[-1]["free"]
     assert abs(fa - fb) / s.n_atoms < 1e-9
     np.testing.assert_allclose(ra.lam[:8], rb.lam[:8], atol=1e-7)
+
+
+# ---------------------------------------------------------------- Pulay mixing
+
+def test_pulay_solves_linear_fixed_point_in_dim_plus_one_steps():
+    """On a linear map x -> A x + b of dimension n, Pulay (Anderson)
+    extrapolation at every step with history >= n reaches the fixed point
+    after n + 1 steps (the residuals span the Krylov space)."""
+    rng = np.random.default_rng(11)
+    n = 6
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * rng.uniform(-0.9, 0.9, n)) @ Q.T
+    b = rng.standard_normal(n)
+    xstar = np.linalg.solve(np.eye(n) - A, b)
+    mixer = scf.PeriodicPulay(m=n, period=1, beta=0.5)
+    x = np.zeros(n)
+    for _ in range(n + 2):
+        x = mixer.step(x, A @ x + b - x)
+    assert np.linalg.norm(x - xstar) <= 1e-9 * np.linalg.norm(xstar)
+    # plain linear mixing is nowhere near after the same number of steps
+    y = np.zeros(n)
+    for _ in range(n + 2):
+        y = y + 0.5 * (A @ y + b - y)
+    assert np.linalg.norm(y - xstar) > 1e-3 * np.linalg.norm(xstar)
+
+
+def test_pulay_without_history_is_linear_mixing_and_residual_is_orthogonal():
+    rng = np.random.default_rng(12)
+    x, f = rng.standard_normal(50), rng.standard_normal(50)
+    assert np.array_equal(scf.PeriodicPulay(m=0, period=1, beta=0.3).step(x, f), x + 0.3 * f)
+    mixer = scf.PeriodicPulay(m=4, period=1, beta=0.3)
+    xs = [rng.standard_normal(50) for _ in range(5)]
+    fs = [rng.standard_normal(50) for _ in range(5)]
+    for xk, fk in zip(xs[:-1], fs[:-1]):
+        mixer.step(xk, fk)
+    F = np.stack([fs[j] - fs[j - 1] for j in range(1, 5)], axis=1)
+    Xd = np.stack([xs[j] - xs[j - 1] for j in range(1, 5)], axis=1)
+    new = mixer.step(xs[-1], fs[-1])
+    gamma = np.linalg.lstsq(F, fs[-1], rcond=None)[0]
+    fbar = fs[-1] - F @ gamma
+    assert np.max(np.abs(F.T @ fbar)) < 1e-10
+    np.testing.assert_allclose(new, xs[-1] - Xd @ gamma + 0.3 * fbar, atol=1e-12)
+
+
+def test_pulay_off_period_steps_are_kerker_linear_mixing():
+    """Between Pulay steps the mixer is exactly the preconditioned linear
+    step; a period longer than the run leaves only those."""
+    sys_ = W.tiny_system(n=(14, 14, 16))
+    rng = np.random.default_rng(13)
+    mixer = scf.PeriodicPulay(m=5, period=100, beta=0.3, sys=sys_, kerker_q0=1.0)
+    for _ in range(4):
+        x, f = rng.standard_normal(sys_.nd), rng.standard_normal(sys_.nd)
+        np.testing.assert_allclose(mixer.step(x, f), scf.mix(x, x + f, 0.3, sys_, 1.0), rtol=0, atol=1e-13)

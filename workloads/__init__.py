@@ -64,6 +64,8 @@ class System:
     cheb_degree: int = 12
     mix_beta: float = 0.3
     kerker_q0: float = 0.0     # 0: plain linear mixing
+    pulay_history: int = 0     # 0: no Pulay extrapolation (linear mixing only)
+    pulay_period: int = 2      # Pulay extrapolation every pulay_period-th iteration
     n_first: int = 4                 # filter passes in the first SCF iteration
     seed: int = 0
     meta: dict = field(default_factory=dict)
