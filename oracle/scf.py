@@ -154,10 +154,15 @@ class PeriodicPulay:
         x_bar = x_k - dX gamma,   f_bar = f_k - dF gamma,
         x_{k+1} = x_bar + beta P f_bar;
     otherwise the linear step x_{k+1} = x_k + beta P f_k.  P is the optional
-    Kerker-type preconditioner (identity when q0 = 0)."""
+    Kerker-type preconditioner (identity when q0 = 0).
 
-    def __init__(self, m: int, period: int, beta: float, sys=None, kerker_q0: float = 0.0):
-        self.m, self.period, self.beta = m, period, beta
+    restart: the restarted variant the paper uses; the paper does not spell
+    out the rule, and here the history is discarded after a Pulay step that
+    used a full history of m pairs (the next pair is formed from x_k, f_k)."""
+
+    def __init__(self, m: int, period: int, beta: float, sys=None, kerker_q0: float = 0.0,
+                 restart: bool = False):
+        self.m, self.period, self.beta, self.restart = m, period, beta, restart
         self.sys, self.q0 = sys, kerker_q0
         self.dX, self.dF = [], []
         self.x_prev = self.f_prev = None
@@ -183,6 +188,8 @@ class PeriodicPulay:
         gamma = np.linalg.solve(F.T @ F, F.T @ f)
         xb = x - Xd @ gamma
         fb = f - F @ gamma
+        if self.restart and len(self.dF) == self.m:
+            self.dX, self.dF = [], []
         return xb + self.beta * self._precondition(fb)
 
 
@@ -225,7 +232,8 @@ def scf(sys, X0: np.ndarray, rho0: np.ndarray = None, max_iter: int = 50, tol: f
     a = a0 = None
     pulay = None
     if getattr(sys, "pulay_history", 0) > 0:
-        pulay = PeriodicPulay(sys.pulay_history, sys.pulay_period, beta, sys, getattr(sys, "kerker_q0", 0.0))
+        pulay = PeriodicPulay(sys.pulay_history, sys.pulay_period, beta, sys, getattr(sys, "kerker_q0", 0.0),
+                              bool(getattr(sys, "pulay_restart", 0)))
     hist = []
     res = None
     for it in range(max_iter):

@@ -462,3 +462,29 @@ def test_pulay_off_period_steps_are_kerker_linear_mixing():
     for _ in range(4):
         x, f = rng.standard_normal(sys_.nd), rng.standard_normal(sys_.nd)
         np.testing.assert_allclose(mixer.step(x, f), scf.mix(x, x + f, 0.3, sys_, 1.0), rtol=0, atol=1e-13)
+
+
+def test_pulay_single_pair_is_projection_and_restart_clears_full_history():
+    """With one difference pair the least-squares weight is the projection
+    <dF, f> / <dF, dF>; the restarted form forgets a full history after it
+    has been used, so the step after a restart again sees exactly one pair."""
+    rng = np.random.default_rng(14)
+    xs = [rng.standard_normal(40) for _ in range(5)]
+    fs = [rng.standard_normal(40) for _ in range(5)]
+    mixer = scf.PeriodicPulay(m=2, period=1, beta=0.25, restart=True)
+    out = [mixer.step(xk, fk) for xk, fk in zip(xs, fs)]
+
+    def one_pair(k):
+        dx, df = xs[k] - xs[k - 1], fs[k] - fs[k - 1]
+        g = np.dot(df, fs[k]) / np.dot(df, df)
+        return xs[k] - g * dx + 0.25 * (fs[k] - g * df)
+
+    np.testing.assert_array_equal(out[0], xs[0] + 0.25 * fs[0])
+    np.testing.assert_allclose(out[1], one_pair(1), atol=1e-12)
+    # iteration 2 uses the pairs (1, 2) and fills the history -> restart
+    assert len(mixer.dF) == 0
+    np.testing.assert_allclose(out[3], one_pair(3), atol=1e-12)
+    # without restart iteration 3 would have used two pairs
+    keep = scf.PeriodicPulay(m=2, period=1, beta=0.25)
+    out_keep = [keep.step(xk, fk) for xk, fk in zip(xs, fs)]
+    assert np.max(np.abs(out_keep[3] - one_pair(3))) > 1e-3

@@ -66,6 +66,7 @@ class System:
     kerker_q0: float = 0.0     # 0: plain linear mixing
     pulay_history: int = 0     # 0: no Pulay extrapolation (linear mixing only)
     pulay_period: int = 2      # Pulay extrapolation every pulay_period-th iteration
+    pulay_restart: int = 0     # 1: discard the history after a Pulay step on a full history
     n_first: int = 4                 # filter passes in the first SCF iteration
     seed: int = 0
     meta: dict = field(default_factory=dict)
