@@ -244,7 +244,10 @@ def main():
         ctx.sad_density(rho)
         eig = torch.empty(ns, dtype=torch.float64, device="cuda")
         occ = torch.empty_like(eig)
-        st = make_state(rho, X, eig, occ, m, system.n_first, system.mix_beta, None, system.kerker_q0)
+        ph = system.pulay_history
+        hist = torch.empty((2 * ph + 2) * nd, dtype=torch.float64, device="cuda") if ph > 0 else None
+        st = make_state(rho, X, eig, occ, m, system.n_first, system.mix_beta, None, system.kerker_q0, ph,
+                        system.pulay_period, bool(system.pulay_restart), hist)
         first = ctx.scf_step(st)                      # iteration 0 (initial RR + n_first passes)
         for _ in range(warmup):
             ctx.scf_step(st)

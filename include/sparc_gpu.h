@@ -56,7 +56,8 @@ typedef enum {
     SPARC_ERR_EIG = 5,        /* subspace eigensolver did not converge     */
     SPARC_ERR_FERMI = 6,      /* Fermi level bracket failed                */
     SPARC_ERR_NOCONV = 7,     /* iteration limit reached                   */
-    SPARC_ERR_NONFINITE = 8   /* NaN/Inf met in a checked quantity         */
+    SPARC_ERR_NONFINITE = 8,  /* NaN/Inf met in a checked quantity         */
+    SPARC_ERR_SINGULAR = 9    /* Pulay normal equations singular           */
 } sparc_status;
 
 /*
@@ -180,6 +181,35 @@ sparc_status sparc_gpu_sad_density(sparc_gpu_ctx ctx, double* d_rho);
  * V_eff extrema, signed projector norms).  Synchronous. */
 sparc_status sparc_gpu_spectrum_bounds(sparc_gpu_ctx ctx, double* lo, double* hi);
 
+/* Density mixing (Sec. 2.1: the restarted form of periodic Pulay mixing
+ * with a real-space preconditioner) for SCF iteration `iter` (0-based), with
+ * x = d_rho_in (updated in place) and f = d_rho_out - d_rho_in:
+ *   linear step:  x <- x + beta P f
+ *   Pulay step, taken when m > 0, the history holds c >= 1 pairs and
+ *   (iter + 1) is a multiple of `period`:
+ *     gamma = argmin_g || f - dF g ||_2 (normal equations dF^T dF gamma =
+ *             dF^T f, solved by LU with partial pivoting),
+ *     x <- x - dX gamma + beta P (f - dF gamma),
+ *   where dX, dF hold the last c differences x_j - x_{j-1}, f_j - f_{j-1}
+ *   (c <= m; each call with iter >= 1 adds the pair for that iteration).
+ *   restart = 1: after a Pulay step that used c = m pairs the history is
+ *   emptied (the paper names the restarted form without stating the rule;
+ *   this is the reading implemented).
+ * P = (-Lap_h)(-Lap_h + q0^2)^-1 in the eigenbasis of the discrete Laplacian
+ * (constant mode removed) when kerker_q0 > 0, else the identity.
+ * d_hist (m > 0): (2 m + 2) x N_d doubles, caller-owned, layout
+ * [x_prev | f_prev | dX slots 0..m-1 | dF slots 0..m-1]; the call with
+ * iter = 0 initialises it and every call with iter = k must follow the call
+ * with k - 1 on the same buffer.  NULL allowed when m = 0.
+ * Errors: SPARC_ERR_ARG (m outside [0, SPARC_PULAY_MAX], period < 1, bad
+ * beta or q0, null buffers, iter < 0); SPARC_ERR_SINGULAR when a pivot of
+ * the normal equations is zero or gamma is not finite (x then holds the
+ * linear step, gamma = 0).  Synchronises once. */
+#define SPARC_PULAY_MAX 10
+sparc_status sparc_gpu_mix(sparc_gpu_ctx ctx, double* d_rho_in, const double* d_rho_out, double beta,
+                           double kerker_q0, int pulay_history, int pulay_period, int restart, double* d_hist,
+                           int iter);
+
 /* State carried across SCF iterations; every device buffer is caller-owned. */
 typedef struct {
     double* d_rho_in;   /* in: rho_in of this iteration; out: mixed density   */
@@ -195,6 +225,13 @@ typedef struct {
                            it is mixed (a Kerker-type preconditioner, in the
                            spirit of the real-space preconditioner of
                            Sec. 2.1).                                          */
+    int pulay_history;  /* m in [0, SPARC_PULAY_MAX]; 0 = linear mixing only.
+                           m > 0: periodic Pulay mixing (sparc_gpu_mix).     */
+    int pulay_period;   /* >= 1 (used when m > 0)                            */
+    int pulay_restart;  /* 0 or 1: restarted form (used when m > 0)          */
+    double* d_pulay;    /* m > 0: (2 m + 2) N_d doubles of mixing history,
+                           caller-owned, carried from call to call; may be
+                           NULL when m = 0                                   */
     int iter;           /* 0 on the first call; incremented by each call     */
     double* d_eig;      /* out: n_states Ritz values (ascending)             */
     double* d_occ;      /* out: n_states occupations                          */
@@ -220,7 +257,9 @@ typedef struct {
  * a = largest and a0 = smallest Ritz value of the preceding step (a0 = lower
  * spectrum bound before the first filter) and b = upper spectrum bound;
  * occupations, rho_out (Sec. 2 eq. (2)), the free energy at rho_in, the
- * residual, and linear mixing rho_in <- rho_in + beta (rho_out - rho_in).
+ * residual, and the mixing step of sparc_gpu_mix with st's mixing fields
+ * (plain linear mixing rho_in <- rho_in + beta (rho_out - rho_in) when
+ * pulay_history = 0 and kerker_q0 = 0).
  * Synchronises once at the end to fill rep (may be NULL). */
 sparc_status sparc_gpu_scf_step(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st, sparc_gpu_scf_report* rep);
 
@@ -242,7 +281,9 @@ sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st,
  * 10 small N_s x N_s products, 11 block copy-back, 12 tridiagonalisation,
  * 13 tridiagonal eigenvalues, 14 inverse iteration, 15 back-transformation
  * (12-15 are the phases inside 9), 16 warm-start network forward,
- * 17 its 16 -> 16 convolution, 18 network gradient; ids < 32. */
+ * 17 its 16 -> 16 convolution, 18 network gradient, 19 density mixing
+ * step of the SCF (linear with preconditioner, or Pulay; the plain linear
+ * step is fused into the energy pass and not listed); ids < 32. */
 sparc_status sparc_gpu_profile(sparc_gpu_ctx ctx, int enable);
 sparc_status sparc_gpu_profile_read(sparc_gpu_ctx ctx, int kernel_id, double* total_ms, long* launches);
 

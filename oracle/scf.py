@@ -167,6 +167,7 @@ class PeriodicPulay:
         self.dX, self.dF = [], []
         self.x_prev = self.f_prev = None
         self.k = 0
+        self.last = None   # (dF, dX, gamma) of the latest Pulay step, for diagnostics
 
     def _precondition(self, f):
         return kerker(self.sys, f, self.q0) if self.q0 > 0.0 else f
@@ -181,11 +182,13 @@ class PeriodicPulay:
         self.x_prev, self.f_prev = x.copy(), f.copy()
         pulay = self.m > 0 and len(self.dF) > 0 and (self.k + 1) % self.period == 0
         self.k += 1
+        self.last = None
         if not pulay:
             return x + self.beta * self._precondition(f)
         F = np.stack(self.dF, axis=1)
         Xd = np.stack(self.dX, axis=1)
         gamma = np.linalg.solve(F.T @ F, F.T @ f)
+        self.last = (F, Xd, gamma)
         xb = x - Xd @ gamma
         fb = f - F @ gamma
         if self.restart and len(self.dF) == self.m:

@@ -26,7 +26,10 @@ STATUS = {
     6: "SPARC_ERR_FERMI",
     7: "SPARC_ERR_NOCONV",
     8: "SPARC_ERR_NONFINITE",
+    9: "SPARC_ERR_SINGULAR",
 }
+
+PULAY_MAX = 10
 
 EXPORTED = [
     "sparc_gpu_create",
@@ -45,6 +48,7 @@ EXPORTED = [
     "sparc_gpu_pseudocharge",
     "sparc_gpu_sad_density",
     "sparc_gpu_spectrum_bounds",
+    "sparc_gpu_mix",
     "sparc_gpu_scf_step",
     "sparc_gpu_final_rr_fp64",
     "sparc_gpu_profile",
@@ -97,6 +101,10 @@ class SCFState(C.Structure):
         ("n_first", C.c_int),
         ("mix_beta", C.c_double),
         ("kerker_q0", C.c_double),
+        ("pulay_history", C.c_int),
+        ("pulay_period", C.c_int),
+        ("pulay_restart", C.c_int),
+        ("d_pulay", C.c_void_p),
         ("iter", C.c_int),
         ("d_eig", C.c_void_p),
         ("d_occ", C.c_void_p),
@@ -161,6 +169,7 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_pseudocharge": ([vp, vp, C.POINTER(d), C.POINTER(d)], i),
         "sparc_gpu_sad_density": ([vp, vp], i),
         "sparc_gpu_spectrum_bounds": ([vp, C.POINTER(d), C.POINTER(d)], i),
+        "sparc_gpu_mix": ([vp, vp, vp, d, d, i, i, i, vp, i], i),
         "sparc_gpu_scf_step": ([vp, C.POINTER(SCFState), C.POINTER(SCFReport)], i),
         "sparc_gpu_final_rr_fp64": ([vp, C.POINTER(SCFState), vp, l, C.POINTER(SCFReport)], i),
         "sparc_gpu_profile": ([vp, i], i),
@@ -306,6 +315,14 @@ class Context:
         self._check(self.lib.sparc_gpu_spectrum_bounds(self.h, C.byref(lo), C.byref(hi)))
         return lo.value, hi.value
 
+    def mix(self, rho_in, rho_out, beta, kerker_q0=0.0, pulay_history=0, pulay_period=1, restart=False,
+            hist=None, iter=0):
+        """rho_in (updated in place), rho_out: (N_d,) float64; hist:
+        ((2 m + 2) N_d,) float64 history buffer when pulay_history = m > 0."""
+        self._check(self.lib.sparc_gpu_mix(self.h, _ptr(rho_in), _ptr(rho_out), float(beta), float(kerker_q0),
+                                           int(pulay_history), int(pulay_period), 1 if restart else 0, _ptr(hist),
+                                           int(iter)))
+
     def scf_step(self, state: SCFState) -> dict:
         rep = SCFReport()
         self._check(self.lib.sparc_gpu_scf_step(self.h, C.byref(state), C.byref(rep)))
@@ -350,7 +367,10 @@ class Context:
         return rep.as_dict()
 
 
-def make_state(rho_in, X, eig, occ, degree, n_first=4, beta=0.3, rho_out=None, kerker_q0=0.0) -> SCFState:
+def make_state(rho_in, X, eig, occ, degree, n_first=4, beta=0.3, rho_out=None, kerker_q0=0.0,
+               pulay_history=0, pulay_period=1, pulay_restart=False, pulay_hist=None) -> SCFState:
+    """pulay_hist: ((2 m + 2) N_d,) float64 device tensor when
+    pulay_history = m > 0 (the caller keeps it alive with the state)."""
     st = SCFState()
     st.d_rho_in = rho_in.data_ptr()
     st.d_X = X.data_ptr()
@@ -360,6 +380,10 @@ def make_state(rho_in, X, eig, occ, degree, n_first=4, beta=0.3, rho_out=None, k
     st.n_first = int(n_first)
     st.mix_beta = float(beta)
     st.kerker_q0 = float(kerker_q0)
+    st.pulay_history = int(pulay_history)
+    st.pulay_period = int(pulay_period)
+    st.pulay_restart = 1 if pulay_restart else 0
+    st.d_pulay = pulay_hist.data_ptr() if pulay_hist is not None else None
     st.iter = 0
     st.d_eig = eig.data_ptr()
     st.d_occ = occ.data_ptr()

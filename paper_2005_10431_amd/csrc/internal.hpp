@@ -178,10 +178,11 @@ enum Scalar {
     S_OCC = 16,                      // mu, entropy term, band energy
     S_EIG = 22,                      // eigensolver norms (2 slots)
     S_CNN = 32,                      // warm-start network head sums (6 slots)
+    S_PULAY = 40,                    // Pulay weights gamma (SPARC_PULAY_MAX slots)
     S_COUNT = 64
 };
 enum Flag {
-    F_NOT_SPD = 0, F_EIG_NOCONV = 1, F_FERMI = 2, F_NONFINITE = 3, F_JACOBI_DONE = 4,
+    F_NOT_SPD = 0, F_EIG_NOCONV = 1, F_FERMI = 2, F_NONFINITE = 3, F_JACOBI_DONE = 4, F_PULAY_SINGULAR = 5,
     F_COUNT = 16
 };
 
@@ -252,6 +253,7 @@ enum ProfKernel {
     PK_CNN_FWD = 16, // warm-start network forward (all launches)
     PK_CNN_CONV2 = 17,  // its 16 -> 16 convolution
     PK_CNN_BWD = 18, // network gradient (all launches)
+    PK_MIX = 19,     // density mixing step (all launches of one step)
     PK_COUNT = 32    // size of the per-context timing tables
 };
 static_assert(PK_COUNT == sizeof(sparc_gpu_ctx_s::prof_n) / sizeof(long), "timing table size");

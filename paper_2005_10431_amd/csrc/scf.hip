@@ -302,6 +302,191 @@ __global__ void k_axpy(double* y, const double* x, double a, long n) {
     if (i < n) y[i] += a * x[i];
 }
 
+// ---- periodic Pulay mixing (Sec. 2.1) --------------------------------------
+// History buffer of N_d-vectors: [x_prev | f_prev | dX slots | dF slots].
+
+static_assert(S_PULAY + SPARC_PULAY_MAX <= S_COUNT, "Pulay weights fit the scalar block");
+
+// Which slots hold valid pairs at iteration `iter`, where this iteration's
+// pair goes, and whether it is a Pulay iteration: the schedule is replayed
+// from iteration 0 (the history buffer carries no bookkeeping of its own).
+struct PulayPlan {
+    int push_slot;   // -1 on iteration 0
+    int count;       // valid pairs after this iteration's push
+    int slots[SPARC_PULAY_MAX];
+    bool pulay;
+};
+
+static PulayPlan pulay_plan(int iter, int m, int period, int restart) {
+    PulayPlan p{};
+    long pushes = 0;
+    int cnt = 0;
+    for (int k = 0; k <= iter; ++k) {
+        int slot = -1;
+        if (k >= 1) {
+            slot = (int)(pushes % m);
+            ++pushes;
+            cnt = std::min(cnt + 1, m);
+        }
+        const bool pul = cnt > 0 && (k + 1) % period == 0;
+        if (k == iter) {
+            p.push_slot = slot;
+            p.count = cnt;
+            for (int j = 0; j < cnt; ++j) p.slots[j] = (int)((pushes - 1 - j) % m);
+            p.pulay = pul;
+        }
+        if (pul && restart && cnt == m) cnt = 0;
+    }
+    return p;
+}
+
+struct SlotList {
+    int s[SPARC_PULAY_MAX];
+};
+
+// x = rho_in, f = rho_out - rho_in; slot >= 0 receives dX = x - x_prev and
+// dF = f - f_prev; then x_prev, f_prev <- x, f.
+__global__ void k_pulay_push(const double* __restrict__ x, const double* __restrict__ ro, double* __restrict__ hist,
+                             long nd, int m, int slot) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    const double xi = x[i], fi = ro[i] - xi;
+    if (slot >= 0) {
+        hist[(2 + slot) * nd + i] = xi - hist[i];
+        hist[(2 + (long)m + slot) * nd + i] = fi - hist[nd + i];
+    }
+    hist[i] = xi;
+    hist[nd + i] = fi;
+}
+
+// Per-block partial sums of the normal equations: the upper triangle of
+// dF^T dF (row-major, a <= b) followed by dF^T f, for the C listed slots.
+// Fixed-order reduction (wave shuffles, then the 4 waves in order).
+template <int C>
+__global__ __launch_bounds__(256) void k_pulay_dots(const double* __restrict__ hist, long nd, int m, SlotList sl,
+                                                    double* __restrict__ part) {
+    constexpr int P = C * (C + 1) / 2 + C;
+    const double* f = hist + nd;
+    const double* dF[C];
+#pragma unroll
+    for (int a = 0; a < C; ++a) dF[a] = hist + (2 + (long)m + sl.s[a]) * nd;
+    double acc[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[q] = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
+        double v[C];
+#pragma unroll
+        for (int a = 0; a < C; ++a) v[a] = dF[a][i];
+        const double fi = f[i];
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < C; ++a)
+#pragma unroll
+            for (int b = a; b < C; ++b) acc[q++] += v[a] * v[b];
+#pragma unroll
+        for (int a = 0; a < C; ++a) acc[q++] += v[a] * fi;
+    }
+    __shared__ double wsum[4][P];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        double t = acc[q];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0) wsum[w][q] = t;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < P; q += blockDim.x)
+        part[(long)blockIdx.x * P + q] = ((wsum[0][q] + wsum[1][q]) + wsum[2][q]) + wsum[3][q];
+}
+
+// Sum the block partials in block order, then solve the C x C normal
+// equations by Gaussian elimination with partial pivoting (one thread).
+// gamma -> scal[S_PULAY..]; a zero pivot or a non-finite gamma raises the
+// flag and leaves gamma = 0.
+__global__ __launch_bounds__(256) void k_pulay_solve(const double* __restrict__ part, int nblk, int C,
+                                                     double* __restrict__ scal, int* __restrict__ flags) {
+    constexpr int PM = SPARC_PULAY_MAX * (SPARC_PULAY_MAX + 1) / 2 + SPARC_PULAY_MAX;
+    __shared__ double red[PM];
+    __shared__ double A[SPARC_PULAY_MAX][SPARC_PULAY_MAX + 1];
+    const int P = C * (C + 1) / 2 + C;
+    const int t = threadIdx.x;
+    if (t < P) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(long)b * P + t];
+        red[t] = s;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    int q = 0;
+    for (int a = 0; a < C; ++a)
+        for (int b = a; b < C; ++b) {
+            A[a][b] = red[q];
+            A[b][a] = red[q];
+            ++q;
+        }
+    for (int a = 0; a < C; ++a) A[a][C] = red[q++];
+    bool bad = false;
+    for (int k = 0; k < C && !bad; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < C; ++r)
+            if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+        if (!(fabs(A[piv][k]) > 0.0)) {
+            bad = true;
+            break;
+        }
+        if (piv != k)
+            for (int j = k; j <= C; ++j) {
+                const double tmp = A[k][j];
+                A[k][j] = A[piv][j];
+                A[piv][j] = tmp;
+            }
+        for (int r = k + 1; r < C; ++r) {
+            const double l = A[r][k] / A[k][k];
+            for (int j = k; j <= C; ++j) A[r][j] -= l * A[k][j];
+        }
+    }
+    double g[SPARC_PULAY_MAX];
+    for (int k = C - 1; k >= 0 && !bad; --k) {
+        double s = A[k][C];
+        for (int j = k + 1; j < C; ++j) s -= A[k][j] * g[j];
+        g[k] = s / A[k][k];
+        if (!isfinite(g[k])) bad = true;
+    }
+    for (int k = 0; k < C; ++k) scal[S_PULAY + k] = bad ? 0.0 : g[k];
+    if (bad) flags[F_PULAY_SINGULAR] = 1;
+}
+
+// x_bar = x - dX gamma, f_bar = f - dF gamma (sums formed first, in slot
+// order); then x <- x_bar + beta f_bar, or x <- x_bar and t <- f_bar when the
+// residual is still to be preconditioned (t != nullptr).
+__global__ void k_pulay_apply(double* __restrict__ x, const double* __restrict__ hist, const double* __restrict__ scal,
+                              long nd, int m, SlotList sl, int C, double beta, double* __restrict__ t) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    double sx = 0.0, sf = 0.0;
+    for (int a = 0; a < C; ++a) {
+        const double g = scal[S_PULAY + a];
+        sx += hist[(2 + (long)sl.s[a]) * nd + i] * g;
+        sf += hist[(2 + (long)m + sl.s[a]) * nd + i] * g;
+    }
+    const double xb = hist[i] - sx;
+    const double fb = hist[nd + i] - sf;
+    if (t) {
+        x[i] = xb;
+        t[i] = fb;
+    } else {
+        x[i] = xb + beta * fb;
+    }
+}
+
+__global__ void k_mix_linear(double* __restrict__ x, const double* __restrict__ ro, double beta, long nd) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nd) {
+        const double xi = x[i];
+        x[i] = xi + beta * (ro[i] - xi);
+    }
+}
+
 // out[q] = sum over blocks of part[i][q]: block q, fixed-order tree.
 __global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ part, int nblk,
                                                       double* __restrict__ out) {
@@ -352,39 +537,104 @@ struct Timer {
     }
 };
 
-// Energy terms and residual at (rho_in, rho_out) into the report; mixes when
-// do_mix.  Fields: phi = f[2], exc = f[3], vxc = f[4].
-static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double* rho_out, double beta, int do_mix,
-                                  sparc_gpu_scf_report* rep, double* hscal, double kerker_q0 = 0.0) {
+// Mixing parameters of one SCF iteration (see sparc_gpu_mix).
+struct MixArgs {
+    double beta, q0;
+    int m, period, restart;
+    double* hist;
+    int iter;
+};
+
+constexpr int kPulayBlocks = 512;
+
+static size_t mix_red_doubles(int m) {
+    return m > 0 ? (size_t)kPulayBlocks * (m * (m + 1) / 2 + m) : 0;
+}
+
+// The mixing step, stream-ordered.  Uses fields 0 and 1 as preconditioner
+// temporaries and c->red for the Pulay partial sums (sized by the caller to
+// mix_red_doubles(m)).
+static sparc_status mix_steps(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs& a);
+
+static sparc_status mix_impl(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs& a) {
+    const int slot = prof_begin(c, PK_MIX);
+    const sparc_status st = mix_steps(c, rho_in, rho_out, a);
+    prof_end(c, slot);
+    return st;
+}
+
+static sparc_status mix_steps(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs& a) {
+    const long nd = c->nd;
+    const int nb = div_up(nd, 256);
+    double* t0 = c->field;
+    double* t1 = c->field + nd;
+    const bool precond = a.q0 > 0.0;
+    bool have_fbar = false;
+    if (a.m > 0) {
+        const PulayPlan pl = pulay_plan(a.iter, a.m, a.period, a.restart);
+        k_pulay_push<<<nb, 256, 0, c->stream>>>(rho_in, rho_out, a.hist, nd, a.m, pl.push_slot);
+        SG_CHECK_LAUNCH(c);
+        if (pl.pulay) {
+            SlotList sl{};
+            for (int j = 0; j < pl.count; ++j) sl.s[j] = pl.slots[j];
+            const int C = pl.count;
+            const int nblk = std::min(kPulayBlocks, nb);
+            switch (C) {
+#define SG_PULAY_DOTS(CC) \
+    case CC: k_pulay_dots<CC><<<nblk, 256, 0, c->stream>>>(a.hist, nd, a.m, sl, c->red); break;
+                SG_PULAY_DOTS(1) SG_PULAY_DOTS(2) SG_PULAY_DOTS(3) SG_PULAY_DOTS(4) SG_PULAY_DOTS(5)
+                SG_PULAY_DOTS(6) SG_PULAY_DOTS(7) SG_PULAY_DOTS(8) SG_PULAY_DOTS(9) SG_PULAY_DOTS(10)
+#undef SG_PULAY_DOTS
+                default: return set_err(c, SPARC_ERR_ARG, "mix: Pulay history too long");
+            }
+            k_pulay_solve<<<1, 256, 0, c->stream>>>(c->red, nblk, C, c->scal, c->flags);
+            k_pulay_apply<<<nb, 256, 0, c->stream>>>(rho_in, a.hist, c->scal, nd, a.m, sl, C, a.beta,
+                                                     precond ? t0 : nullptr);
+            SG_CHECK_LAUNCH(c);
+            if (!precond) return SPARC_OK;
+            have_fbar = true;
+        }
+    }
+    if (!precond) {
+        k_mix_linear<<<nb, 256, 0, c->stream>>>(rho_in, rho_out, a.beta, nd);
+        SG_CHECK_LAUNCH(c);
+        return SPARC_OK;
+    }
+    // rho_in += beta P r with r = f (or f_bar after a Pulay step), P =
+    // (-Lap)(-Lap + q0^2)^-1 in the eigenbasis of the discrete Laplacian
+    if (!have_fbar) k_residual<<<nb, 256, 0, c->stream>>>(rho_out, rho_in, t0, nd);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_ux, c->nx, c->ny, c->nz, 0, 1);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uy, c->nx, c->ny, c->nz, 1, 1);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uz, c->nx, c->ny, c->nz, 2, 1);
+    k_kerker<<<nb, 256, 0, c->stream>>>(t1, c->pois_inv, a.q0 * a.q0, nd);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uz, c->nx, c->ny, c->nz, 2, 0);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uy, c->nx, c->ny, c->nz, 1, 0);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_ux, c->nx, c->ny, c->nz, 0, 0);
+    k_axpy<<<nb, 256, 0, c->stream>>>(rho_in, t0, a.beta, nd);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+// Energy terms and residual at (rho_in, rho_out) into the report, then the
+// mixing step when mix != nullptr.  Fields: phi = f[2], exc = f[3],
+// vxc = f[4]; fields 0, 1 are free.
+static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs* mix,
+                                  sparc_gpu_scf_report* rep, double* hscal) {
     const int nblk = std::min(1024, div_up(c->nd, 256));
-    sparc_status st = ensure_red(c, (size_t)nblk * kRed);
+    sparc_status st = ensure_red(c, std::max((size_t)nblk * kRed, mix ? mix_red_doubles(mix->m) : 0));
     if (st != SPARC_OK) return st;
     const double* phi = c->field + 2 * c->nd;
     const double* exc = c->field + 3 * c->nd;
     const double* vxc = c->field + 4 * c->nd;
-    const bool kerker = do_mix && kerker_q0 > 0.0;
-    k_energy_mix<<<nblk, 256, 0, c->stream>>>(rho_in, rho_out, exc, vxc, phi, c->b, c->nd, beta, kerker ? 0 : do_mix,
-                                              c->red);
+    // plain linear mixing is fused into the energy pass
+    const bool fused = mix && mix->m == 0 && !(mix->q0 > 0.0);
+    k_energy_mix<<<nblk, 256, 0, c->stream>>>(rho_in, rho_out, exc, vxc, phi, c->b, c->nd, fused ? mix->beta : 0.0,
+                                              fused ? 1 : 0, c->red);
     SG_CHECK_LAUNCH(c);
-    if (kerker) {
-        // rho_in += beta P (rho_out - rho_in), P = (-Lap)(-Lap + q0^2)^-1 in
-        // the eigenbasis of the discrete Laplacian (fields 0, 1 are free)
-        double* t0 = c->field;
-        double* t1 = c->field + c->nd;
-        const int nb = div_up(c->nd, 256);
-        k_residual<<<nb, 256, 0, c->stream>>>(rho_out, rho_in, t0, c->nd);
-        k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_ux, c->nx, c->ny, c->nz, 0, 1);
-        k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uy, c->nx, c->ny, c->nz, 1, 1);
-        k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uz, c->nx, c->ny, c->nz, 2, 1);
-        k_kerker<<<nb, 256, 0, c->stream>>>(t1, c->pois_inv, kerker_q0 * kerker_q0, c->nd);
-        k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uz, c->nx, c->ny, c->nz, 2, 0);
-        k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uy, c->nx, c->ny, c->nz, 1, 0);
-        k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_ux, c->nx, c->ny, c->nz, 0, 0);
-        k_axpy<<<nb, 256, 0, c->stream>>>(rho_in, t0, beta, c->nd);
-        SG_CHECK_LAUNCH(c);
-    }
     k_energy_final<<<kRed, 256, 0, c->stream>>>(c->red, nblk, c->scal + S_RED0);
     SG_CHECK_LAUNCH(c);
+    if (mix && !fused)
+        if ((st = mix_impl(c, rho_in, rho_out, *mix)) != SPARC_OK) return st;
     double hloc[S_COUNT];
     double* h = hscal ? hscal : hloc;
     int fl[F_COUNT];
@@ -392,6 +642,7 @@ static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double*
     SG_HIP(c, hipMemcpyAsync(fl, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     SG_HIP(c, hipStreamSynchronize(c->stream));
     if (fl[F_FERMI]) return set_err(c, SPARC_ERR_FERMI, "Fermi level bisection failed");
+    if (fl[F_PULAY_SINGULAR]) return set_err(c, SPARC_ERR_SINGULAR, "Pulay normal equations singular");
     const double* r = h + S_RED0;
     const double dV = c->dV;
     sparc_gpu_scf_report R;
@@ -457,7 +708,9 @@ static sparc_status scf_step_impl(sparc_gpu_ctx c, sparc_gpu_scf_state* s, sparc
     tm.mark(6);
     sparc_gpu_scf_report R;
     double hs[S_COUNT];
-    if ((st = finish_energy(c, s->d_rho_in, rho_out, s->mix_beta, 1, &R, hs, s->kerker_q0)) != SPARC_OK) return st;
+    const MixArgs mix{s->mix_beta, s->kerker_q0, s->pulay_history, s->pulay_period, s->pulay_restart, s->d_pulay,
+                      s->iter};
+    if ((st = finish_energy(c, s->d_rho_in, rho_out, &mix, &R, hs)) != SPARC_OK) return st;
     tm.mark(7);
     SG_HIP(c, hipEventSynchronize(c->ev[7]));
     s->bounds[0] = hs[S_A];
@@ -484,6 +737,11 @@ static sparc_status check_state(sparc_gpu_ctx c, const sparc_gpu_scf_state* s) {
     if (s->n_first < 1 || s->n_first > 100) return set_err(c, SPARC_ERR_ARG, "scf: bad n_first");
     if (!(s->mix_beta > 0.0 && s->mix_beta <= 1.0)) return set_err(c, SPARC_ERR_ARG, "scf: bad mix_beta");
     if (!(s->kerker_q0 >= 0.0) || !std::isfinite(s->kerker_q0)) return set_err(c, SPARC_ERR_ARG, "scf: bad kerker_q0");
+    if (s->pulay_history < 0 || s->pulay_history > SPARC_PULAY_MAX)
+        return set_err(c, SPARC_ERR_ARG, "scf: pulay_history outside [0, SPARC_PULAY_MAX]");
+    if (s->pulay_history > 0 && (s->pulay_period < 1 || (s->pulay_restart != 0 && s->pulay_restart != 1) ||
+                                 !s->d_pulay))
+        return set_err(c, SPARC_ERR_ARG, "scf: bad Pulay period, restart flag or history buffer");
     if (s->iter < 0) return set_err(c, SPARC_ERR_ARG, "scf: negative iter");
     if (s->iter > 0 && !(s->bounds[2] < s->bounds[0]))
         return set_err(c, SPARC_ERR_ARG, "scf: bounds need a0 < a after the first iteration");
@@ -535,7 +793,7 @@ sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx c, sparc_gpu_scf_state* s, do
     if ((st = density_impl<double>(c, d_X64, N, ldx64, s->d_occ, rho_out)) != SPARC_OK) return st;
     tm.mark(3);
     sparc_gpu_scf_report R;
-    if ((st = finish_energy(c, s->d_rho_in, rho_out, 0.0, 0, &R, nullptr)) != SPARC_OK) return st;
+    if ((st = finish_energy(c, s->d_rho_in, rho_out, nullptr, &R, nullptr)) != SPARC_OK) return st;
     tm.mark(4);
     SG_HIP(c, hipEventSynchronize(c->ev[4]));
     R.t_potential_ms = tm.ms(0, 1);
@@ -558,6 +816,31 @@ sparc_status sparc_gpu_density(sparc_gpu_ctx c, sparc_prec prec, const void* d_X
     if (ldx < c->nd) return set_err(c, SPARC_ERR_ARG, "density: ldx < N_d");
     if (prec == SPARC_FP64) return density_impl<double>(c, (const double*)d_X, ncol, ldx, d_occ, d_rho);
     return density_impl<float>(c, (const float*)d_X, ncol, ldx, d_occ, d_rho);
+}
+
+sparc_status sparc_gpu_mix(sparc_gpu_ctx c, double* d_rho_in, const double* d_rho_out, double beta, double kerker_q0,
+                           int pulay_history, int pulay_period, int restart, double* d_hist, int iter) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_rho_in || !d_rho_out) return set_err(c, SPARC_ERR_ARG, "mix: null density");
+    if (!(beta > 0.0 && beta <= 1.0)) return set_err(c, SPARC_ERR_ARG, "mix: bad beta");
+    if (!(kerker_q0 >= 0.0) || !std::isfinite(kerker_q0)) return set_err(c, SPARC_ERR_ARG, "mix: bad kerker_q0");
+    if (pulay_history < 0 || pulay_history > SPARC_PULAY_MAX)
+        return set_err(c, SPARC_ERR_ARG, "mix: pulay_history outside [0, SPARC_PULAY_MAX]");
+    if (pulay_history > 0 && (pulay_period < 1 || (restart != 0 && restart != 1) || !d_hist))
+        return set_err(c, SPARC_ERR_ARG, "mix: bad Pulay period, restart flag or history buffer");
+    if (iter < 0) return set_err(c, SPARC_ERR_ARG, "mix: negative iter");
+    sparc_status st;
+    if ((st = ensure_fields(c, 2)) != SPARC_OK) return st;
+    if ((st = ensure_red(c, mix_red_doubles(pulay_history))) != SPARC_OK) return st;
+    SG_HIP(c, hipMemsetAsync(c->flags + F_PULAY_SINGULAR, 0, sizeof(int), c->stream));
+    const MixArgs mix{beta, kerker_q0, pulay_history, pulay_period, restart, d_hist, iter};
+    if ((st = mix_impl(c, d_rho_in, d_rho_out, mix)) != SPARC_OK) return st;
+    int flag = 0;
+    SG_HIP(c, hipMemcpyAsync(&flag, c->flags + F_PULAY_SINGULAR, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    if (flag) return set_err(c, SPARC_ERR_SINGULAR, "Pulay normal equations singular");
+    return SPARC_OK;
 }
 
 sparc_status sparc_gpu_occupations(sparc_gpu_ctx c, const double* d_eig, int ncol, double* d_occ, double* d_mu) {

@@ -9,7 +9,8 @@ from ._lib import SPARC_FP32, Context, make_state
 
 def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100, tol: float = 1e-10,
             device: str = "cuda", final_fp64_rr: bool = True, ctx: Context = None, callback=None,
-            n_first: int = None, degree: int = None, beta: float = None, kerker_q0: float = None):
+            n_first: int = None, degree: int = None, beta: float = None, kerker_q0: float = None,
+            pulay_history: int = None, pulay_period: int = None, pulay_restart: bool = None):
     """Run the SCF iteration on the GPU.
 
     X0: (N_s, N_d) numpy array (random block, see ``workloads.initial_orbitals``);
@@ -33,11 +34,16 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
     eig = torch.empty(ns, dtype=torch.float64, device=device)
     occ = torch.empty(ns, dtype=torch.float64, device=device)
     rho_out = torch.empty(nd, dtype=torch.float64, device=device)
+    m = pulay_history if pulay_history is not None else getattr(system, "pulay_history", 0)
+    period = pulay_period if pulay_period is not None else getattr(system, "pulay_period", 2)
+    restart = pulay_restart if pulay_restart is not None else bool(getattr(system, "pulay_restart", 0))
+    hist_buf = torch.empty((2 * m + 2) * nd, dtype=torch.float64, device=device) if m > 0 else None
     st = make_state(rho_in, X, eig, occ,
                     degree if degree is not None else system.cheb_degree,
                     n_first if n_first is not None else system.n_first,
                     beta if beta is not None else system.mix_beta, rho_out,
-                    kerker_q0 if kerker_q0 is not None else system.kerker_q0)
+                    kerker_q0 if kerker_q0 is not None else system.kerker_q0,
+                    m, period, restart, hist_buf)
     hist = []
     for _ in range(max_iter):
         rep = ctx.scf_step(st)
@@ -47,7 +53,8 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
             callback(rep)
         if rep["residual"] < tol:
             break
-    out = dict(history=hist, X=X, eig=eig, occ=occ, rho_in=rho_in, rho_out=rho_out, state=st, ctx=ctx)
+    out = dict(history=hist, X=X, eig=eig, occ=occ, rho_in=rho_in, rho_out=rho_out, state=st, ctx=ctx,
+               pulay_hist=hist_buf)
     if prec != "fp64" and final_fp64_rr:
         X64 = torch.empty((ns, nd), dtype=torch.float64, device=device)
         # one FP64 Rayleigh-Ritz at the (converged) input density

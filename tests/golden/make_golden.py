@@ -1,7 +1,7 @@
 """Writes the stored SCF reference values under tests/golden/ from the CPU
 oracle alone (no GPU code is imported).
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py [file names to rewrite; default all]
 
 cfg1_scf.json: the 8-atom, 24^3 system (seed 0) iterated by the oracle's
 SCF (Sec. 2.1: Chebyshev-filtered subspace iteration with linear density
@@ -9,6 +9,9 @@ mixing) from the seeded random block until the density residual is below
 1e-10: the free energy per atom and eigenvalues at the fixed point, the
 per-iteration trajectory of the first iterations, and the density at seeded
 sample points together with its integrals.
+
+cfg1_scf_pulay.json: the same system and record with the restarted periodic
+Pulay mixing of Sec. 2.1 (history 7, period 2) in place of linear mixing.
 """
 import json
 import os
@@ -26,15 +29,18 @@ N_TRAJ = 12
 N_SAMPLES = 64
 
 
-def cfg1_scf():
+def cfg1_scf(pulay=None):
     s = W.config1(0)
+    if pulay is not None:
+        s.pulay_history, s.pulay_period, s.pulay_restart = pulay
     X0 = W.initial_orbitals(s.nd, s.n_states, s.seed)
     r = scf.scf(s, X0, max_iter=200, tol=1e-10)
     dv = float(np.prod(s.h))
     idx = np.sort(np.random.default_rng(2024).choice(s.nd, N_SAMPLES, replace=False))
     last = r.history[-1]
     return {
-        "system": "workloads.config1(0)",
+        "system": "workloads.config1(0)" + ("" if pulay is None else
+                                            " with pulay_history, pulay_period, pulay_restart = %d, %d, %d" % pulay),
         "tol": 1e-10,
         "n_iter": len(r.history),
         "free_per_atom": last["free"] / s.n_atoms,
@@ -52,10 +58,13 @@ def cfg1_scf():
 
 
 def main():
-    out = os.path.join(HERE, "cfg1_scf.json")
-    with open(out, "w") as f:
-        json.dump(cfg1_scf(), f, indent=1)
-    print("wrote", out)
+    for name, pulay in (("cfg1_scf.json", None), ("cfg1_scf_pulay.json", (7, 2, 1))):
+        if len(sys.argv) > 1 and name not in sys.argv[1:]:
+            continue
+        out = os.path.join(HERE, name)
+        with open(out, "w") as f:
+            json.dump(cfg1_scf(pulay), f, indent=1)
+        print("wrote", out)
 
 
 if __name__ == "__main__":

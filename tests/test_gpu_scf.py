@@ -107,7 +107,9 @@ def test_scf_cfg2_fixed_point():
     eig = torch.empty(ns, dtype=torch.float64, device="cuda")
     occ = torch.empty_like(eig)
     rho_out = torch.empty_like(rho)
-    st = make_state(rho, X, eig, occ, s.cheb_degree, s.n_first, s.mix_beta, rho_out, s.kerker_q0)
+    hist = torch.empty((2 * s.pulay_history + 2) * nd, dtype=torch.float64, device="cuda")
+    st = make_state(rho, X, eig, occ, s.cheb_degree, s.n_first, s.mix_beta, rho_out, s.kerker_q0,
+                    s.pulay_history, s.pulay_period, bool(s.pulay_restart), hist)
     tol = 1e-7
     rep = None
     for it in range(150):

@@ -162,9 +162,10 @@ def config1(seed: int = 0, n: int = 24) -> System:
 def config2(seed: int = 0) -> System:
     """L = 20 Bohr cube, 72^3 grid, 108 atoms (FCC 3x3x3 conventional cells,
     jitter N(0, 0.1)), Z = 4, rc_loc = 1.0, s+p projectors with rc = 1.2 and
-    energies U[-1, 1] Ha, 260 states for 432 electrons, degree 20.  Linear
-    mixing 0.3 with the Kerker-type residual preconditioner q0 = 1 / Bohr
-    (plain linear mixing sloshes at this cell size)."""
+    energies U[-1, 1] Ha, 260 states for 432 electrons, degree 20.  Mixing:
+    restarted periodic Pulay (history 7, period 2) with beta = 0.3 and the
+    Kerker-type residual preconditioner q0 = 1 / Bohr (plain linear mixing
+    sloshes at this cell size)."""
     rng = np.random.default_rng(seed)
     L = 20.0
     pos = fcc_jittered(L, 3, 0.1, rng)
@@ -173,6 +174,7 @@ def config2(seed: int = 0) -> System:
         name="cfg2", n=(72, 72, 72), L=(L, L, L), pos=pos,
         Z=np.full(na, 4.0), rc_loc=np.full(na, 1.0),
         n_states=260, n_electrons=432.0, kT=0.01, cheb_degree=20, mix_beta=0.3, kerker_q0=1.0,
+        pulay_history=7, pulay_period=2, pulay_restart=1,
         nl_lmax=1, gamma=_gamma(na, 1, seed), rc_nl=1.2, rcut_nl=3.6, seed=seed,
     )
 
@@ -187,8 +189,8 @@ def config3(seed: int = 0) -> System:
 
 def config4(seed: int = 0) -> System:
     """L = 34 Bohr cube, 120^3 grid, 500 atoms (FCC 5x5x5, jitter N(0, 0.1)),
-    Z = 4, the same local and s+p model as config 2, 1200 states for 2000
-    electrons, degree 24."""
+    Z = 4, the same local and s+p model and mixing as config 2, 1200 states
+    for 2000 electrons, degree 24."""
     rng = np.random.default_rng(seed)
     L = 34.0
     pos = fcc_jittered(L, 5, 0.1, rng)
@@ -197,6 +199,7 @@ def config4(seed: int = 0) -> System:
         name="cfg4", n=(120, 120, 120), L=(L, L, L), pos=pos,
         Z=np.full(na, 4.0), rc_loc=np.full(na, 1.0),
         n_states=1200, n_electrons=2000.0, kT=0.01, cheb_degree=24, mix_beta=0.3, kerker_q0=1.0,
+        pulay_history=7, pulay_period=2, pulay_restart=1,
         nl_lmax=1, gamma=_gamma(na, 1, seed), rc_nl=1.2, rcut_nl=3.6, seed=seed,
     )
 
