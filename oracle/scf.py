@@ -161,15 +161,18 @@ class PeriodicPulay:
     used a full history of m pairs (the next pair is formed from x_k, f_k)."""
 
     def __init__(self, m: int, period: int, beta: float, sys=None, kerker_q0: float = 0.0,
-                 restart: bool = False):
+                 restart: bool = False, precondition=None):
         self.m, self.period, self.beta, self.restart = m, period, beta, restart
         self.sys, self.q0 = sys, kerker_q0
+        self.precondition = precondition   # optional callable in place of the Kerker step
         self.dX, self.dF = [], []
         self.x_prev = self.f_prev = None
         self.k = 0
         self.last = None   # (dF, dX, gamma) of the latest Pulay step, for diagnostics
 
     def _precondition(self, f):
+        if self.precondition is not None:
+            return self.precondition(f)
         return kerker(self.sys, f, self.q0) if self.q0 > 0.0 else f
 
     def step(self, x, f):
@@ -266,3 +269,163 @@ def scf(sys, X0: np.ndarray, rho0: np.ndarray = None, max_iter: int = 50, tol: f
         if res < tol:
             break
     return SCFResult(X=X, lam=lam, g=g, mu=mu, rho_in=rho_prev, rho_out=rho_out, history=hist)
+
+
+# ---------------------------------------------------------------- spin
+# Spin-polarised form (eq. (1)-(2) with a spin index): one orbital block per
+# spin with H_s = -1/2 Lap + phi + v_xc^s + V_nl; occupations f_n^s (one
+# electron per state) with a common Fermi level, sum_s sum_n f_n^s = N_e;
+# rho^s = sum_n f_n^s |psi_n^s|^2; phi from the total density.  Sec. 2.1:
+# the mixing acts on the vector of both spin densities at once.
+
+
+def occupations_spin(lam_up, lam_dn, n_electrons: float, kT: float, tol: float = 1e-13, max_iter: int = 500):
+    """Common mu over both spins by bisection (one electron per state);
+    returns (mu, f_up, f_dn)."""
+    lam = np.concatenate([np.asarray(lam_up, dtype=np.float64), np.asarray(lam_dn, dtype=np.float64)])
+    if n_electrons > lam.size or n_electrons <= 0.0:
+        raise FermiError("electron count outside (0, N_up + N_dn]")
+    lo = float(lam.min()) - 40.0 * kT
+    hi = float(lam.max()) + 40.0 * kT
+    mu = 0.5 * (lo + hi)
+    for _ in range(max_iter):
+        mu = 0.5 * (lo + hi)
+        n = float(np.sum(fermi(lam, mu, kT)))
+        if abs(n - n_electrons) < tol:
+            break
+        if n < n_electrons:
+            lo = mu
+        else:
+            hi = mu
+        if not (lo < 0.5 * (lo + hi) < hi):
+            break
+    f = fermi(lam, mu, kT)
+    return mu, f[:len(lam_up)], f[len(lam_up):]
+
+
+def entropy_term_spin(f, kT):
+    """kT sum [f ln f + (1-f) ln(1-f)] over spin states (0 ln 0 = 0)."""
+    s = 0.0
+    for v in np.asarray(f):
+        if 0.0 < v < 1.0:
+            s += v * np.log(v) + (1.0 - v) * np.log(1.0 - v)
+    return kT * s
+
+
+def potential_spin(sys, st: Setup, rho_up: np.ndarray, rho_dn: np.ndarray):
+    """(phi, eps_xc, v_xc_up, v_xc_dn, V_eff_up, V_eff_dn)."""
+    phi = electrostatics.hartree_ionic_potential(sys, rho_up + rho_dn, st.b)
+    exc, vu, vd = xc.lsda(rho_up, rho_dn, sys.rho_floor)
+    return phi, exc, vu, vd, phi + vu, phi + vd
+
+
+def energy_terms_spin(sys, st: Setup, rho_up, rho_dn, phi, exc, vu, vd, lam_up, lam_dn, f_up, f_dn):
+    """Harris-Foulkes free energy at the input spin densities (the spin form
+    of ``energy_terms``)."""
+    dV = sys.dV
+    rho = rho_up + rho_dn
+    t = {
+        "band": float(np.sum(f_up * lam_up) + np.sum(f_dn * lam_dn)),
+        "exc": dV * float(np.sum(rho * exc)),
+        "vxc_dc": -dV * float(np.sum(rho_up * vu + rho_dn * vd)),
+        "elec": 0.5 * dV * float(np.sum((st.b - rho) * phi)),
+        "self": -st.e_self,
+        "corr": st.e_c,
+        "entropy": entropy_term_spin(np.concatenate([f_up, f_dn]), sys.kT),
+    }
+    t["free"] = sum(t.values())
+    return t
+
+
+def spin_precondition(sys, f: np.ndarray, q0: float) -> np.ndarray:
+    """Preconditioner of the spin mixing vector [f_up; f_dn]: the Kerker step
+    acts on the total f_up + f_dn, the magnetisation part f_up - f_dn is
+    passed unchanged (filtering each spin separately would remove the
+    constant mode of the magnetisation and freeze the total moment)."""
+    if not q0 > 0.0:
+        return f
+    nd = sys.nd
+    t = kerker(sys, f[:nd] + f[nd:], q0)
+    m = f[:nd] - f[nd:]
+    return np.concatenate([0.5 * (t + m), 0.5 * (t - m)])
+
+
+def sad_density_spin(sys):
+    """Atomic-density guess split by the starting polarisation zeta0 =
+    sys.spin_zeta0: rho_up = (1 + zeta0) rho / 2, rho_dn = (1 - zeta0) rho / 2."""
+    rho = atoms.sad_density(sys)
+    z = float(getattr(sys, "spin_zeta0", 0.0))
+    return 0.5 * (1.0 + z) * rho, 0.5 * (1.0 - z) * rho
+
+
+@dataclass
+class SpinSCFResult:
+    X: tuple
+    lam: tuple
+    f: tuple
+    mu: float
+    rho_in: np.ndarray      # [rho_up; rho_dn] of the last iteration
+    rho_out: np.ndarray
+    history: list
+
+
+def scf_spin(sys, X0_up: np.ndarray, X0_dn: np.ndarray, rho0: np.ndarray = None, max_iter: int = 50,
+             tol: float = 1e-10, st: Setup = None, n_first: int = None, degree: int = None,
+             beta: float = None) -> SpinSCFResult:
+    """The SCF schedule of ``scf`` for the spin-polarised form: per spin the
+    filter bounds and passes are those of ``scf`` with that spin's V_eff and
+    block; occupations with a common mu; residual and mixing over
+    [rho_up; rho_dn] (linear, or periodic Pulay when sys.pulay_history > 0,
+    with ``spin_precondition``).  rho0: [rho_up; rho_dn] or None (split SAD).
+    Parity unpinned away from the fixed point, as for ``scf``."""
+    st = st or setup(sys)
+    n_first = sys.n_first if n_first is None else n_first
+    m = sys.cheb_degree if degree is None else degree
+    beta = sys.mix_beta if beta is None else beta
+    nd = sys.nd
+    q0 = getattr(sys, "kerker_q0", 0.0)
+    if rho0 is None:
+        ru, rd = sad_density_spin(sys)
+        x = np.concatenate([ru, rd])
+    else:
+        x = np.array(rho0, dtype=np.float64)
+    Xs = [X0_up.copy(), X0_dn.copy()]
+    ab = [None, None]
+    pulay = None
+    if getattr(sys, "pulay_history", 0) > 0:
+        pulay = PeriodicPulay(sys.pulay_history, sys.pulay_period, beta, restart=bool(getattr(sys, "pulay_restart", 0)),
+                              precondition=lambda f: spin_precondition(sys, f, q0))
+    hist = []
+    lams = [None, None]
+    for it in range(max_iter):
+        phi, exc, vu, vd, veu, ved = potential_spin(sys, st, x[:nd], x[nd:])
+        for s, veff in enumerate((veu, ved)):
+            lo, hi = hamiltonian.spectrum_bounds(sys, veff, st.projs)
+            if it == 0:
+                Xs[s], lam = chefsi.rayleigh_ritz(sys, veff, st.projs, Xs[s])
+                a, a0 = float(lam[-1]), lo
+            else:
+                a, a0 = ab[s]
+            npass = n_first if it == 0 else 1
+            for _ in range(npass):
+                Y = chefsi.chebyshev_filter(sys, veff, st.projs, Xs[s], m, a, hi, a0)
+                Xs[s], lam = chefsi.rayleigh_ritz(sys, veff, st.projs, Y)
+                a, a0 = float(lam[-1]), float(lam[0])
+            ab[s] = (a, a0)
+            lams[s] = lam
+        mu, fu, fd = occupations_spin(lams[0], lams[1], sys.n_electrons, sys.kT)
+        rho_out = np.concatenate([density(Xs[0], fu), density(Xs[1], fd)])
+        terms = energy_terms_spin(sys, st, x[:nd], x[nd:], phi, exc, vu, vd, lams[0], lams[1], fu, fd)
+        res = float(np.linalg.norm(rho_out - x) / np.linalg.norm(rho_out))
+        mag = sys.dV * float(np.sum(rho_out[:nd] - rho_out[nd:]))
+        rec = dict(it=it, residual=res, mu=mu, lam=(lams[0].copy(), lams[1].copy()), magnetization=mag, **terms)
+        hist.append(rec)
+        x_prev = x
+        if pulay is not None:
+            x = pulay.step(x, rho_out - x)
+        else:
+            x = x + beta * spin_precondition(sys, rho_out - x, q0)
+        if res < tol:
+            break
+    return SpinSCFResult(X=tuple(Xs), lam=tuple(lams), f=(fu, fd), mu=mu, rho_in=x_prev, rho_out=rho_out,
+                         history=hist)

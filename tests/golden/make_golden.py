@@ -12,6 +12,12 @@ sample points together with its integrals.
 
 cfg1_scf_pulay.json: the same system and record with the restarted periodic
 Pulay mixing of Sec. 2.1 (history 7, period 2) in place of linear mixing.
+
+cfg1s_spin_scf.json: the spin-polarised config 1 (workloads.config1_spin(0),
+15 electrons) iterated by the oracle's spin SCF from the seeded (up, down)
+blocks to a residual below 1e-10: free energy, both spectra, occupations,
+the moment, the trajectory of the first iterations and samples of both
+output spin densities.
 """
 import json
 import os
@@ -57,13 +63,43 @@ def cfg1_scf(pulay=None):
     }
 
 
+def cfg1s_spin_scf():
+    s = W.config1_spin(0)
+    Xu, Xd = W.initial_orbitals_spin(s.nd, s.n_states, s.seed)
+    r = scf.scf_spin(s, Xu, Xd, max_iter=300, tol=1e-10)
+    nd = s.nd
+    idx = np.sort(np.random.default_rng(2025).choice(nd, N_SAMPLES, replace=False))
+    last = r.history[-1]
+    return {
+        "system": "workloads.config1_spin(0)",
+        "tol": 1e-10,
+        "n_iter": len(r.history),
+        "free_per_atom": last["free"] / s.n_atoms,
+        "terms": {k: last[k] for k in ("band", "exc", "vxc_dc", "elec", "self", "corr", "entropy", "free")},
+        "mu": float(r.mu),
+        "magnetization": last["magnetization"],
+        "eig_up": [float(x) for x in r.lam[0]],
+        "eig_dn": [float(x) for x in r.lam[1]],
+        "occ_up": [float(x) for x in r.f[0]],
+        "occ_dn": [float(x) for x in r.f[1]],
+        "residual": last["residual"],
+        "trajectory": [{"free_per_atom": h["free"] / s.n_atoms, "residual": h["residual"],
+                        "magnetization": h["magnetization"]} for h in r.history[:N_TRAJ]],
+        "rho_out_samples": {"index": [int(i) for i in idx],
+                            "up": [float(r.rho_out[i]) for i in idx],
+                            "dn": [float(r.rho_out[nd + i]) for i in idx]},
+    }
+
+
 def main():
-    for name, pulay in (("cfg1_scf.json", None), ("cfg1_scf_pulay.json", (7, 2, 1))):
+    jobs = (("cfg1_scf.json", lambda: cfg1_scf()), ("cfg1_scf_pulay.json", lambda: cfg1_scf((7, 2, 1))),
+            ("cfg1s_spin_scf.json", cfg1s_spin_scf))
+    for name, job in jobs:
         if len(sys.argv) > 1 and name not in sys.argv[1:]:
             continue
         out = os.path.join(HERE, name)
         with open(out, "w") as f:
-            json.dump(cfg1_scf(pulay), f, indent=1)
+            json.dump(job(), f, indent=1)
         print("wrote", out)
 
 

@@ -30,6 +30,9 @@ __all__ = [
     "config3",
     "config4",
     "config5_snapshot",
+    "config1_spin",
+    "config2_spin",
+    "initial_orbitals_spin",
     "tiny_system",
     "initial_orbitals",
     "CONFIG_NAMES",
@@ -68,6 +71,8 @@ class System:
     pulay_period: int = 2      # Pulay extrapolation every pulay_period-th iteration
     pulay_restart: int = 0     # 1: discard the history after a Pulay step on a full history
     n_first: int = 4                 # filter passes in the first SCF iteration
+    spin: int = 1                    # 1: spin-unpolarised, 2: spin-polarised (n_states per spin)
+    spin_zeta0: float = 0.0          # starting polarisation of the split atomic-density guess
     seed: int = 0
     meta: dict = field(default_factory=dict)
 
@@ -267,9 +272,41 @@ def initial_orbitals_rows(nd: int, ns: int, seed: int = 0, rows: int = 16):
         yield r0, rng.uniform(-0.5, 0.5, (k, nd))
 
 
+def config1_spin(seed: int = 0) -> System:
+    """Spin-polarised config 1: the config-1 cell and geometry with the last
+    atom's charge set to Z = 1 (15 electrons), 12 states per spin, starting
+    polarisation zeta0 = 1/15 (one unpaired electron), linear mixing 0.3,
+    kT = 0.002 Ha (at config 1's 0.01 Ha the smearing exceeds the exchange
+    splitting of the odd electron and the ground state is unpolarised)."""
+    s = config1(seed)
+    Z = s.Z.copy()
+    Z[-1] = 1.0
+    return replace(s, name="cfg1s", Z=Z, n_electrons=float(Z.sum()), kT=0.002, spin=2, spin_zeta0=1.0 / 15.0)
+
+
+def config2_spin(seed: int = 0) -> System:
+    """Spin-polarised config 2: the config-2 system with the last atom's
+    charge set to Z = 3 (431 electrons), 260 states per spin, starting
+    polarisation zeta0 = 1/431, config 2's mixing."""
+    s = config2(seed)
+    Z = s.Z.copy()
+    Z[-1] = 3.0
+    return replace(s, name="cfg2s", Z=Z, n_electrons=float(Z.sum()), spin=2, spin_zeta0=1.0 / 431.0)
+
+
+def initial_orbitals_spin(nd: int, ns: int, seed: int = 0):
+    """Starting blocks (up, down) for the spin-polarised form: up is
+    ``initial_orbitals(nd, ns, seed)``, down an independent draw."""
+    up = initial_orbitals(nd, ns, seed)
+    rng = np.random.default_rng([seed, 11, 1])
+    return up, rng.uniform(-0.5, 0.5, (ns, nd))
+
+
 CONFIG_NAMES = {
     "cfg1": config1,
     "cfg2": config2,
     "cfg3": config3,
     "cfg4": config4,
+    "cfg1s": config1_spin,
+    "cfg2s": config2_spin,
 }
