@@ -183,7 +183,9 @@ sparc_status sparc_gpu_spectrum_bounds(sparc_gpu_ctx ctx, double* lo, double* hi
 
 /* Density mixing (Sec. 2.1: the restarted form of periodic Pulay mixing
  * with a real-space preconditioner) for SCF iteration `iter` (0-based), with
- * x = d_rho_in (updated in place) and f = d_rho_out - d_rho_in:
+ * x = d_rho_in (updated in place) and f = d_rho_out - d_rho_in, vectors of
+ * n_spin x N_d doubles (n_spin = 2: the up then the down spin density; the
+ * paper mixes both spin components as one vector of twice the length):
  *   linear step:  x <- x + beta P f
  *   Pulay step, taken when m > 0, the history holds c >= 1 pairs and
  *   (iter + 1) is a multiple of `period`:
@@ -196,17 +198,20 @@ sparc_status sparc_gpu_spectrum_bounds(sparc_gpu_ctx ctx, double* lo, double* hi
  *   emptied (the paper names the restarted form without stating the rule;
  *   this is the reading implemented).
  * P = (-Lap_h)(-Lap_h + q0^2)^-1 in the eigenbasis of the discrete Laplacian
- * (constant mode removed) when kerker_q0 > 0, else the identity.
- * d_hist (m > 0): (2 m + 2) x N_d doubles, caller-owned, layout
+ * (constant mode removed) when kerker_q0 > 0, else the identity.  With
+ * n_spin = 2, P acts on the total f_up + f_dn and passes the magnetisation
+ * part f_up - f_dn unchanged.
+ * d_hist (m > 0): (2 m + 2) x n_spin N_d doubles, caller-owned, layout
  * [x_prev | f_prev | dX slots 0..m-1 | dF slots 0..m-1]; the call with
  * iter = 0 initialises it and every call with iter = k must follow the call
  * with k - 1 on the same buffer.  NULL allowed when m = 0.
  * Errors: SPARC_ERR_ARG (m outside [0, SPARC_PULAY_MAX], period < 1, bad
- * beta or q0, null buffers, iter < 0); SPARC_ERR_SINGULAR when a pivot of
+ * beta or q0, n_spin not 1 or 2, null buffers, iter < 0); SPARC_ERR_SINGULAR
+ * when a pivot of
  * the normal equations is zero or gamma is not finite (x then holds the
  * linear step, gamma = 0).  Synchronises once. */
 #define SPARC_PULAY_MAX 10
-sparc_status sparc_gpu_mix(sparc_gpu_ctx ctx, double* d_rho_in, const double* d_rho_out, double beta,
+sparc_status sparc_gpu_mix(sparc_gpu_ctx ctx, double* d_rho_in, const double* d_rho_out, int n_spin, double beta,
                            double kerker_q0, int pulay_history, int pulay_period, int restart, double* d_hist,
                            int iter);
 
@@ -269,6 +274,59 @@ sparc_status sparc_gpu_scf_step(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st, spar
  * energy at rho_in.  No mixing; st->iter unchanged.  Synchronises once. */
 sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st, double* d_X64, long ldx64,
                                      sparc_gpu_scf_report* rep);
+
+/* ---- Spin-polarised form (eq. (1)-(2) with a spin index; Sec. 2.1) -------
+ * One orbital block per spin, each with n_states columns; the Hamiltonian
+ * of spin s has V_eff^s = phi + v_xc^s(rho_up, rho_dn) with phi from the
+ * total density; occupations are one electron per state with a common
+ * Fermi level; rho^s = sum_n f_n^s |psi_n^s|^2.  LSDA: exchange by the exact
+ * spin-scaling relation, correlation by the PW92 interpolation in
+ * zeta = (rho_up - rho_dn) / rho; each spin density is floored at
+ * rho_floor / 2. */
+
+/* phi (N_d), eps_xc (N_d), v_xc (2 N_d: up, down) and V_eff (2 N_d) for the
+ * spin densities d_rho (2 N_d: up, down).  Outputs may be NULL.  Uses the
+ * context's scratch fields. */
+sparc_status sparc_gpu_potential_spin(sparc_gpu_ctx ctx, const double* d_rho, double* d_phi, double* d_exc,
+                                      double* d_vxc, double* d_veff);
+
+/* Occupations of 2 x ncol spin states: d_eig holds the ncol up then the ncol
+ * down eigenvalues; d_occ receives f in the same order (one electron per
+ * state), mu by bisection with sum f = N_e; *d_mu (device, may be NULL).
+ * Errors: SPARC_ERR_ARG (ncol outside [1, n_states], N_e > 2 ncol). */
+sparc_status sparc_gpu_occupations_spin(sparc_gpu_ctx ctx, const double* d_eig, int ncol, double* d_occ,
+                                        double* d_mu);
+
+typedef struct {
+    double* d_rho_in;   /* in/out: 2 N_d doubles, rho_up then rho_dn         */
+    void* d_X_up;       /* in/out: N_d x n_states block of the up spin       */
+    void* d_X_dn;       /* in/out: same for the down spin (no overlap)       */
+    long ldx;           /* leading dimension of both blocks                  */
+    int prec;           /* sparc_prec of both blocks                         */
+    int cheb_degree;
+    int n_first;
+    double mix_beta;
+    double kerker_q0;   /* on the total density of the mixing vector         */
+    int pulay_history;  /* as in sparc_gpu_scf_state, over 2 N_d vectors     */
+    int pulay_period;
+    int pulay_restart;
+    double* d_pulay;    /* m > 0: (2 m + 2) x 2 N_d doubles, caller-owned    */
+    int iter;
+    double* d_eig;      /* out: 2 n_states Ritz values (up, then down)       */
+    double* d_occ;      /* out: 2 n_states occupations                       */
+    double* d_rho_out;  /* optional out: 2 N_d (may be NULL)                 */
+    double bounds[6];   /* a, b, a0 of the up spin, then of the down spin    */
+} sparc_gpu_scf_spin_state;
+
+/* One spin-polarised SCF iteration: V_eff^up, V_eff^dn from rho_in; for
+ * each spin the filter + Rayleigh-Ritz schedule of sparc_gpu_scf_step with
+ * that spin's V_eff, block and bounds; common-mu occupations, both output
+ * densities, the free energy at rho_in (band and entropy terms over all
+ * spin states, v_xc double counting per spin), the residual over the
+ * 2 N_d vector and the mixing step of sparc_gpu_mix with n_spin = 2.
+ * The context's V_eff holds the down spin's potential afterwards.
+ * Synchronises once at the end to fill rep (may be NULL). */
+sparc_status sparc_gpu_scf_step_spin(sparc_gpu_ctx ctx, sparc_gpu_scf_spin_state* st, sparc_gpu_scf_report* rep);
 
 /* Kernel timing (tracing aid).  When enabled, every launch of the listed
  * kernels is bracketed by HIP events on the context's stream.

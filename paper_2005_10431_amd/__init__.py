@@ -12,7 +12,9 @@ from ._lib import (  # noqa: F401
     SCFReport,
     SCFState,
     SparcError,
+    SpinSCFState,
     load,
+    make_spin_state,
     make_state,
 )
-from .driver import run_scf  # noqa: F401
+from .driver import run_scf, run_scf_spin  # noqa: F401

@@ -49,6 +49,9 @@ EXPORTED = [
     "sparc_gpu_sad_density",
     "sparc_gpu_spectrum_bounds",
     "sparc_gpu_mix",
+    "sparc_gpu_potential_spin",
+    "sparc_gpu_occupations_spin",
+    "sparc_gpu_scf_step_spin",
     "sparc_gpu_scf_step",
     "sparc_gpu_final_rr_fp64",
     "sparc_gpu_profile",
@@ -113,6 +116,29 @@ class SCFState(C.Structure):
     ]
 
 
+class SpinSCFState(C.Structure):
+    _fields_ = [
+        ("d_rho_in", C.c_void_p),
+        ("d_X_up", C.c_void_p),
+        ("d_X_dn", C.c_void_p),
+        ("ldx", C.c_long),
+        ("prec", C.c_int),
+        ("cheb_degree", C.c_int),
+        ("n_first", C.c_int),
+        ("mix_beta", C.c_double),
+        ("kerker_q0", C.c_double),
+        ("pulay_history", C.c_int),
+        ("pulay_period", C.c_int),
+        ("pulay_restart", C.c_int),
+        ("d_pulay", C.c_void_p),
+        ("iter", C.c_int),
+        ("d_eig", C.c_void_p),
+        ("d_occ", C.c_void_p),
+        ("d_rho_out", C.c_void_p),
+        ("bounds", C.c_double * 6),
+    ]
+
+
 class SCFReport(C.Structure):
     _fields_ = [
         ("free_energy", C.c_double),
@@ -169,7 +195,10 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_pseudocharge": ([vp, vp, C.POINTER(d), C.POINTER(d)], i),
         "sparc_gpu_sad_density": ([vp, vp], i),
         "sparc_gpu_spectrum_bounds": ([vp, C.POINTER(d), C.POINTER(d)], i),
-        "sparc_gpu_mix": ([vp, vp, vp, d, d, i, i, i, vp, i], i),
+        "sparc_gpu_mix": ([vp, vp, vp, i, d, d, i, i, i, vp, i], i),
+        "sparc_gpu_potential_spin": ([vp, vp, vp, vp, vp, vp], i),
+        "sparc_gpu_occupations_spin": ([vp, vp, i, vp, vp], i),
+        "sparc_gpu_scf_step_spin": ([vp, C.POINTER(SpinSCFState), C.POINTER(SCFReport)], i),
         "sparc_gpu_scf_step": ([vp, C.POINTER(SCFState), C.POINTER(SCFReport)], i),
         "sparc_gpu_final_rr_fp64": ([vp, C.POINTER(SCFState), vp, l, C.POINTER(SCFReport)], i),
         "sparc_gpu_profile": ([vp, i], i),
@@ -316,12 +345,27 @@ class Context:
         return lo.value, hi.value
 
     def mix(self, rho_in, rho_out, beta, kerker_q0=0.0, pulay_history=0, pulay_period=1, restart=False,
-            hist=None, iter=0):
-        """rho_in (updated in place), rho_out: (N_d,) float64; hist:
-        ((2 m + 2) N_d,) float64 history buffer when pulay_history = m > 0."""
-        self._check(self.lib.sparc_gpu_mix(self.h, _ptr(rho_in), _ptr(rho_out), float(beta), float(kerker_q0),
-                                           int(pulay_history), int(pulay_period), 1 if restart else 0, _ptr(hist),
-                                           int(iter)))
+            hist=None, iter=0, n_spin=1):
+        """rho_in (updated in place), rho_out: (n_spin N_d,) float64; hist:
+        ((2 m + 2) n_spin N_d,) float64 history buffer when pulay_history = m > 0."""
+        self._check(self.lib.sparc_gpu_mix(self.h, _ptr(rho_in), _ptr(rho_out), int(n_spin), float(beta),
+                                           float(kerker_q0), int(pulay_history), int(pulay_period),
+                                           1 if restart else 0, _ptr(hist), int(iter)))
+
+    def potential_spin(self, rho, phi=None, exc=None, vxc=None, veff=None):
+        """rho: (2 N_d,) up then down; vxc, veff: (2 N_d,)."""
+        self._check(self.lib.sparc_gpu_potential_spin(self.h, _ptr(rho), _ptr(phi), _ptr(exc), _ptr(vxc),
+                                                       _ptr(veff)))
+
+    def occupations_spin(self, eig, occ, mu=None):
+        """eig, occ: (2 ncol,) float64, up then down."""
+        self._check(self.lib.sparc_gpu_occupations_spin(self.h, _ptr(eig), int(eig.numel()) // 2, _ptr(occ),
+                                                        _ptr(mu)))
+
+    def scf_step_spin(self, state) -> dict:
+        rep = SCFReport()
+        self._check(self.lib.sparc_gpu_scf_step_spin(self.h, C.byref(state), C.byref(rep)))
+        return rep.as_dict()
 
     def scf_step(self, state: SCFState) -> dict:
         rep = SCFReport()
@@ -389,4 +433,33 @@ def make_state(rho_in, X, eig, occ, degree, n_first=4, beta=0.3, rho_out=None, k
     st.d_occ = occ.data_ptr()
     st.d_rho_out = rho_out.data_ptr() if rho_out is not None else None
     st.bounds = (C.c_double * 3)(0.0, 0.0, 0.0)
+    return st
+
+
+def make_spin_state(rho_in, X_up, X_dn, eig, occ, degree, n_first=4, beta=0.3, rho_out=None, kerker_q0=0.0,
+                    pulay_history=0, pulay_period=1, pulay_restart=False, pulay_hist=None) -> SpinSCFState:
+    """rho_in: (2 N_d,) float64 (up, down); X_up, X_dn: (n_states, ld) blocks of
+    one dtype and ld; eig, occ: (2 n_states,) float64; pulay_hist:
+    ((2 m + 2) 2 N_d,) float64 when pulay_history = m > 0."""
+    if X_up.stride(0) != X_dn.stride(0) or X_up.dtype != X_dn.dtype:
+        raise ValueError("spin blocks must share dtype and leading dimension")
+    st = SpinSCFState()
+    st.d_rho_in = rho_in.data_ptr()
+    st.d_X_up = X_up.data_ptr()
+    st.d_X_dn = X_dn.data_ptr()
+    st.ldx = X_up.stride(0)
+    st.prec = _prec_of(X_up)
+    st.cheb_degree = int(degree)
+    st.n_first = int(n_first)
+    st.mix_beta = float(beta)
+    st.kerker_q0 = float(kerker_q0)
+    st.pulay_history = int(pulay_history)
+    st.pulay_period = int(pulay_period)
+    st.pulay_restart = 1 if pulay_restart else 0
+    st.d_pulay = pulay_hist.data_ptr() if pulay_hist is not None else None
+    st.iter = 0
+    st.d_eig = eig.data_ptr()
+    st.d_occ = occ.data_ptr()
+    st.d_rho_out = rho_out.data_ptr() if rho_out is not None else None
+    st.bounds = (C.c_double * 6)(*([0.0] * 6))
     return st

@@ -92,6 +92,7 @@ struct sparc_gpu_ctx_s {
     // device fields
     double* veff = nullptr;     // N_d
     float* veff32 = nullptr;    // N_d
+    double* veff_spin = nullptr;  // 2 N_d: V_eff of both spins (spin-polarised SCF, allocated on use)
     double* b = nullptr;        // pseudocharge, N_d
     double e_self = 0, e_c = 0;
     sg::NonlocalTables nl;
@@ -179,6 +180,7 @@ enum Scalar {
     S_EIG = 22,                      // eigensolver norms (2 slots)
     S_CNN = 32,                      // warm-start network head sums (6 slots)
     S_PULAY = 40,                    // Pulay weights gamma (SPARC_PULAY_MAX slots)
+    S_SPINB = 50,                    // filter bounds a, b, a0 of both spins (6 slots)
     S_COUNT = 64
 };
 enum Flag {
@@ -225,7 +227,9 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int ncol, long ldx, doubl
 // Grid-field kernels
 sparc_status potential_impl(sparc_gpu_ctx c, const double* rho, double* phi, double* exc, double* vxc,
                             double* veff);
-sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu);
+// deg: electrons per state (2 spin-unpolarised, 1 per spin state)
+sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu,
+                              double deg = 2.0);
 template <typename T>
 sparc_status density_impl(sparc_gpu_ctx c, const T* X, int ncol, long ldx, const double* occ, double* rho);
 sparc_status set_veff_impl(sparc_gpu_ctx c, const double* d_veff);

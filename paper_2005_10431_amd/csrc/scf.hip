@@ -127,6 +127,100 @@ sparc_status potential_impl(sparc_gpu_ctx c, const double* rho, double* phi, dou
     return SPARC_OK;
 }
 
+// ---- spin-polarised LDA --------------------------------------------------
+// Exchange: E_x[rho_up, rho_dn] = (E_x[2 rho_up] + E_x[2 rho_dn]) / 2.
+// Correlation: PW92 interpolation in zeta between the unpolarised fit, the
+// fully polarised fit and the spin stiffness alpha_c (all of the form G).
+
+__device__ inline void pw92_form(double rs, double srs, double A, double a1, double b1, double b2, double b3,
+                                 double b4, double& G, double& dG) {
+    const double Q0 = -2.0 * A * (1.0 + a1 * rs);
+    const double Q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
+    const double dQ1 = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs);
+    const double lg = log1p(1.0 / Q1);
+    G = Q0 * lg;
+    dG = -2.0 * A * a1 * lg - Q0 * dQ1 / (Q1 * Q1 + Q1);
+}
+
+__device__ inline void lsda_point(double ru, double rd, double floor_, double& exc, double& vu, double& vd) {
+    const double pi = 3.14159265358979323846;
+    ru = fmax(ru, 0.5 * floor_);
+    rd = fmax(rd, 0.5 * floor_);
+    const double r = ru + rd;
+    const double z = (ru - rd) / r;
+    const double exu = -0.75 * cbrt(6.0 * ru / pi);
+    const double exd = -0.75 * cbrt(6.0 * rd / pi);
+    const double ex = (ru * exu + rd * exd) / r;
+    const double rs = cbrt(3.0 / (4.0 * pi * r));
+    const double srs = sqrt(rs);
+    double e0, d0, e1, d1, ma, dma;
+    pw92_form(rs, srs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294, e0, d0);
+    pw92_form(rs, srs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517, e1, d1);
+    pw92_form(rs, srs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671, ma, dma);
+    const double ac = -ma, dac = -dma;
+    const double fden = 0.51984209978974632953;     // 2^(4/3) - 2
+    const double fz20 = 8.0 / (9.0 * fden);          // f''(0)
+    const double up = 1.0 + z, dn = 1.0 - z;
+    const double cu = cbrt(up), cd = cbrt(dn);
+    const double f = (up * cu + dn * cd - 2.0) / fden;
+    const double df = (4.0 / 3.0) * (cu - cd) / fden;
+    const double z3 = z * z * z, z4 = z3 * z;
+    const double ec = e0 + ac * f / fz20 * (1.0 - z4) + (e1 - e0) * f * z4;
+    const double dec_rs = d0 + dac * f / fz20 * (1.0 - z4) + (d1 - d0) * f * z4;
+    const double dec_z = ac / fz20 * (df * (1.0 - z4) - 4.0 * z3 * f) + (e1 - e0) * (df * z4 + 4.0 * z3 * f);
+    const double common = ec - rs / 3.0 * dec_rs;
+    exc = ex + ec;
+    vu = (4.0 / 3.0) * exu + common + (1.0 - z) * dec_z;
+    vd = (4.0 / 3.0) * exd + common - (1.0 + z) * dec_z;
+}
+
+// rho: 2 n (up, down); vxc, veff: 2 n (may be null); exc: n (may be null)
+__global__ void k_lsda(const double* __restrict__ rho, const double* __restrict__ phi, double floor_,
+                       double* __restrict__ exc, double* __restrict__ vxc, double* __restrict__ veff, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double e, vu, vd;
+    lsda_point(rho[i], rho[n + i], floor_, e, vu, vd);
+    if (exc) exc[i] = e;
+    if (vxc) {
+        vxc[i] = vu;
+        vxc[n + i] = vd;
+    }
+    if (veff) {
+        veff[i] = phi[i] + vu;
+        veff[n + i] = phi[i] + vd;
+    }
+}
+
+__global__ void k_add3(const double* a, const double* b, const double* c, double* out, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (a[i] + b[i]) + c[i];
+}
+
+// phi of the total density, eps_xc, v_xc and V_eff of both spins.  Uses
+// fields[0..1] as scratch (phi falls back to field 2).
+static sparc_status potential_spin_impl(sparc_gpu_ctx c, const double* rho, double* phi, double* exc, double* vxc,
+                                        double* veff) {
+    sparc_status st = ensure_fields(c, 3);
+    if (st != SPARC_OK) return st;
+    const long nd = c->nd;
+    double* t0 = c->field;
+    double* t1 = c->field + nd;
+    double* ph = phi ? phi : c->field + 2 * nd;
+    const int nb = div_up(nd, 256);
+    k_add3<<<nb, 256, 0, c->stream>>>(rho, rho + nd, c->b, t0, nd);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_ux, c->nx, c->ny, c->nz, 0, 1);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uy, c->nx, c->ny, c->nz, 1, 1);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uz, c->nx, c->ny, c->nz, 2, 1);
+    k_mul<<<nb, 256, 0, c->stream>>>(t1, c->pois_inv, nd);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uz, c->nx, c->ny, c->nz, 2, 0);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uy, c->nx, c->ny, c->nz, 1, 0);
+    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, ph, c->pois_ux, c->nx, c->ny, c->nz, 0, 0);
+    k_lsda<<<nb, 256, 0, c->stream>>>(rho, ph, c->rho_floor, exc, vxc, veff, nd);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
 // ------------------------------------------------------------ occupations
 
 __device__ inline double fermi(double lam, double mu, double kT) {
@@ -138,11 +232,12 @@ __device__ inline double fermi(double lam, double mu, double kT) {
     return 1.0 / (1.0 + exp(x));
 }
 
-// One block: bisection for mu, then occupations and the entropy term
-// out[0] = mu, out[1] = 2 kT sum [f ln f + (1-f) ln(1-f)], out[2] = sum g lam.
+// One block: bisection for mu, then occupations g = deg f and the entropy
+// term: out[0] = mu, out[1] = deg kT sum [f ln f + (1-f) ln(1-f)],
+// out[2] = sum g lam.  deg = 2 spin-unpolarised, 1 per spin state.
 __global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ eig, int N, double ne, double kT,
-                                                     double* __restrict__ occ, double* __restrict__ out,
-                                                     int* __restrict__ flag) {
+                                                     double deg, double* __restrict__ occ,
+                                                     double* __restrict__ out, int* __restrict__ flag) {
     __shared__ double red[256];
     __shared__ double s_lo, s_hi, s_mu;
     __shared__ int s_done;
@@ -160,7 +255,7 @@ __global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ 
     for (int it = 0; it < 500; ++it) {
         double mu = 0.5 * (s_lo + s_hi);
         double acc = 0.0;
-        for (int i = t; i < N; i += blockDim.x) acc += 2.0 * fermi(eig[i], mu, kT);
+        for (int i = t; i < N; i += blockDim.x) acc += deg * fermi(eig[i], mu, kT);
         red[t] = acc;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
@@ -188,8 +283,8 @@ __global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ 
     double ent = 0.0, band = 0.0;
     for (int i = t; i < N; i += blockDim.x) {
         double f = fermi(eig[i], mu, kT);
-        occ[i] = 2.0 * f;
-        band += 2.0 * f * eig[i];
+        occ[i] = deg * f;
+        band += deg * f * eig[i];
         if (f > 0.0 && f < 1.0) ent += f * log(f) + (1.0 - f) * log(1.0 - f);
     }
     __syncthreads();
@@ -209,14 +304,14 @@ __global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ 
     }
     if (t == 0) {
         out[0] = mu;
-        out[1] = 2.0 * kT * ent_sum;
+        out[1] = deg * kT * ent_sum;
         out[2] = red[0];
         if (!s_done || !isfinite(mu)) flag[0] = 1;
     }
 }
 
-sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu) {
-    k_occupations<<<1, 256, 0, c->stream>>>(eig, ncol, c->n_electrons, c->kT, occ, c->scal + S_OCC,
+sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu, double deg) {
+    k_occupations<<<1, 256, 0, c->stream>>>(eig, ncol, c->n_electrons, c->kT, deg, occ, c->scal + S_OCC,
                                            c->flags + F_FERMI);
     SG_CHECK_LAUNCH(c);
     if (mu) SG_HIP(c, hipMemcpyAsync(mu, c->scal + S_OCC, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -282,6 +377,37 @@ __global__ __launch_bounds__(256) void k_energy_mix(double* __restrict__ rho_in,
     if (t < kRed) part[(long)blockIdx.x * kRed + t] = red[t][0];
 }
 
+// The same partial sums for spin densities (2 nd vectors, up then down):
+// rho exc with the total rho, sum_s rho_s vxc_s, (b - rho) phi, and the
+// residual sums over both spins.
+__global__ __launch_bounds__(256) void k_energy_spin(const double* __restrict__ rin, const double* __restrict__ rout,
+                                                     const double* __restrict__ exc, const double* __restrict__ vxc,
+                                                     const double* __restrict__ phi, const double* __restrict__ b,
+                                                     long nd, double* __restrict__ part) {
+    __shared__ double red[kRed][256];
+    const int t = threadIdx.x;
+    double s[kRed] = {0, 0, 0, 0, 0, 0};
+    for (long i = (long)blockIdx.x * blockDim.x + t; i < nd; i += (long)gridDim.x * blockDim.x) {
+        const double ru = rin[i], rd = rin[nd + i], ou = rout[i], od = rout[nd + i];
+        const double r = ru + rd;
+        s[0] += r * exc[i];
+        s[1] += ru * vxc[i] + rd * vxc[nd + i];
+        s[2] += (b[i] - r) * phi[i];
+        const double du = ou - ru, dd = od - rd;
+        s[3] += du * du + dd * dd;
+        s[4] += ou * ou + od * od;
+        s[5] += ou + od;
+    }
+    for (int k = 0; k < kRed; ++k) red[k][t] = s[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st)
+            for (int k = 0; k < kRed; ++k) red[k][t] += red[k][t + st];
+        __syncthreads();
+    }
+    if (t < kRed) part[(long)blockIdx.x * kRed + t] = red[t][0];
+}
+
 __global__ void k_residual(const double* a, const double* b, double* out, long n) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = a[i] - b[i];
@@ -305,7 +431,7 @@ __global__ void k_axpy(double* y, const double* x, double a, long n) {
 // ---- periodic Pulay mixing (Sec. 2.1) --------------------------------------
 // History buffer of N_d-vectors: [x_prev | f_prev | dX slots | dF slots].
 
-static_assert(S_PULAY + SPARC_PULAY_MAX <= S_COUNT, "Pulay weights fit the scalar block");
+static_assert(S_PULAY + SPARC_PULAY_MAX <= S_SPINB && S_SPINB + 6 <= S_COUNT, "scalar block layout");
 
 // Which slots hold valid pairs at iteration `iter`, where this iteration's
 // pair goes, and whether it is a Pulay iteration: the schedule is replayed
@@ -479,6 +605,26 @@ __global__ void k_pulay_apply(double* __restrict__ x, const double* __restrict__
     }
 }
 
+// Spin mixing vector f = [f_up; f_dn] (f = a - b, or f = a when b is
+// null): sum <- f_up + f_dn, diff <- f_up - f_dn.  diff may alias a.
+__global__ void k_spin_split(const double* a, const double* b, double* __restrict__ sum, double* diff, long nd) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    const double fu = b ? a[i] - b[i] : a[i];
+    const double fd = b ? a[nd + i] - b[nd + i] : a[nd + i];
+    sum[i] = fu + fd;
+    diff[i] = fu - fd;
+}
+
+// x_up += beta (P sum + diff) / 2, x_dn += beta (P sum - diff) / 2
+__global__ void k_spin_combine(double* __restrict__ x, const double* __restrict__ psum,
+                               const double* __restrict__ diff, double beta, long nd) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    x[i] += beta * (0.5 * (psum[i] + diff[i]));
+    x[nd + i] += beta * (0.5 * (psum[i] - diff[i]));
+}
+
 __global__ void k_mix_linear(double* __restrict__ x, const double* __restrict__ ro, double beta, long nd) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nd) {
@@ -543,6 +689,7 @@ struct MixArgs {
     int m, period, restart;
     double* hist;
     int iter;
+    int nspin;   // 1, or 2 for [rho_up; rho_dn] vectors
 };
 
 constexpr int kPulayBlocks = 512;
@@ -552,8 +699,8 @@ static size_t mix_red_doubles(int m) {
 }
 
 // The mixing step, stream-ordered.  Uses fields 0 and 1 as preconditioner
-// temporaries and c->red for the Pulay partial sums (sized by the caller to
-// mix_red_doubles(m)).
+// temporaries (and fields 8, 9 with two spins) and c->red for the Pulay
+// partial sums (sized by the caller to mix_red_doubles(m)).
 static sparc_status mix_steps(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs& a);
 
 static sparc_status mix_impl(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs& a) {
@@ -565,14 +712,17 @@ static sparc_status mix_impl(sparc_gpu_ctx c, double* rho_in, const double* rho_
 
 static sparc_status mix_steps(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs& a) {
     const long nd = c->nd;
-    const int nb = div_up(nd, 256);
+    const long n = nd * a.nspin;   // length of the mixing vectors
+    const int nb = div_up(n, 256);
+    const int nb1 = div_up(nd, 256);
     double* t0 = c->field;
     double* t1 = c->field + nd;
+    double* fbar = a.nspin == 1 ? t0 : c->field + 8 * nd;
     const bool precond = a.q0 > 0.0;
     bool have_fbar = false;
     if (a.m > 0) {
         const PulayPlan pl = pulay_plan(a.iter, a.m, a.period, a.restart);
-        k_pulay_push<<<nb, 256, 0, c->stream>>>(rho_in, rho_out, a.hist, nd, a.m, pl.push_slot);
+        k_pulay_push<<<nb, 256, 0, c->stream>>>(rho_in, rho_out, a.hist, n, a.m, pl.push_slot);
         SG_CHECK_LAUNCH(c);
         if (pl.pulay) {
             SlotList sl{};
@@ -581,36 +731,45 @@ static sparc_status mix_steps(sparc_gpu_ctx c, double* rho_in, const double* rho
             const int nblk = std::min(kPulayBlocks, nb);
             switch (C) {
 #define SG_PULAY_DOTS(CC) \
-    case CC: k_pulay_dots<CC><<<nblk, 256, 0, c->stream>>>(a.hist, nd, a.m, sl, c->red); break;
+    case CC: k_pulay_dots<CC><<<nblk, 256, 0, c->stream>>>(a.hist, n, a.m, sl, c->red); break;
                 SG_PULAY_DOTS(1) SG_PULAY_DOTS(2) SG_PULAY_DOTS(3) SG_PULAY_DOTS(4) SG_PULAY_DOTS(5)
                 SG_PULAY_DOTS(6) SG_PULAY_DOTS(7) SG_PULAY_DOTS(8) SG_PULAY_DOTS(9) SG_PULAY_DOTS(10)
 #undef SG_PULAY_DOTS
                 default: return set_err(c, SPARC_ERR_ARG, "mix: Pulay history too long");
             }
             k_pulay_solve<<<1, 256, 0, c->stream>>>(c->red, nblk, C, c->scal, c->flags);
-            k_pulay_apply<<<nb, 256, 0, c->stream>>>(rho_in, a.hist, c->scal, nd, a.m, sl, C, a.beta,
-                                                     precond ? t0 : nullptr);
+            k_pulay_apply<<<nb, 256, 0, c->stream>>>(rho_in, a.hist, c->scal, n, a.m, sl, C, a.beta,
+                                                     precond ? fbar : nullptr);
             SG_CHECK_LAUNCH(c);
             if (!precond) return SPARC_OK;
             have_fbar = true;
         }
     }
     if (!precond) {
-        k_mix_linear<<<nb, 256, 0, c->stream>>>(rho_in, rho_out, a.beta, nd);
+        k_mix_linear<<<nb, 256, 0, c->stream>>>(rho_in, rho_out, a.beta, n);
         SG_CHECK_LAUNCH(c);
         return SPARC_OK;
     }
     // rho_in += beta P r with r = f (or f_bar after a Pulay step), P =
-    // (-Lap)(-Lap + q0^2)^-1 in the eigenbasis of the discrete Laplacian
-    if (!have_fbar) k_residual<<<nb, 256, 0, c->stream>>>(rho_out, rho_in, t0, nd);
-    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_ux, c->nx, c->ny, c->nz, 0, 1);
-    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uy, c->nx, c->ny, c->nz, 1, 1);
-    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uz, c->nx, c->ny, c->nz, 2, 1);
-    k_kerker<<<nb, 256, 0, c->stream>>>(t1, c->pois_inv, a.q0 * a.q0, nd);
-    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_uz, c->nx, c->ny, c->nz, 2, 0);
-    k_axis_transform<<<nb, 256, 0, c->stream>>>(t0, t1, c->pois_uy, c->nx, c->ny, c->nz, 1, 0);
-    k_axis_transform<<<nb, 256, 0, c->stream>>>(t1, t0, c->pois_ux, c->nx, c->ny, c->nz, 0, 0);
-    k_axpy<<<nb, 256, 0, c->stream>>>(rho_in, t0, a.beta, nd);
+    // (-Lap)(-Lap + q0^2)^-1 in the eigenbasis of the discrete Laplacian;
+    // with two spins P acts on r_up + r_dn and r_up - r_dn passes unchanged
+    double* diff = c->field + 8 * nd;
+    if (a.nspin == 2)
+        k_spin_split<<<nb1, 256, 0, c->stream>>>(have_fbar ? fbar : rho_out, have_fbar ? nullptr : rho_in, t0, diff,
+                                                 nd);
+    else if (!have_fbar)
+        k_residual<<<nb1, 256, 0, c->stream>>>(rho_out, rho_in, t0, nd);
+    k_axis_transform<<<nb1, 256, 0, c->stream>>>(t0, t1, c->pois_ux, c->nx, c->ny, c->nz, 0, 1);
+    k_axis_transform<<<nb1, 256, 0, c->stream>>>(t1, t0, c->pois_uy, c->nx, c->ny, c->nz, 1, 1);
+    k_axis_transform<<<nb1, 256, 0, c->stream>>>(t0, t1, c->pois_uz, c->nx, c->ny, c->nz, 2, 1);
+    k_kerker<<<nb1, 256, 0, c->stream>>>(t1, c->pois_inv, a.q0 * a.q0, nd);
+    k_axis_transform<<<nb1, 256, 0, c->stream>>>(t1, t0, c->pois_uz, c->nx, c->ny, c->nz, 2, 0);
+    k_axis_transform<<<nb1, 256, 0, c->stream>>>(t0, t1, c->pois_uy, c->nx, c->ny, c->nz, 1, 0);
+    k_axis_transform<<<nb1, 256, 0, c->stream>>>(t1, t0, c->pois_ux, c->nx, c->ny, c->nz, 0, 0);
+    if (a.nspin == 2)
+        k_spin_combine<<<nb1, 256, 0, c->stream>>>(rho_in, t0, diff, a.beta, nd);
+    else
+        k_axpy<<<nb1, 256, 0, c->stream>>>(rho_in, t0, a.beta, nd);
     SG_CHECK_LAUNCH(c);
     return SPARC_OK;
 }
@@ -619,17 +778,20 @@ static sparc_status mix_steps(sparc_gpu_ctx c, double* rho_in, const double* rho
 // mixing step when mix != nullptr.  Fields: phi = f[2], exc = f[3],
 // vxc = f[4]; fields 0, 1 are free.
 static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs* mix,
-                                  sparc_gpu_scf_report* rep, double* hscal) {
+                                  sparc_gpu_scf_report* rep, double* hscal, int nspin = 1) {
     const int nblk = std::min(1024, div_up(c->nd, 256));
     sparc_status st = ensure_red(c, std::max((size_t)nblk * kRed, mix ? mix_red_doubles(mix->m) : 0));
     if (st != SPARC_OK) return st;
     const double* phi = c->field + 2 * c->nd;
     const double* exc = c->field + 3 * c->nd;
     const double* vxc = c->field + 4 * c->nd;
-    // plain linear mixing is fused into the energy pass
-    const bool fused = mix && mix->m == 0 && !(mix->q0 > 0.0);
-    k_energy_mix<<<nblk, 256, 0, c->stream>>>(rho_in, rho_out, exc, vxc, phi, c->b, c->nd, fused ? mix->beta : 0.0,
-                                              fused ? 1 : 0, c->red);
+    // plain linear mixing is fused into the energy pass (one spin)
+    const bool fused = nspin == 1 && mix && mix->m == 0 && !(mix->q0 > 0.0);
+    if (nspin == 1)
+        k_energy_mix<<<nblk, 256, 0, c->stream>>>(rho_in, rho_out, exc, vxc, phi, c->b, c->nd,
+                                                  fused ? mix->beta : 0.0, fused ? 1 : 0, c->red);
+    else
+        k_energy_spin<<<nblk, 256, 0, c->stream>>>(rho_in, rho_out, exc, vxc, phi, c->b, c->nd, c->red);
     SG_CHECK_LAUNCH(c);
     k_energy_final<<<kRed, 256, 0, c->stream>>>(c->red, nblk, c->scal + S_RED0);
     SG_CHECK_LAUNCH(c);
@@ -709,7 +871,7 @@ static sparc_status scf_step_impl(sparc_gpu_ctx c, sparc_gpu_scf_state* s, sparc
     sparc_gpu_scf_report R;
     double hs[S_COUNT];
     const MixArgs mix{s->mix_beta, s->kerker_q0, s->pulay_history, s->pulay_period, s->pulay_restart, s->d_pulay,
-                      s->iter};
+                      s->iter, 1};
     if ((st = finish_energy(c, s->d_rho_in, rho_out, &mix, &R, hs)) != SPARC_OK) return st;
     tm.mark(7);
     SG_HIP(c, hipEventSynchronize(c->ev[7]));
@@ -725,6 +887,123 @@ static sparc_status scf_step_impl(sparc_gpu_ctx c, sparc_gpu_scf_state* s, sparc
     R.iter = s->iter;
     s->iter += 1;
     if (rep) *rep = R;
+    return SPARC_OK;
+}
+
+__global__ void k_stash_bounds(double* scal, int spin) {
+    scal[S_SPINB + 3 * spin + 0] = scal[S_A];
+    scal[S_SPINB + 3 * spin + 1] = scal[S_B];
+    scal[S_SPINB + 3 * spin + 2] = scal[S_A0];
+}
+
+static sparc_status ensure_veff_spin(sparc_gpu_ctx c) {
+    if (c->veff_spin) return SPARC_OK;
+    SG_HIP(c, hipMalloc((void**)&c->veff_spin, 2 * (size_t)c->nd * sizeof(double)));
+    return SPARC_OK;
+}
+
+template <typename T>
+static sparc_status scf_step_spin_impl(sparc_gpu_ctx c, sparc_gpu_scf_spin_state* s, sparc_gpu_scf_report* rep) {
+    sparc_status st;
+    const int N = c->n_states;
+    const long nd = c->nd;
+    T* Xs[2] = {(T*)s->d_X_up, (T*)s->d_X_dn};
+    if ((st = ensure_fields(c, 10)) != SPARC_OK) return st;
+    if ((st = ensure_work(c, ((size_t)(N - 1) * s->ldx + nd) * sizeof(T))) != SPARC_OK) return st;
+    if ((st = ensure_veff_spin(c)) != SPARC_OK) return st;
+    double* phi = c->field + 2 * nd;
+    double* exc = c->field + 3 * nd;
+    double* vxc = c->field + 4 * nd;   // 2 N_d
+    double* rho_out = s->d_rho_out ? s->d_rho_out : c->field + 6 * nd;
+    SG_HIP(c, hipMemsetAsync(c->flags, 0, F_COUNT * sizeof(int), c->stream));
+    Timer tm(c);
+    tm.mark(0);
+    if ((st = potential_spin_impl(c, s->d_rho_in, phi, exc, vxc, c->veff_spin)) != SPARC_OK) return st;
+    tm.mark(1);
+    const bool first = s->iter == 0;
+    const int npass = first ? s->n_first : 1;
+    double t_filter = 0.0, t_rr = 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+        T* X = Xs[sp];
+        double* eig = s->d_eig + (long)sp * N;
+        if ((st = set_veff_impl(c, c->veff_spin + sp * nd)) != SPARC_OK) return st;
+        if ((st = bounds_impl(c)) != SPARC_OK) return st;
+        if (first) {
+            if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, eig, true)) != SPARC_OK) return st;
+            k_bounds_from_eig<<<1, 1, 0, c->stream>>>(eig, N, c->scal, 1);
+        } else {
+            k_set_ab<<<1, 1, 0, c->stream>>>(c->scal, s->bounds[3 * sp], s->bounds[3 * sp + 2]);
+        }
+        SG_CHECK_LAUNCH(c);
+        for (int pass = 0; pass < npass; ++pass) {
+            tm.mark(2);
+            if ((st = filter_impl<T>(c, X, (T*)c->work, N, s->ldx, s->cheb_degree)) != SPARC_OK) return st;
+            tm.mark(3);
+            if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, eig, true)) != SPARC_OK) return st;
+            k_bounds_from_eig<<<1, 1, 0, c->stream>>>(eig, N, c->scal, 0);
+            SG_CHECK_LAUNCH(c);
+            tm.mark(4);
+            SG_HIP(c, hipEventSynchronize(c->ev[4]));
+            t_filter += tm.ms(2, 3);
+            t_rr += tm.ms(3, 4);
+        }
+        k_stash_bounds<<<1, 1, 0, c->stream>>>(c->scal, sp);
+        SG_CHECK_LAUNCH(c);
+    }
+    tm.mark(5);
+    if ((st = occupations_impl(c, s->d_eig, 2 * N, s->d_occ, nullptr, 1.0)) != SPARC_OK) return st;
+    for (int sp = 0; sp < 2; ++sp)
+        if ((st = density_impl<T>(c, Xs[sp], N, s->ldx, s->d_occ + (long)sp * N, rho_out + sp * nd)) != SPARC_OK)
+            return st;
+    tm.mark(6);
+    sparc_gpu_scf_report R;
+    double hs[S_COUNT];
+    const MixArgs mix{s->mix_beta, s->kerker_q0, s->pulay_history, s->pulay_period, s->pulay_restart, s->d_pulay,
+                      s->iter, 2};
+    if ((st = finish_energy(c, s->d_rho_in, rho_out, &mix, &R, hs, 2)) != SPARC_OK) return st;
+    tm.mark(7);
+    SG_HIP(c, hipEventSynchronize(c->ev[7]));
+    for (int k = 0; k < 6; ++k) s->bounds[k] = hs[S_SPINB + k];
+    R.t_potential_ms = tm.ms(0, 1);
+    R.t_filter_ms = t_filter;
+    R.t_rr_ms = t_rr;
+    R.t_density_ms = tm.ms(5, 6);
+    R.t_total_ms = tm.ms(0, 7);
+    R.n_passes = 2 * npass;
+    R.iter = s->iter;
+    s->iter += 1;
+    if (rep) *rep = R;
+    return SPARC_OK;
+}
+
+static bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+static sparc_status check_spin_state(sparc_gpu_ctx c, const sparc_gpu_scf_spin_state* s) {
+    if (!s) return set_err(c, SPARC_ERR_ARG, "scf_spin: null state");
+    if (!s->d_rho_in || !s->d_X_up || !s->d_X_dn || !s->d_eig || !s->d_occ)
+        return set_err(c, SPARC_ERR_ARG, "scf_spin: null buffer");
+    if (s->prec != SPARC_FP64 && s->prec != SPARC_FP32) return set_err(c, SPARC_ERR_ARG, "scf_spin: bad precision");
+    if (s->ldx < c->nd) return set_err(c, SPARC_ERR_ARG, "scf_spin: ldx < N_d");
+    const size_t es = s->prec == SPARC_FP64 ? 8 : 4;
+    if (ranges_overlap(s->d_X_up, s->d_X_dn, ((size_t)(c->n_states - 1) * s->ldx + c->nd) * es))
+        return set_err(c, SPARC_ERR_ARG, "scf_spin: the two spin blocks overlap");
+    if (s->cheb_degree < 1 || s->cheb_degree > 10000) return set_err(c, SPARC_ERR_ARG, "scf_spin: bad degree");
+    if (s->n_first < 1 || s->n_first > 100) return set_err(c, SPARC_ERR_ARG, "scf_spin: bad n_first");
+    if (!(s->mix_beta > 0.0 && s->mix_beta <= 1.0)) return set_err(c, SPARC_ERR_ARG, "scf_spin: bad mix_beta");
+    if (!(s->kerker_q0 >= 0.0) || !std::isfinite(s->kerker_q0))
+        return set_err(c, SPARC_ERR_ARG, "scf_spin: bad kerker_q0");
+    if (s->pulay_history < 0 || s->pulay_history > SPARC_PULAY_MAX)
+        return set_err(c, SPARC_ERR_ARG, "scf_spin: pulay_history outside [0, SPARC_PULAY_MAX]");
+    if (s->pulay_history > 0 && (s->pulay_period < 1 || (s->pulay_restart != 0 && s->pulay_restart != 1) ||
+                                 !s->d_pulay))
+        return set_err(c, SPARC_ERR_ARG, "scf_spin: bad Pulay period, restart flag or history buffer");
+    if (s->iter < 0) return set_err(c, SPARC_ERR_ARG, "scf_spin: negative iter");
+    if (s->iter > 0 && !(s->bounds[2] < s->bounds[0] && s->bounds[5] < s->bounds[3]))
+        return set_err(c, SPARC_ERR_ARG, "scf_spin: bounds need a0 < a after the first iteration");
     return SPARC_OK;
 }
 
@@ -818,11 +1097,13 @@ sparc_status sparc_gpu_density(sparc_gpu_ctx c, sparc_prec prec, const void* d_X
     return density_impl<float>(c, (const float*)d_X, ncol, ldx, d_occ, d_rho);
 }
 
-sparc_status sparc_gpu_mix(sparc_gpu_ctx c, double* d_rho_in, const double* d_rho_out, double beta, double kerker_q0,
-                           int pulay_history, int pulay_period, int restart, double* d_hist, int iter) {
+sparc_status sparc_gpu_mix(sparc_gpu_ctx c, double* d_rho_in, const double* d_rho_out, int n_spin, double beta,
+                           double kerker_q0, int pulay_history, int pulay_period, int restart, double* d_hist,
+                           int iter) {
     if (!c) return SPARC_ERR_ARG;
     c->err.clear();
     if (!d_rho_in || !d_rho_out) return set_err(c, SPARC_ERR_ARG, "mix: null density");
+    if (n_spin != 1 && n_spin != 2) return set_err(c, SPARC_ERR_ARG, "mix: n_spin must be 1 or 2");
     if (!(beta > 0.0 && beta <= 1.0)) return set_err(c, SPARC_ERR_ARG, "mix: bad beta");
     if (!(kerker_q0 >= 0.0) || !std::isfinite(kerker_q0)) return set_err(c, SPARC_ERR_ARG, "mix: bad kerker_q0");
     if (pulay_history < 0 || pulay_history > SPARC_PULAY_MAX)
@@ -831,16 +1112,43 @@ sparc_status sparc_gpu_mix(sparc_gpu_ctx c, double* d_rho_in, const double* d_rh
         return set_err(c, SPARC_ERR_ARG, "mix: bad Pulay period, restart flag or history buffer");
     if (iter < 0) return set_err(c, SPARC_ERR_ARG, "mix: negative iter");
     sparc_status st;
-    if ((st = ensure_fields(c, 2)) != SPARC_OK) return st;
+    if ((st = ensure_fields(c, n_spin == 2 ? 10 : 2)) != SPARC_OK) return st;
     if ((st = ensure_red(c, mix_red_doubles(pulay_history))) != SPARC_OK) return st;
     SG_HIP(c, hipMemsetAsync(c->flags + F_PULAY_SINGULAR, 0, sizeof(int), c->stream));
-    const MixArgs mix{beta, kerker_q0, pulay_history, pulay_period, restart, d_hist, iter};
+    const MixArgs mix{beta, kerker_q0, pulay_history, pulay_period, restart, d_hist, iter, n_spin};
     if ((st = mix_impl(c, d_rho_in, d_rho_out, mix)) != SPARC_OK) return st;
     int flag = 0;
     SG_HIP(c, hipMemcpyAsync(&flag, c->flags + F_PULAY_SINGULAR, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     SG_HIP(c, hipStreamSynchronize(c->stream));
     if (flag) return set_err(c, SPARC_ERR_SINGULAR, "Pulay normal equations singular");
     return SPARC_OK;
+}
+
+sparc_status sparc_gpu_scf_step_spin(sparc_gpu_ctx c, sparc_gpu_scf_spin_state* s, sparc_gpu_scf_report* rep) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = check_spin_state(c, s);
+    if (st != SPARC_OK) return st;
+    if (s->prec == SPARC_FP64) return scf_step_spin_impl<double>(c, s, rep);
+    return scf_step_spin_impl<float>(c, s, rep);
+}
+
+sparc_status sparc_gpu_potential_spin(sparc_gpu_ctx c, const double* d_rho, double* d_phi, double* d_exc,
+                                      double* d_vxc, double* d_veff) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_rho) return set_err(c, SPARC_ERR_ARG, "potential_spin: null density");
+    return potential_spin_impl(c, d_rho, d_phi, d_exc, d_vxc, d_veff);
+}
+
+sparc_status sparc_gpu_occupations_spin(sparc_gpu_ctx c, const double* d_eig, int ncol, double* d_occ,
+                                        double* d_mu) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!d_eig || !d_occ) return set_err(c, SPARC_ERR_ARG, "occupations_spin: null pointer");
+    if (ncol < 1 || ncol > c->n_states) return set_err(c, SPARC_ERR_ARG, "occupations_spin: ncol out of range");
+    if (c->n_electrons > 2.0 * ncol) return set_err(c, SPARC_ERR_ARG, "occupations_spin: N_e > 2 ncol");
+    return occupations_impl(c, d_eig, 2 * ncol, d_occ, d_mu, 1.0);
 }
 
 sparc_status sparc_gpu_occupations(sparc_gpu_ctx c, const double* d_eig, int ncol, double* d_occ, double* d_mu) {

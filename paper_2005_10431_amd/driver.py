@@ -4,7 +4,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from ._lib import SPARC_FP32, Context, make_state
+from ._lib import SPARC_FP32, Context, make_spin_state, make_state
 
 
 def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100, tol: float = 1e-10,
@@ -63,3 +63,57 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
         out["final"] = rep
         out["X64"] = X64
     return out
+
+
+def run_scf_spin(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100, tol: float = 1e-10,
+                 device: str = "cuda", ctx: Context = None, callback=None, n_first: int = None,
+                 degree: int = None):
+    """Spin-polarised SCF on the GPU (``sparc_gpu_scf_step_spin``).
+
+    X0: (X0_up, X0_dn) numpy arrays of shape (N_s, N_d) (default
+    ``workloads.initial_orbitals_spin``); rho0: (2 N_d,) up then down, or
+    None for the atomic-density guess split by ``system.spin_zeta0``.
+    Mixing, preconditioner and Pulay settings come from the system.
+    Each report gains "magnetization" = dV sum (rho_out_up - rho_out_dn)."""
+    import torch
+    ctx = ctx or Context(system)
+    nd, ns = system.nd, system.n_states
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if X0 is None:
+        from workloads import initial_orbitals_spin
+        X0 = initial_orbitals_spin(nd, ns, system.seed)
+    Xu = torch.as_tensor(np.asarray(X0[0]), dtype=dt).to(device).contiguous()
+    Xd = torch.as_tensor(np.asarray(X0[1]), dtype=dt).to(device).contiguous()
+    rho_in = torch.empty(2 * nd, dtype=torch.float64, device=device)
+    if rho0 is None:
+        ctx.sad_density(rho_in[:nd])
+        z = float(getattr(system, "spin_zeta0", 0.0))
+        rho_in[nd:].copy_(rho_in[:nd])
+        rho_in[:nd].mul_(0.5 * (1.0 + z))
+        rho_in[nd:].mul_(0.5 * (1.0 - z))
+    else:
+        src = rho0 if isinstance(rho0, torch.Tensor) else torch.as_tensor(np.asarray(rho0), dtype=torch.float64)
+        rho_in.copy_(src)
+    eig = torch.empty(2 * ns, dtype=torch.float64, device=device)
+    occ = torch.empty(2 * ns, dtype=torch.float64, device=device)
+    rho_out = torch.empty(2 * nd, dtype=torch.float64, device=device)
+    m = getattr(system, "pulay_history", 0)
+    hist_buf = torch.empty((2 * m + 2) * 2 * nd, dtype=torch.float64, device=device) if m > 0 else None
+    st = make_spin_state(rho_in, Xu, Xd, eig, occ,
+                         degree if degree is not None else system.cheb_degree,
+                         n_first if n_first is not None else system.n_first,
+                         system.mix_beta, rho_out, system.kerker_q0, m, getattr(system, "pulay_period", 2),
+                         bool(getattr(system, "pulay_restart", 0)), hist_buf)
+    hist = []
+    for _ in range(max_iter):
+        rep = ctx.scf_step_spin(st)
+        e = eig.detach().cpu().numpy()
+        rep["eig_up"], rep["eig_dn"] = e[:ns].copy(), e[ns:].copy()
+        rep["magnetization"] = float(system.dV * (rho_out[:nd].sum() - rho_out[nd:].sum()).item())
+        hist.append(rep)
+        if callback is not None:
+            callback(rep)
+        if rep["residual"] < tol:
+            break
+    return dict(history=hist, X=(Xu, Xd), eig=eig, occ=occ, rho_in=rho_in, rho_out=rho_out, state=st, ctx=ctx,
+                pulay_hist=hist_buf)
