@@ -328,6 +328,31 @@ typedef struct {
  * Synchronises once at the end to fill rep (may be NULL). */
 sparc_status sparc_gpu_scf_step_spin(sparc_gpu_ctx ctx, sparc_gpu_scf_spin_state* st, sparc_gpu_scf_report* rep);
 
+/* ---- Atomic forces ---------------------------------------------------------
+ * Hellmann-Feynman forces (Sec. 2: the forces that drive structural
+ * relaxation and molecular dynamics): at self-consistency the negative
+ * gradient of the free energy with respect to the atom positions has only
+ * explicit contributions,
+ *   local:    dV sum_x phi(x) grad b_I(x - R_I) - 1/2 dV sum grad(b_I V_I)
+ *             (pseudocharge in the electrostatic potential, and the grid
+ *             quadrature of the self energy over the atom's 8 rc ball),
+ *   overlap:  sum_{J,n}' Z_I Z_J u'(d) (R_J + nL - R_I)/d, u(d) = erfc(d/s)/d,
+ *             s = sqrt(rc_I^2 + rc_J^2), images with d < 10 Bohr,
+ *   nonlocal: 2 sum_n w_n sum_k gamma_Ik (dV chi_Ik^T psi_n)(dV (grad chi_Ik)^T psi_n)
+ *             over the projectors' (point, image) pairs within rcut_nl.
+ * d_phi: N_d electrostatic potential of the self-consistent density (from
+ * sparc_gpu_potential or sparc_gpu_potential_spin).  d_X: host array of
+ * n_blocks device pointers to N_d x ncol orbital blocks (ldx, prec): one
+ * block spin-unpolarised, or the up and down blocks (n_blocks = 0 skips the
+ * nonlocal part).  d_occ: n_blocks x ncol weights w_n (g_n = 2 f_n
+ * unpolarised, f_n per spin block).  d_forces: 3 n_atoms doubles (atom-major
+ * x, y, z), Ha/Bohr, overwritten.  Uses the context's scratch reductions;
+ * stream-ordered, no synchronisation.
+ * Errors: SPARC_ERR_ARG (null pointers, n_blocks outside 0..2, ncol outside
+ * [1, n_states], ldx < N_d, bad precision). */
+sparc_status sparc_gpu_forces(sparc_gpu_ctx ctx, const double* d_phi, sparc_prec prec, const void* const* d_X,
+                              int n_blocks, int ncol, long ldx, const double* d_occ, double* d_forces);
+
 /* Kernel timing (tracing aid).  When enabled, every launch of the listed
  * kernels is bracketed by HIP events on the context's stream.
  * sparc_gpu_profile_read() synchronises, returns the summed device time (ms)
@@ -341,7 +366,8 @@ sparc_status sparc_gpu_scf_step_spin(sparc_gpu_ctx ctx, sparc_gpu_scf_spin_state
  * (12-15 are the phases inside 9), 16 warm-start network forward,
  * 17 its 16 -> 16 convolution, 18 network gradient, 19 density mixing
  * step of the SCF (linear with preconditioner, or Pulay; the plain linear
- * step is fused into the energy pass and not listed); ids < 32. */
+ * step is fused into the energy pass and not listed), 20 local and overlap
+ * forces, 21 nonlocal forces; ids < 32. */
 sparc_status sparc_gpu_profile(sparc_gpu_ctx ctx, int enable);
 sparc_status sparc_gpu_profile_read(sparc_gpu_ctx ctx, int kernel_id, double* total_ms, long* launches);
 

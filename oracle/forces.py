@@ -35,10 +35,15 @@ from scipy.special import erf as _erf
 from . import atoms
 
 
-def local_forces(sys, phi: np.ndarray) -> np.ndarray:
-    """Electrostatic (pseudocharge) plus self-energy part, (n_atoms, 3)."""
+def _atoms(sys, atoms_subset):
+    return range(sys.n_atoms) if atoms_subset is None else atoms_subset
+
+
+def local_forces(sys, phi: np.ndarray, atoms_subset=None) -> np.ndarray:
+    """Electrostatic (pseudocharge) plus self-energy part, (n_atoms, 3); rows
+    outside ``atoms_subset`` (all atoms when None) are left zero."""
     F = np.zeros((sys.n_atoms, 3))
-    for I in range(sys.n_atoms):
+    for I in _atoms(sys, atoms_subset):
         Z, rc = sys.Z[I], sys.rc_loc[I]
         flat, dx, dy, dz, r2 = atoms.ball_points(sys.n, sys.h, sys.pos[I], 8.0 * rc)
         b = -Z * (pi * rc * rc) ** -1.5 * np.exp(-r2 / (rc * rc))
@@ -57,12 +62,12 @@ def local_forces(sys, phi: np.ndarray) -> np.ndarray:
     return F
 
 
-def overlap_forces(sys, rmax: float = 10.0) -> np.ndarray:
+def overlap_forces(sys, rmax: float = 10.0, atoms_subset=None) -> np.ndarray:
     """-dE_c/dR_I over the pairs and images of ``atoms.overlap_correction``."""
     L = np.asarray(sys.L)
     nimg = [int(np.ceil(rmax / L[d])) + 1 for d in range(3)]
     F = np.zeros((sys.n_atoms, 3))
-    for I in range(sys.n_atoms):
+    for I in _atoms(sys, atoms_subset):
         for J in range(sys.n_atoms):
             s = sqrt(sys.rc_loc[I] ** 2 + sys.rc_loc[J] ** 2)
             for a in range(-nimg[0], nimg[0] + 1):
@@ -78,7 +83,7 @@ def overlap_forces(sys, rmax: float = 10.0) -> np.ndarray:
     return F
 
 
-def nonlocal_forces(sys, blocks, weights) -> np.ndarray:
+def nonlocal_forces(sys, blocks, weights, atoms_subset=None) -> np.ndarray:
     """blocks: orbital blocks (rows are orbitals); weights: their occupation
     weights (g_n, or f_n^s per spin block)."""
     F = np.zeros((sys.n_atoms, 3))
@@ -87,7 +92,7 @@ def nonlocal_forces(sys, blocks, weights) -> np.ndarray:
     rc = sys.rc_nl
     N0 = (2.0 / (pi * rc * rc)) ** 0.75
     N1 = (2.0 / rc) * N0
-    for I in range(sys.n_atoms):
+    for I in _atoms(sys, atoms_subset):
         flat, dx, dy, dz, r2 = atoms.ball_points(sys.n, sys.h, sys.pos[I], sys.rcut_nl)
         e = np.exp(-r2 / (rc * rc))
         d = np.stack([dx, dy, dz])
@@ -108,7 +113,9 @@ def nonlocal_forces(sys, blocks, weights) -> np.ndarray:
     return F
 
 
-def forces(sys, phi: np.ndarray, blocks, weights) -> np.ndarray:
+def forces(sys, phi: np.ndarray, blocks, weights, atoms_subset=None) -> np.ndarray:
     """Total Hellmann-Feynman force (n_atoms, 3) at the density whose
-    electrostatic potential is phi and the orbital blocks with weights."""
-    return local_forces(sys, phi) + overlap_forces(sys) + nonlocal_forces(sys, blocks, weights)
+    electrostatic potential is phi and the orbital blocks with weights (rows
+    of ``atoms_subset`` only, when given)."""
+    return (local_forces(sys, phi, atoms_subset) + overlap_forces(sys, atoms_subset=atoms_subset)
+            + nonlocal_forces(sys, blocks, weights, atoms_subset))

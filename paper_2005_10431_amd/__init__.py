@@ -17,4 +17,4 @@ from ._lib import (  # noqa: F401
     make_spin_state,
     make_state,
 )
-from .driver import run_scf, run_scf_spin  # noqa: F401
+from .driver import run_scf, run_scf_spin, scf_forces  # noqa: F401

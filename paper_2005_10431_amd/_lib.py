@@ -52,6 +52,7 @@ EXPORTED = [
     "sparc_gpu_potential_spin",
     "sparc_gpu_occupations_spin",
     "sparc_gpu_scf_step_spin",
+    "sparc_gpu_forces",
     "sparc_gpu_scf_step",
     "sparc_gpu_final_rr_fp64",
     "sparc_gpu_profile",
@@ -199,6 +200,7 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_potential_spin": ([vp, vp, vp, vp, vp, vp], i),
         "sparc_gpu_occupations_spin": ([vp, vp, i, vp, vp], i),
         "sparc_gpu_scf_step_spin": ([vp, C.POINTER(SpinSCFState), C.POINTER(SCFReport)], i),
+        "sparc_gpu_forces": ([vp, vp, i, C.POINTER(vp), i, i, l, vp, vp], i),
         "sparc_gpu_scf_step": ([vp, C.POINTER(SCFState), C.POINTER(SCFReport)], i),
         "sparc_gpu_final_rr_fp64": ([vp, C.POINTER(SCFState), vp, l, C.POINTER(SCFReport)], i),
         "sparc_gpu_profile": ([vp, i], i),
@@ -361,6 +363,21 @@ class Context:
         """eig, occ: (2 ncol,) float64, up then down."""
         self._check(self.lib.sparc_gpu_occupations_spin(self.h, _ptr(eig), int(eig.numel()) // 2, _ptr(occ),
                                                         _ptr(mu)))
+
+    def forces(self, phi, blocks, occ, out):
+        """phi: (N_d,) float64; blocks: list of 0-2 orbital blocks (ncol, ld)
+        of one dtype; occ: (len(blocks) ncol,) float64 weights; out: (n_atoms, 3)
+        float64, overwritten."""
+        n = len(blocks)
+        ptrs = (C.c_void_p * max(n, 1))(*[b.data_ptr() for b in blocks])
+        ncol, ld, prec = (0, 0, SPARC_FP64)
+        if n:
+            ncol, ld = _block(blocks[0])
+            prec = _prec_of(blocks[0])
+            for b in blocks[1:]:
+                if _block(b) != (ncol, ld) or _prec_of(b) != prec:
+                    raise ValueError("orbital blocks must share shape, leading dimension and dtype")
+        self._check(self.lib.sparc_gpu_forces(self.h, _ptr(phi), prec, ptrs, n, ncol, ld, _ptr(occ), _ptr(out)))
 
     def scf_step_spin(self, state) -> dict:
         rep = SCFReport()

@@ -93,6 +93,7 @@ struct sparc_gpu_ctx_s {
     double* veff = nullptr;     // N_d
     float* veff32 = nullptr;    // N_d
     double* veff_spin = nullptr;  // 2 N_d: V_eff of both spins (spin-polarised SCF, allocated on use)
+    double* force_tab = nullptr;  // per-atom force table: pos (3n), Z (n), rc (n), gamma (4n); on use
     double* b = nullptr;        // pseudocharge, N_d
     double e_self = 0, e_c = 0;
     sg::NonlocalTables nl;
@@ -258,6 +259,8 @@ enum ProfKernel {
     PK_CNN_CONV2 = 17,  // its 16 -> 16 convolution
     PK_CNN_BWD = 18, // network gradient (all launches)
     PK_MIX = 19,     // density mixing step (all launches of one step)
+    PK_FORCE_LOCAL = 20,  // local and overlap forces
+    PK_FORCE_NL = 21,     // nonlocal forces (all orbital blocks)
     PK_COUNT = 32    // size of the per-context timing tables
 };
 static_assert(PK_COUNT == sizeof(sparc_gpu_ctx_s::prof_n) / sizeof(long), "timing table size");

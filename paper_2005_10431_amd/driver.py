@@ -117,3 +117,23 @@ def run_scf_spin(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int =
             break
     return dict(history=hist, X=(Xu, Xd), eig=eig, occ=occ, rho_in=rho_in, rho_out=rho_out, state=st, ctx=ctx,
                 pulay_hist=hist_buf)
+
+
+def scf_forces(system, out) -> "np.ndarray":
+    """Hellmann-Feynman forces (n_atoms, 3) in Ha/Bohr after ``run_scf`` or
+    ``run_scf_spin``: the electrostatic potential of the last output density
+    (the density of the final orbitals), then ``sparc_gpu_forces`` with the
+    final blocks and occupations."""
+    import torch
+    ctx = out["ctx"]
+    nd = system.nd
+    phi = torch.empty(nd, dtype=torch.float64, device=out["rho_out"].device)
+    if isinstance(out["X"], tuple):
+        ctx.potential_spin(out["rho_out"], phi)
+        blocks = list(out["X"])
+    else:
+        ctx.potential(out["rho_out"], phi)
+        blocks = [out.get("X64", out["X"])]
+    F = torch.empty((system.n_atoms, 3), dtype=torch.float64, device=phi.device)
+    ctx.forces(phi, blocks, out["occ"], F)
+    return F.cpu().numpy()
