@@ -328,6 +328,67 @@ typedef struct {
  * Synchronises once at the end to fill rep (may be NULL). */
 sparc_status sparc_gpu_scf_step_spin(sparc_gpu_ctx ctx, sparc_gpu_scf_spin_state* st, sparc_gpu_scf_report* rep);
 
+/* ---- Bloch k-points (Sec. 2.1) ----------------------------------------------
+ * Orbitals obey psi(x + nL) = exp(i k . nL) psi(x); for one k
+ *   H_k z = -1/2 Lap_h^k z + V_eff z + sum_I sum_lm gamma_Il chi~_Ilm <chi~_Ilm, z>
+ * with the stencil's neighbours past a face taken from the image times
+ * exp(+-i k_d L_d), chi~_Ilm(x) = sum_s chi_lm(x + sL - R_I) exp(-i k . sL) over
+ * the periodic images s, and <a, b> = dV sum conj(a) b.
+ * Layout: a complex orbital z = u + i v is one real column [u ; v] of 2 N_d
+ * values (leading dimension ldx >= 2 N_d).  On such columns H_k is the real
+ * symmetric operator [[Re H_k, -Im H_k], [Im H_k, Re H_k]]; the k-point
+ * filter and Rayleigh-Ritz are the Gamma ones on 2 N_d rows, so a block
+ * whose span is closed under z -> i z (columns in pairs [u; v], [-v; u])
+ * yields every Bloch eigenvalue twice.  Up to 2 n_states columns per block.
+ * k: host array of 3 doubles (1/Bohr).  The last k used stays set in the
+ * context (the V_eff of sparc_gpu_set_veff / the SCF applies). */
+sparc_status sparc_gpu_apply_H_k(sparc_gpu_ctx ctx, const double* k, sparc_prec prec, const void* d_X, void* d_Y,
+                                 int ncol, long ldx);
+sparc_status sparc_gpu_chebyshev_filter_k(sparc_gpu_ctx ctx, const double* k, sparc_prec prec, void* d_X,
+                                          void* d_work, int ncol, long ldx, int degree, double a, double b,
+                                          double a0);
+/* Ascending Ritz values of the block (each Bloch eigenvalue of a
+ * z -> i z closed span appears twice); X is rotated to the Ritz vectors. */
+sparc_status sparc_gpu_rayleigh_ritz_k(sparc_gpu_ctx ctx, const double* k, sparc_prec prec, void* d_X, int ncol,
+                                       long ldx, double* d_eig);
+/* lo <= spec(H_k) <= hi: V_eff extrema, kinetic symbol bound and the signed
+ * k-dependent projector norms dV ||chi~||^2.  Synchronous. */
+sparc_status sparc_gpu_spectrum_bounds_k(sparc_gpu_ctx ctx, const double* k, double* lo, double* hi);
+
+typedef struct {
+    int n_k;                /* number of k-points (1 .. 4096)                  */
+    const double* kpts;     /* host: 3 n_k (1/Bohr)                            */
+    const double* kweights; /* host: n_k positive weights summing to 1         */
+    void* const* d_X;       /* host array of n_k device blocks, 2 n_states
+                               Bloch columns each (ldx, prec)                  */
+    long ldx;               /* >= 2 N_d                                        */
+    int prec;
+    int cheb_degree;
+    int n_first;
+    double mix_beta;
+    double kerker_q0;
+    int pulay_history;
+    int pulay_period;
+    int pulay_restart;
+    double* d_pulay;        /* m > 0: (2 m + 2) N_d doubles                    */
+    double* d_rho_in;       /* in/out: N_d                                     */
+    int iter;
+    double* d_eig;          /* out: n_k x 2 n_states Ritz values               */
+    double* d_occ;          /* out: n_k x 2 n_states occupations f per column  */
+    double* d_rho_out;      /* optional out: N_d                               */
+    double* bounds;         /* host in/out: (a, b, a0) per k-point             */
+} sparc_gpu_scf_k_state;
+
+/* One SCF iteration over a k-point set: V_eff from rho_in; per k the filter
+ * + Rayleigh-Ritz schedule of sparc_gpu_scf_step with H_k and that k's
+ * bounds; one Fermi level with sum_k w_k sum_j f_jk = N_e over the Bloch
+ * columns (the 2 f_n of a spin-unpolarised state is split over its two
+ * columns [u; v], [-v; u]); rho_out
+ * = sum_k w_k sum_j f_jk (u_j^2 + v_j^2); the free energy at rho_in with the
+ * k-weighted band and entropy terms; the residual and the mixing step of
+ * sparc_gpu_mix.  Synchronises once at the end. */
+sparc_status sparc_gpu_scf_step_k(sparc_gpu_ctx ctx, sparc_gpu_scf_k_state* st, sparc_gpu_scf_report* rep);
+
 /* ---- Atomic forces ---------------------------------------------------------
  * Hellmann-Feynman forces (Sec. 2: the forces that drive structural
  * relaxation and molecular dynamics): at self-consistency the negative
@@ -367,7 +428,8 @@ sparc_status sparc_gpu_forces(sparc_gpu_ctx ctx, const double* d_phi, sparc_prec
  * 17 its 16 -> 16 convolution, 18 network gradient, 19 density mixing
  * step of the SCF (linear with preconditioner, or Pulay; the plain linear
  * step is fused into the energy pass and not listed), 20 local and overlap
- * forces, 21 nonlocal forces; ids < 32. */
+ * forces, 21 nonlocal forces, 22 Bloch H_k application / filter step,
+ * 23 Bloch projections; ids < 32. */
 sparc_status sparc_gpu_profile(sparc_gpu_ctx ctx, int enable);
 sparc_status sparc_gpu_profile_read(sparc_gpu_ctx ctx, int kernel_id, double* total_ms, long* launches);
 

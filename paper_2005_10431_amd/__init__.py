@@ -12,9 +12,11 @@ from ._lib import (  # noqa: F401
     SCFReport,
     SCFState,
     SparcError,
+    KSCFState,
     SpinSCFState,
     load,
+    make_k_state,
     make_spin_state,
     make_state,
 )
-from .driver import run_scf, run_scf_spin, scf_forces  # noqa: F401
+from .driver import run_scf, run_scf_k, run_scf_spin, scf_forces  # noqa: F401

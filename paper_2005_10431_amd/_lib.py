@@ -53,6 +53,11 @@ EXPORTED = [
     "sparc_gpu_occupations_spin",
     "sparc_gpu_scf_step_spin",
     "sparc_gpu_forces",
+    "sparc_gpu_apply_H_k",
+    "sparc_gpu_chebyshev_filter_k",
+    "sparc_gpu_rayleigh_ritz_k",
+    "sparc_gpu_spectrum_bounds_k",
+    "sparc_gpu_scf_step_k",
     "sparc_gpu_scf_step",
     "sparc_gpu_final_rr_fp64",
     "sparc_gpu_profile",
@@ -140,6 +145,31 @@ class SpinSCFState(C.Structure):
     ]
 
 
+class KSCFState(C.Structure):
+    _fields_ = [
+        ("n_k", C.c_int),
+        ("kpts", C.POINTER(C.c_double)),
+        ("kweights", C.POINTER(C.c_double)),
+        ("d_X", C.POINTER(C.c_void_p)),
+        ("ldx", C.c_long),
+        ("prec", C.c_int),
+        ("cheb_degree", C.c_int),
+        ("n_first", C.c_int),
+        ("mix_beta", C.c_double),
+        ("kerker_q0", C.c_double),
+        ("pulay_history", C.c_int),
+        ("pulay_period", C.c_int),
+        ("pulay_restart", C.c_int),
+        ("d_pulay", C.c_void_p),
+        ("d_rho_in", C.c_void_p),
+        ("iter", C.c_int),
+        ("d_eig", C.c_void_p),
+        ("d_occ", C.c_void_p),
+        ("d_rho_out", C.c_void_p),
+        ("bounds", C.POINTER(C.c_double)),
+    ]
+
+
 class SCFReport(C.Structure):
     _fields_ = [
         ("free_energy", C.c_double),
@@ -201,6 +231,11 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_occupations_spin": ([vp, vp, i, vp, vp], i),
         "sparc_gpu_scf_step_spin": ([vp, C.POINTER(SpinSCFState), C.POINTER(SCFReport)], i),
         "sparc_gpu_forces": ([vp, vp, i, C.POINTER(vp), i, i, l, vp, vp], i),
+        "sparc_gpu_apply_H_k": ([vp, C.POINTER(d), i, vp, vp, i, l], i),
+        "sparc_gpu_chebyshev_filter_k": ([vp, C.POINTER(d), i, vp, vp, i, l, i, d, d, d], i),
+        "sparc_gpu_rayleigh_ritz_k": ([vp, C.POINTER(d), i, vp, i, l, vp], i),
+        "sparc_gpu_spectrum_bounds_k": ([vp, C.POINTER(d), C.POINTER(d), C.POINTER(d)], i),
+        "sparc_gpu_scf_step_k": ([vp, C.POINTER(KSCFState), C.POINTER(SCFReport)], i),
         "sparc_gpu_scf_step": ([vp, C.POINTER(SCFState), C.POINTER(SCFReport)], i),
         "sparc_gpu_final_rr_fp64": ([vp, C.POINTER(SCFState), vp, l, C.POINTER(SCFReport)], i),
         "sparc_gpu_profile": ([vp, i], i),
@@ -379,6 +414,35 @@ class Context:
                     raise ValueError("orbital blocks must share shape, leading dimension and dtype")
         self._check(self.lib.sparc_gpu_forces(self.h, _ptr(phi), prec, ptrs, n, ncol, ld, _ptr(occ), _ptr(out)))
 
+    # ---- Bloch k-points: blocks of columns [Re z; Im z], shape (ncol, >= 2 N_d)
+    @staticmethod
+    def _k(k):
+        return (C.c_double * 3)(*[float(v) for v in k])
+
+    def apply_H_k(self, k, X, Y):
+        ncol, ld = _block(X)
+        self._check(self.lib.sparc_gpu_apply_H_k(self.h, self._k(k), _prec_of(X), _ptr(X), _ptr(Y), ncol, ld))
+
+    def chebyshev_filter_k(self, k, X, work, degree, a, b, a0):
+        ncol, ld = _block(X)
+        self._check(self.lib.sparc_gpu_chebyshev_filter_k(self.h, self._k(k), _prec_of(X), _ptr(X), _ptr(work), ncol,
+                                                          ld, int(degree), float(a), float(b), float(a0)))
+
+    def rayleigh_ritz_k(self, k, X, eig):
+        ncol, ld = _block(X)
+        self._check(self.lib.sparc_gpu_rayleigh_ritz_k(self.h, self._k(k), _prec_of(X), _ptr(X), ncol, ld,
+                                                       _ptr(eig)))
+
+    def spectrum_bounds_k(self, k):
+        lo, hi = C.c_double(), C.c_double()
+        self._check(self.lib.sparc_gpu_spectrum_bounds_k(self.h, self._k(k), C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def scf_step_k(self, state) -> dict:
+        rep = SCFReport()
+        self._check(self.lib.sparc_gpu_scf_step_k(self.h, C.byref(state), C.byref(rep)))
+        return rep.as_dict()
+
     def scf_step_spin(self, state) -> dict:
         rep = SCFReport()
         self._check(self.lib.sparc_gpu_scf_step_spin(self.h, C.byref(state), C.byref(rep)))
@@ -479,4 +543,44 @@ def make_spin_state(rho_in, X_up, X_dn, eig, occ, degree, n_first=4, beta=0.3, r
     st.d_occ = occ.data_ptr()
     st.d_rho_out = rho_out.data_ptr() if rho_out is not None else None
     st.bounds = (C.c_double * 6)(*([0.0] * 6))
+    return st
+
+
+def make_k_state(rho_in, blocks, kpts, kweights, eig, occ, degree, n_first=4, beta=0.3, rho_out=None,
+                 kerker_q0=0.0, pulay_history=0, pulay_period=1, pulay_restart=False, pulay_hist=None) -> KSCFState:
+    """blocks: list of n_k device tensors (2 n_states, ld >= 2 N_d) of one
+    dtype and ld; kpts (n_k, 3), kweights (n_k,) host arrays; eig, occ:
+    (n_k 2 n_states,) float64.  The host arrays the state points to are kept
+    on the returned object."""
+    import numpy as np
+    n = len(blocks)
+    ld = blocks[0].stride(0)
+    for b in blocks:
+        if b.stride(0) != ld or b.dtype != blocks[0].dtype:
+            raise ValueError("k-point blocks must share dtype and leading dimension")
+    st = KSCFState()
+    st._kp = (C.c_double * (3 * n))(*[float(v) for v in np.asarray(kpts, dtype=np.float64).ravel()])
+    st._kw = (C.c_double * n)(*[float(v) for v in kweights])
+    st._px = (C.c_void_p * n)(*[b.data_ptr() for b in blocks])
+    st._bd = (C.c_double * (3 * n))(*([0.0] * (3 * n)))
+    st.n_k = n
+    st.kpts = C.cast(st._kp, C.POINTER(C.c_double))
+    st.kweights = C.cast(st._kw, C.POINTER(C.c_double))
+    st.d_X = C.cast(st._px, C.POINTER(C.c_void_p))
+    st.ldx = ld
+    st.prec = _prec_of(blocks[0])
+    st.cheb_degree = int(degree)
+    st.n_first = int(n_first)
+    st.mix_beta = float(beta)
+    st.kerker_q0 = float(kerker_q0)
+    st.pulay_history = int(pulay_history)
+    st.pulay_period = int(pulay_period)
+    st.pulay_restart = 1 if pulay_restart else 0
+    st.d_pulay = pulay_hist.data_ptr() if pulay_hist is not None else None
+    st.d_rho_in = rho_in.data_ptr()
+    st.iter = 0
+    st.d_eig = eig.data_ptr()
+    st.d_occ = occ.data_ptr()
+    st.d_rho_out = rho_out.data_ptr() if rho_out is not None else None
+    st.bounds = C.cast(st._bd, C.POINTER(C.c_double))
     return st

@@ -444,12 +444,14 @@ __global__ void k_copy_cols(const T* __restrict__ src, T* __restrict__ dst, long
 }
 
 // X <- Y R^-1 Q with dV Y^T Y = R^T R (R = L^T) and
-// R^-T (dV Y^T H Y) R^-1 = Q diag(eig) Q^T.  Workspace: c->work (one block)
-// and c->small (>= 12 N^2 doubles).
-template <typename T>
-sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* d_eig, bool check) {
+// R^-T (dV Y^T H Y) R^-1 = Q diag(eig) Q^T, for columns of `rows` values
+// (N_d, or 2 N_d for Bloch columns) and the operator applied by applyH(Y, W).
+// Workspace: c->work (one block) and c->small (>= 12 N^2 doubles).
+template <typename T, typename ApplyH>
+static sparc_status rr_core(sparc_gpu_ctx c, T* X, int N, long ldx, double* d_eig, bool check, long rows,
+                            ApplyH&& applyH) {
     sparc_status st;
-    const size_t blk = ((size_t)(N - 1) * ldx + c->nd) * sizeof(T);
+    const size_t blk = ((size_t)(N - 1) * ldx + rows) * sizeof(T);
     if ((st = ensure_work(c, blk)) != SPARC_OK) return st;
     if ((st = ensure_small(c, 9 * (size_t)N * N + eigh_work_doubles(N))) != SPARC_OK) return st;
     T* W = (T*)c->work;
@@ -463,7 +465,7 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* 
     double* Rot = M + 6 * NN;
     double* ework = M + 9 * NN;     // eigensolver workspace; Lt lives at 8 NN
     SG_HIP(c, hipMemsetAsync(c->flags + F_NOT_SPD, 0, sizeof(int), c->stream));
-    if ((st = gemm_tn<T>(c, N, N, c->nd, X, ldx, X, ldx, c->dV, M, N, true)) != SPARC_OK) return st;
+    if ((st = gemm_tn<T>(c, N, N, rows, X, ldx, X, ldx, c->dV, M, N, true)) != SPARC_OK) return st;
     if ((st = dense_cholesky(c, M, N, c->flags + F_NOT_SPD)) != SPARC_OK) return st;
     if (check) {
         int f = 0;
@@ -473,10 +475,9 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* 
     }
     if ((st = dense_tri_inverse_lower(c, M, Linv, N)) != SPARC_OK) return st;
     // H Y into W
-    if ((st = launch_projection<T>(c, X, N, ldx)) != SPARC_OK) return st;
-    if ((st = launch_hsweep<T>(c, X, W, nullptr, N, ldx, 0, 0)) != SPARC_OK) return st;
+    if ((st = applyH(X, W)) != SPARC_OK) return st;
     // dV Y^T (H Y) is symmetric (H is): its upper tiles are computed and mirrored
-    if ((st = gemm_tn<T>(c, N, N, c->nd, X, ldx, W, ldx, c->dV, K, N, true)) != SPARC_OK) return st;
+    if ((st = gemm_tn<T>(c, N, N, rows, X, ldx, W, ldx, c->dV, K, N, true)) != SPARC_OK) return st;
     if ((st = dense_gemm(c, 'N', 'N', N, Linv, K, T1)) != SPARC_OK) return st;
     if ((st = dense_gemm(c, 'N', 'T', N, T1, Linv, Hs)) != SPARC_OK) return st;
     if ((st = dense_symmetrize(c, Hs, N)) != SPARC_OK) return st;
@@ -487,14 +488,33 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* 
         if (st != SPARC_OK) return st;
     }
     if ((st = dense_gemm(c, 'T', 'N', N, Linv, Vq, Rot)) != SPARC_OK) return st;
-    if ((st = gemm_nn<T>(c, c->nd, N, N, X, ldx, Rot, N, W, ldx)) != SPARC_OK) return st;
-    dim3 grid(div_up(c->nd, 256), N);
+    if ((st = gemm_nn<T>(c, rows, N, N, X, ldx, Rot, N, W, ldx)) != SPARC_OK) return st;
+    dim3 grid(div_up(rows, 256), N);
     const int slot = prof_begin(c, PK_COPY);
-    k_copy_cols<T><<<grid, 256, 0, c->stream>>>(W, X, c->nd, N, ldx);
+    k_copy_cols<T><<<grid, 256, 0, c->stream>>>(W, X, rows, N, ldx);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
     return SPARC_OK;
 }
+
+template <typename T>
+sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* d_eig, bool check) {
+    return rr_core<T>(c, X, N, ldx, d_eig, check, c->nd, [&](T* Y, T* W) -> sparc_status {
+        sparc_status st = launch_projection<T>(c, Y, N, ldx);
+        if (st != SPARC_OK) return st;
+        return launch_hsweep<T>(c, Y, W, nullptr, N, ldx, 0, 0);
+    });
+}
+
+// Bloch columns at the context's k: the real embedding of the Hermitian H_k.
+template <typename T>
+sparc_status rayleigh_ritz_k_impl(sparc_gpu_ctx c, T* X, int N, long ldx, double* d_eig, bool check) {
+    return rr_core<T>(c, X, N, ldx, d_eig, check, 2 * c->nd,
+                      [&](T* Y, T* W) -> sparc_status { return bloch_apply_impl<T>(c, Y, W, N, ldx); });
+}
+
+template sparc_status rayleigh_ritz_k_impl<double>(sparc_gpu_ctx, double*, int, long, double*, bool);
+template sparc_status rayleigh_ritz_k_impl<float>(sparc_gpu_ctx, float*, int, long, double*, bool);
 
 template sparc_status rayleigh_ritz_impl<double>(sparc_gpu_ctx, double*, int, long, double*, bool);
 template sparc_status rayleigh_ritz_impl<float>(sparc_gpu_ctx, float*, int, long, double*, bool);

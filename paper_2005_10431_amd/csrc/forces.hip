@@ -221,6 +221,8 @@ __global__ __launch_bounds__(256) void k_force_nl_reduce(const double* __restric
 constexpr int kForceNB = 4;
 constexpr int kLocalChunks = 8;
 
+}  // namespace
+
 sparc_status ensure_force_tables(sparc_gpu_ctx c) {
     if (c->force_tab) return SPARC_OK;
     const int n = c->n_atoms;
@@ -239,6 +241,8 @@ sparc_status ensure_force_tables(sparc_gpu_ctx c) {
     SG_HIP(c, hipStreamSynchronize(c->stream));
     return SPARC_OK;
 }
+
+namespace {
 
 template <typename T>
 sparc_status nl_force(sparc_gpu_ctx c, const T* X, int ncol, long ldx, const double* w, double* pd, double* out) {

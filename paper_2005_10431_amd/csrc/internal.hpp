@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -94,6 +95,17 @@ struct sparc_gpu_ctx_s {
     float* veff32 = nullptr;    // N_d
     double* veff_spin = nullptr;  // 2 N_d: V_eff of both spins (spin-polarised SCF, allocated on use)
     double* force_tab = nullptr;  // per-atom force table: pos (3n), Z (n), rc (n), gamma (4n); on use
+    // Bloch k-points (allocated on use)
+    double kvec[3] = {0, 0, 0};   // current k (1/Bohr)
+    int* kp_off = nullptr;        // N_d + 1: point-major projector entries
+    uint32_t* kp_ent = nullptr;   // (atom, image) entries
+    double* kp_proj = nullptr;    // n_atoms x ncol x 8 complex projections
+    size_t kp_proj_elems = 0;
+    double* kp_bounds = nullptr;  // 3 per k-point: filter bounds of the k-point SCF
+    int kp_bounds_n = 0;
+    double* kp_wts = nullptr;     // per-state k weights of the k-point SCF
+    int kp_wts_n = 0;
+    std::vector<std::array<double, 5>> kp_bound_cache;  // (k, nonlocal lo, hi)
     double* b = nullptr;        // pseudocharge, N_d
     double e_self = 0, e_c = 0;
     sg::NonlocalTables nl;
@@ -228,13 +240,25 @@ sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int ncol, long ldx, doubl
 // Grid-field kernels
 sparc_status potential_impl(sparc_gpu_ctx c, const double* rho, double* phi, double* exc, double* vxc,
                             double* veff);
-// deg: electrons per state (2 spin-unpolarised, 1 per spin state)
+// deg: electrons per state (2 spin-unpolarised, 1 per spin state); wts:
+// optional per-state weights (k-point weights), null for 1
 sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu,
-                              double deg = 2.0);
+                              double deg = 2.0, const double* wts = nullptr);
 template <typename T>
 sparc_status density_impl(sparc_gpu_ctx c, const T* X, int ncol, long ldx, const double* occ, double* rho);
 sparc_status set_veff_impl(sparc_gpu_ctx c, const double* d_veff);
 sparc_status bounds_impl(sparc_gpu_ctx c);  // writes S_LO / S_HI on device
+sparc_status ensure_force_tables(sparc_gpu_ctx c);
+// Bloch k-points at c->kvec; blocks hold columns [Re z; Im z] of 2 N_d rows
+sparc_status ensure_kp_tables(sparc_gpu_ctx c);
+sparc_status kp_nl_bounds(sparc_gpu_ctx c, const double* k, double* nl_lo, double* nl_hi);
+sparc_status bloch_bounds_impl(sparc_gpu_ctx c);
+template <typename T>
+sparc_status bloch_apply_impl(sparc_gpu_ctx c, const T* X, T* Y, int ncol, long ldx);
+template <typename T>
+sparc_status bloch_filter_impl(sparc_gpu_ctx c, T* X, T* W, int ncol, long ldx, int m);
+template <typename T>
+sparc_status rayleigh_ritz_k_impl(sparc_gpu_ctx c, T* X, int ncol, long ldx, double* d_eig, bool check);
 
 // Kernel timing: prof_begin returns a slot (or -1 when disabled), prof_end
 // records its closing event.
@@ -261,6 +285,8 @@ enum ProfKernel {
     PK_MIX = 19,     // density mixing step (all launches of one step)
     PK_FORCE_LOCAL = 20,  // local and overlap forces
     PK_FORCE_NL = 21,     // nonlocal forces (all orbital blocks)
+    PK_BLOCH = 22,        // Bloch H_k application / filter step
+    PK_BLOCH_PROJ = 23,   // Bloch projections
     PK_COUNT = 32    // size of the per-context timing tables
 };
 static_assert(PK_COUNT == sizeof(sparc_gpu_ctx_s::prof_n) / sizeof(long), "timing table size");

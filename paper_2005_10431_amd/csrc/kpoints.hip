@@ -1,0 +1,560 @@
+// Bloch-periodic k-points (Sec. 2.1: Bloch-periodic boundary conditions on
+// the orbitals along extended directions, Brillouin-zone integration over
+// k-points).
+//
+// Representation: a complex orbital z = u + i v on the home cell is stored as
+// one real column [u ; v] of 2 N_d values.  The complex-linear Hermitian H_k
+// acts on such columns as the real symmetric operator [[Re H, -Im H],
+// [Im H, Re H]]; a block whose span is closed under z -> i z (the columns
+// come in pairs [u; v], [-v; u]) is filtered and Rayleigh-Ritz-rotated by the
+// real machinery of the Gamma point with every Bloch eigenvalue appearing
+// twice.
+//
+// H_k z = -1/2 Lap_h^k z + V_eff z + sum_I sum_lm gamma_Il chi~_Ilm <chi~_Ilm, z>,
+//   Lap_h^k: the stencil with exp(+-i k_d L_d) on neighbours past the faces;
+//   chi~_Ilm(x) = sum_s chi_lm(x + sL - R_I) exp(-i k . sL), over the images s.
+#include "internal.hpp"
+
+#include <algorithm>
+#include <array>
+
+namespace sg {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct BlochGeom {
+    int nx, ny, nz, no;
+    double cx[kMaxHalfOrder + 1], cy[kMaxHalfOrder + 1], cz[kMaxHalfOrder + 1], c0;
+    double cph[3], sph[3];   // cos, sin of k_d L_d
+    double k[3], L[3], h[3];
+    double rc2inv, N0, N1, rcut;
+};
+
+BlochGeom bloch_geom(sparc_gpu_ctx c, const double* k) {
+    BlochGeom g{};
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    g.no = c->n_o;
+    for (int q = 0; q <= kMaxHalfOrder; ++q) {
+        g.cx[q] = c->cf64.cx[q];
+        g.cy[q] = c->cf64.cy[q];
+        g.cz[q] = c->cf64.cz[q];
+    }
+    g.c0 = c->cf64.c0;
+    const double L[3] = {c->Lx, c->Ly, c->Lz}, h[3] = {c->hx, c->hy, c->hz};
+    for (int d = 0; d < 3; ++d) {
+        g.k[d] = k[d];
+        g.L[d] = L[d];
+        g.h[d] = h[d];
+        g.cph[d] = std::cos(k[d] * L[d]);
+        g.sph[d] = std::sin(k[d] * L[d]);
+    }
+    const double rc = c->nl_lmax >= 1 ? c->rc_nl : 1.0;
+    g.rc2inv = 1.0 / (rc * rc);
+    g.N0 = std::pow(2.0 / (kPi * rc * rc), 0.75);
+    g.N1 = (2.0 / rc) * g.N0;
+    g.rcut = c->rcut_nl;
+    return g;
+}
+
+// Scaled Chebyshev recurrence coefficients of step `step` (the same
+// recurrence as the Gamma filter): out = alpha (H y - c y) + beta y_prev.
+__device__ inline void bloch_coefs(const double* params, int mode, int step, double& alpha, double& cs, double& beta) {
+    alpha = 1.0;
+    cs = 0.0;
+    beta = 0.0;
+    if (mode == 0) return;
+    const double A = params[0], B = params[1], A0 = params[2];
+    const double e = 0.5 * (B - A), c = 0.5 * (B + A);
+    const double s1 = e / (A0 - c);
+    cs = c;
+    if (mode == 1) {
+        alpha = s1 / e;
+        return;
+    }
+    const double tau = 2.0 / s1;
+    double sp = s1, s = s1;
+    for (int k = 2; k <= step; ++k) {
+        sp = s;
+        s = 1.0 / (tau - s);
+    }
+    alpha = 2.0 * s / e;
+    beta = -sp * s;
+}
+
+__device__ inline int floor_div(int i, int n) { return i >= 0 ? i / n : -((-i + n - 1) / n); }
+
+// Projections of NB columns on the complex projectors of one atom:
+// proj[(a ncol + col) 8 + r], r < 4: Re, r >= 4: Im of gamma_l dV <chi~_l, z>,
+// accumulated over the atom's (point, image) pairs inside rcut.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_bloch_proj(const T* __restrict__ X, long ldx, long nd, int ncol,
+                                                   const double* __restrict__ pos, const double* __restrict__ gamma4,
+                                                   BlochGeom g, double dV, double* __restrict__ proj) {
+    const int a = blockIdx.x;
+    const int col0 = blockIdx.y * NB;
+    const double cx = pos[3 * a], cy = pos[3 * a + 1], cz = pos[3 * a + 2];
+    const double rcut2 = g.rcut * g.rcut;
+    const int lx = (int)ceil((cx - g.rcut) / g.h[0]), ux = (int)floor((cx + g.rcut) / g.h[0]);
+    const int ly = (int)ceil((cy - g.rcut) / g.h[1]), uy = (int)floor((cy + g.rcut) / g.h[1]);
+    const int lz = (int)ceil((cz - g.rcut) / g.h[2]), uz = (int)floor((cz + g.rcut) / g.h[2]);
+    const int nxb = ux - lx + 1, nyb = uy - ly + 1, nzb = uz - lz + 1;
+    const long tot = (long)nxb * nyb * nzb;
+    double acc[NB * 8];
+#pragma unroll
+    for (int q = 0; q < NB * 8; ++q) acc[q] = 0.0;
+    for (long t = threadIdx.x; t < tot; t += blockDim.x) {
+        const int i = lx + (int)(t % nxb);
+        const int j = ly + (int)((t / nxb) % nyb);
+        const int k = lz + (int)(t / ((long)nxb * nyb));
+        const double dx = i * g.h[0] - cx, dy = j * g.h[1] - cy, dz = k * g.h[2] - cz;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 > rcut2) continue;
+        const int sx = floor_div(i, g.nx), sy = floor_div(j, g.ny), sz = floor_div(k, g.nz);
+        const long p = (i - sx * g.nx) + (long)g.nx * ((j - sy * g.ny) + (long)g.ny * (k - sz * g.nz));
+        const double ex = exp(-r2 * g.rc2inv);
+        const double chi[4] = {g.N0 * ex, g.N1 * dx * ex, g.N1 * dy * ex, g.N1 * dz * ex};
+        double sn, cs;
+        sincos(g.k[0] * sx * g.L[0] + g.k[1] * sy * g.L[1] + g.k[2] * sz * g.L[2], &sn, &cs);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (col0 + c < ncol) {
+                const double u = (double)X[p + (long)(col0 + c) * ldx];
+                const double v = (double)X[nd + p + (long)(col0 + c) * ldx];
+                // conj(chi~) z = chi exp(+i theta) (u + i v)
+                const double zr = cs * u - sn * v, zi = sn * u + cs * v;
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    acc[8 * c + l] += chi[l] * zr;
+                    acc[8 * c + 4 + l] += chi[l] * zi;
+                }
+            }
+        }
+    }
+    __shared__ double lds[4][NB * 8];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NB * 8; ++q) {
+        double t = acc[q];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0) lds[w][q] = t;
+    }
+    __syncthreads();
+    const int q = threadIdx.x;
+    if (q < NB * 8) {
+        const int c = q / 8, r = q % 8;
+        if (col0 + c < ncol) {
+            const double sum = ((lds[0][q] + lds[1][q]) + lds[2][q]) + lds[3][q];
+            proj[((long)a * ncol + col0 + c) * 8 + r] = dV * gamma4[4 * a + (r & 3)] * sum;
+        }
+    }
+}
+
+// out = alpha (H_k y - c y) + beta prev for every point of every column
+// (mode 0: out = H_k y).  out may alias prev (each element is read before it
+// is written, by the same thread); y must not alias either.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bloch_apply(const T* __restrict__ Y, T* out, const T* prev, long ldx, long nd,
+                                                    const double* __restrict__ veff, BlochGeom g,
+                                                    const double* __restrict__ proj, int ncol,
+                                                    const int* __restrict__ off, const uint32_t* __restrict__ ent,
+                                                    const double* __restrict__ pos,
+                                                    const double* __restrict__ params, int mode, int step) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int col = blockIdx.y;
+    if (p >= nd) return;
+    const int nx = g.nx, ny = g.ny;
+    const long nxy = (long)nx * ny;
+    const int ix = (int)(p % nx), iy = (int)((p / nx) % ny), iz = (int)(p / nxy);
+    const T* yu = Y + (long)col * ldx;
+    const T* yv = yu + nd;
+    const double u0 = (double)yu[p], v0 = (double)yv[p];
+    double lu = g.c0 * u0, lv = g.c0 * v0;
+    // one axis: neighbours at +-q with stride `st`; past a face the value is
+    // the image's, times exp(+-i k L) on that axis
+    auto axis = [&](int i, int n, long st, long span, const double* cf, double cph, double sph) {
+        for (int q = 1; q <= g.no; ++q) {
+            const double w = cf[q];
+            if (i + q < n) {
+                lu += w * (double)yu[p + q * st];
+                lv += w * (double)yv[p + q * st];
+            } else {
+                const long pp = p + q * st - span;
+                const double a = (double)yu[pp], b = (double)yv[pp];
+                lu += w * (a * cph - b * sph);
+                lv += w * (a * sph + b * cph);
+            }
+            if (i - q >= 0) {
+                lu += w * (double)yu[p - q * st];
+                lv += w * (double)yv[p - q * st];
+            } else {
+                const long pp = p - q * st + span;
+                const double a = (double)yu[pp], b = (double)yv[pp];
+                lu += w * (a * cph + b * sph);
+                lv += w * (-a * sph + b * cph);
+            }
+        }
+    };
+    axis(ix, nx, 1, nx, g.cx, g.cph[0], g.sph[0]);
+    axis(iy, ny, nx, nxy, g.cy, g.cph[1], g.sph[1]);
+    axis(iz, g.nz, nxy, nd, g.cz, g.cph[2], g.sph[2]);
+    double hu = lu + veff[p] * u0, hv = lv + veff[p] * v0;
+    if (proj) {
+        for (int e = off[p]; e < off[p + 1]; ++e) {
+            const uint32_t w = ent[e];
+            const int a = (int)(w & 0xFFFFFu);
+            const int sx = (int)((w >> 20) & 15u) - 8, sy = (int)((w >> 24) & 15u) - 8, sz = (int)(w >> 28) - 8;
+            const double dx = (ix + sx * nx) * g.h[0] - pos[3 * a];
+            const double dy = (iy + sy * ny) * g.h[1] - pos[3 * a + 1];
+            const double dz = (iz + sz * g.nz) * g.h[2] - pos[3 * a + 2];
+            const double ex = exp(-(dx * dx + dy * dy + dz * dz) * g.rc2inv);
+            const double c0 = g.N0 * ex, c1 = g.N1 * dx * ex, c2 = g.N1 * dy * ex, c3 = g.N1 * dz * ex;
+            const double* C = proj + ((long)a * ncol + col) * 8;
+            const double cre = c0 * C[0] + c1 * C[1] + c2 * C[2] + c3 * C[3];
+            const double cim = c0 * C[4] + c1 * C[5] + c2 * C[6] + c3 * C[7];
+            double sn, cs;
+            sincos(g.k[0] * sx * g.L[0] + g.k[1] * sy * g.L[1] + g.k[2] * sz * g.L[2], &sn, &cs);
+            // chi~ C = chi exp(-i theta) (cre + i cim)
+            hu += cre * cs + cim * sn;
+            hv += cim * cs - cre * sn;
+        }
+    }
+    double alpha, cs, beta;
+    bloch_coefs(params, mode, step, alpha, cs, beta);
+    double ou = alpha * (hu - cs * u0), ov = alpha * (hv - cs * v0);
+    const long o = (long)col * ldx + p;
+    if (mode == 2) {
+        ou += beta * (double)prev[o];
+        ov += beta * (double)prev[o + nd];
+    }
+    out[o] = (T)ou;
+    out[o + nd] = (T)ov;
+}
+
+template <typename T>
+__global__ void k_copy_block_k(const T* __restrict__ src, T* __restrict__ dst, long rows, int ncol, long ld) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < rows && j < ncol) dst[i + (long)j * ld] = src[i + (long)j * ld];
+}
+
+constexpr int kProjNB = 4;
+
+}  // namespace
+
+// Point-major (atom, image) entries of the projector supports: for grid
+// point p, entries off[p] .. off[p+1] of ent, each packing the atom (20 bits)
+// and its image offset s + 8 per axis (4 bits each).
+sparc_status ensure_kp_tables(sparc_gpu_ctx c) {
+    if (c->kp_off || c->nl_lmax < 1) return SPARC_OK;
+    const int n = c->n_atoms;
+    if (n >= (1 << 20)) return set_err(c, SPARC_ERR_ARG, "k-points: too many atoms for the entry tables");
+    const double h[3] = {c->hx, c->hy, c->hz};
+    const int N[3] = {c->nx, c->ny, c->nz};
+    const double rc = c->rcut_nl;
+    std::vector<std::pair<long, uint32_t>> list;
+    for (int a = 0; a < n; ++a) {
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = (int)std::ceil((c->pos[3 * a + d] - rc) / h[d]);
+            hi[d] = (int)std::floor((c->pos[3 * a + d] + rc) / h[d]);
+        }
+        for (int k = lo[2]; k <= hi[2]; ++k)
+            for (int j = lo[1]; j <= hi[1]; ++j)
+                for (int i = lo[0]; i <= hi[0]; ++i) {
+                    const double dx = i * h[0] - c->pos[3 * a], dy = j * h[1] - c->pos[3 * a + 1];
+                    const double dz = k * h[2] - c->pos[3 * a + 2];
+                    if (dx * dx + dy * dy + dz * dz > rc * rc) continue;
+                    const int ii[3] = {i, j, k};
+                    int s[3], w[3];
+                    for (int d = 0; d < 3; ++d) {
+                        s[d] = ii[d] >= 0 ? ii[d] / N[d] : -((-ii[d] + N[d] - 1) / N[d]);
+                        w[d] = ii[d] - s[d] * N[d];
+                        if (s[d] < -8 || s[d] > 7)
+                            return set_err(c, SPARC_ERR_ARG, "k-points: projector support spans too many images");
+                    }
+                    const long flat = w[0] + (long)N[0] * (w[1] + (long)N[1] * w[2]);
+                    const uint32_t code = (uint32_t)a | ((uint32_t)(s[0] + 8) << 20) | ((uint32_t)(s[1] + 8) << 24) |
+                                          ((uint32_t)(s[2] + 8) << 28);
+                    list.push_back({flat, code});
+                }
+    }
+    if (list.size() >= (size_t)1 << 31) return set_err(c, SPARC_ERR_ARG, "k-points: too many projector entries");
+    std::vector<int> off(c->nd + 1, 0);
+    for (auto& e : list) off[e.first + 1]++;
+    for (long p = 0; p < c->nd; ++p) off[p + 1] += off[p];
+    std::vector<uint32_t> ent(list.size());
+    std::vector<int> fill(off.begin(), off.end() - 1);
+    for (auto& e : list) ent[fill[e.first]++] = e.second;
+    SG_HIP(c, hipMalloc((void**)&c->kp_off, off.size() * sizeof(int)));
+    SG_HIP(c, hipMalloc((void**)&c->kp_ent, std::max<size_t>(1, ent.size()) * sizeof(uint32_t)));
+    SG_HIP(c, hipMemcpy(c->kp_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!ent.empty())
+        SG_HIP(c, hipMemcpy(c->kp_ent, ent.data(), ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    return SPARC_OK;
+}
+
+// Signed nonlocal bounds at k: sum over atoms and lm of min/max(gamma, 0)
+// dV ||chi~_lm||^2 (the k-dependent projector norms), cached per k.
+sparc_status kp_nl_bounds(sparc_gpu_ctx c, const double* k, double* nl_lo, double* nl_hi) {
+    *nl_lo = *nl_hi = 0.0;
+    if (c->nl_lmax < 1) return SPARC_OK;
+    for (auto& e : c->kp_bound_cache)
+        if (e[0] == k[0] && e[1] == k[1] && e[2] == k[2]) {
+            *nl_lo = e[3];
+            *nl_hi = e[4];
+            return SPARC_OK;
+        }
+    const double h[3] = {c->hx, c->hy, c->hz}, L[3] = {c->Lx, c->Ly, c->Lz};
+    const int N[3] = {c->nx, c->ny, c->nz};
+    const double rc = c->rc_nl, rcut = c->rcut_nl;
+    const double N0 = std::pow(2.0 / (kPi * rc * rc), 0.75), N1 = (2.0 / rc) * N0;
+    double lo = 0.0, hi = 0.0;
+    for (int a = 0; a < c->n_atoms; ++a) {
+        std::vector<std::pair<long, std::array<double, 8>>> pts;
+        int l0[3], h0[3];
+        for (int d = 0; d < 3; ++d) {
+            l0[d] = (int)std::ceil((c->pos[3 * a + d] - rcut) / h[d]);
+            h0[d] = (int)std::floor((c->pos[3 * a + d] + rcut) / h[d]);
+        }
+        for (int kk = l0[2]; kk <= h0[2]; ++kk)
+            for (int j = l0[1]; j <= h0[1]; ++j)
+                for (int i = l0[0]; i <= h0[0]; ++i) {
+                    const int ii[3] = {i, j, kk};
+                    double dd[3], r2 = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        dd[d] = ii[d] * h[d] - c->pos[3 * a + d];
+                        r2 += dd[d] * dd[d];
+                    }
+                    if (r2 > rcut * rcut) continue;
+                    int s[3], w[3];
+                    double th = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        s[d] = ii[d] >= 0 ? ii[d] / N[d] : -((-ii[d] + N[d] - 1) / N[d]);
+                        w[d] = ii[d] - s[d] * N[d];
+                        th += k[d] * s[d] * L[d];
+                    }
+                    const double ex = std::exp(-r2 / (rc * rc));
+                    const double chi[4] = {N0 * ex, N1 * dd[0] * ex, N1 * dd[1] * ex, N1 * dd[2] * ex};
+                    std::array<double, 8> v;
+                    for (int l = 0; l < 4; ++l) {
+                        v[l] = chi[l] * std::cos(th);
+                        v[4 + l] = -chi[l] * std::sin(th);
+                    }
+                    pts.push_back({w[0] + (long)N[0] * (w[1] + (long)N[1] * w[2]), v});
+                }
+        std::sort(pts.begin(), pts.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+        double nrm[4] = {0, 0, 0, 0};
+        for (size_t b = 0; b < pts.size();) {
+            std::array<double, 8> s{};
+            size_t e = b;
+            for (; e < pts.size() && pts[e].first == pts[b].first; ++e)
+                for (int r = 0; r < 8; ++r) s[r] += pts[e].second[r];
+            for (int l = 0; l < 4; ++l) nrm[l] += s[l] * s[l] + s[4 + l] * s[4 + l];
+            b = e;
+        }
+        const double g[4] = {c->gamma[2 * a], c->gamma[2 * a + 1], c->gamma[2 * a + 1], c->gamma[2 * a + 1]};
+        for (int l = 0; l < 4; ++l) {
+            lo += std::min(g[l], 0.0) * c->dV * nrm[l];
+            hi += std::max(g[l], 0.0) * c->dV * nrm[l];
+        }
+    }
+    c->kp_bound_cache.push_back({k[0], k[1], k[2], lo, hi});
+    *nl_lo = lo;
+    *nl_hi = hi;
+    return SPARC_OK;
+}
+
+static sparc_status ensure_kp_proj(sparc_gpu_ctx c, size_t elems) {
+    if (c->kp_proj_elems >= elems) return SPARC_OK;
+    if (c->kp_proj) {
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+        SG_HIP(c, hipFree(c->kp_proj));
+        c->kp_proj = nullptr;
+        c->kp_proj_elems = 0;
+    }
+    SG_HIP(c, hipMalloc((void**)&c->kp_proj, elems * sizeof(double)));
+    c->kp_proj_elems = elems;
+    return SPARC_OK;
+}
+
+// One application of H_k (mode 0) or one filter step (modes 1, 2) at the
+// context's current k; projections first when the system has projectors.
+template <typename T>
+static sparc_status bloch_step(sparc_gpu_ctx c, const T* Y, T* out, const T* prev, int ncol, long ldx, int mode,
+                               int step) {
+    sparc_status st;
+    const BlochGeom g = bloch_geom(c, c->kvec);
+    const bool nl = c->nl_lmax >= 1;
+    double* proj = nullptr;
+    if (nl) {
+        if ((st = ensure_force_tables(c)) != SPARC_OK) return st;
+        if ((st = ensure_kp_tables(c)) != SPARC_OK) return st;
+        if ((st = ensure_kp_proj(c, (size_t)c->n_atoms * ncol * 8)) != SPARC_OK) return st;
+        proj = c->kp_proj;
+        const int slot = prof_begin(c, PK_BLOCH_PROJ);
+        const int n = c->n_atoms;
+        k_bloch_proj<T, kProjNB><<<dim3(n, div_up(ncol, kProjNB)), 256, 0, c->stream>>>(
+            Y, ldx, c->nd, ncol, c->force_tab, c->force_tab + 5 * n, g, c->dV, proj);
+        SG_CHECK_LAUNCH(c);
+        prof_end(c, slot);
+    }
+    const int slot = prof_begin(c, PK_BLOCH);
+    k_bloch_apply<T><<<dim3(div_up(c->nd, 256), ncol), 256, 0, c->stream>>>(
+        Y, out, prev, ldx, c->nd, c->veff, g, proj, ncol, c->kp_off, c->kp_ent, nl ? c->force_tab : nullptr,
+        c->scal + S_A, mode, step);
+    SG_CHECK_LAUNCH(c);
+    prof_end(c, slot);
+    return SPARC_OK;
+}
+
+template <typename T>
+sparc_status bloch_apply_impl(sparc_gpu_ctx c, const T* X, T* Y, int ncol, long ldx) {
+    return bloch_step<T>(c, X, Y, nullptr, ncol, ldx, 0, 0);
+}
+template sparc_status bloch_apply_impl<double>(sparc_gpu_ctx, const double*, double*, int, long);
+template sparc_status bloch_apply_impl<float>(sparc_gpu_ctx, const float*, float*, int, long);
+
+// Filter with bounds in c->scal[S_A..S_A0]: Y_k in X for even k, in W for
+// odd k; the result ends in X (the Gamma filter's schedule).
+template <typename T>
+sparc_status bloch_filter_impl(sparc_gpu_ctx c, T* X, T* W, int ncol, long ldx, int m) {
+    sparc_status st;
+    if ((st = bloch_step<T>(c, X, W, nullptr, ncol, ldx, 1, 1)) != SPARC_OK) return st;
+    for (int k = 2; k <= m; ++k) {
+        T* cur = (k % 2 == 0) ? W : X;
+        T* dst = (k % 2 == 0) ? X : W;
+        if ((st = bloch_step<T>(c, cur, dst, dst, ncol, ldx, 2, k)) != SPARC_OK) return st;
+    }
+    if (m % 2 == 1) {
+        k_copy_block_k<T><<<dim3(div_up(2 * c->nd, 256), ncol), 256, 0, c->stream>>>(W, X, 2 * c->nd, ncol, ldx);
+        SG_CHECK_LAUNCH(c);
+    }
+    return SPARC_OK;
+}
+template sparc_status bloch_filter_impl<double>(sparc_gpu_ctx, double*, double*, int, long, int);
+template sparc_status bloch_filter_impl<float>(sparc_gpu_ctx, float*, float*, int, long, int);
+
+// Spectrum bounds of H_k into S_LO / S_HI (V_eff extrema plus the
+// k-dependent nonlocal bounds).
+sparc_status bloch_bounds_impl(sparc_gpu_ctx c) {
+    double lo, hi;
+    sparc_status st = kp_nl_bounds(c, c->kvec, &lo, &hi);
+    if (st != SPARC_OK) return st;
+    // the Gamma routine with the k-dependent nonlocal terms (its kernels take
+    // them as launch arguments)
+    const double glo = c->nl.nl_lo, ghi = c->nl.nl_hi;
+    c->nl.nl_lo = lo;
+    c->nl.nl_hi = hi;
+    st = bounds_impl(c);
+    c->nl.nl_lo = glo;
+    c->nl.nl_hi = ghi;
+    return st;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+namespace {
+
+__global__ void k_set_params3(double* dst, double a, double b, double c) {
+    dst[0] = a;
+    dst[1] = b;
+    dst[2] = c;
+}
+
+sparc_status check_k_block(sparc_gpu_ctx c, const double* k, int prec, const void* X, int ncol, long ldx,
+                           const char* who) {
+    if (!k || !std::isfinite(k[0]) || !std::isfinite(k[1]) || !std::isfinite(k[2]))
+        return set_err(c, SPARC_ERR_ARG, std::string(who) + ": bad k");
+    if (prec != SPARC_FP64 && prec != SPARC_FP32) return set_err(c, SPARC_ERR_ARG, std::string(who) + ": bad precision");
+    if (!X) return set_err(c, SPARC_ERR_ARG, std::string(who) + ": null block");
+    if (ncol < 1 || ncol > 2 * c->n_states)
+        return set_err(c, SPARC_ERR_ARG, std::string(who) + ": ncol outside [1, 2 n_states]");
+    if (ldx < 2 * c->nd) return set_err(c, SPARC_ERR_ARG, std::string(who) + ": ldx < 2 N_d");
+    return SPARC_OK;
+}
+
+bool blocks_overlap(const void* a, const void* b, size_t bytes) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+void set_k(sparc_gpu_ctx c, const double* k) {
+    for (int d = 0; d < 3; ++d) c->kvec[d] = k[d];
+}
+
+}  // namespace
+
+extern "C" {
+
+sparc_status sparc_gpu_apply_H_k(sparc_gpu_ctx c, const double* k, sparc_prec prec, const void* d_X, void* d_Y,
+                                 int ncol, long ldx) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = check_k_block(c, k, prec, d_X, ncol, ldx, "apply_H_k");
+    if (st != SPARC_OK) return st;
+    if (!d_Y) return set_err(c, SPARC_ERR_ARG, "apply_H_k: null output");
+    const size_t es = prec == SPARC_FP64 ? 8 : 4;
+    if (blocks_overlap(d_X, d_Y, ((size_t)(ncol - 1) * ldx + 2 * c->nd) * es))
+        return set_err(c, SPARC_ERR_ARG, "apply_H_k: X and Y overlap");
+    set_k(c, k);
+    if (prec == SPARC_FP64) return bloch_apply_impl<double>(c, (const double*)d_X, (double*)d_Y, ncol, ldx);
+    return bloch_apply_impl<float>(c, (const float*)d_X, (float*)d_Y, ncol, ldx);
+}
+
+sparc_status sparc_gpu_chebyshev_filter_k(sparc_gpu_ctx c, const double* k, sparc_prec prec, void* d_X, void* d_work,
+                                          int ncol, long ldx, int degree, double a, double b, double a0) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = check_k_block(c, k, prec, d_X, ncol, ldx, "chebyshev_filter_k");
+    if (st != SPARC_OK) return st;
+    if (!d_work) return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_k: null work block");
+    if (degree < 1 || degree > 10000) return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_k: degree out of range");
+    if (!(a0 < a && a < b) || !std::isfinite(a0) || !std::isfinite(b))
+        return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_k: need a0 < a < b");
+    const size_t es = prec == SPARC_FP64 ? 8 : 4;
+    if (blocks_overlap(d_X, d_work, ((size_t)(ncol - 1) * ldx + 2 * c->nd) * es))
+        return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_k: X and work overlap");
+    set_k(c, k);
+    k_set_params3<<<1, 1, 0, c->stream>>>(c->scal + S_A, a, b, a0);
+    SG_CHECK_LAUNCH(c);
+    if (prec == SPARC_FP64) return bloch_filter_impl<double>(c, (double*)d_X, (double*)d_work, ncol, ldx, degree);
+    return bloch_filter_impl<float>(c, (float*)d_X, (float*)d_work, ncol, ldx, degree);
+}
+
+sparc_status sparc_gpu_rayleigh_ritz_k(sparc_gpu_ctx c, const double* k, sparc_prec prec, void* d_X, int ncol,
+                                       long ldx, double* d_eig) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = check_k_block(c, k, prec, d_X, ncol, ldx, "rayleigh_ritz_k");
+    if (st != SPARC_OK) return st;
+    if (!d_eig) return set_err(c, SPARC_ERR_ARG, "rayleigh_ritz_k: null eigenvalue output");
+    if (ncol > kEighMaxN) return set_err(c, SPARC_ERR_ARG, "rayleigh_ritz_k: ncol above the eigensolver limit");
+    set_k(c, k);
+    if (prec == SPARC_FP64) return rayleigh_ritz_k_impl<double>(c, (double*)d_X, ncol, ldx, d_eig, true);
+    return rayleigh_ritz_k_impl<float>(c, (float*)d_X, ncol, ldx, d_eig, true);
+}
+
+sparc_status sparc_gpu_spectrum_bounds_k(sparc_gpu_ctx c, const double* k, double* lo, double* hi) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    if (!k || !std::isfinite(k[0]) || !std::isfinite(k[1]) || !std::isfinite(k[2]))
+        return set_err(c, SPARC_ERR_ARG, "spectrum_bounds_k: bad k");
+    set_k(c, k);
+    sparc_status st = bloch_bounds_impl(c);
+    if (st != SPARC_OK) return st;
+    double h2[2];
+    SG_HIP(c, hipMemcpyAsync(h2, c->scal + S_LO, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    if (lo) *lo = h2[0];
+    if (hi) *hi = h2[1];
+    return SPARC_OK;
+}
+
+}  // extern "C"

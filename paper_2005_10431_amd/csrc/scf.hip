@@ -236,8 +236,9 @@ __device__ inline double fermi(double lam, double mu, double kT) {
 // term: out[0] = mu, out[1] = deg kT sum [f ln f + (1-f) ln(1-f)],
 // out[2] = sum g lam.  deg = 2 spin-unpolarised, 1 per spin state.
 __global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ eig, int N, double ne, double kT,
-                                                     double deg, double* __restrict__ occ,
-                                                     double* __restrict__ out, int* __restrict__ flag) {
+                                                     double deg, const double* __restrict__ wts,
+                                                     double* __restrict__ occ, double* __restrict__ out,
+                                                     int* __restrict__ flag) {
     __shared__ double red[256];
     __shared__ double s_lo, s_hi, s_mu;
     __shared__ int s_done;
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ 
     for (int it = 0; it < 500; ++it) {
         double mu = 0.5 * (s_lo + s_hi);
         double acc = 0.0;
-        for (int i = t; i < N; i += blockDim.x) acc += deg * fermi(eig[i], mu, kT);
+        for (int i = t; i < N; i += blockDim.x) acc += deg * (wts ? wts[i] : 1.0) * fermi(eig[i], mu, kT);
         red[t] = acc;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
@@ -283,9 +284,10 @@ __global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ 
     double ent = 0.0, band = 0.0;
     for (int i = t; i < N; i += blockDim.x) {
         double f = fermi(eig[i], mu, kT);
+        const double wi = wts ? wts[i] : 1.0;
         occ[i] = deg * f;
-        band += deg * f * eig[i];
-        if (f > 0.0 && f < 1.0) ent += f * log(f) + (1.0 - f) * log(1.0 - f);
+        band += wi * deg * f * eig[i];
+        if (f > 0.0 && f < 1.0) ent += wi * (f * log(f) + (1.0 - f) * log(1.0 - f));
     }
     __syncthreads();
     red[t] = ent;
@@ -310,8 +312,9 @@ __global__ __launch_bounds__(256) void k_occupations(const double* __restrict__ 
     }
 }
 
-sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu, double deg) {
-    k_occupations<<<1, 256, 0, c->stream>>>(eig, ncol, c->n_electrons, c->kT, deg, occ, c->scal + S_OCC,
+sparc_status occupations_impl(sparc_gpu_ctx c, const double* eig, int ncol, double* occ, double* mu, double deg,
+                              const double* wts) {
+    k_occupations<<<1, 256, 0, c->stream>>>(eig, ncol, c->n_electrons, c->kT, deg, wts, occ, c->scal + S_OCC,
                                            c->flags + F_FERMI);
     SG_CHECK_LAUNCH(c);
     if (mu) SG_HIP(c, hipMemcpyAsync(mu, c->scal + S_OCC, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1007,6 +1010,161 @@ static sparc_status check_spin_state(sparc_gpu_ctx c, const sparc_gpu_scf_spin_s
     return SPARC_OK;
 }
 
+// ---- Bloch k-points ---------------------------------------------------------
+
+// rho (+)= w_k sum_j occ_j (u_j^2 + v_j^2) over Bloch columns [u; v]
+template <typename T>
+__global__ __launch_bounds__(256) void k_density_k(const T* __restrict__ X, int ncol, long ldx, long nd,
+                                                   const double* __restrict__ occ, double wk,
+                                                   double* __restrict__ rho, int accumulate) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nd) return;
+    double acc = 0.0;
+    for (int j = 0; j < ncol; ++j) {
+        const double u = (double)X[p + (long)j * ldx], v = (double)X[nd + p + (long)j * ldx];
+        acc += occ[j] * (u * u + v * v);
+    }
+    rho[p] = (accumulate ? rho[p] : 0.0) + wk * acc;
+}
+
+__global__ void k_stash_kbounds(const double* scal, double* dst, int q) {
+    dst[3 * q + 0] = scal[S_A];
+    dst[3 * q + 1] = scal[S_B];
+    dst[3 * q + 2] = scal[S_A0];
+}
+
+static sparc_status ensure_dev(sparc_gpu_ctx c, double** p, int* have, int need) {
+    if (*have >= need) return SPARC_OK;
+    if (*p) {
+        SG_HIP(c, hipStreamSynchronize(c->stream));
+        SG_HIP(c, hipFree(*p));
+        *p = nullptr;
+        *have = 0;
+    }
+    SG_HIP(c, hipMalloc((void**)p, (size_t)need * sizeof(double)));
+    *have = need;
+    return SPARC_OK;
+}
+
+template <typename T>
+static sparc_status scf_step_k_impl(sparc_gpu_ctx c, sparc_gpu_scf_k_state* s, sparc_gpu_scf_report* rep) {
+    sparc_status st;
+    const int N2 = 2 * c->n_states;
+    const int nk = s->n_k;
+    const long nd = c->nd;
+    if ((st = ensure_fields(c, 6)) != SPARC_OK) return st;
+    if ((st = ensure_work(c, ((size_t)(N2 - 1) * s->ldx + 2 * nd) * sizeof(T))) != SPARC_OK) return st;
+    if ((st = ensure_dev(c, &c->kp_bounds, &c->kp_bounds_n, 3 * nk)) != SPARC_OK) return st;
+    if ((st = ensure_dev(c, &c->kp_wts, &c->kp_wts_n, nk * N2)) != SPARC_OK) return st;
+    {
+        std::vector<double> w((size_t)nk * N2);
+        for (int q = 0; q < nk; ++q)
+            for (int j = 0; j < N2; ++j) w[(size_t)q * N2 + j] = s->kweights[q];
+        SG_HIP(c, hipMemcpy(c->kp_wts, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    double* phi = c->field + 2 * nd;
+    double* exc = c->field + 3 * nd;
+    double* vxc = c->field + 4 * nd;
+    double* rho_out = s->d_rho_out ? s->d_rho_out : c->field + 5 * nd;
+    SG_HIP(c, hipMemsetAsync(c->flags, 0, F_COUNT * sizeof(int), c->stream));
+    Timer tm(c);
+    tm.mark(0);
+    if ((st = potential_impl(c, s->d_rho_in, phi, exc, vxc, c->veff)) != SPARC_OK) return st;
+    tm.mark(1);
+    const bool first = s->iter == 0;
+    const int npass = first ? s->n_first : 1;
+    double t_filter = 0.0, t_rr = 0.0;
+    for (int q = 0; q < nk; ++q) {
+        for (int d = 0; d < 3; ++d) c->kvec[d] = s->kpts[3 * q + d];
+        T* X = (T*)s->d_X[q];
+        double* eig = s->d_eig + (long)q * N2;
+        if ((st = bloch_bounds_impl(c)) != SPARC_OK) return st;
+        if (first) {
+            if ((st = rayleigh_ritz_k_impl<T>(c, X, N2, s->ldx, eig, true)) != SPARC_OK) return st;
+            k_bounds_from_eig<<<1, 1, 0, c->stream>>>(eig, N2, c->scal, 1);
+        } else {
+            k_set_ab<<<1, 1, 0, c->stream>>>(c->scal, s->bounds[3 * q], s->bounds[3 * q + 2]);
+        }
+        SG_CHECK_LAUNCH(c);
+        for (int pass = 0; pass < npass; ++pass) {
+            tm.mark(2);
+            if ((st = bloch_filter_impl<T>(c, X, (T*)c->work, N2, s->ldx, s->cheb_degree)) != SPARC_OK) return st;
+            tm.mark(3);
+            if ((st = rayleigh_ritz_k_impl<T>(c, X, N2, s->ldx, eig, true)) != SPARC_OK) return st;
+            k_bounds_from_eig<<<1, 1, 0, c->stream>>>(eig, N2, c->scal, 0);
+            SG_CHECK_LAUNCH(c);
+            tm.mark(4);
+            SG_HIP(c, hipEventSynchronize(c->ev[4]));
+            t_filter += tm.ms(2, 3);
+            t_rr += tm.ms(3, 4);
+        }
+        k_stash_kbounds<<<1, 1, 0, c->stream>>>(c->scal, c->kp_bounds, q);
+        SG_CHECK_LAUNCH(c);
+    }
+    tm.mark(5);
+    if ((st = occupations_impl(c, s->d_eig, nk * N2, s->d_occ, nullptr, 1.0, c->kp_wts)) != SPARC_OK) return st;
+    for (int q = 0; q < nk; ++q) {
+        k_density_k<T><<<div_up(nd, 256), 256, 0, c->stream>>>((const T*)s->d_X[q], N2, s->ldx, nd,
+                                                               s->d_occ + (long)q * N2, s->kweights[q], rho_out,
+                                                               q > 0 ? 1 : 0);
+        SG_CHECK_LAUNCH(c);
+    }
+    tm.mark(6);
+    sparc_gpu_scf_report R;
+    double hs[S_COUNT];
+    const MixArgs mix{s->mix_beta, s->kerker_q0, s->pulay_history, s->pulay_period, s->pulay_restart, s->d_pulay,
+                      s->iter, 1};
+    if ((st = finish_energy(c, s->d_rho_in, rho_out, &mix, &R, hs)) != SPARC_OK) return st;
+    tm.mark(7);
+    SG_HIP(c, hipEventSynchronize(c->ev[7]));
+    SG_HIP(c, hipMemcpy(s->bounds, c->kp_bounds, 3 * (size_t)nk * sizeof(double), hipMemcpyDeviceToHost));
+    R.t_potential_ms = tm.ms(0, 1);
+    R.t_filter_ms = t_filter;
+    R.t_rr_ms = t_rr;
+    R.t_density_ms = tm.ms(5, 6);
+    R.t_total_ms = tm.ms(0, 7);
+    R.n_passes = nk * npass;
+    R.iter = s->iter;
+    s->iter += 1;
+    if (rep) *rep = R;
+    return SPARC_OK;
+}
+
+static sparc_status check_k_state(sparc_gpu_ctx c, const sparc_gpu_scf_k_state* s) {
+    if (!s) return set_err(c, SPARC_ERR_ARG, "scf_k: null state");
+    if (s->n_k < 1 || s->n_k > 4096) return set_err(c, SPARC_ERR_ARG, "scf_k: n_k outside [1, 4096]");
+    if (!s->kpts || !s->kweights || !s->d_X || !s->bounds) return set_err(c, SPARC_ERR_ARG, "scf_k: null host array");
+    double wsum = 0.0;
+    for (int q = 0; q < s->n_k; ++q) {
+        if (!s->d_X[q]) return set_err(c, SPARC_ERR_ARG, "scf_k: null orbital block");
+        if (!(s->kweights[q] > 0.0) || !std::isfinite(s->kweights[q]))
+            return set_err(c, SPARC_ERR_ARG, "scf_k: k weights must be positive");
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(s->kpts[3 * q + d])) return set_err(c, SPARC_ERR_ARG, "scf_k: non-finite k");
+        wsum += s->kweights[q];
+    }
+    if (std::fabs(wsum - 1.0) > 1e-12) return set_err(c, SPARC_ERR_ARG, "scf_k: k weights must sum to 1");
+    if (!s->d_rho_in || !s->d_eig || !s->d_occ) return set_err(c, SPARC_ERR_ARG, "scf_k: null buffer");
+    if (s->prec != SPARC_FP64 && s->prec != SPARC_FP32) return set_err(c, SPARC_ERR_ARG, "scf_k: bad precision");
+    if (s->ldx < 2 * c->nd) return set_err(c, SPARC_ERR_ARG, "scf_k: ldx < 2 N_d");
+    if (2 * c->n_states > kEighMaxN) return set_err(c, SPARC_ERR_ARG, "scf_k: 2 n_states above the eigensolver limit");
+    if (s->cheb_degree < 1 || s->cheb_degree > 10000) return set_err(c, SPARC_ERR_ARG, "scf_k: bad degree");
+    if (s->n_first < 1 || s->n_first > 100) return set_err(c, SPARC_ERR_ARG, "scf_k: bad n_first");
+    if (!(s->mix_beta > 0.0 && s->mix_beta <= 1.0)) return set_err(c, SPARC_ERR_ARG, "scf_k: bad mix_beta");
+    if (!(s->kerker_q0 >= 0.0) || !std::isfinite(s->kerker_q0)) return set_err(c, SPARC_ERR_ARG, "scf_k: bad kerker_q0");
+    if (s->pulay_history < 0 || s->pulay_history > SPARC_PULAY_MAX)
+        return set_err(c, SPARC_ERR_ARG, "scf_k: pulay_history outside [0, SPARC_PULAY_MAX]");
+    if (s->pulay_history > 0 && (s->pulay_period < 1 || (s->pulay_restart != 0 && s->pulay_restart != 1) ||
+                                 !s->d_pulay))
+        return set_err(c, SPARC_ERR_ARG, "scf_k: bad Pulay period, restart flag or history buffer");
+    if (s->iter < 0) return set_err(c, SPARC_ERR_ARG, "scf_k: negative iter");
+    if (s->iter > 0)
+        for (int q = 0; q < s->n_k; ++q)
+            if (!(s->bounds[3 * q + 2] < s->bounds[3 * q]))
+                return set_err(c, SPARC_ERR_ARG, "scf_k: bounds need a0 < a after the first iteration");
+    return SPARC_OK;
+}
+
 static sparc_status check_state(sparc_gpu_ctx c, const sparc_gpu_scf_state* s) {
     if (!s) return set_err(c, SPARC_ERR_ARG, "scf: null state");
     if (!s->d_rho_in || !s->d_X || !s->d_eig || !s->d_occ) return set_err(c, SPARC_ERR_ARG, "scf: null buffer");
@@ -1131,6 +1289,15 @@ sparc_status sparc_gpu_scf_step_spin(sparc_gpu_ctx c, sparc_gpu_scf_spin_state* 
     if (st != SPARC_OK) return st;
     if (s->prec == SPARC_FP64) return scf_step_spin_impl<double>(c, s, rep);
     return scf_step_spin_impl<float>(c, s, rep);
+}
+
+sparc_status sparc_gpu_scf_step_k(sparc_gpu_ctx c, sparc_gpu_scf_k_state* s, sparc_gpu_scf_report* rep) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = check_k_state(c, s);
+    if (st != SPARC_OK) return st;
+    if (s->prec == SPARC_FP64) return scf_step_k_impl<double>(c, s, rep);
+    return scf_step_k_impl<float>(c, s, rep);
 }
 
 sparc_status sparc_gpu_potential_spin(sparc_gpu_ctx c, const double* d_rho, double* d_phi, double* d_exc,

@@ -4,7 +4,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from ._lib import SPARC_FP32, Context, make_spin_state, make_state
+from ._lib import SPARC_FP32, Context, make_k_state, make_spin_state, make_state
 
 
 def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100, tol: float = 1e-10,
@@ -137,3 +137,62 @@ def scf_forces(system, out) -> "np.ndarray":
     F = torch.empty((system.n_atoms, 3), dtype=torch.float64, device=phi.device)
     ctx.forces(phi, blocks, out["occ"], F)
     return F.cpu().numpy()
+
+
+def bloch_block(Z, dtype, device="cuda"):
+    """Device block of Bloch columns for complex start orbitals Z (N_s, N_d):
+    columns 2n = [Re z_n; Im z_n] and 2n + 1 = [-Im z_n; Re z_n] (the span is
+    closed under z -> i z), shape (2 N_s, 2 N_d)."""
+    import torch
+    Z = np.asarray(Z)
+    u, v = np.real(Z), np.imag(Z)
+    B = np.empty((2 * Z.shape[0], 2 * Z.shape[1]))
+    B[0::2, :Z.shape[1]], B[0::2, Z.shape[1]:] = u, v
+    B[1::2, :Z.shape[1]], B[1::2, Z.shape[1]:] = -v, u
+    return torch.as_tensor(B, dtype=dtype).to(device).contiguous()
+
+
+def run_scf_k(system, kpts, kweights, Z0s=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
+              tol: float = 1e-10, device: str = "cuda", ctx: Context = None, callback=None, n_first: int = None,
+              degree: int = None):
+    """SCF over a k-point set on the GPU (``sparc_gpu_scf_step_k``).  Z0s: one
+    complex (N_s, N_d) start block per k (default
+    ``workloads.initial_orbitals_k``).  Each report gains "eig_k": the Ritz
+    values per k with each Bloch eigenvalue once (every second entry of the
+    doubled list)."""
+    import torch
+    ctx = ctx or Context(system)
+    nd, ns = system.nd, system.n_states
+    nk = len(kpts)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if Z0s is None:
+        from workloads import initial_orbitals_k
+        Z0s = [initial_orbitals_k(nd, ns, system.seed, q) for q in range(nk)]
+    blocks = [bloch_block(Z, dt, device) for Z in Z0s]
+    rho_in = torch.empty(nd, dtype=torch.float64, device=device)
+    if rho0 is None:
+        ctx.sad_density(rho_in)
+    else:
+        rho_in.copy_(torch.as_tensor(np.asarray(rho0), dtype=torch.float64))
+    eig = torch.empty(nk * 2 * ns, dtype=torch.float64, device=device)
+    occ = torch.empty_like(eig)
+    rho_out = torch.empty(nd, dtype=torch.float64, device=device)
+    m = getattr(system, "pulay_history", 0)
+    hist_buf = torch.empty((2 * m + 2) * nd, dtype=torch.float64, device=device) if m > 0 else None
+    st = make_k_state(rho_in, blocks, kpts, kweights, eig, occ,
+                      degree if degree is not None else system.cheb_degree,
+                      n_first if n_first is not None else system.n_first, system.mix_beta, rho_out,
+                      system.kerker_q0, m, getattr(system, "pulay_period", 2), bool(getattr(system, "pulay_restart", 0)),
+                      hist_buf)
+    hist = []
+    for _ in range(max_iter):
+        rep = ctx.scf_step_k(st)
+        e = eig.detach().cpu().numpy().reshape(nk, 2 * ns)
+        rep["eig_k"] = [row[0::2].copy() for row in e]
+        hist.append(rep)
+        if callback is not None:
+            callback(rep)
+        if rep["residual"] < tol:
+            break
+    return dict(history=hist, X=blocks, eig=eig, occ=occ, rho_in=rho_in, rho_out=rho_out, state=st, ctx=ctx,
+                pulay_hist=hist_buf)

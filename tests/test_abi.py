@@ -48,7 +48,7 @@ def test_binding_struct_layout_matches_header():
     from paper_2005_10431_amd import _lib
     txt = open(HEADER).read()
     for cname, py in (("sparc_gpu_system", _lib.System), ("sparc_gpu_scf_state", _lib.SCFState),
-                      ("sparc_gpu_scf_spin_state", _lib.SpinSCFState),
+                      ("sparc_gpu_scf_spin_state", _lib.SpinSCFState), ("sparc_gpu_scf_k_state", _lib.KSCFState),
                       ("sparc_gpu_scf_report", _lib.SCFReport)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", txt).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)

@@ -33,6 +33,7 @@ __all__ = [
     "config1_spin",
     "config2_spin",
     "initial_orbitals_spin",
+    "initial_orbitals_k",
     "tiny_system",
     "initial_orbitals",
     "CONFIG_NAMES",
@@ -300,6 +301,15 @@ def initial_orbitals_spin(nd: int, ns: int, seed: int = 0):
     up = initial_orbitals(nd, ns, seed)
     rng = np.random.default_rng([seed, 11, 1])
     return up, rng.uniform(-0.5, 0.5, (ns, nd))
+
+
+def initial_orbitals_k(nd: int, ns: int, seed: int = 0, q: int = 0) -> np.ndarray:
+    """Complex starting block for k-point number q: (ns, nd) with real and
+    imaginary parts U(-0.5, 0.5) from their own seeded streams."""
+    rng = np.random.default_rng([seed, 11, 2, q])
+    re = rng.uniform(-0.5, 0.5, (ns, nd))
+    im = rng.uniform(-0.5, 0.5, (ns, nd))
+    return re + 1j * im
 
 
 CONFIG_NAMES = {
