@@ -182,18 +182,6 @@ def density_k(Xs, gs, wk) -> np.ndarray:
     return sum(w * np.sum(g[:, None] * np.abs(X) ** 2, axis=0) for X, g, w in zip(Xs, gs, wk))
 
 
-def monkhorst_pack(sys, grid):
-    """Monkhorst-Pack k-points of a (n1, n2, n3) grid (unshifted for odd,
-    half-shifted for even n) with equal weights; k in 1/Bohr."""
-    pts = []
-    for a in range(grid[0]):
-        for b in range(grid[1]):
-            for c in range(grid[2]):
-                f = [(2 * i - n + 1) / (2.0 * n) for i, n in zip((a, b, c), grid)]
-                pts.append([2.0 * pi * f[d] / sys.L[d] for d in range(3)])
-    return np.array(pts), np.full(len(pts), 1.0 / len(pts))
-
-
 def scf_k(sys, kpts, wk, Z0s, rho0=None, max_iter: int = 50, tol: float = 1e-10, st=None, n_first: int = None,
           degree: int = None, beta: float = None):
     """The SCF schedule of ``scf.scf`` with one CheFSI block per k-point

@@ -97,6 +97,7 @@ struct sparc_gpu_ctx_s {
     double* force_tab = nullptr;  // per-atom force table: pos (3n), Z (n), rc (n), gamma (4n); on use
     // Bloch k-points (allocated on use)
     double kvec[3] = {0, 0, 0};   // current k (1/Bohr)
+    int sweep_local_only = 0;     // sweeps skip the nonlocal term (Bloch path adds its own)
     int* kp_off = nullptr;        // N_d + 1: point-major projector entries
     uint32_t* kp_ent = nullptr;   // (atom, image) entries
     double* kp_proj = nullptr;    // n_atoms x ncol x 8 complex projections

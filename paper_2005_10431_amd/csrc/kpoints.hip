@@ -234,6 +234,101 @@ __global__ __launch_bounds__(256) void k_bloch_apply(const T* __restrict__ Y, T*
     out[o + nd] = (T)ov;
 }
 
+// Bloch terms on top of the Gamma local sweep (which applied the periodic
+// real stencil and V_eff to u and v separately and the filter recurrence):
+// out += alpha (boundary phase corrections + phased nonlocal term), only at
+// points within the stencil's reach of a face or inside a projector support.
+// Each thread serves NC columns, so the projector values and phases of a
+// point's entries are evaluated once for all of them.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_bloch_fix(const T* __restrict__ Y, T* __restrict__ out, long ldx, long nd,
+                                                  BlochGeom g, const double* __restrict__ proj, int ncol,
+                                                  const int* __restrict__ off, const uint32_t* __restrict__ ent,
+                                                  const double* __restrict__ pos,
+                                                  const double* __restrict__ params, int mode, int step) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int col0 = blockIdx.y * NC;
+    if (p >= nd) return;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, no = g.no;
+    const long nxy = (long)nx * ny;
+    const int ix = (int)(p % nx), iy = (int)((p / nx) % ny), iz = (int)(p / nxy);
+    const bool edge = ix < no || ix >= nx - no || iy < no || iy >= ny - no || iz < no || iz >= nz - no;
+    const bool has_nl = proj && off[p + 1] > off[p];
+    if (!edge && !has_nl) return;
+    const int nc = min(NC, ncol - col0);
+    double cu[NC], cv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) cu[c] = cv[c] = 0.0;
+    if (edge) {
+        // the sweep used y(wrapped); the Bloch value is y(wrapped) exp(+-i k L)
+        auto axis = [&](int i, int n, long st, long span, const double* cf, double cph, double sph) {
+            for (int q = 1; q <= no; ++q) {
+                const double w = cf[q];
+                if (i + q >= n) {
+                    const long pp = p + q * st - span;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        if (c < nc) {
+                            const T* yu = Y + (long)(col0 + c) * ldx;
+                            const double a = (double)yu[pp], b = (double)yu[nd + pp];
+                            cu[c] += w * (a * (cph - 1.0) - b * sph);
+                            cv[c] += w * (a * sph + b * (cph - 1.0));
+                        }
+                }
+                if (i - q < 0) {
+                    const long pp = p - q * st + span;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        if (c < nc) {
+                            const T* yu = Y + (long)(col0 + c) * ldx;
+                            const double a = (double)yu[pp], b = (double)yu[nd + pp];
+                            cu[c] += w * (a * (cph - 1.0) + b * sph);
+                            cv[c] += w * (-a * sph + b * (cph - 1.0));
+                        }
+                }
+            }
+        };
+        axis(ix, nx, 1, nx, g.cx, g.cph[0], g.sph[0]);
+        axis(iy, ny, nx, nxy, g.cy, g.cph[1], g.sph[1]);
+        axis(iz, nz, nxy, nd, g.cz, g.cph[2], g.sph[2]);
+    }
+    if (has_nl) {
+        for (int e = off[p]; e < off[p + 1]; ++e) {
+            const uint32_t w = ent[e];
+            const int a = (int)(w & 0xFFFFFu);
+            const int sx = (int)((w >> 20) & 15u) - 8, sy = (int)((w >> 24) & 15u) - 8, sz = (int)(w >> 28) - 8;
+            const double dx = (ix + sx * nx) * g.h[0] - pos[3 * a];
+            const double dy = (iy + sy * ny) * g.h[1] - pos[3 * a + 1];
+            const double dz = (iz + sz * nz) * g.h[2] - pos[3 * a + 2];
+            const double ex = exp(-(dx * dx + dy * dy + dz * dz) * g.rc2inv);
+            const double c0 = g.N0 * ex, c1 = g.N1 * dx * ex, c2 = g.N1 * dy * ex, c3 = g.N1 * dz * ex;
+            double sn, cs;
+            sincos(g.k[0] * sx * g.L[0] + g.k[1] * sy * g.L[1] + g.k[2] * sz * g.L[2], &sn, &cs);
+            const double* Cb = proj + ((long)a * ncol + col0) * 8;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < nc) {
+                    const double* C = Cb + 8 * c;
+                    const double cre = c0 * C[0] + c1 * C[1] + c2 * C[2] + c3 * C[3];
+                    const double cim = c0 * C[4] + c1 * C[5] + c2 * C[6] + c3 * C[7];
+                    cu[c] += cre * cs + cim * sn;
+                    cv[c] += cim * cs - cre * sn;
+                }
+        }
+    }
+    double alpha, csh, beta;
+    bloch_coefs(params, mode, step, alpha, csh, beta);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (c < nc) {
+            const long o = (long)(col0 + c) * ldx + p;
+            out[o] = (T)((double)out[o] + alpha * cu[c]);
+            out[o + nd] = (T)((double)out[o + nd] + alpha * cv[c]);
+        }
+}
+
+constexpr int kFixNC = 8;
+
 template <typename T>
 __global__ void k_copy_block_k(const T* __restrict__ src, T* __restrict__ dst, long rows, int ncol, long ld) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -403,9 +498,21 @@ static sparc_status bloch_step(sparc_gpu_ctx c, const T* Y, T* out, const T* pre
         prof_end(c, slot);
     }
     const int slot = prof_begin(c, PK_BLOCH);
-    k_bloch_apply<T><<<dim3(div_up(c->nd, 256), ncol), 256, 0, c->stream>>>(
-        Y, out, prev, ldx, c->nd, c->veff, g, proj, ncol, c->kp_off, c->kp_ent, nl ? c->force_tab : nullptr,
-        c->scal + S_A, mode, step);
+    if (ldx == 2 * c->nd) {
+        // unpadded blocks: the halves u, v are real columns of N_d rows, swept
+        // by the Gamma local kernel (recurrence fused); then the Bloch terms
+        c->sweep_local_only = 1;
+        st = launch_hsweep<T>(c, Y, out, prev, 2 * ncol, c->nd, mode, step);
+        c->sweep_local_only = 0;
+        if (st != SPARC_OK) return st;
+        k_bloch_fix<T, kFixNC><<<dim3(div_up(c->nd, 256), div_up(ncol, kFixNC)), 256, 0, c->stream>>>(
+            Y, out, ldx, c->nd, g, proj, ncol, c->kp_off, c->kp_ent, nl ? c->force_tab : nullptr, c->scal + S_A,
+            mode, step);
+    } else {
+        k_bloch_apply<T><<<dim3(div_up(c->nd, 256), ncol), 256, 0, c->stream>>>(
+            Y, out, prev, ldx, c->nd, c->veff, g, proj, ncol, c->kp_off, c->kp_ent, nl ? c->force_tab : nullptr,
+            c->scal + S_A, mode, step);
+    }
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
     return SPARC_OK;

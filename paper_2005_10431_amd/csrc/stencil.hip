@@ -558,7 +558,7 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     a.ntiles_y = div_up(c->ny, a.ty);
     a.cf = coef<T>(c);
     a.veff = veff_of<T>(c);
-    const bool nl = c->nl_lmax >= 1 && c->nl.n_pe > 0;
+    const bool nl = !c->sweep_local_only && c->nl_lmax >= 1 && c->nl.n_pe > 0;
     if (nl) {
         a.ty = c->nl_ty;
         a.ntiles_y = div_up(c->ny, a.ty);

@@ -67,6 +67,31 @@ def test_apply_H_k_matches_oracle(which):
         ctx.close()
 
 
+def test_padded_blocks_take_the_per_point_kernel():
+    """With ldx > 2 N_d the Bloch step runs the per-point kernel (the
+    unpadded path reuses the Gamma local sweep): same results."""
+    torch = require_gpu()
+    s = small_images_system(n_states=6)
+    k = np.array([-0.33, 0.71, 0.12])
+    ctx, v = _ctx_with_veff(torch, s, 27)
+    try:
+        pk = kpoints.projectors_k(s, k)
+        Z = _rand_Z(s, 4, 28)
+        Xp = torch.zeros((4, 2 * s.nd + 64), dtype=torch.float64, device="cuda")
+        Xp[:, : 2 * s.nd] = _to_block(torch, Z)
+        Yp = torch.zeros_like(Xp)
+        ctx.apply_H_k(k, Xp, Yp)
+        ref = kpoints.apply_H_k(s, v, pk, Z, k)
+        assert rel_err(_from_block(Yp[:, : 2 * s.nd], s.nd), ref) <= 1e-12
+        lo, hi = kpoints.spectrum_bounds_k(s, v, pk)
+        Wp = torch.zeros_like(Xp)
+        ctx.chebyshev_filter_k(k, Xp, Wp, 6, lo + 0.5 * (hi - lo), hi, lo)
+        fref = kpoints.chebyshev_filter_k(s, v, pk, Z, k, 6, lo + 0.5 * (hi - lo), hi, lo)
+        assert rel_err(_from_block(Xp[:, : 2 * s.nd], s.nd), fref) <= 1e-10
+    finally:
+        ctx.close()
+
+
 def test_apply_H_k_at_gamma_equals_the_gamma_operator():
     torch = require_gpu()
     s = ragged_system(n_states=6)
@@ -130,7 +155,7 @@ def test_k_point_scf_matches_oracle():
     require_gpu()
     from paper_2005_10431_amd.driver import run_scf_k
     s = W.tiny_system(n=(14, 16, 18), n_states=8)
-    kpts, wk = kpoints.monkhorst_pack(s, (2, 1, 1))
+    kpts, wk = W.monkhorst_pack(s.L, (2, 1, 1))
     Z0 = [W.initial_orbitals_k(s.nd, s.n_states, s.seed, q) for q in range(len(kpts))]
     ref = kpoints.scf_k(s, kpts, wk, Z0, max_iter=200, tol=1e-10)
     out = run_scf_k(s, kpts, wk, Z0, max_iter=200, tol=1e-10)

@@ -34,6 +34,7 @@ __all__ = [
     "config2_spin",
     "initial_orbitals_spin",
     "initial_orbitals_k",
+    "monkhorst_pack",
     "tiny_system",
     "initial_orbitals",
     "CONFIG_NAMES",
@@ -310,6 +311,20 @@ def initial_orbitals_k(nd: int, ns: int, seed: int = 0, q: int = 0) -> np.ndarra
     re = rng.uniform(-0.5, 0.5, (ns, nd))
     im = rng.uniform(-0.5, 0.5, (ns, nd))
     return re + 1j * im
+
+
+def monkhorst_pack(L, grid):
+    """Monkhorst-Pack k-points of a (n1, n2, n3) grid for an orthorhombic
+    cell of lengths L (offsets (2 i - n + 1) / (2 n) of the reciprocal
+    vectors: unshifted for odd n, half-shifted for even n), equal weights;
+    returns (k (n_k, 3) in 1/Bohr, weights (n_k,))."""
+    pts = []
+    for a in range(grid[0]):
+        for b in range(grid[1]):
+            for c in range(grid[2]):
+                f = [(2 * i - n + 1) / (2.0 * n) for i, n in zip((a, b, c), grid)]
+                pts.append([2.0 * np.pi * f[d] / L[d] for d in range(3)])
+    return np.array(pts), np.full(len(pts), 1.0 / len(pts))
 
 
 CONFIG_NAMES = {
