@@ -100,6 +100,10 @@ struct sparc_gpu_ctx_s {
     int sweep_local_only = 0;     // sweeps skip the nonlocal term (Bloch path adds its own)
     int* kp_off = nullptr;        // N_d + 1: point-major projector entries
     uint32_t* kp_ent = nullptr;   // (atom, image) entries
+    uint16_t* kp_slot = nullptr;  // per entry: the atom's slot in its point's tile list
+    int* kp_tile_off = nullptr;   // per 256-point tile: offsets into kp_tile_atoms
+    int* kp_tile_atoms = nullptr; // distinct atoms with entries in each tile
+    int kp_tile_max = 0;          // largest tile atom list
     double* kp_proj = nullptr;    // n_atoms x ncol x 8 complex projections
     size_t kp_proj_elems = 0;
     double* kp_bounds = nullptr;  // 3 per k-point: filter bounds of the k-point SCF

@@ -23,6 +23,7 @@ namespace sg {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kTile = 256;   // points per correction-pass workgroup (one per thread)
 
 struct BlochGeom {
     int nx, ny, nz, no;
@@ -244,10 +245,25 @@ template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_bloch_fix(const T* __restrict__ Y, T* __restrict__ out, long ldx, long nd,
                                                   BlochGeom g, const double* __restrict__ proj, int ncol,
                                                   const int* __restrict__ off, const uint32_t* __restrict__ ent,
+                                                  const uint16_t* __restrict__ slot,
+                                                  const int* __restrict__ tile_off,
+                                                  const int* __restrict__ tile_atoms,
                                                   const double* __restrict__ pos,
                                                   const double* __restrict__ params, int mode, int step) {
+    // the tile's projection coefficients for its NC columns, staged in LDS:
+    // cl[(slot NC + c) 8 + r]
+    extern __shared__ double cl[];
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int col0 = blockIdx.y * NC;
+    const int nc = min(NC, ncol - col0);
+    if (proj) {
+        const int t0 = tile_off[blockIdx.x], na = tile_off[blockIdx.x + 1] - t0;
+        for (int q = threadIdx.x; q < na * NC * 8; q += blockDim.x) {
+            const int sl = q / (NC * 8), c = (q / 8) % NC, r = q % 8;
+            cl[q] = c < nc ? proj[((long)tile_atoms[t0 + sl] * ncol + col0 + c) * 8 + r] : 0.0;
+        }
+        __syncthreads();
+    }
     if (p >= nd) return;
     const int nx = g.nx, ny = g.ny, nz = g.nz, no = g.no;
     const long nxy = (long)nx * ny;
@@ -255,7 +271,6 @@ __global__ __launch_bounds__(256) void k_bloch_fix(const T* __restrict__ Y, T* _
     const bool edge = ix < no || ix >= nx - no || iy < no || iy >= ny - no || iz < no || iz >= nz - no;
     const bool has_nl = proj && off[p + 1] > off[p];
     if (!edge && !has_nl) return;
-    const int nc = min(NC, ncol - col0);
     double cu[NC], cv[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) cu[c] = cv[c] = 0.0;
@@ -304,7 +319,7 @@ __global__ __launch_bounds__(256) void k_bloch_fix(const T* __restrict__ Y, T* _
             const double c0 = g.N0 * ex, c1 = g.N1 * dx * ex, c2 = g.N1 * dy * ex, c3 = g.N1 * dz * ex;
             double sn, cs;
             sincos(g.k[0] * sx * g.L[0] + g.k[1] * sy * g.L[1] + g.k[2] * sz * g.L[2], &sn, &cs);
-            const double* Cb = proj + ((long)a * ncol + col0) * 8;
+            const double* Cb = cl + (long)slot[e] * NC * 8;
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 if (c < nc) {
@@ -384,11 +399,39 @@ sparc_status ensure_kp_tables(sparc_gpu_ctx c) {
     std::vector<uint32_t> ent(list.size());
     std::vector<int> fill(off.begin(), off.end() - 1);
     for (auto& e : list) ent[fill[e.first]++] = e.second;
+    // tiles of kTile consecutive points: the distinct atoms of their entries,
+    // and for each entry the atom's position in its tile's list
+    const long ntile = (c->nd + kTile - 1) / kTile;
+    std::vector<int> toff(ntile + 1, 0), tatoms;
+    std::vector<uint16_t> slot(ent.size());
+    int tmax = 0;
+    for (long t = 0; t < ntile; ++t) {
+        const long p0 = t * kTile, p1 = std::min<long>(c->nd, p0 + kTile);
+        std::vector<int> atoms_t;
+        for (int e = off[p0]; e < off[p1]; ++e) atoms_t.push_back((int)(ent[e] & 0xFFFFFu));
+        std::sort(atoms_t.begin(), atoms_t.end());
+        atoms_t.erase(std::unique(atoms_t.begin(), atoms_t.end()), atoms_t.end());
+        if (atoms_t.size() > 65535) return set_err(c, SPARC_ERR_ARG, "k-points: too many atoms in one tile");
+        for (int e = off[p0]; e < off[p1]; ++e)
+            slot[e] = (uint16_t)(std::lower_bound(atoms_t.begin(), atoms_t.end(), (int)(ent[e] & 0xFFFFFu)) -
+                                 atoms_t.begin());
+        tatoms.insert(tatoms.end(), atoms_t.begin(), atoms_t.end());
+        toff[t + 1] = (int)tatoms.size();
+        tmax = std::max(tmax, (int)atoms_t.size());
+    }
     SG_HIP(c, hipMalloc((void**)&c->kp_off, off.size() * sizeof(int)));
     SG_HIP(c, hipMalloc((void**)&c->kp_ent, std::max<size_t>(1, ent.size()) * sizeof(uint32_t)));
+    SG_HIP(c, hipMalloc((void**)&c->kp_slot, std::max<size_t>(1, slot.size()) * sizeof(uint16_t)));
+    SG_HIP(c, hipMalloc((void**)&c->kp_tile_off, toff.size() * sizeof(int)));
+    SG_HIP(c, hipMalloc((void**)&c->kp_tile_atoms, std::max<size_t>(1, tatoms.size()) * sizeof(int)));
     SG_HIP(c, hipMemcpy(c->kp_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
-    if (!ent.empty())
+    SG_HIP(c, hipMemcpy(c->kp_tile_off, toff.data(), toff.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!ent.empty()) {
         SG_HIP(c, hipMemcpy(c->kp_ent, ent.data(), ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        SG_HIP(c, hipMemcpy(c->kp_slot, slot.data(), slot.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+        SG_HIP(c, hipMemcpy(c->kp_tile_atoms, tatoms.data(), tatoms.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    c->kp_tile_max = tmax;
     return SPARC_OK;
 }
 
@@ -498,16 +541,18 @@ static sparc_status bloch_step(sparc_gpu_ctx c, const T* Y, T* out, const T* pre
         prof_end(c, slot);
     }
     const int slot = prof_begin(c, PK_BLOCH);
-    if (ldx == 2 * c->nd) {
+    // correction pass LDS: the coefficients of a tile's atoms for kFixNC columns
+    const size_t lds = nl ? (size_t)c->kp_tile_max * kFixNC * 8 * sizeof(double) : 0;
+    if (ldx == 2 * c->nd && lds <= 64 * 1024) {
         // unpadded blocks: the halves u, v are real columns of N_d rows, swept
         // by the Gamma local kernel (recurrence fused); then the Bloch terms
         c->sweep_local_only = 1;
         st = launch_hsweep<T>(c, Y, out, prev, 2 * ncol, c->nd, mode, step);
         c->sweep_local_only = 0;
         if (st != SPARC_OK) return st;
-        k_bloch_fix<T, kFixNC><<<dim3(div_up(c->nd, 256), div_up(ncol, kFixNC)), 256, 0, c->stream>>>(
-            Y, out, ldx, c->nd, g, proj, ncol, c->kp_off, c->kp_ent, nl ? c->force_tab : nullptr, c->scal + S_A,
-            mode, step);
+        k_bloch_fix<T, kFixNC><<<dim3(div_up(c->nd, kTile), div_up(ncol, kFixNC)), kTile, lds, c->stream>>>(
+            Y, out, ldx, c->nd, g, proj, ncol, c->kp_off, c->kp_ent, c->kp_slot, c->kp_tile_off, c->kp_tile_atoms,
+            nl ? c->force_tab : nullptr, c->scal + S_A, mode, step);
     } else {
         k_bloch_apply<T><<<dim3(div_up(c->nd, 256), ncol), 256, 0, c->stream>>>(
             Y, out, prev, ldx, c->nd, c->veff, g, proj, ncol, c->kp_off, c->kp_ent, nl ? c->force_tab : nullptr,
