@@ -192,3 +192,38 @@ def test_k_state_rejects_bad_weights():
             ctx.apply_H_k([0.1, 0.0, 0.0], B[:, : s.nd].contiguous(), B.clone()[:, : s.nd].contiguous())
     finally:
         ctx.close()
+
+
+def test_filter_k_fp32_and_k_point_scf_fp32():
+    """FP32 Bloch blocks: the filter against the oracle on the same
+    FP32-rounded input (bar 2e-5 relative after degree 7, FP32 rounding
+    of every step), and the FP32 k-point SCF converged to 1e-5 within 1e-5
+    Ha/atom of the oracle's FP64 fixed point."""
+    torch = require_gpu()
+    from paper_2005_10431_amd.driver import run_scf_k
+    s = small_images_system(n_states=6)
+    k = np.array([0.5, -0.25, 0.75])
+    ctx, v = _ctx_with_veff(torch, s, 29)
+    try:
+        pk = kpoints.projectors_k(s, k)
+        lo, hi = kpoints.spectrum_bounds_k(s, v, pk)
+        X = _to_block(torch, _rand_Z(s, 4, 30), torch.float32)
+        Z32 = _from_block(X, s.nd)
+        Wk = torch.empty_like(X)
+        a = lo + 0.4 * (hi - lo)
+        ctx.chebyshev_filter_k(k, X, Wk, 7, a, hi, lo)
+        ref = kpoints.chebyshev_filter_k(s, v, pk, Z32, k, 7, a, hi, lo)
+        assert rel_err(_from_block(X, s.nd), ref) <= 2e-5
+    finally:
+        ctx.close()
+    s2 = W.tiny_system(n=(14, 16, 18), n_states=8)
+    kpts, wk = W.monkhorst_pack(s2.L, (2, 1, 1))
+    Z0 = [W.initial_orbitals_k(s2.nd, s2.n_states, s2.seed, q) for q in range(len(kpts))]
+    ref = kpoints.scf_k(s2, kpts, wk, Z0, max_iter=200, tol=1e-10)
+    out = run_scf_k(s2, kpts, wk, Z0, prec="fp32", max_iter=200, tol=1e-5)
+    h = out["history"]
+    dF = abs(h[-1]["free_energy"] - ref["history"][-1]["free"]) / s2.n_atoms
+    log(f"k-point SCF FP32: {len(h)} iterations, dF/atom {dF:.2e}")
+    assert h[-1]["residual"] < 1e-5
+    assert dF <= 1e-5
+    out["ctx"].close()
