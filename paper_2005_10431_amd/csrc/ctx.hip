@@ -823,7 +823,7 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
 sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
     if (!c) return SPARC_ERR_ARG;
     hipStreamSynchronize(c->stream);
-    void* ptrs[] = {c->veff, c->veff32, c->veff_spin, c->force_tab, c->kp_off, c->kp_ent, c->kp_slot,
+    void* ptrs[] = {c->veff, c->veff32, c->veff_spin, c->force_tab, c->kp_off, c->kp_ent, c->kp_slot, c->kp_etab,
                     c->kp_tile_off, c->kp_tile_atoms, c->kp_proj,
                     c->kp_bounds, c->kp_wts, c->b, c->pois_ux, c->pois_uy, c->pois_uz, c->pois_inv, c->work, c->D,
                     c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,

@@ -104,6 +104,10 @@ struct sparc_gpu_ctx_s {
     int* kp_tile_off = nullptr;   // per 256-point tile: offsets into kp_tile_atoms
     int* kp_tile_atoms = nullptr; // distinct atoms with entries in each tile
     int kp_tile_max = 0;          // largest tile atom list
+    long kp_n_ent = 0;            // number of entries
+    double* kp_etab = nullptr;    // per entry: chi_s, chi_px, chi_py, chi_pz, cos, sin at kp_etab_k
+    double kp_etab_k[3] = {0, 0, 0};
+    int kp_etab_valid = 0;
     double* kp_proj = nullptr;    // n_atoms x ncol x 8 complex projections
     size_t kp_proj_elems = 0;
     double* kp_bounds = nullptr;  // 3 per k-point: filter bounds of the k-point SCF

@@ -235,6 +235,35 @@ __global__ __launch_bounds__(256) void k_bloch_apply(const T* __restrict__ Y, T*
     out[o + nd] = (T)ov;
 }
 
+// Projector values and Bloch phase of every (point, atom, image) entry at
+// one k: et[6 e] = chi_s, chi_px, chi_py, chi_pz, cos(k . sL), sin(k . sL).
+__global__ void k_bloch_entry_table(const int* __restrict__ off, const uint32_t* __restrict__ ent, long nd,
+                                    const double* __restrict__ pos, BlochGeom g, double* __restrict__ et) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nd) return;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const long nxy = (long)nx * ny;
+    const int ix = (int)(p % nx), iy = (int)((p / nx) % ny), iz = (int)(p / nxy);
+    for (int e = off[p]; e < off[p + 1]; ++e) {
+        const uint32_t w = ent[e];
+        const int a = (int)(w & 0xFFFFFu);
+        const int sx = (int)((w >> 20) & 15u) - 8, sy = (int)((w >> 24) & 15u) - 8, sz = (int)(w >> 28) - 8;
+        const double dx = (ix + sx * nx) * g.h[0] - pos[3 * a];
+        const double dy = (iy + sy * ny) * g.h[1] - pos[3 * a + 1];
+        const double dz = (iz + sz * nz) * g.h[2] - pos[3 * a + 2];
+        const double ex = exp(-(dx * dx + dy * dy + dz * dz) * g.rc2inv);
+        double sn, cs;
+        sincos(g.k[0] * sx * g.L[0] + g.k[1] * sy * g.L[1] + g.k[2] * sz * g.L[2], &sn, &cs);
+        double* o = et + 6L * e;
+        o[0] = g.N0 * ex;
+        o[1] = g.N1 * dx * ex;
+        o[2] = g.N1 * dy * ex;
+        o[3] = g.N1 * dz * ex;
+        o[4] = cs;
+        o[5] = sn;
+    }
+}
+
 // Bloch terms on top of the Gamma local sweep (which applied the periodic
 // real stencil and V_eff to u and v separately and the filter recurrence):
 // out += alpha (boundary phase corrections + phased nonlocal term), only at
@@ -248,7 +277,7 @@ __global__ __launch_bounds__(256) void k_bloch_fix(const T* __restrict__ Y, T* _
                                                   const uint16_t* __restrict__ slot,
                                                   const int* __restrict__ tile_off,
                                                   const int* __restrict__ tile_atoms,
-                                                  const double* __restrict__ pos,
+                                                  const double* __restrict__ et,
                                                   const double* __restrict__ params, int mode, int step) {
     // the tile's projection coefficients for its NC columns, staged in LDS:
     // cl[(slot NC + c) 8 + r]
@@ -309,16 +338,8 @@ __global__ __launch_bounds__(256) void k_bloch_fix(const T* __restrict__ Y, T* _
     }
     if (has_nl) {
         for (int e = off[p]; e < off[p + 1]; ++e) {
-            const uint32_t w = ent[e];
-            const int a = (int)(w & 0xFFFFFu);
-            const int sx = (int)((w >> 20) & 15u) - 8, sy = (int)((w >> 24) & 15u) - 8, sz = (int)(w >> 28) - 8;
-            const double dx = (ix + sx * nx) * g.h[0] - pos[3 * a];
-            const double dy = (iy + sy * ny) * g.h[1] - pos[3 * a + 1];
-            const double dz = (iz + sz * nz) * g.h[2] - pos[3 * a + 2];
-            const double ex = exp(-(dx * dx + dy * dy + dz * dz) * g.rc2inv);
-            const double c0 = g.N0 * ex, c1 = g.N1 * dx * ex, c2 = g.N1 * dy * ex, c3 = g.N1 * dz * ex;
-            double sn, cs;
-            sincos(g.k[0] * sx * g.L[0] + g.k[1] * sy * g.L[1] + g.k[2] * sz * g.L[2], &sn, &cs);
+            const double* te = et + 6L * e;
+            const double c0 = te[0], c1 = te[1], c2 = te[2], c3 = te[3], cs = te[4], sn = te[5];
             const double* Cb = cl + (long)slot[e] * NC * 8;
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -432,6 +453,7 @@ sparc_status ensure_kp_tables(sparc_gpu_ctx c) {
         SG_HIP(c, hipMemcpy(c->kp_tile_atoms, tatoms.data(), tatoms.size() * sizeof(int), hipMemcpyHostToDevice));
     }
     c->kp_tile_max = tmax;
+    c->kp_n_ent = (long)ent.size();
     return SPARC_OK;
 }
 
@@ -550,9 +572,17 @@ static sparc_status bloch_step(sparc_gpu_ctx c, const T* Y, T* out, const T* pre
         st = launch_hsweep<T>(c, Y, out, prev, 2 * ncol, c->nd, mode, step);
         c->sweep_local_only = 0;
         if (st != SPARC_OK) return st;
+        if (nl && !(c->kp_etab_valid && c->kp_etab_k[0] == c->kvec[0] && c->kp_etab_k[1] == c->kvec[1] &&
+                    c->kp_etab_k[2] == c->kvec[2])) {
+            if (!c->kp_etab) SG_HIP(c, hipMalloc((void**)&c->kp_etab, 6 * std::max(1L, c->kp_n_ent) * sizeof(double)));
+            k_bloch_entry_table<<<div_up(c->nd, 256), 256, 0, c->stream>>>(c->kp_off, c->kp_ent, c->nd, c->force_tab,
+                                                                           g, c->kp_etab);
+            for (int d = 0; d < 3; ++d) c->kp_etab_k[d] = c->kvec[d];
+            c->kp_etab_valid = 1;
+        }
         k_bloch_fix<T, kFixNC><<<dim3(div_up(c->nd, kTile), div_up(ncol, kFixNC)), kTile, lds, c->stream>>>(
             Y, out, ldx, c->nd, g, proj, ncol, c->kp_off, c->kp_ent, c->kp_slot, c->kp_tile_off, c->kp_tile_atoms,
-            nl ? c->force_tab : nullptr, c->scal + S_A, mode, step);
+            c->kp_etab, c->scal + S_A, mode, step);
     } else {
         k_bloch_apply<T><<<dim3(div_up(c->nd, 256), ncol), 256, 0, c->stream>>>(
             Y, out, prev, ldx, c->nd, c->veff, g, proj, ncol, c->kp_off, c->kp_ent, nl ? c->force_tab : nullptr,
