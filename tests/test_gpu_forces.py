@@ -137,3 +137,24 @@ def test_forces_reject_bad_arguments():
             ctx.forces(phi, [big], torch.zeros(s.n_states + 1, dtype=torch.float64, device="cuda"), F)
     finally:
         ctx.close()
+
+
+def test_forces_after_spin_polarised_scf_match_oracle():
+    """Spin-polarised SCF (two blocks, LSDA) to a residual of 1e-10 on both
+    sides from the same start, then forces from both spin blocks with their
+    occupations and the potential of the total density."""
+    require_gpu()
+    from paper_2005_10431_amd.driver import run_scf_spin, scf_forces
+    s = replace(W.tiny_system(n=(14, 16, 18), n_states=8), spin=2, spin_zeta0=0.2, kT=0.005)
+    Xu, Xd = W.initial_orbitals_spin(s.nd, s.n_states, 3)
+    r = scf.scf_spin(s, Xu, Xd, max_iter=400, tol=1e-10)
+    st = scf.setup(s)
+    nd = s.nd
+    phi, _, _, _, _, _ = scf.potential_spin(s, st, r.rho_out[:nd], r.rho_out[nd:])
+    ref = forces.forces(s, phi, list(r.X), list(r.f))
+    out = run_scf_spin(s, (Xu, Xd), max_iter=400, tol=1e-10)
+    got = scf_forces(s, out)
+    log(f"spin forces: {len(out['history'])} iterations (oracle {len(r.history)}), max |F| "
+        f"{np.max(np.abs(ref)):.4e}, max diff {np.max(np.abs(got - ref)):.2e}")
+    assert np.max(np.abs(got - ref)) <= 1e-8
+    out["ctx"].close()
