@@ -67,6 +67,30 @@ def test_apply_H_k_matches_oracle(which):
         ctx.close()
 
 
+def test_apply_and_filter_k_without_projectors():
+    """Local part only (no nonlocal term): the correction pass adds only the
+    boundary phases."""
+    torch = require_gpu()
+    s = ragged_system(nonlocal_part=False, n_states=6)
+    k = np.array([0.25, 0.5, -0.75])
+    ctx, v = _ctx_with_veff(torch, s, 31)
+    try:
+        Z = _rand_Z(s, 5, 32)
+        X = _to_block(torch, Z)
+        Y = torch.empty_like(X)
+        ctx.apply_H_k(k, X, Y)
+        assert rel_err(_from_block(Y, s.nd), kpoints.apply_H_k(s, v, [], Z, k)) <= 1e-12
+        lo, hi = ctx.spectrum_bounds_k(k)
+        lo_r, hi_r = kpoints.spectrum_bounds_k(s, v, [])
+        assert abs(lo - lo_r) <= 1e-10 and abs(hi - hi_r) <= 1e-10
+        Wk = torch.empty_like(X)
+        ctx.chebyshev_filter_k(k, X, Wk, 5, lo + 0.3 * (hi - lo), hi, lo)
+        ref = kpoints.chebyshev_filter_k(s, v, [], Z, k, 5, lo + 0.3 * (hi - lo), hi, lo)
+        assert rel_err(_from_block(X, s.nd), ref) <= 1e-10
+    finally:
+        ctx.close()
+
+
 def test_padded_blocks_take_the_per_point_kernel():
     """With ldx > 2 N_d the Bloch step runs the per-point kernel (the
     unpadded path reuses the Gamma local sweep): same results."""
