@@ -84,6 +84,66 @@ def cpu_baseline(system, ncols: int, degree: int, bounds):
     }
 
 
+def oracle_timing():
+    """The CPU oracle's step times on this host: H x, one filter call, one
+    Rayleigh-Ritz and one SCF iteration at config 1 (whole problem) and at
+    config 2 (a 40-column slice, scaled linearly in the columns for the
+    filter and H x and quadratically for the Rayleigh-Ritz products; the
+    scaled figures are labelled), once on one BLAS thread and once on all."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    import workloads as W
+    from oracle import atoms, chefsi, hamiltonian, scf
+
+    def timed(f):
+        t0 = time.perf_counter()
+        f()
+        return time.perf_counter() - t0
+
+    out = {"host_cpu_count": os.cpu_count(),
+           "blas": [{k: i.get(k) for k in ("internal_api", "num_threads")} for i in threadpool_info()]}
+    for threads in (1, None):
+        key = "one_thread" if threads == 1 else "all_threads"
+        rec = {}
+        with threadpool_limits(limits=threads):
+            s1 = W.config1(0)
+            st1 = scf.setup(s1)
+            X1 = W.initial_orbitals(s1.nd, s1.n_states, 0)
+            v1 = np.random.default_rng(5).uniform(-1, 1, s1.nd)
+            lo, hi = hamiltonian.spectrum_bounds(s1, v1, st1.projs)
+            a = lo + 0.3 * (hi - lo)
+            rec["cfg1"] = {
+                "apply_H_s": timed(lambda: hamiltonian.apply_H(s1, v1, st1.projs, X1)),
+                "filter_s": timed(lambda: chefsi.chebyshev_filter(s1, v1, st1.projs, X1, s1.cheb_degree, a, hi, lo)),
+                "rayleigh_ritz_s": timed(lambda: chefsi.rayleigh_ritz(s1, v1, st1.projs, X1)),
+            }
+            stamps = []
+            scf.scf(s1, X1, max_iter=3, tol=0.0, st=st1, callback=lambda r: stamps.append(time.perf_counter()))
+            rec["cfg1"]["scf_step_s"] = stamps[2] - stamps[1]
+            s2 = W.config2(0)
+            projs2 = atoms.projectors(s2)
+            X2 = W.initial_orbitals(s2.nd, 40, 7)
+            v2 = np.random.default_rng(6).uniform(-1, 1, s2.nd)
+            lo2, hi2 = hamiltonian.spectrum_bounds(s2, v2, projs2)
+            a2 = lo2 + 0.3 * (hi2 - lo2)
+            t_h = timed(lambda: hamiltonian.apply_H(s2, v2, projs2, X2))
+            t_f = timed(lambda: chefsi.chebyshev_filter(s2, v2, projs2, X2, s2.cheb_degree, a2, hi2, lo2))
+            t_r = timed(lambda: chefsi.rayleigh_ritz(s2, v2, projs2, X2))
+            f = s2.n_states / 40.0
+            rec["cfg2_40_columns"] = {"apply_H_s": t_h, "filter_s": t_f, "rayleigh_ritz_s": t_r}
+            print(f"oracle timing ({key}): cfg1 step {rec['cfg1']['scf_step_s']:.3f} s, cfg2 40-column filter "
+                  f"{t_f:.1f} s", file=sys.stderr, flush=True)
+            rec["cfg2_scaled_to_260_columns"] = {
+                "apply_H_s": t_h * f, "filter_s": t_f * f,
+                "rayleigh_ritz_s_lower": t_r * f, "rayleigh_ritz_s_upper": t_r * f * f,
+                "scf_step_s_estimate": t_f * f + t_r * f * f,
+                "note": "scaled from the 40-column slice: filter and H x linear in the columns, the Rayleigh-Ritz "
+                        "between linear (H x) and quadratic (Gram and rotation products)"}
+        out[key] = rec
+    return out
+
+
 def traffic_probe(system, prec):
     """One degree-3 Chebyshev filter (one first sweep, two later sweeps) of
     the full block, then an elementwise copy of COPY_BYTES bytes; each step is
@@ -213,6 +273,8 @@ def main():
     ap.add_argument("--no-cnn", action="store_true", help="skip the warm-start network measurement")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the converged FP32-vs-FP64 comparison on the workload")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time only the CPU oracle (config 1 whole, config 2 on a column slice) and print it")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only one degree-3 filter of the workload and a plain copy of known size "
                          "(the program profiled with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
@@ -222,6 +284,10 @@ def main():
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1"}))
         sys.exit(2)
+
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()))
+        return
 
     import numpy as np
     import torch
