@@ -185,8 +185,16 @@ def fp32_accuracy(system, tol64=1e-7, tol32=1e-6, max_iter=200):
 
     X0 = W.initial_orbitals(system.nd, system.n_states, system.seed)
     t0 = time.perf_counter()
-    r64 = run_scf(system, X0, prec="fp64", max_iter=max_iter, tol=tol64)
-    r32 = run_scf(system, X0, prec="fp32", max_iter=max_iter, tol=tol32, final_fp64_rr=True)
+
+    def progress(tag):
+        def cb(rep):
+            if rep["iter"] % 10 == 0:
+                print(f"accuracy run {tag}: iteration {rep['iter']}, residual {rep['residual']:.2e}",
+                      file=sys.stderr, flush=True)
+        return cb
+    r64 = run_scf(system, X0, prec="fp64", max_iter=max_iter, tol=tol64, callback=progress("fp64"))
+    r32 = run_scf(system, X0, prec="fp32", max_iter=max_iter, tol=tol32, final_fp64_rr=True,
+                  callback=progress("fp32"))
     torch.cuda.synchronize()
     f64 = r64["history"][-1]["free_energy"] / system.n_atoms
     f32 = r32["final"]["free_energy"] / system.n_atoms
