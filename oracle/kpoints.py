@@ -186,8 +186,9 @@ def scf_k(sys, kpts, wk, Z0s, rho0=None, max_iter: int = 50, tol: float = 1e-10,
           degree: int = None, beta: float = None):
     """The SCF schedule of ``scf.scf`` with one CheFSI block per k-point
     (filter bounds tracked per k), occupations with one Fermi level over all
-    k, and the k-weighted density; linear mixing (with the Kerker-type
-    preconditioner when sys.kerker_q0 > 0).  Parity unpinned away from the
+    k, and the k-weighted density; linear mixing with the Kerker-type
+    preconditioner when sys.kerker_q0 > 0, or periodic Pulay mixing when
+    sys.pulay_history > 0 (as in ``scf.scf``).  Parity unpinned away from the
     fixed point, as for ``scf.scf``."""
     st = st or scf.setup(sys)
     n_first = sys.n_first if n_first is None else n_first
@@ -198,6 +199,10 @@ def scf_k(sys, kpts, wk, Z0s, rho0=None, max_iter: int = 50, tol: float = 1e-10,
     Xs = [np.array(Z, dtype=np.complex128) for Z in Z0s]
     pk = [projectors_k(sys, k) for k in kpts]
     ab = [None] * len(kpts)
+    pulay = None
+    if getattr(sys, "pulay_history", 0) > 0:
+        pulay = scf.PeriodicPulay(sys.pulay_history, sys.pulay_period, beta, sys, getattr(sys, "kerker_q0", 0.0),
+                                  bool(getattr(sys, "pulay_restart", 0)))
     hist = []
     for it in range(max_iter):
         phi, exc, vxc, veff = scf.potential(sys, st, rho_in)
@@ -234,7 +239,10 @@ def scf_k(sys, kpts, wk, Z0s, rho0=None, max_iter: int = 50, tol: float = 1e-10,
         res = float(np.linalg.norm(rho_out - rho_in) / np.linalg.norm(rho_out))
         hist.append(dict(it=it, residual=res, mu=mu, lam=[l.copy() for l in lams], **terms))
         rho_prev = rho_in
-        rho_in = scf.mix(rho_in, rho_out, beta, sys, getattr(sys, "kerker_q0", 0.0))
+        if pulay is not None:
+            rho_in = pulay.step(rho_in, rho_out - rho_in)
+        else:
+            rho_in = scf.mix(rho_in, rho_out, beta, sys, getattr(sys, "kerker_q0", 0.0))
         if res < tol:
             break
     return dict(X=Xs, lam=lams, g=gs, mu=mu, rho_in=rho_prev, rho_out=rho_out, history=hist)

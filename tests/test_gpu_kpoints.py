@@ -251,3 +251,26 @@ def test_filter_k_fp32_and_k_point_scf_fp32():
     assert h[-1]["residual"] < 1e-5
     assert dF <= 1e-5
     out["ctx"].close()
+
+
+def test_k_point_scf_with_pulay_and_kerker_matches_oracle():
+    """Two k-points with restarted periodic Pulay mixing (history 7, period
+    2) and the Kerker-type preconditioner: trajectory and fixed point
+    against the oracle."""
+    require_gpu()
+    from dataclasses import replace
+    from paper_2005_10431_amd.driver import run_scf_k
+    s = replace(W.tiny_system(n=(14, 16, 18), n_states=8), pulay_history=7, pulay_period=2, pulay_restart=1,
+                kerker_q0=1.0)
+    kpts, wk = W.monkhorst_pack(s.L, (2, 1, 1))
+    Z0 = [W.initial_orbitals_k(s.nd, s.n_states, s.seed, q) for q in range(len(kpts))]
+    ref = kpoints.scf_k(s, kpts, wk, Z0, max_iter=200, tol=1e-10)
+    out = run_scf_k(s, kpts, wk, Z0, max_iter=200, tol=1e-10)
+    h, hr = out["history"], ref["history"]
+    log(f"k-point Pulay SCF: {len(h)} iterations (oracle {len(hr)})")
+    for k in range(min(8, len(hr))):
+        assert abs(h[k]["free_energy"] - hr[k]["free"]) <= 1e-8, k
+    assert h[-1]["residual"] < 1e-10
+    assert abs(h[-1]["free_energy"] - hr[-1]["free"]) <= 1e-9
+    assert abs(len(h) - len(hr)) <= 2
+    out["ctx"].close()

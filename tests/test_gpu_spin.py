@@ -211,3 +211,24 @@ def test_spin_scf_fp32_blocks_reach_the_fp64_fixed_point():
     assert dF <= 1e-5
     assert abs(h[-1]["magnetization"] - ref["magnetization"]) <= 1e-4
     out["ctx"].close()
+
+
+def test_spin_scf_with_pulay_matches_oracle():
+    """cfg1s with restarted periodic Pulay mixing over the doubled vector
+    (history 7, period 2): trajectory, fixed point and moment against the
+    oracle's spin SCF with the same mixing."""
+    require_gpu()
+    from paper_2005_10431_amd.driver import run_scf_spin
+    s = replace(W.config1_spin(0), pulay_history=7, pulay_period=2, pulay_restart=1)
+    Xu, Xd = W.initial_orbitals_spin(s.nd, s.n_states, s.seed)
+    r = scf.scf_spin(s, Xu, Xd, max_iter=300, tol=1e-10)
+    out = run_scf_spin(s, (Xu, Xd), max_iter=300, tol=1e-10)
+    h = out["history"]
+    log(f"cfg1s Pulay: {len(h)} iterations (oracle {len(r.history)}), M {h[-1]['magnetization']:.8f}")
+    for k in range(min(10, len(r.history))):
+        assert abs(h[k]["free_energy"] - r.history[k]["free"]) <= 1e-8, k
+    assert h[-1]["residual"] < 1e-10
+    assert abs(h[-1]["free_energy"] - r.history[-1]["free"]) <= 1e-9
+    assert abs(h[-1]["magnetization"] - r.history[-1]["magnetization"]) <= 1e-8
+    assert abs(len(h) - len(r.history)) <= 2
+    out["ctx"].close()
