@@ -797,6 +797,8 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     c->nl_ty = choose_sweep_ty(c->nx, c->ny, 512);
     if (const char* e = std::getenv("SPARC_GPU_DEBUG")) c->debug = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_EIG")) c->eig_jacobi = std::string(e) == "jacobi";
+    if (const char* e = std::getenv("SPARC_GPU_TRD_MULTI_MIN")) c->trd_multi_min = std::atoi(e);
+    if (const char* e = std::getenv("SPARC_GPU_TRD_TAIL")) c->trd_tail = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("SPARC_GPU_SPLIT_FILTER")) c->split_filter = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_PROJ_NB")) c->proj_nb = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_GEMM_TILE")) c->gemm_tile = std::atoi(e);

@@ -119,6 +119,104 @@ __device__ inline void trd_pass(double* A, int N, int lo, const double* v, const
     }
 }
 
+// Steps i0, i0+1, ..., N-3 of the reduction, then the last diagonal and
+// subdiagonal entries.  On entry v (LDS, global row index) holds reflector
+// i0 with factor tau_i, and A[i0+1:, i0+1:] is updated through step i0-1.
+__device__ inline void trd_run(double* A, int N, int i0, double* v, double* w, double* vn, double* part,
+                               double tau_i, double* d, double* e, double* tau, double* red, double* sbeta) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    TrdLayout L = trd_layout(N - (i0 + 1), nt);
+    trd_pass<false>(A, N, i0 + 1, v, w, v, part, L);
+    __syncthreads();
+    for (int i = i0; i + 2 < N; ++i) {
+        // p = tau A22 v from the partial sums, rows g >= i+1
+        const int lo = i + 1;
+        double pv = 0.0;
+        for (int lr = t; lr < L.rows; lr += nt) {
+            double acc = 0.0;
+            for (int q = 0; q < L.G; ++q) acc += part[q * L.R + lr];
+            const double p = tau_i * acc;
+            w[lo + lr] = p;
+            pv += p * v[lo + lr];
+        }
+        pv = block_sum(pv, red);
+        const double k2 = 0.5 * tau_i * pv;
+        for (int g = lo + t; g < N; g += nt) w[g] -= k2 * v[g];
+        __syncthreads();
+        // reflector i is stored below the subdiagonal of column i
+        {
+            double* x = A + (long)i * N;
+            for (int r = i + 2 + t; r < N; r += nt) x[r] = v[r];
+        }
+        const bool more = (i + 1) + 2 < N;
+        const int h = i + 1;
+        double* col = A + (long)h * N;
+        const double vh = v[h], wh = w[h];
+        double tau_n = 0.0;
+        if (more) {
+            // column i+1 (rows >= i+1) is updated in registers and yields
+            // the next reflector directly: its diagonal is d[i+1], row
+            // i+2 is alpha, rows >= i+3 the rest of x
+            double cv[4];  // N <= 4 nt
+            double ss = 0.0;
+            int q = 0;
+            for (int g = h + t; g < N; g += nt, ++q) {
+                const double val = col[g] - (v[g] * wh + w[g] * vh);
+                cv[q] = val;
+                if (g == h) d[h] = val;
+                if (g == h + 1) *sbeta = val;  // alpha, read after the reduction's barriers
+                if (g >= h + 2) ss += val * val;
+            }
+            const double xnorm2 = block_sum(ss, red);
+            const double alpha = *sbeta;
+            double bn = alpha;
+            if (xnorm2 > 0.0) {
+                bn = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+                tau_n = (bn - alpha) / bn;
+            }
+            const double scal = (xnorm2 > 0.0) ? 1.0 / (alpha - bn) : 0.0;
+            q = 0;
+            for (int g = h + t; g < N; g += nt, ++q) {
+                if (g == h + 1) {
+                    vn[g] = 1.0;
+                } else if (g >= h + 2) {
+                    const double vv = cv[q] * scal;
+                    vn[g] = vv;
+                    col[g] = vv;
+                }
+            }
+            if (t == 0) {
+                e[h] = bn;
+                tau[h] = tau_n;
+            }
+        } else {
+            // last step: the updated column gives the final d and e
+            for (int g = h + t; g < N; g += nt) col[g] -= v[g] * wh + w[g] * vh;
+            for (int g = t; g < N; g += nt) vn[g] = 0.0;
+        }
+        __syncthreads();
+        L = trd_layout(N - (i + 2), nt);
+        trd_pass<true>(A, N, i + 2, v, w, vn, part, L);
+        __syncthreads();
+        if (!more) break;
+        double* tmp = v;
+        v = vn;
+        vn = tmp;
+        tau_i = tau_n;
+    }
+}
+
+__device__ inline void trd_final(const double* A, int N, double* d, double* e, double* tau) {
+    if (threadIdx.x == 0) {
+        if (N >= 2) {
+            d[N - 2] = A[(N - 2) + (long)(N - 2) * N];
+            e[N - 2] = A[(N - 1) + (long)(N - 2) * N];
+            tau[N - 2] = 0.0;
+        }
+        d[N - 1] = A[(N - 1) + (long)(N - 1) * N];
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_sytrd(double* A, int N, double* d, double* e, double* tau, double* shift) {
     extern __shared__ double sh[];
     double* v = sh;             // N: current reflector (global row index)
@@ -138,101 +236,251 @@ __global__ __launch_bounds__(1024) void k_sytrd(double* A, int N, double* d, dou
     __syncthreads();
     if (N >= 3) {
         double beta;
-        double tau_i = trd_householder(A, N, 0, v, red, &beta);
+        const double tau0 = trd_householder(A, N, 0, v, red, &beta);
         if (t == 0) {
             d[0] = A[0];
             e[0] = beta;
-            tau[0] = tau_i;
+            tau[0] = tau0;
         }
         __syncthreads();
-        TrdLayout L = trd_layout(N - 1, nt);
-        trd_pass<false>(A, N, 1, v, w, v, part, L);
-        __syncthreads();
-        for (int i = 0; i + 2 < N; ++i) {
-            // p = tau A22 v from the partial sums, rows g >= i+1
-            const int lo = i + 1;
-            double pv = 0.0;
-            for (int lr = t; lr < L.rows; lr += nt) {
-                double acc = 0.0;
-                for (int q = 0; q < L.G; ++q) acc += part[q * L.R + lr];
-                const double p = tau_i * acc;
-                w[lo + lr] = p;
-                pv += p * v[lo + lr];
-            }
-            pv = block_sum(pv, red);
-            const double k2 = 0.5 * tau_i * pv;
-            for (int g = lo + t; g < N; g += nt) w[g] -= k2 * v[g];
-            __syncthreads();
-            // reflector i is stored below the subdiagonal of column i
-            {
-                double* x = A + (long)i * N;
-                for (int r = i + 2 + t; r < N; r += nt) x[r] = v[r];
-            }
-            const bool more = (i + 1) + 2 < N;
-            const int h = i + 1;
-            double* col = A + (long)h * N;
-            const double vh = v[h], wh = w[h];
-            double tau_n = 0.0;
-            if (more) {
-                // column i+1 (rows >= i+1) is updated in registers and yields
-                // the next reflector directly: its diagonal is d[i+1], row
-                // i+2 is alpha, rows >= i+3 the rest of x
-                double cv[4];  // N <= 4 nt
-                double ss = 0.0;
-                int q = 0;
-                for (int g = h + t; g < N; g += nt, ++q) {
-                    const double val = col[g] - (v[g] * wh + w[g] * vh);
-                    cv[q] = val;
-                    if (g == h) d[h] = val;
-                    if (g == h + 1) s_beta = val;  // alpha, read after the reduction's barriers
-                    if (g >= h + 2) ss += val * val;
-                }
-                const double xnorm2 = block_sum(ss, red);
-                const double alpha = s_beta;
-                double bn = alpha;
-                if (xnorm2 > 0.0) {
-                    bn = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-                    tau_n = (bn - alpha) / bn;
-                }
-                const double scal = (xnorm2 > 0.0) ? 1.0 / (alpha - bn) : 0.0;
-                q = 0;
-                for (int g = h + t; g < N; g += nt, ++q) {
-                    if (g == h + 1) {
-                        vn[g] = 1.0;
-                    } else if (g >= h + 2) {
-                        const double vv = cv[q] * scal;
-                        vn[g] = vv;
-                        col[g] = vv;
-                    }
-                }
-                if (t == 0) {
-                    e[h] = bn;
-                    tau[h] = tau_n;
-                }
-            } else {
-                // last step: the updated column gives the final d and e
-                for (int g = h + t; g < N; g += nt) col[g] -= v[g] * wh + w[g] * vh;
-                for (int g = t; g < N; g += nt) vn[g] = 0.0;
-            }
-            __syncthreads();
-            L = trd_layout(N - (i + 2), nt);
-            trd_pass<true>(A, N, i + 2, v, w, vn, part, L);
-            __syncthreads();
-            if (!more) break;
-            double* tmp = v;
-            v = vn;
-            vn = tmp;
-            tau_i = tau_n;
-        }
+        trd_run(A, N, 0, v, w, vn, part, tau0, d, e, tau, red, &s_beta);
     }
+    trd_final(A, N, d, e, tau);
+}
+
+// The last steps of the many-workgroup reduction, from step i0 on, in one
+// workgroup: vg holds reflector i0 (global row index), sc[i0 & 1] its tau.
+__global__ __launch_bounds__(1024) void k_sytrd_tail(double* A, int N, int i0, const double* __restrict__ vg,
+                                                     const double* __restrict__ sc, double* d, double* e,
+                                                     double* tau) {
+    extern __shared__ double sh[];
+    double* v = sh;
+    double* w = sh + N;
+    double* vn = sh + 2 * N;
+    double* part = sh + 3 * N;
+    __shared__ double red[16];
+    __shared__ double s_beta;
+    for (int r = i0 + 1 + threadIdx.x; r < N; r += blockDim.x) v[r] = vg[r];
+    const double tau_i = sc[i0 & 1];
+    __syncthreads();
+    trd_run(A, N, i0, v, w, vn, part, tau_i, d, e, tau, red, &s_beta);
+    trd_final(A, N, d, e, tau);
+}
+
+// ---- the same reduction over many workgroups (large N) ---------------------
+// Each step is two launches: one workgroup turns the per-block partial
+// products of the previous pass into w, stores the reflector and forms the
+// next reflector from the updated next column (as k_sytrd does); then a grid
+// of (64-row x 128-column) tiles applies the rank-2 update to the trailing
+// matrix and forms the partial products with the next reflector, one
+// partial per (column tile, row), summed in tile order by the next step.
+
+constexpr int kTrdRB = 64;   // rows per pass workgroup (one wave's lanes)
+constexpr int kTrdCB = 128;  // columns per pass workgroup
+constexpr int kTrdCG = 16;  // waves per pass workgroup, each a column stride
+constexpr int kTrdCW = kTrdCB / kTrdCG;  // columns per wave
+
+__global__ __launch_bounds__(1024) void k_trd_first(double* A, int N, double* d, double* e, double* tau,
+                                                    double* shift, double* v, double* sc) {
+    __shared__ double red[16];
+    const int t = threadIdx.x, nt = blockDim.x;
+    double tr = 0.0;
+    for (int i = t; i < N; i += nt) tr += A[i + (long)i * N];
+    const double sigma = block_sum(tr, red) / N;
+    __syncthreads();
+    for (int i = t; i < N; i += nt) A[i + (long)i * N] -= sigma;
+    __syncthreads();
+    double beta;
+    const double tau0 = trd_householder(A, N, 0, v, red, &beta);
     if (t == 0) {
-        if (N >= 2) {
-            d[N - 2] = A[(N - 2) + (long)(N - 2) * N];
-            e[N - 2] = A[(N - 1) + (long)(N - 2) * N];
-            tau[N - 2] = 0.0;
-        }
-        d[N - 1] = A[(N - 1) + (long)(N - 1) * N];
+        shift[0] = sigma;
+        d[0] = A[0];
+        e[0] = beta;
+        tau[0] = tau0;
+        sc[0] = tau0;
     }
+}
+
+// Rows [lo, N) x columns of tile blockIdx.x: optional rank-2 update
+// A -= v w^T + w v^T, and part[tile][g] = sum over the tile's columns of
+// A[g, h] vn[h] (wave partials summed in wave order).
+template <bool UPDATE>
+__global__ __launch_bounds__(1024) void k_trd_pass_multi(double* A, int N, int lo, const double* __restrict__ v,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ vn, double* __restrict__ part) {
+    __shared__ double red[kTrdCG][kTrdRB];
+    const int lane = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    const int g = lo + blockIdx.y * kTrdRB + lane;
+    const int hb = lo + blockIdx.x * kTrdCB;
+    const int he = min(N, hb + kTrdCB);
+    double acc = 0.0;
+    if (g < N) {
+        const double vg = UPDATE ? v[g] : 0.0, wg = UPDATE ? w[g] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kTrdCW; ++j) {
+            const int h = hb + cg + j * kTrdCG;
+            if (h < he) {
+                double* p = A + g + (long)h * N;
+                double x = *p;
+                if (UPDATE) {
+                    x -= vg * w[h] + wg * v[h];
+                    *p = x;
+                }
+                acc += x * vn[h];
+            }
+        }
+    }
+    red[cg][lane] = acc;
+    __syncthreads();
+    if (cg == 0 && g < N) {
+        double sum = 0.0;
+        for (int q = 0; q < kTrdCG; ++q) sum += red[q][lane];
+        part[(long)blockIdx.x * N + g] = sum;
+    }
+}
+
+// Step i: p = tau A22 v from the nbp partial tiles, w = p - (tau/2)(p.v) v,
+// reflector i into column i, column i+1 updated and turned into the next
+// reflector vn (or, on the last step, just updated).  sc[i & 1] holds the
+// tau of v, sc[(i + 1) & 1] receives that of vn.
+__global__ __launch_bounds__(1024) void k_trd_step(double* A, int N, int i, int nbp, const double* __restrict__ part,
+                                                   const double* __restrict__ v, double* __restrict__ w,
+                                                   double* __restrict__ vn, double* d, double* e, double* tau,
+                                                   double* sc) {
+    __shared__ double red[16];
+    __shared__ double s_wh, s_beta;
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int h = i + 1;  // first row of the trailing block, and the next column
+    const double tau_i = sc[i & 1];
+    double* col = A + (long)h * N;
+    double* x = A + (long)i * N;
+    // rows g = h + t + q nt (N <= 4 nt): every load up front
+    double vg[4], wg[4], cg[4];
+    double pv = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int g = h + t + q * nt;
+        vg[q] = wg[q] = cg[q] = 0.0;
+        if (g < N) {
+            vg[q] = v[g];
+            cg[q] = col[g];
+            double acc = 0.0;
+            for (int b = 0; b < nbp; ++b) acc += part[(long)b * N + g];
+            wg[q] = tau_i * acc;
+            pv += wg[q] * vg[q];
+            if (g >= i + 2) x[g] = vg[q];  // reflector i below the subdiagonal of column i
+        }
+    }
+    pv = block_sum(pv, red);
+    const double k2 = 0.5 * tau_i * pv;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int g = h + t + q * nt;
+        if (g < N) {
+            wg[q] -= k2 * vg[q];
+            w[g] = wg[q];
+            if (g == h) s_wh = wg[q];
+        }
+    }
+    __syncthreads();
+    const double wh = s_wh, vh = v[h];
+    if (h + 2 < N) {
+        double ss = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int g = h + t + q * nt;
+            if (g < N) {
+                const double val = cg[q] - (vg[q] * wh + wg[q] * vh);
+                cg[q] = val;
+                if (g == h) d[h] = val;
+                if (g == h + 1) s_beta = val;
+                if (g >= h + 2) ss += val * val;
+            }
+        }
+        const double xnorm2 = block_sum(ss, red);
+        const double alpha = s_beta;
+        double bn = alpha, tau_n = 0.0;
+        if (xnorm2 > 0.0) {
+            bn = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+            tau_n = (bn - alpha) / bn;
+        }
+        const double scal = (xnorm2 > 0.0) ? 1.0 / (alpha - bn) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int g = h + t + q * nt;
+            if (g == h + 1) {
+                vn[g] = 1.0;
+            } else if (g >= h + 2 && g < N) {
+                const double vv = cg[q] * scal;
+                vn[g] = vv;
+                col[g] = vv;
+            }
+        }
+        if (t == 0) {
+            e[h] = bn;
+            tau[h] = tau_n;
+            sc[(i + 1) & 1] = tau_n;
+        }
+    } else {
+        // last step: the updated column gives the final d and e
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int g = h + t + q * nt;
+            if (g < N) col[g] = cg[q] - (vg[q] * wh + wg[q] * vh);
+        }
+        for (int g = t; g < N; g += nt) vn[g] = 0.0;
+    }
+}
+
+__global__ void k_trd_final(const double* A, int N, double* d, double* e, double* tau) {
+    trd_final(A, N, d, e, tau);
+}
+
+// The k_sytrd reduction with the trailing passes spread over the chip; once
+// the trailing matrix has at most `tail` rows, one workgroup (k_sytrd_tail)
+// takes the remaining steps.  scratch: 3 N + 8 + ceil(N / kTrdCB) N doubles.
+// N >= 3.
+static sparc_status sytrd_multi(sparc_gpu_ctx c, double* A, int N, int tail, double* d, double* e, double* tau,
+                                double* shift, double* scratch) {
+    double* v = scratch;
+    double* w = v + N;
+    double* vn = w + N;
+    double* sc = vn + N;
+    double* part = sc + 8;
+    const int threads = std::min(1024, std::max(64, div_up(N, 64) * 64));
+    k_trd_first<<<1, threads, 0, c->stream>>>(A, N, d, e, tau, shift, v, sc);
+    SG_CHECK_LAUNCH(c);
+    if (N - 1 > tail) {
+        const int m = N - 1;
+        k_trd_pass_multi<false><<<dim3(div_up(m, kTrdCB), div_up(m, kTrdRB)), 64 * kTrdCG, 0, c->stream>>>(A, N, 1, v, w, v,
+                                                                                                  part);
+        SG_CHECK_LAUNCH(c);
+    }
+    int i = 0;
+    bool done = false;
+    for (; i + 2 < N; ++i) {
+        if (N - (i + 1) <= tail) break;
+        const int nbp = div_up(N - (i + 1), kTrdCB);
+        k_trd_step<<<1, threads, 0, c->stream>>>(A, N, i, nbp, part, v, w, vn, d, e, tau, sc);
+        const int lo = i + 2, m = N - lo;
+        if (m > 0)
+            k_trd_pass_multi<true><<<dim3(div_up(m, kTrdCB), div_up(m, kTrdRB)), 64 * kTrdCG, 0, c->stream>>>(A, N, lo, v, w,
+                                                                                                     vn, part);
+        SG_CHECK_LAUNCH(c);
+        if (i + 3 >= N) {
+            done = true;
+            break;
+        }
+        std::swap(v, vn);
+    }
+    if (done) {
+        k_trd_final<<<1, 64, 0, c->stream>>>(A, N, d, e, tau);
+    } else {
+        const size_t lds = (3 * (size_t)N + std::max(1024, N + 64)) * sizeof(double);
+        k_sytrd_tail<<<1, threads, lds, c->stream>>>(A, N, i, v, sc, d, e, tau);
+    }
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
 }
 
 // Number of eigenvalues of T smaller than x (Sturm count of the LDL^T
@@ -627,9 +875,15 @@ sparc_status dense_eigh_tridiag(sparc_gpu_ctx c, double* A, int N, double* V, do
     double* stw = zt + (size_t)N * N;        // 5 N nthr
     const int threads = std::min(1024, std::max(64, div_up(N, 64) * 64));
     int slot = prof_begin(c, PK_EIG_TRD);
-    const size_t trd_lds = (3 * (size_t)N + std::max(1024, N + 64)) * sizeof(double);
-    k_sytrd<<<1, threads, trd_lds, c->stream>>>(A, N, d, e, tau, shift);
-    SG_CHECK_LAUNCH(c);
+    if (N >= 3 && N >= c->trd_multi_min) {
+        // zt and stw are free until the inverse iteration
+        sparc_status st = sytrd_multi(c, A, N, c->trd_tail, d, e, tau, shift, zt);
+        if (st != SPARC_OK) return st;
+    } else {
+        const size_t trd_lds = (3 * (size_t)N + std::max(1024, N + 64)) * sizeof(double);
+        k_sytrd<<<1, threads, trd_lds, c->stream>>>(A, N, d, e, tau, shift);
+        SG_CHECK_LAUNCH(c);
+    }
     prof_end(c, slot);
     slot = prof_begin(c, PK_EIG_BIS);
     k_bisect<<<N, 64, 2 * N * sizeof(double), c->stream>>>(d, e, N, shift, lamw, eig);

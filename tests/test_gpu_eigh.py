@@ -59,12 +59,14 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("case", sorted(CASES))
-def test_subspace_eigh(case):
+def _check(case, a, monkeypatch=None, trd_multi_min=None, trd_tail=None):
     torch = require_gpu()
-    a = CASES[case]()
     n = a.shape[0]
-    log("subspace_eigh", case, n)
+    log("subspace_eigh", case, n, "" if trd_multi_min is None
+        else f"multi-workgroup reduction from N={trd_multi_min}, one-workgroup tail {trd_tail}")
+    if trd_multi_min is not None:
+        monkeypatch.setenv("SPARC_GPU_TRD_MULTI_MIN", str(trd_multi_min))
+        monkeypatch.setenv("SPARC_GPU_TRD_TAIL", str(trd_tail))
     ctx = _ctx()
     Ad = to_dev(torch, a.T)           # column-major storage
     Vd = torch.zeros((n, n), dtype=torch.float64, device="cuda")
@@ -82,3 +84,22 @@ def test_subspace_eigh(case):
     assert eerr <= 1e-12
     assert res <= 1e-11
     assert orth <= 5e-11
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_subspace_eigh(case):
+    _check(case, CASES[case]())
+
+
+# The reduction to tridiagonal form spread over many workgroups (used from
+# N = 320 on by default), forced down to N = 3 so that one-tile, ragged and
+# degenerate cases run through it too, with no one-workgroup tail, a tail of
+# 20 rows (the hand-over mid-way) and the default tail of 256 rows; n1200 is
+# the cfg4 subspace size.
+@pytest.mark.parametrize("tail", [0, 20, 256])
+@pytest.mark.parametrize("case", ["n3", "n37", "n260_clustered", "graded", "block_diagonal", "identity",
+                                  "n700_random", "n1200_clustered"])
+def test_subspace_eigh_multi_workgroup_reduction(case, tail, monkeypatch):
+    a = _clustered(1200, 10) if case == "n1200_clustered" else CASES[case]()
+    _check(case, a, monkeypatch, trd_multi_min=3, trd_tail=tail)
+
