@@ -90,47 +90,106 @@ __device__ inline int floor_div(int i, int n) { return i >= 0 ? i / n : -((-i + 
 
 // Projections of NB columns on the complex projectors of one atom:
 // proj[(a ncol + col) 8 + r], r < 4: Re, r >= 4: Im of gamma_l dV <chi~_l, z>,
-// accumulated over the atom's (point, image) pairs inside rcut.
-template <typename T, int NB>
+// accumulated over the atom's (point, image) pairs inside rcut.  The pairs
+// are those of the Gamma projector tables (flat index and offset in the
+// atom's bounding box); the Gaussian, the displacements and the Bloch phase
+// exp(i k_d s_d L_d) of the image shift s_d are separable per axis and are
+// tabulated in LDS for the box, so a pair costs table reads and the gather.
+// U pairs per thread are in flight at once.
+template <typename T, int NB, int U>
 __global__ __launch_bounds__(256) void k_bloch_proj(const T* __restrict__ X, long ldx, long nd, int ncol,
+                                                   const long* __restrict__ ip_off, const int* __restrict__ ip_idx,
+                                                   const uint32_t* __restrict__ ip_box,
+                                                   const int* __restrict__ box_lo, int ext,
                                                    const double* __restrict__ pos, const double* __restrict__ gamma4,
-                                                   BlochGeom g, double dV, double* __restrict__ proj) {
-    const int a = blockIdx.x;
-    const int col0 = blockIdx.y * NB;
-    const double cx = pos[3 * a], cy = pos[3 * a + 1], cz = pos[3 * a + 2];
-    const double rcut2 = g.rcut * g.rcut;
-    const int lx = (int)ceil((cx - g.rcut) / g.h[0]), ux = (int)floor((cx + g.rcut) / g.h[0]);
-    const int ly = (int)ceil((cy - g.rcut) / g.h[1]), uy = (int)floor((cy + g.rcut) / g.h[1]);
-    const int lz = (int)ceil((cz - g.rcut) / g.h[2]), uz = (int)floor((cz + g.rcut) / g.h[2]);
-    const int nxb = ux - lx + 1, nyb = uy - ly + 1, nzb = uz - lz + 1;
-    const long tot = (long)nxb * nyb * nzb;
+                                                   const int* __restrict__ atom_order, int n_atoms, BlochGeom g,
+                                                   double dV, double* __restrict__ proj) {
+    // ex ey ez | dx dy dz | cos_x cos_y cos_z | sin_x sin_y sin_z, ext each
+    extern __shared__ double ptab[];
+    // Block b runs on XCD b % 8; each XCD takes a contiguous range of the
+    // atoms in space-filling order for one column chunk at a time, so the
+    // overlapping supports of neighbouring atoms hit in that XCD's L2.
+    const int bid = blockIdx.x;
+    const int xcd = bid % 8, slot = bid / 8;
+    const int per = (n_atoms + 7) / 8;
+    const int rank = xcd * per + slot % per;
+    const int chunk = slot / per;
+    if (rank >= n_atoms || chunk * NB >= ncol) return;
+    const int a = atom_order[rank];
+    const int col0 = chunk * NB;
+    const int nt = blockDim.x;
+    for (int q = threadIdx.x; q < 3 * ext; q += nt) {
+        const int d = q / ext, i = q - d * ext;
+        const int gi = box_lo[3 * a + d] + i;
+        const double dv = gi * g.h[d] - pos[3 * a + d];
+        ptab[q] = exp(-dv * dv * g.rc2inv);
+        ptab[3 * ext + q] = dv;
+        const int sd = floor_div(gi, d == 0 ? g.nx : (d == 1 ? g.ny : g.nz));
+        double sn, cs;
+        sincos(g.k[d] * sd * g.L[d], &sn, &cs);
+        ptab[6 * ext + q] = cs;
+        ptab[9 * ext + q] = sn;
+    }
+    __syncthreads();
+    const double* ex = ptab;
+    const double* ey = ptab + ext;
+    const double* ez = ptab + 2 * ext;
+    const double* dxt = ptab + 3 * ext;
+    const double* dyt = ptab + 4 * ext;
+    const double* dzt = ptab + 5 * ext;
+    const double* cxt = ptab + 6 * ext;
+    const double* cyt = ptab + 7 * ext;
+    const double* czt = ptab + 8 * ext;
+    const double* sxt = ptab + 9 * ext;
+    const double* syt = ptab + 10 * ext;
+    const double* szt = ptab + 11 * ext;
+    const int nb = min(NB, ncol - col0);
     double acc[NB * 8];
 #pragma unroll
     for (int q = 0; q < NB * 8; ++q) acc[q] = 0.0;
-    for (long t = threadIdx.x; t < tot; t += blockDim.x) {
-        const int i = lx + (int)(t % nxb);
-        const int j = ly + (int)((t / nxb) % nyb);
-        const int k = lz + (int)(t / ((long)nxb * nyb));
-        const double dx = i * g.h[0] - cx, dy = j * g.h[1] - cy, dz = k * g.h[2] - cz;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 > rcut2) continue;
-        const int sx = floor_div(i, g.nx), sy = floor_div(j, g.ny), sz = floor_div(k, g.nz);
-        const long p = (i - sx * g.nx) + (long)g.nx * ((j - sy * g.ny) + (long)g.ny * (k - sz * g.nz));
-        const double ex = exp(-r2 * g.rc2inv);
-        const double chi[4] = {g.N0 * ex, g.N1 * dx * ex, g.N1 * dy * ex, g.N1 * dz * ex};
-        double sn, cs;
-        sincos(g.k[0] * sx * g.L[0] + g.k[1] * sy * g.L[1] + g.k[2] * sz * g.L[2], &sn, &cs);
+    const long s0 = ip_off[a], s1 = ip_off[a + 1];
+    for (long s = s0 + threadIdx.x; s < s1; s += (long)U * nt) {
+        long idx[U];
+        uint32_t bb[U];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            if (col0 + c < ncol) {
-                const double u = (double)X[p + (long)(col0 + c) * ldx];
-                const double v = (double)X[nd + p + (long)(col0 + c) * ldx];
-                // conj(chi~) z = chi exp(+i theta) (u + i v)
-                const double zr = cs * u - sn * v, zi = sn * u + cs * v;
+        for (int u = 0; u < U; ++u) {
+            const long su = s + (long)u * nt;
+            const bool ok = su < s1;
+            idx[u] = ok ? ip_idx[su] : 0;
+            bb[u] = ok ? ip_box[su] : 0xFFFFFFFFu;
+        }
+        double xu[U][NB], xv[U][NB];
 #pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    acc[8 * c + l] += chi[l] * zr;
-                    acc[8 * c + 4 + l] += chi[l] * zi;
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const bool ok = bb[u] != 0xFFFFFFFFu && c < nb;
+                const long o = idx[u] + (long)(col0 + c) * ldx;
+                xu[u][c] = ok ? (double)X[o] : 0.0;
+                xv[u][c] = ok ? (double)X[nd + o] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (bb[u] == 0xFFFFFFFFu) break;
+            const uint32_t b = bb[u];
+            const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
+            const double e = ex[bx] * ey[by] * ez[bz];
+            const double chi[4] = {g.N0 * e, g.N1 * dxt[bx] * e, g.N1 * dyt[by] * e, g.N1 * dzt[bz] * e};
+            // exp(i (theta_x + theta_y + theta_z)) as a product of the axis factors
+            const double cxy = cxt[bx] * cyt[by] - sxt[bx] * syt[by];
+            const double sxy = sxt[bx] * cyt[by] + cxt[bx] * syt[by];
+            const double cs = cxy * czt[bz] - sxy * szt[bz];
+            const double sn = sxy * czt[bz] + cxy * szt[bz];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                if (c < nb) {
+                    // conj(chi~) z = chi exp(+i theta) (u + i v)
+                    const double zr = cs * xu[u][c] - sn * xv[u][c], zi = sn * xu[u][c] + cs * xv[u][c];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        acc[8 * c + l] += chi[l] * zr;
+                        acc[8 * c + 4 + l] += chi[l] * zi;
+                    }
                 }
             }
         }
@@ -557,8 +616,12 @@ static sparc_status bloch_step(sparc_gpu_ctx c, const T* Y, T* out, const T* pre
         proj = c->kp_proj;
         const int slot = prof_begin(c, PK_BLOCH_PROJ);
         const int n = c->n_atoms;
-        k_bloch_proj<T, kProjNB><<<dim3(n, div_up(ncol, kProjNB)), 256, 0, c->stream>>>(
-            Y, ldx, c->nd, ncol, c->force_tab, c->force_tab + 5 * n, g, c->dV, proj);
+        const int ext = std::max(1, c->nl.box_ext);
+        const int per = (n + 7) / 8;
+        k_bloch_proj<T, kProjNB, 2><<<dim3(8 * per * div_up(ncol, kProjNB)), 256, 12 * ext * sizeof(double),
+                                      c->stream>>>(Y, ldx, c->nd, ncol, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box,
+                                                   c->nl.box_lo, ext, c->force_tab, c->force_tab + 5 * n,
+                                                   c->nl.atom_order, n, g, c->dV, proj);
         SG_CHECK_LAUNCH(c);
         prof_end(c, slot);
     }

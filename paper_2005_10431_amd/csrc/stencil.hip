@@ -411,7 +411,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, NL ? 512 : 1024))) void
 // (deterministic).  chi_s = N0 e, chi_p = N1 {dx, dy, dz} e with
 // e = ex(x) ey(y) ez(z) from per-axis tables of the atom's bounding box,
 // evaluated in LDS (no per-point projector table is read).
-template <typename T, int NB>
+template <typename T, int NB, int U>
 __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, long ldx, int ncol,
                                                     const long* __restrict__ ip_off, const int* __restrict__ ip_idx,
                                                     const uint32_t* __restrict__ ip_box, const int* __restrict__ box_lo,
@@ -451,21 +451,42 @@ __global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, lon
     for (int n = 0; n < NB; ++n)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[n][k] = 0.0;
+    // U points per thread are in flight at once: their indices, then their
+    // X values, are loaded before any is accumulated (each thread still
+    // accumulates its points s0 + t, s0 + t + nt, ... in increasing order).
     const long s0 = ip_off[a], s1 = ip_off[a + 1];
-    for (long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-        const long idx = ip_idx[s];
-        const uint32_t b = ip_box[s];
-        const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
-        const double e = ex[bx] * ey[by] * ez[bz];
-        const double c0 = N0 * e, c1 = N1 * dxt[bx] * e, c2 = N1 * dyt[by] * e, c3 = N1 * dzt[bz] * e;
+    const int nt = blockDim.x;
+    for (long s = s0 + threadIdx.x; s < s1; s += (long)U * nt) {
+        long idx[U];
+        uint32_t bb[U];
 #pragma unroll
-        for (int n = 0; n < NB; ++n) {
-            if (n < nb) {
-                double v = (double)x[idx + (long)(n0 + n) * ldx];
-                acc[n][0] += c0 * v;
-                acc[n][1] += c1 * v;
-                acc[n][2] += c2 * v;
-                acc[n][3] += c3 * v;
+        for (int u = 0; u < U; ++u) {
+            const long su = s + (long)u * nt;
+            const bool ok = su < s1;
+            idx[u] = ok ? ip_idx[su] : 0;
+            bb[u] = ok ? ip_box[su] : 0xFFFFFFFFu;
+        }
+        double v[U][NB];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                v[u][n] = (bb[u] != 0xFFFFFFFFu && n < nb) ? (double)x[idx[u] + (long)(n0 + n) * ldx] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (bb[u] == 0xFFFFFFFFu) break;
+            const uint32_t b = bb[u];
+            const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
+            const double e = ex[bx] * ey[by] * ez[bz];
+            const double c0 = N0 * e, c1 = N1 * dxt[bx] * e, c2 = N1 * dyt[by] * e, c3 = N1 * dzt[bz] * e;
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                if (n < nb) {
+                    acc[n][0] += c0 * v[u][n];
+                    acc[n][1] += c1 * v[u][n];
+                    acc[n][2] += c2 * v[u][n];
+                    acc[n][3] += c3 * v[u][n];
+                }
             }
         }
     }
@@ -643,18 +664,23 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, 
     const double N0 = std::pow(2.0 / (pi * rc * rc), 0.75), N1 = (2.0 / rc) * N0;
     const int ext = c->nl.box_ext;
     T* Dd = D_of<T>(c) + (long)dcol0 * 4 * c->n_atoms;
-#define SG_PROJ(NBV)                                                                                               \
-    k_projection<T, NBV><<<dim3(8 * per * div_up(ncol, NBV)), 256, 6 * ext * sizeof(double), stream>>>(            \
+#define SG_PROJ(NBV, UV)                                                                                           \
+    k_projection<T, NBV, UV><<<dim3(8 * per * div_up(ncol, NBV)), 256, 6 * ext * sizeof(double), stream>>>(            \
         x, ldx, ncol, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo, ext, c->atom_pos, c->hx, c->hy, c->hz, \
         1.0 / (rc * rc), N0, N1, c->nl.gamma4, c->dV, Dd, 4 * c->n_atoms, c->nl.atom_order, c->n_atoms)
     // columns per workgroup (tuning override SPARC_GPU_PROJ_NB = 2, 4 or 8):
     // fewer accumulators per thread keep more waves in flight for the gather
+    // and points in flight per thread (SPARC_GPU_PROJ_U = 1, 2 or 4)
     if (c->proj_nb == 2)
-        SG_PROJ(2);
+        SG_PROJ(2, 4);
     else if (c->proj_nb == 8)
-        SG_PROJ(8);
+        SG_PROJ(8, 2);
+    else if (c->proj_u == 1)
+        SG_PROJ(4, 1);
+    else if (c->proj_u == 4)
+        SG_PROJ(4, 4);
     else
-        SG_PROJ(4);
+        SG_PROJ(4, 2);
 #undef SG_PROJ
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot, stream);
