@@ -670,14 +670,16 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, 
         1.0 / (rc * rc), N0, N1, c->nl.gamma4, c->dV, Dd, 4 * c->n_atoms, c->nl.atom_order, c->n_atoms)
     // columns per workgroup (tuning override SPARC_GPU_PROJ_NB = 2, 4 or 8):
     // fewer accumulators per thread keep more waves in flight for the gather
-    // and points in flight per thread (SPARC_GPU_PROJ_U = 1, 2 or 4)
+    // and points in flight per thread (SPARC_GPU_PROJ_U = 1, 2 or 4; by
+    // default 2 in FP64 and 1 in FP32, the faster of each on cfg2)
+    const int pu = c->proj_u > 0 ? c->proj_u : (sizeof(T) == 8 ? 2 : 1);
     if (c->proj_nb == 2)
         SG_PROJ(2, 4);
     else if (c->proj_nb == 8)
         SG_PROJ(8, 2);
-    else if (c->proj_u == 1)
+    else if (pu == 1)
         SG_PROJ(4, 1);
-    else if (c->proj_u == 4)
+    else if (pu == 4)
         SG_PROJ(4, 4);
     else
         SG_PROJ(4, 2);

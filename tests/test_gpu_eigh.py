@@ -56,6 +56,7 @@ CASES = {
     "identity": lambda: np.eye(33),
     "graded": lambda: _with_spectrum(np.geomspace(1e-8, 1.0, 64), 8),
     "n700_random": lambda: _random_sym(700, 9),
+    "n4096_random": lambda: _random_sym(4096, 11),   # the largest N the library accepts
 }
 
 
