@@ -276,6 +276,16 @@ def test_argument_errors():
     short = torch.zeros((4, s.nd - 1), dtype=torch.float64, device="cuda")
     with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
         ctx.apply_H(short, torch.zeros_like(short))    # ldx < N_d
+    # occupations: the electrons must fit in the states (N_e <= 2 ncol)
+    ncol = int(s.n_electrons // 2) - 1
+    assert ncol >= 1
+    eig = torch.linspace(-1.0, 1.0, ncol, dtype=torch.float64, device="cuda")
+    occ = torch.zeros_like(eig)
+    with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
+        ctx.occupations(eig, occ)
+    empty = torch.zeros(0, dtype=torch.float64, device="cuda")
+    with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
+        ctx.occupations(empty, torch.zeros_like(empty))  # no states
 
 
 def test_filter_split_over_two_streams_is_bitwise_identical(monkeypatch):
