@@ -279,6 +279,8 @@ constexpr int kTrdRB = 64;   // rows per pass workgroup (one wave's lanes)
 constexpr int kTrdCB = 128;  // columns per pass workgroup
 constexpr int kTrdCG = 16;  // waves per pass workgroup, each a column stride
 constexpr int kTrdCW = kTrdCB / kTrdCG;  // columns per wave
+static_assert(kTrdCB % kTrdCG == 0, "pass tile width must split evenly over its waves");
+static_assert(kEighMaxN <= 4 * 1024, "k_trd_step and trd_run hold at most 4 rows per thread of 1024");
 
 __global__ __launch_bounds__(1024) void k_trd_first(double* A, int N, double* d, double* e, double* tau,
                                                     double* shift, double* v, double* sc) {
