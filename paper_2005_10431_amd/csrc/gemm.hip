@@ -196,9 +196,12 @@ sparc_status gemm_tn(sparc_gpu_ctx c, int M, int N, long K, const T* A, long lda
     const int mx = std::max(M, N);
     if (mx <= 32) return gemm_tn_launch<T, 1>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
     if (mx <= 64) return gemm_tn_launch<T, 2>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
-    // 160-wide tiles (one wave per SIMD) or 128-wide (two per SIMD); tuning
-    // override SPARC_GPU_GEMM_TILE = 128 | 160
-    if (c->gemm_tile == 128) return gemm_tn_launch<T, 4>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
+    // 160-wide tiles (one wave per SIMD) or 128-wide (two per SIMD): 160 up
+    // to two tiles per edge (N <= 320, where 128 would need three), 128
+    // above, where the extra tiles keep more workgroups busy (measured at
+    // N = 520 and 1200); override SPARC_GPU_GEMM_TILE = 128 | 160
+    const int tile = c->gemm_tile > 0 ? c->gemm_tile : (mx <= 320 ? 160 : 128);
+    if (tile == 128) return gemm_tn_launch<T, 4>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
     return gemm_tn_launch<T, 5>(c, M, N, K, A, lda, B, ldb, alpha, C, ldc, symmetric);
 }
 

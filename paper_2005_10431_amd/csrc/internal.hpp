@@ -152,7 +152,7 @@ struct sparc_gpu_ctx_s {
     int split_filter = 0;       // SPARC_GPU_SPLIT_FILTER=1: filter halves on two streams
     int proj_nb = 4;            // SPARC_GPU_PROJ_NB: orbitals per projection workgroup (2, 4, 8)
     int proj_u = 0;             // SPARC_GPU_PROJ_U: ball points in flight per projection thread (1, 2, 4; 0: 2 in FP64, 1 in FP32)
-    int gemm_tile = 160;        // SPARC_GPU_GEMM_TILE: Gram/projected-H tile edge (128, 160)
+    int gemm_tile = 0;          // SPARC_GPU_GEMM_TILE: Gram/projected-H tile edge (128, 160; 0: by size)
     int gemm_nn_cols = 160;     // SPARC_GPU_GEMM_NN_COLS: rotation tile width (160, 288)
     hipGraphExec_t jac_exec = nullptr;
     int jac_N = 0;

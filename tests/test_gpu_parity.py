@@ -166,6 +166,36 @@ def test_rayleigh_ritz_fp64():
         assert abs(abs(c) - 1.0) < 1e-9, j
 
 
+@pytest.mark.parametrize("tile", ["by_size", "160"])
+def test_rayleigh_ritz_wide_block(tile, monkeypatch):
+    """400 columns: above the size from which the Gram and projected-H
+    products use 128-wide tiles (checked against the 160-wide tiles too)."""
+    torch = require_gpu()
+    ncol = 400
+    if tile != "by_size":
+        monkeypatch.setenv("SPARC_GPU_GEMM_TILE", tile)
+    s = small_images_system(n_states=ncol)
+    log("rayleigh_ritz wide block", ncol, "tile", tile)
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 16)
+    X = W.initial_orbitals(s.nd, ncol, 6)
+    Xr, lam = chefsi.rayleigh_ritz(s, v, projs, X)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    eig = torch.zeros(ncol, dtype=torch.float64, device="cuda")
+    ctx.rayleigh_ritz(Xd, eig)
+    Xg = to_np(Xd)
+    scale = max(1.0, float(np.max(np.abs(lam))))
+    np.testing.assert_allclose(to_np(eig), lam, atol=1e-10 * scale)
+    O = s.dV * Xg @ Xg.T
+    assert np.max(np.abs(O - np.eye(ncol))) < 1e-11
+    # the lowest 20 Ritz vectors span the oracle's (projector difference)
+    P = s.dV * Xg[:20].T @ Xg[:20]
+    Pr = s.dV * Xr[:20].T @ Xr[:20]
+    assert np.max(np.abs(P - Pr)) < 1e-8
+
+
 def test_rayleigh_ritz_fp32():
     torch = require_gpu()
     s = small_images_system(n_states=8)
