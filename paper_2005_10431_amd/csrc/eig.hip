@@ -452,10 +452,11 @@ static sparc_status sytrd_multi(sparc_gpu_ctx c, double* A, int N, int tail, dou
     const int threads = std::min(1024, std::max(64, div_up(N, 64) * 64));
     k_trd_first<<<1, threads, 0, c->stream>>>(A, N, d, e, tau, shift, v, sc);
     SG_CHECK_LAUNCH(c);
+    const int pass_threads = 64 * kTrdCG;
     if (N - 1 > tail) {
         const int m = N - 1;
-        k_trd_pass_multi<false><<<dim3(div_up(m, kTrdCB), div_up(m, kTrdRB)), 64 * kTrdCG, 0, c->stream>>>(A, N, 1, v, w, v,
-                                                                                                  part);
+        const dim3 grid(div_up(m, kTrdCB), div_up(m, kTrdRB));
+        k_trd_pass_multi<false><<<grid, pass_threads, 0, c->stream>>>(A, N, 1, v, w, v, part);
         SG_CHECK_LAUNCH(c);
     }
     int i = 0;
@@ -465,9 +466,10 @@ static sparc_status sytrd_multi(sparc_gpu_ctx c, double* A, int N, int tail, dou
         const int nbp = div_up(N - (i + 1), kTrdCB);
         k_trd_step<<<1, threads, 0, c->stream>>>(A, N, i, nbp, part, v, w, vn, d, e, tau, sc);
         const int lo = i + 2, m = N - lo;
-        if (m > 0)
-            k_trd_pass_multi<true><<<dim3(div_up(m, kTrdCB), div_up(m, kTrdRB)), 64 * kTrdCG, 0, c->stream>>>(A, N, lo, v, w,
-                                                                                                     vn, part);
+        if (m > 0) {
+            const dim3 grid(div_up(m, kTrdCB), div_up(m, kTrdRB));
+            k_trd_pass_multi<true><<<grid, pass_threads, 0, c->stream>>>(A, N, lo, v, w, vn, part);
+        }
         SG_CHECK_LAUNCH(c);
         if (i + 3 >= N) {
             done = true;

@@ -422,7 +422,8 @@ __global__ __launch_bounds__(256) void k_bloch_fix(const T* __restrict__ Y, T* _
         }
 }
 
-constexpr int kFixNC = 4;  // columns per thread of the correction pass: 72 VGPRs, 7 waves per SIMD (8 and 2 were slower)
+// columns per thread of the correction pass: 72 VGPRs, 7 waves per SIMD (8 and 2 were slower)
+constexpr int kFixNC = 4;
 
 template <typename T>
 __global__ void k_copy_block_k(const T* __restrict__ src, T* __restrict__ dst, long rows, int ncol, long ld) {
