@@ -799,6 +799,7 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     if (const char* e = std::getenv("SPARC_GPU_EIG")) c->eig_jacobi = std::string(e) == "jacobi";
     if (const char* e = std::getenv("SPARC_GPU_TRD_MULTI_MIN")) c->trd_multi_min = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_TRD_TAIL")) c->trd_tail = std::max(0, std::atoi(e));
+    if (const char* e = std::getenv("SPARC_GPU_CHOL_MULTI_MIN")) c->chol_multi_min = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_SPLIT_FILTER")) c->split_filter = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_PROJ_NB")) c->proj_nb = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_PROJ_U")) c->proj_u = std::atoi(e);
@@ -827,7 +828,7 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
     if (!c) return SPARC_ERR_ARG;
     hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->veff, c->veff32, c->veff_spin, c->force_tab, c->kp_off, c->kp_ent, c->kp_slot, c->kp_etab,
-                    c->kp_tile_off, c->kp_tile_atoms, c->kp_proj,
+                    c->kp_tile_off, c->kp_tile_atoms, c->kp_proj, c->chol_dorig,
                     c->kp_bounds, c->kp_wts, c->b, c->pois_ux, c->pois_uy, c->pois_uz, c->pois_inv, c->work, c->D,
                     c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,
                     c->nl.sup_chi, c->nl.gamma4, c->nl.atom_order, c->atom_pos, c->nl.pe8, c->nl.slab_cand,

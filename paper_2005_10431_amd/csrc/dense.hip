@@ -120,10 +120,122 @@ __global__ __launch_bounds__(1024) void k_cholesky(double* M, int N, int jbmax, 
     }
 }
 
+// ---- the same factorisation over many workgroups (large N) ---------------
+// Per panel: one workgroup factors it exactly as k_cholesky does, then a
+// grid of 64 x 64 tiles applies its rank-jb update to the trailing lower
+// triangle.  Each entry receives the same operations in the same order as
+// in k_cholesky, so the factor is bitwise the same.
+
+__global__ void k_chol_diag(const double* __restrict__ M, int N, double* __restrict__ dorig) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) dorig[i] = M[i + (long)i * N];
+}
+
+// Panel columns j0 .. j0 + jb - 1, rows j0 .. N - 1.  On a bad pivot the
+// panel is not written back and flag[0] is set.
+__global__ __launch_bounds__(1024) void k_chol_panel(double* M, int N, int j0, int jb,
+                                                     const double* __restrict__ dorig, int* flag) {
+    extern __shared__ double P[];  // (N - j0) rows x jb columns, row-major
+    __shared__ int bad;
+    __shared__ double piv;
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int nr = N - j0;
+    if (t == 0) bad = 0;
+    for (int q = t; q < nr * jb; q += nt) {
+        const int r = q / jb, p = q - r * jb;
+        P[q] = M[(j0 + r) + (long)(j0 + p) * N];
+    }
+    __syncthreads();
+    for (int p = 0; p < jb; ++p) {
+        for (int r = p + t; r < nr; r += nt) {
+            double v = P[r * jb + p];
+            for (int q = 0; q < p; ++q) v -= P[r * jb + q] * P[p * jb + q];
+            P[r * jb + p] = v;
+        }
+        __syncthreads();
+        if (t == 0) {
+            const double d = P[p * jb + p];
+            if (!(d > kPivotRtol * dorig[j0 + p]) || !isfinite(d)) {
+                bad = 1;
+            } else {
+                piv = sqrt(d);
+            }
+        }
+        __syncthreads();
+        if (bad) {
+            if (t == 0) flag[0] = 1;
+            return;
+        }
+        const double ljj = piv, inv = 1.0 / ljj;
+        for (int r = p + t; r < nr; r += nt) P[r * jb + p] = (r == p) ? ljj : P[r * jb + p] * inv;
+        __syncthreads();
+    }
+    for (int q = t; q < nr * jb; q += nt) {
+        const int r = q / jb, p = q - r * jb;
+        M[(j0 + r) + (long)(j0 + p) * N] = P[q];
+    }
+}
+
+constexpr int kCholT = 64;  // trailing-update tile edge
+
+// A[i][k] -= sum_q L[i][j0+q] L[k][j0+q] for k0 <= k <= i < N, tile
+// (blockIdx.x, blockIdx.y) = (row block, column block); jb <= 16.
+__global__ __launch_bounds__(256) void k_chol_update(double* M, int N, int k0, int j0, int jb) {
+    const int bi = blockIdx.x, bk = blockIdx.y;
+    if (bi < bk) return;
+    __shared__ double Li[kCholT][16], Lk[kCholT][16];
+    const int t = threadIdx.x;
+    const int i0 = k0 + bi * kCholT, c0 = k0 + bk * kCholT;
+    for (int q = t; q < kCholT * jb; q += blockDim.x) {
+        const int r = q % kCholT, p = q / kCholT;
+        const int gi = i0 + r, gk = c0 + r;
+        Li[r][p] = gi < N ? M[gi + (long)(j0 + p) * N] : 0.0;
+        Lk[r][p] = gk < N ? M[gk + (long)(j0 + p) * N] : 0.0;
+    }
+    __syncthreads();
+    const int r = t & (kCholT - 1);
+    const int i = i0 + r;
+    if (i >= N) return;
+    for (int kc = t >> 6; kc < kCholT; kc += blockDim.x / kCholT) {
+        const int k = c0 + kc;
+        if (k > i) break;
+        double* a = M + i + (long)k * N;
+        double x = *a;
+        for (int q = 0; q < jb; ++q) x -= Li[r][q] * Lk[kc][q];
+        *a = x;
+    }
+}
+
+__global__ void k_zero_upper(double* M, int N) {
+    const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= (long)N * N) return;
+    const int i = (int)(f % N), k = (int)(f / N);
+    if (k > i) M[f] = 0.0;
+}
+
 sparc_status dense_cholesky(sparc_gpu_ctx c, double* M, int N, int* flag) {
     const int slot = prof_begin(c, PK_CHOL);
     // panel width: the panel (N x jb) and the original diagonal fit in LDS
     const int jb = std::max(1, std::min(16, (int)((120 * 1024) / (8 * (size_t)N))));
+    if (N >= c->chol_multi_min) {
+        if (!c->chol_dorig) SG_HIP(c, hipMalloc((void**)&c->chol_dorig, kEighMaxN * sizeof(double)));
+        if (N > kEighMaxN) return set_err(c, SPARC_ERR_ARG, "cholesky: N above the subspace limit");
+        k_chol_diag<<<div_up(N, 256), 256, 0, c->stream>>>(M, N, c->chol_dorig);
+        for (int j0 = 0; j0 < N; j0 += jb) {
+            const int w = std::min(jb, N - j0);
+            k_chol_panel<<<1, 1024, (size_t)(N - j0) * w * sizeof(double), c->stream>>>(M, N, j0, w, c->chol_dorig,
+                                                                                      flag);
+            const int k0 = j0 + w, m = N - k0;
+            if (m > 0) {
+                const int nb = div_up(m, kCholT);
+                k_chol_update<<<dim3(nb, nb), 256, 0, c->stream>>>(M, N, k0, j0, w);
+            }
+        }
+        k_zero_upper<<<div_up((long)N * N, 256L), 256, 0, c->stream>>>(M, N);
+        SG_CHECK_LAUNCH(c);
+        prof_end(c, slot);
+        return SPARC_OK;
+    }
     const size_t lds = ((size_t)N + (size_t)N * jb) * sizeof(double);
     k_cholesky<<<1, 1024, lds, c->stream>>>(M, N, jb, flag);
     SG_CHECK_LAUNCH(c);

@@ -213,6 +213,49 @@ def test_rayleigh_ritz_fp32():
     assert np.max(np.abs(s.dV * Xg @ Xg.T - np.eye(8))) < 1e-5
 
 
+def test_cholesky_over_many_workgroups_is_bitwise_identical(monkeypatch):
+    """From N = 384 the Cholesky factor's trailing updates run over many
+    workgroups; each entry gets the same operations in the same order as in
+    the one-workgroup kernel, so the Rayleigh-Ritz results are bitwise
+    equal."""
+    torch = require_gpu()
+    ncol = 400
+    s = small_images_system(n_states=ncol)
+    v = _veff(s, 17)
+    X = W.initial_orbitals(s.nd, ncol, 8)
+    out = {}
+    for name, threshold in (("one workgroup", 1 << 30), ("many workgroups", 384)):
+        monkeypatch.setenv("SPARC_GPU_CHOL_MULTI_MIN", str(threshold))
+        log("rayleigh_ritz", ncol, "cholesky", name)
+        ctx = _ctx(s)
+        ctx.set_veff(to_dev(torch, v))
+        Xd = to_dev(torch, X)
+        eig = torch.zeros(ncol, dtype=torch.float64, device="cuda")
+        ctx.rayleigh_ritz(Xd, eig)
+        out[name] = (to_np(eig), to_np(Xd))
+        ctx.close()
+    np.testing.assert_array_equal(out["one workgroup"][0], out["many workgroups"][0])
+    np.testing.assert_array_equal(out["one workgroup"][1], out["many workgroups"][1])
+
+
+def test_rayleigh_ritz_rank_deficient_wide_block():
+    """The many-workgroup Cholesky reports a rank-deficient block too."""
+    from paper_2005_10431_amd import SparcError
+    torch = require_gpu()
+    ncol = 400
+    s = small_images_system(n_states=ncol)
+    ctx = _ctx(s)
+    ctx.set_veff(to_dev(torch, _veff(s)))
+    X = W.initial_orbitals(s.nd, ncol, 9)
+    X[350] = X[10]
+    Xd = to_dev(torch, X)
+    eig = torch.zeros(ncol, dtype=torch.float64, device="cuda")
+    with pytest.raises(SparcError) as ei:
+        ctx.rayleigh_ritz(Xd, eig)
+    assert ei.value.name == "SPARC_ERR_NOT_SPD"
+    np.testing.assert_array_equal(to_np(Xd), X)
+
+
 def test_rayleigh_ritz_rank_deficient_block():
     from paper_2005_10431_amd import SparcError
     torch = require_gpu()
