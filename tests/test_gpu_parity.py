@@ -213,6 +213,33 @@ def test_rayleigh_ritz_fp32():
     assert np.max(np.abs(s.dV * Xg @ Xg.T - np.eye(8))) < 1e-5
 
 
+def test_rayleigh_ritz_1200_columns():
+    """The cfg4 subspace size on a 40 x 37 x 13 grid: Gram and projected H
+    on 128-wide tiles, Cholesky and tridiagonalisation over many workgroups,
+    all against the oracle."""
+    torch = require_gpu()
+    ncol = 1200
+    s = ragged_system(n_states=ncol)
+    log("rayleigh_ritz", ncol, "columns on", s.n)
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 18)
+    X = W.initial_orbitals(s.nd, ncol, 7)
+    Xr, lam = chefsi.rayleigh_ritz(s, v, projs, X)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    eig = torch.zeros(ncol, dtype=torch.float64, device="cuda")
+    ctx.rayleigh_ritz(Xd, eig)
+    Xg = to_np(Xd)
+    scale = max(1.0, float(np.max(np.abs(lam))))
+    np.testing.assert_allclose(to_np(eig), lam, atol=1e-10 * scale)
+    O = s.dV * Xg @ Xg.T
+    assert np.max(np.abs(O - np.eye(ncol))) < 1e-10
+    # lowest 40 Ritz vectors: the same subspace (all principal cosines 1)
+    cos = np.linalg.svd(s.dV * Xg[:40] @ Xr[:40].T, compute_uv=False)
+    assert 1.0 - np.min(cos) < 1e-9
+
+
 def test_cholesky_over_many_workgroups_is_bitwise_identical(monkeypatch):
     """From N = 384 the Cholesky factor's trailing updates run over many
     workgroups; each entry gets the same operations in the same order as in
