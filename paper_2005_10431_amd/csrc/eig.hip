@@ -839,14 +839,17 @@ __global__ __launch_bounds__(256) void k_clusters(const double* d, const double*
 }
 
 // Z <- H_0 H_1 ... H_{N-3} Z^T (input zt = Z^T column-major), one wave per
-// output column; Z is written in column-major order.
+// output column, the column held in LDS while the reflectors are applied;
+// Z is written in column-major order.  LDS: 4 N doubles.
 __global__ __launch_bounds__(256) void k_backtransform(const double* A, const double* tau, int N, const double* zt,
                                                        double* Z) {
-    const int lane = threadIdx.x & 63;
-    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    extern __shared__ double zs[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = blockIdx.x * 4 + wv;
     if (col >= N) return;
-    double* zc = Z + (long)col * N;
-    // every element of the column is owned by one lane throughout
+    double* zc = zs + (long)wv * N;
+    // every element of the column is owned by one lane throughout (no
+    // other lane reads or writes it, so no barrier is needed)
     for (int r = lane; r < N; r += 64) zc[r] = zt[(long)r * N + col];
     for (int i = N - 3; i >= 0; --i) {
         const double ti = tau[i];
@@ -861,6 +864,8 @@ __global__ __launch_bounds__(256) void k_backtransform(const double* A, const do
         for (int r = r0; r < N; r += 64)
             if (r >= i + 1) zc[r] -= s * ((r == i + 1) ? 1.0 : vi[r]);
     }
+    double* out = Z + (long)col * N;
+    for (int r = lane; r < N; r += 64) out[r] = zc[r];
 }
 
 // A (destroyed) -> ascending eigenvalues eig and eigenvectors V (columns).
@@ -924,7 +929,7 @@ sparc_status dense_eigh_tridiag(sparc_gpu_ctx c, double* A, int N, double* V, do
     }
     prof_end(c, slot);
     slot = prof_begin(c, PK_EIG_BACK);
-    k_backtransform<<<div_up(N, 4), 256, 0, c->stream>>>(A, tau, N, zt, V);
+    k_backtransform<<<div_up(N, 4), 256, 4 * (size_t)N * sizeof(double), c->stream>>>(A, tau, N, zt, V);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
     return SPARC_OK;
