@@ -800,6 +800,7 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     if (const char* e = std::getenv("SPARC_GPU_TRD_MULTI_MIN")) c->trd_multi_min = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_TRD_TAIL")) c->trd_tail = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("SPARC_GPU_CHOL_MULTI_MIN")) c->chol_multi_min = std::atoi(e);
+    if (const char* e = std::getenv("SPARC_GPU_STEIN_LDS_MIN_TPW")) c->stein_lds_min_tpw = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_SPLIT_FILTER")) c->split_filter = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_PROJ_NB")) c->proj_nb = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_PROJ_U")) c->proj_u = std::atoi(e);

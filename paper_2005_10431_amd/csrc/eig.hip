@@ -902,10 +902,13 @@ sparc_status dense_eigh_tridiag(sparc_gpu_ctx c, double* A, int N, double* V, do
     k_clusters<<<1, 256, N * sizeof(double), c->stream>>>(d, e, lamw, N, cl, ncl_d);
     SG_CHECK_LAUNCH(c);
     {
-        // threads per workgroup whose LU factors and vector fit in LDS
+        // threads per workgroup whose LU factors and vector fit in LDS; with
+        // fewer than 3 per workgroup (N above about 800) LDS caps the solves
+        // in flight, and the factors in global memory (every solve at once)
+        // are faster: N = 1200 3.2 against 4.2 ms, N = 2000 6.1 against 20.5
         const long lds_doubles = (150L * 1024) / 8;
         const int tpw = (int)std::min<long>(64, (lds_doubles - 2L * N) / (6L * N));
-        if (tpw >= 1) {
+        if (tpw >= std::max(1, c->stein_lds_min_tpw)) {
             const size_t lds = (2 * (size_t)N + 6 * (size_t)N * tpw) * sizeof(double);
             k_stein_lds<<<div_up(N, tpw), 64, lds, c->stream>>>(d, e, lamw, N, cl, ncl_d, zt, tpw);
         } else {

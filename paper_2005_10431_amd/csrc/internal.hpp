@@ -162,6 +162,7 @@ struct sparc_gpu_ctx_s {
     int eig_jacobi = 0;         // SPARC_GPU_EIG=jacobi: parallel Jacobi instead of tridiagonal
     int trd_multi_min = 320;    // SPARC_GPU_TRD_MULTI_MIN: N from which the reduction uses many workgroups
     int trd_tail = 256;         // SPARC_GPU_TRD_TAIL: trailing size below which one workgroup finishes it
+    int stein_lds_min_tpw = 3;  // SPARC_GPU_STEIN_LDS_MIN_TPW: fewest solves per workgroup for the LDS inverse iteration
     int chol_multi_min = 384;   // SPARC_GPU_CHOL_MULTI_MIN: N from which Cholesky updates over many workgroups
     double* chol_dorig = nullptr;  // original diagonal for the many-workgroup Cholesky (kEighMaxN)
     std::vector<int> pe_off_host;  // point offsets of the image-level entries (host)
