@@ -437,7 +437,7 @@ sparc_status sparc_gpu_profile_read(sparc_gpu_ctx ctx, int kernel_id, double* to
  * The SCF of Sec. 2.1 starts from a superposition of atomic densities; the
  * warm start replaces that guess by the prediction of a small periodic
  * convolutional network trained on converged densities of related
- * geometries (machine-learning methods are a direction named in Sec. 5).
+ * geometries (machine-learning methods are a direction named in Sec. 4).
  *
  * Features: 3 channels f_c(x) = sum over atoms and periodic images within
  * 6 w_c of exp(-|x - R_I - n L|^2 / (2 w_c^2)); d_feat is 3 x N_d float32,

@@ -18,8 +18,9 @@ steps and no blocking or fusion.
 
 Functions whose results have no pin outside the oracle itself are marked
 "parity unpinned" in their docstrings:
-  * ``xc.pw92_correlation`` beyond its high-density coefficient (the PW92
-    fit constants are not printed in the paper);
+  * ``xc.pw92_correlation`` and ``xc.pw92_G`` beyond their high-density
+    coefficients and the relation b2 = 2 A b1^2 (the PW92 fit constants a1,
+    b1, b3, b4 are not printed in the paper);
   * ``scf.scf`` trajectories away from the fixed point (only GPU <-> oracle
     parity, no outside reference exists for the model systems).
 """

@@ -1,6 +1,6 @@
 """Learned initial density (the machine-learned warm start of the SCF; the
 paper's SCF starts from a superposition of atomic densities, Sec. 2.1, and
-names machine-learning methods as a direction, Sec. 5): CPU reference of the
+names machine-learning methods as a direction, Sec. 4): CPU reference of the
 feature map, the three-layer periodic convolutional network, its gradient and
 the Adam update.  Test infrastructure only: nothing in the GPU library or
 its binding imports this module.

@@ -9,8 +9,10 @@ Correlation (PW92 fit, unpolarised), with r_s = (3 / (4 pi rho))^(1/3):
     v_c   = eps_c - (r_s / 3) d eps_c / d r_s
 
 The PW92 constants are not printed in the paper.  A is pinned by the exact
-high-density coefficient (1 - ln 2) / pi^2 of the uniform electron gas; the
-remaining fit constants (a1, b1..b4) are parity unpinned in this repository.
+high-density coefficient (1 - ln 2) / pi^2 of the uniform electron gas, and
+b2 = 2 A b1^2 by the absence of an r_s^(1/2) term from the exact high-density
+expansion; the remaining fit constants (a1, b1, b3, b4) are parity unpinned
+in this repository.
 """
 from __future__ import annotations
 
@@ -65,8 +67,9 @@ def lda(rho: np.ndarray, rho_floor: float = 1e-14):
 #     f(zeta) = ((1 + zeta)^(4/3) + (1 - zeta)^(4/3) - 2) / (2^(4/3) - 2),
 # with eps_c(rs, 1) and -alpha_c(rs) of the same G(rs) form as eps_c(rs, 0).
 # Their A constants are pinned by the exact high-density coefficients
-# (1 - ln 2) / (2 pi^2) and 1 / (6 pi^2); the other fit constants are parity
-# unpinned.
+# (1 - ln 2) / (2 pi^2) and 1 / (6 pi^2), and b2 = 2 A b1^2 in each fit by the
+# absence of an r_s^(1/2) term; the other fit constants (a1, b1, b3, b4) are
+# parity unpinned.
 
 PW92_POL = (0.015545, 0.20548, (14.1189, 6.1977, 3.3662, 0.62517))      # eps_c(rs, 1)
 PW92_MALPHA = (0.016887, 0.11125, (10.357, 3.6231, 0.88026, 0.49671))   # -alpha_c(rs)

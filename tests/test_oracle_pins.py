@@ -268,6 +268,31 @@ def test_pw92_high_density_coefficient():
     assert abs(slope - xc.PW92_A) < 1e-4
 
 
+def sqrt_rs_coefficient(G_of_rs, A):
+    """Coefficient c of r_s^(1/2) in G(r_s) = A ln r_s + const + c r_s^(1/2)
+    + O(r_s ln r_s), from two points r and 4r at r = 1e-14, where the
+    O(r_s ln r_s) remainder changes by less than 1e-6 of the r_s^(1/2) term
+    of a fit whose b2 is off by a quarter percent."""
+    r1, r2 = 1e-14, 4e-14
+    g1, g2 = G_of_rs(r1) - A * log(r1), G_of_rs(r2) - A * log(r2)
+    return (g2 - g1) / (sqrt(r2) - sqrt(r1))
+
+
+def test_pw92_fit_has_no_sqrt_rs_term():
+    """The exact high-density expansion of the correlation energy is
+    A ln r_s - c1 + O(r_s ln r_s): it has no r_s^(1/2) term.  Expanding
+    ln(1 + 1/Q1) with Q1 = 2A (b1 r_s^(1/2) + b2 r_s + ...) gives that term
+    the coefficient -2A (2A b1 - b2/b1), which vanishes iff b2 = 2 A b1^2.
+    Checked on the constants and numerically on the oracle's function, so a
+    typo in b1 or b2 (a quarter percent moves the coefficient 300-fold past
+    the bar) fails."""
+    b1, b2 = xc.PW92_BETA[0], xc.PW92_BETA[1]
+    assert abs(b2 - 2.0 * xc.PW92_A * b1 * b1) / b2 < 1e-4
+    coef = sqrt_rs_coefficient(lambda r: xc.pw92_correlation(np.array([r]))[0][0], xc.PW92_A)
+    scale = 2.0 * xc.PW92_A * (2.0 * xc.PW92_A * b1)   # either half of the cancelling pair
+    assert abs(coef) < 2e-4 * scale, coef
+
+
 def test_vxc_is_derivative_of_energy_density():
     rho = np.array([1e-4, 3e-3, 0.02, 0.1, 0.7, 3.0])
     eps, v = xc.lda(rho)

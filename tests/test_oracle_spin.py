@@ -69,6 +69,18 @@ def test_pw92_spin_fits_have_the_exact_high_density_logarithms():
         assert abs((G[0] - G[1]) / np.log(rs[0] / rs[1]) - A) < 1e-6
 
 
+def test_pw92_spin_fits_have_no_sqrt_rs_term():
+    """The fully polarised fit and the spin stiffness fit obey the same
+    exact high-density form as the unpolarised one (A ln r_s + const +
+    O(r_s ln r_s), no r_s^(1/2) term), which fixes b2 = 2 A b1^2 in each."""
+    from test_oracle_pins import sqrt_rs_coefficient
+    for A, a1, beta in (xc.PW92_POL, xc.PW92_MALPHA):
+        b1, b2 = beta[0], beta[1]
+        assert abs(b2 - 2.0 * A * b1 * b1) / b2 < 1e-4
+        coef = sqrt_rs_coefficient(lambda r: xc.pw92_G(np.array([r]), A, a1, beta)[0][0], A)
+        assert abs(coef) < 2e-4 * (2.0 * A * 2.0 * A * b1), (A, coef)
+
+
 def test_spin_occupations_common_fermi_level():
     rng = np.random.default_rng(4)
     lu = np.sort(rng.uniform(-1, 1, 10))
