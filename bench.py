@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the CheFSI hot path on one MI355X.
 
-Workload (default): the 108-atom / 72^3-grid / 260-state system with s+p
-nonlocal projectors, Chebyshev degree 20, FP64 (config 2 of the build's
-workload list).  A step is one SCF iteration after the first: potential
-(Poisson + LDA), one Chebyshev filter pass, Rayleigh-Ritz, occupations,
-density, energy and mixing, all on the GPU with inputs resident in HBM.
+Workload (default): the 500-atom / 120^3-grid / 1200-state system with s+p
+nonlocal projectors, Chebyshev degree 24 (the largest single-GPU workload,
+the one the FP64 / FP32 pair is quoted on); ``--workload cfg2`` selects the
+108-atom / 72^3 / 260-state system.  A step is one SCF iteration after the
+first: potential (Poisson + LDA), one Chebyshev filter pass, Rayleigh-Ritz,
+occupations, density, energy and mixing, all on the GPU with inputs resident
+in HBM.
 
 Printed (one JSON line): filter HBM throughput in algorithmic GB/s
 (3 * s * N_d * N_s * m bytes per filter), time per SCF step, the roofline of
-the dominant kernel (the filter sweep), and the CPU oracle's filter rate on a
-bounded sample.
+the dominant kernel (the filter sweep), the FP32 form's step, the GPU time of
+both forms to a free energy within 1e-5 Ha/atom of the converged FP64 value,
+and the CPU oracle's filter rate on a bounded column sample.
+
+Other measurements: ``python bench.py --mode {mixing,spin,eigh,forces,kpoints}``
+(see bench_modes.py), ``--oracle-timing``, ``--traffic-probe``.
 """
 from __future__ import annotations
 
@@ -173,51 +179,97 @@ def traffic_probe(system, prec):
     print("probe: done", flush=True)
 
 
-def fp32_accuracy(system, tol64=1e-7, tol32=1e-6, max_iter=200):
-    """The FP32 form against FP64 on the same workload and seed: both SCFs to
-    convergence (FP32 followed by one FP64 Rayleigh-Ritz), then the free
-    energy per atom, occupied eigenvalues and density compared."""
+def time_to_accuracy(system, X0, eps=1e-5, tol_ref=1e-6, max_iter=120, deadline=None):
+    """GPU time of the FP64 form and of the FP32 form (with its final FP64
+    Rayleigh-Ritz) until the free energy per atom is within ``eps`` of the
+    converged FP64 value F_ref, both SCFs from the same seeded block and the
+    atomic-density guess with the workload's mixing.
+
+    F_ref: the FP64 SCF run on to a density residual below ``tol_ref``.  A
+    form has reached ``eps`` at the first iteration k from which three
+    consecutive free energies lie within ``eps`` of F_ref (a single crossing
+    of a still-oscillating energy does not count); its time is the summed
+    device time of SCF iterations 0..k+2.  The FP32 SCF stops there, then one
+    FP64 Rayleigh-Ritz gives its final free energy, whose distance to F_ref is
+    reported beside the time.  ``deadline`` (a time.perf_counter value) stops
+    the FP64 reference run early; the result then says so.  Returns a dict."""
     import numpy as np
     import torch
 
-    import workloads as W
     from paper_2005_10431_amd.driver import run_scf
 
-    X0 = W.initial_orbitals(system.nd, system.n_states, system.seed)
+    n_at = system.n_atoms
     t0 = time.perf_counter()
 
     def progress(tag):
         def cb(rep):
             if rep["iter"] % 10 == 0:
-                print(f"accuracy run {tag}: iteration {rep['iter']}, residual {rep['residual']:.2e}",
-                      file=sys.stderr, flush=True)
+                print(f"accuracy run {tag}: iteration {rep['iter']}, residual {rep['residual']:.2e}, "
+                      f"F/atom {rep['free_energy'] / n_at:.10f}", file=sys.stderr, flush=True)
         return cb
-    r64 = run_scf(system, X0, prec="fp64", max_iter=max_iter, tol=tol64, callback=progress("fp64"))
-    r32 = run_scf(system, X0, prec="fp32", max_iter=max_iter, tol=tol32, final_fp64_rr=True,
-                  callback=progress("fp32"))
-    torch.cuda.synchronize()
-    f64 = r64["history"][-1]["free_energy"] / system.n_atoms
-    f32 = r32["final"]["free_energy"] / system.n_atoms
-    occ = r64["occ"].cpu().numpy()
-    dl = np.abs(r32["final"]["eig"] - r64["eig"].cpu().numpy())
-    rho64 = r64["rho_out"].cpu().numpy()
-    rho32 = r32["rho_out"].cpu().numpy()
+
+    cut = {"hit": False}
+
+    def ref_cb(rep):
+        progress("fp64")(rep)
+        if deadline is not None and time.perf_counter() > deadline:
+            cut["hit"] = True
+            return True
+        return False
+
+    r64 = run_scf(system, X0, prec="fp64", max_iter=max_iter, tol=tol_ref, callback=ref_cb)
+    h64 = r64["history"]
+    r64["ctx"].close()
+    del r64
+    torch.cuda.empty_cache()
+    if cut["hit"]:
+        return {"skipped": f"the FP64 reference run passed the bench's time budget after {len(h64)} iterations"}
+    F_ref = h64[-1]["free_energy"] / n_at
+
+    def first_within(F, k_run=3):
+        inside = [abs(f - F_ref) <= eps for f in F]
+        for k in range(len(F) - k_run + 1):
+            if all(inside[k:k + k_run]):
+                return k
+        return None
+
+    F64 = [r["free_energy"] / n_at for r in h64]
+    k64 = first_within(F64)
+    t64 = [r["t_total_ms"] for r in h64]
+
+    F32, t32 = [], []
+
+    def cb32(rep):
+        progress("fp32")(rep)
+        F32.append(rep["free_energy"] / n_at)
+        t32.append(rep["t_total_ms"])
+        return first_within(F32) is not None
+
+    r32 = run_scf(system, X0, prec="fp32", max_iter=max_iter, tol=0.0, final_fp64_rr=True, callback=cb32)
+    reached = first_within(F32) is not None
+    fin = r32["final"]
+    r32["ctx"].close()
+    del r32
+    torch.cuda.empty_cache()
     out = {
-        "free_energy_per_atom_fp64": f64,
-        "abs_diff_per_atom": abs(f32 - f64),
-        # fully occupied states, and the partly occupied ones at the Fermi
-        # level (which sit next to the filter cut, where the subspace
-        # converges slowest, and carry little weight in F and rho)
-        "max_abs_dlambda_full": float(np.max(dl[occ > 1.9])),
-        "max_abs_dlambda_partial": float(np.max(dl[(occ > 1e-6) & (occ <= 1.9)])) if np.any((occ > 1e-6) & (occ <= 1.9)) else 0.0,
-        "density_l1_per_electron": float(system.dV * np.sum(np.abs(rho32 - rho64)) / system.n_electrons),
-        "iterations": {"fp64": len(r64["history"]), "fp32": len(r32["history"])},
-        "residual_tol": {"fp64": tol64, "fp32": tol32},
-        "target_abs_diff_per_atom": 1e-5,
-        "seconds": time.perf_counter() - t0,
+        "eps_per_atom": eps,
+        "F_ref_per_atom": F_ref,
+        "F_ref_iterations": len(h64),
+        "F_ref_residual": h64[-1]["residual"],
+        "rule": "first iteration k from which 3 consecutive F_k lie within eps of F_ref; time = summed device "
+                "time of SCF iterations 0..k+2 (FP32: plus its final FP64 Rayleigh-Ritz)",
+        "fp64": {"reached": k64 is not None,
+                 "iterations": (k64 + 3) if k64 is not None else None,
+                 "gpu_ms": float(np.sum(t64[:k64 + 3])) if k64 is not None else None},
+        "fp32": {"reached": reached, "iterations": len(F32),
+                 "gpu_ms_scf": float(np.sum(t32)),
+                 "gpu_ms_final_rr": fin["t_total_ms"],
+                 "gpu_ms": float(np.sum(t32)) + fin["t_total_ms"],
+                 "abs_diff_per_atom_after_final_rr": abs(fin["free_energy"] / n_at - F_ref)},
     }
-    for r in (r64, r32):
-        r["ctx"].close()
+    if out["fp64"]["reached"] and reached:
+        out["fp32_time_over_fp64"] = out["fp32"]["gpu_ms"] / out["fp64"]["gpu_ms"]
+    out["seconds"] = time.perf_counter() - t0
     return out
 
 
@@ -270,17 +322,33 @@ def cnn_measure(steps: int = 10):
 
 
 def main():
+    t_start = time.perf_counter()
+    if "--mode" in sys.argv[1:]:
+        i = sys.argv.index("--mode")
+        if i + 1 >= len(sys.argv):
+            sys.exit("--mode needs a name: mixing, spin, eigh, forces or kpoints")
+        import bench_modes
+        name = sys.argv[i + 1]
+        if name not in bench_modes.MODES:
+            sys.exit(f"unknown mode {name!r}; modes: {', '.join(sorted(bench_modes.MODES))}")
+        bench_modes.MODES[name](sys.argv[1:i] + sys.argv[i + 2:])
+        return
+
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cfg4", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--cpu-cols", type=int, default=40, help="columns in the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-cols", type=int, default=None,
+                    help="columns in the CPU oracle sample (0: skip; default 2 at cfg4, 40 at cfg2, 12 at cfg1)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-filter companion measurement")
     ap.add_argument("--no-cnn", action="store_true", help="skip the warm-start network measurement")
     ap.add_argument("--no-accuracy", action="store_true",
-                    help="skip the converged FP32-vs-FP64 comparison on the workload")
+                    help="skip the time-to-1e-5-Ha/atom comparison of the FP64 and FP32 forms")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock budget of the whole run: the time-to-accuracy leg is skipped, or its FP64 "
+                         "reference run cut, when it would pass it")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="time only the CPU oracle (config 1 whole, config 2 on a column slice) and print it")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -290,7 +358,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path is built): "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     if args.oracle_timing:
@@ -303,17 +372,27 @@ def main():
     import workloads as W
     from paper_2005_10431_amd import Context, make_state
 
+    def log(msg):
+        print(f"[bench {time.perf_counter() - t_start:6.1f} s] {msg}", file=sys.stderr, flush=True)
+
     system = {"cfg1": W.config1, "cfg2": W.config2, "cfg4": W.config4}[args.workload](0)
     nd, ns, m = system.nd, system.n_states, system.cheb_degree
     if args.traffic_probe:
         traffic_probe(system, args.prec)
         return
+    cpu_cols = args.cpu_cols if args.cpu_cols is not None else {"cfg4": 2, "cfg2": 40, "cfg1": 12}[args.workload]
+
+    # the seeded start block, generated once on the host and kept on the device
+    log(f"start block {ns} x {nd}")
+    X0 = torch.as_tensor(W.initial_orbitals(nd, ns, 0)).cuda()
+    torch.cuda.synchronize()
 
     def run(prec, steps, warmup, profile):
         dt = torch.float64 if prec == "fp64" else torch.float32
         s = 8 if prec == "fp64" else 4
+        log(f"{prec}: context")
         ctx = Context(system)
-        X = torch.as_tensor(W.initial_orbitals(nd, ns, 0)).to(dt).cuda()
+        X = X0.to(dt) if dt != X0.dtype else X0.clone()
         rho = torch.empty(nd, dtype=torch.float64, device="cuda")
         ctx.sad_density(rho)
         eig = torch.empty(ns, dtype=torch.float64, device="cuda")
@@ -322,6 +401,7 @@ def main():
         hist = torch.empty((2 * ph + 2) * nd, dtype=torch.float64, device="cuda") if ph > 0 else None
         st = make_state(rho, X, eig, occ, m, system.n_first, system.mix_beta, None, system.kerker_q0, ph,
                         system.pulay_period, bool(system.pulay_restart), hist)
+        log(f"{prec}: iteration 0 and {warmup} warm-up steps")
         first = ctx.scf_step(st)                      # iteration 0 (initial RR + n_first passes)
         for _ in range(warmup):
             ctx.scf_step(st)
@@ -332,6 +412,7 @@ def main():
                 ctx.profile_read(k)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         reps = []
+        log(f"{prec}: {steps} timed steps")
         torch.cuda.synchronize()
         e0.record()
         for _ in range(steps):
@@ -365,6 +446,9 @@ def main():
             s=s,
         )
         ctx.close()
+        del X, hist
+        torch.cuda.empty_cache()
+        log(f"{prec}: {out['ms_per_step']:.1f} ms per step, filter {out['filter_gbs']:.0f} GB/s")
         return out
 
     res = run(args.prec, args.steps, args.warmup, True)
@@ -380,7 +464,12 @@ def main():
     kernel_name = f"k_hsweep<{'double' if s == 8 else 'float'}, nonlocal, mode 2>"
     traffic = traffic_record(f"{args.workload}_{args.prec}_sweep")
     gt_ms, gt_n = prof["gemm_tn"]
-    gemm_flops = 2.0 * ns * ns * nd * gt_n   # two N_s x N_s products from K = N_d per RR (Gram counted full)
+    gn_ms, gn_n = prof["gemm_nn"]
+    # Gram and projected H: symmetric products from K = N_d, N_s (N_s + 1) N_d
+    # flops each (upper tiles only); rotation: a full 2 N_d N_s^2 product
+    flops_tn = float(ns) * (ns + 1) * nd * gt_n
+    flops_nn = 2.0 * ns * ns * nd * gn_n
+    peak_mm = PEAK_FP64_TFLOPS if s == 8 else PEAK_FP32_TFLOPS
     line = {
         "metric": "CheFSI filter HBM GB/s + time/SCF step",
         "value": res["filter_gbs"],
@@ -412,19 +501,35 @@ def main():
         "scf_step_breakdown_ms": {k: res[k] for k in ("t_potential_ms", "t_filter_ms", "t_rr_ms", "t_density_ms")},
         "first_iteration_ms": res["first_iter_ms"],
         "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
-        "gemm_tn_tflops": (gemm_flops / (gt_ms * 1e-3) / 1e12) if gt_ms else None,
+        "subspace_gemms": {
+            "bound": "mfma", "peak_tflops": peak_mm,
+            "gram_and_projected_h_tflops": (flops_tn / (gt_ms * 1e-3) / 1e12) if gt_ms else None,
+            "rotation_tflops": (flops_nn / (gn_ms * 1e-3) / 1e12) if gn_ms else None,
+            "flop_count": "Gram and projected H N_s (N_s + 1) N_d each (symmetric), rotation 2 N_d N_s^2",
+        },
     }
     if args.prec == "fp64" and not args.no_fp32:
         r32 = run("fp32", max(2, args.steps // 2), 1, False)
         line["fp32"] = {"filter_gbs": r32["filter_gbs"], "ms_per_step": r32["ms_per_step"],
+                        "step_speedup_over_fp64": res["ms_per_step"] / r32["ms_per_step"],
                         "scf_step_breakdown_ms": {k: r32[k] for k in ("t_potential_ms", "t_filter_ms",
                                                                        "t_rr_ms", "t_density_ms")}}
     if args.prec == "fp64" and not args.no_fp32 and not args.no_accuracy:
-        line["fp32"]["accuracy_vs_fp64"] = fp32_accuracy(system)
+        elapsed = time.perf_counter() - t_start
+        if elapsed > 0.6 * args.budget_s:
+            line["time_to_1e-5_ha_per_atom"] = {"skipped": f"{elapsed:.0f} s elapsed before it started"}
+        else:
+            log("time to 1e-5 Ha/atom: FP64 reference run, then the FP32 form")
+            line["time_to_1e-5_ha_per_atom"] = time_to_accuracy(system, X0, deadline=t_start + args.budget_s)
+    del X0
+    torch.cuda.empty_cache()
     if not args.no_cnn:
+        log("warm-start network forward")
         line["warm_start_cnn"] = cnn_measure()
-    if args.cpu_cols > 0:
-        line["cpu_baseline"] = cpu_baseline(system, args.cpu_cols, m, res["bounds"])
+    if cpu_cols > 0:
+        log(f"CPU oracle filter on {cpu_cols} columns")
+        line["cpu_baseline"] = cpu_baseline(system, cpu_cols, m, res["bounds"])
+    log("done")
     print(json.dumps(line), flush=True)
 
 

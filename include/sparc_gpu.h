@@ -13,7 +13,8 @@
  *  - Grid: n[0] x n[1] x n[2] points on an orthorhombic cell L[0..2] (Bohr);
  *    point (ix, iy, iz) sits at (ix*hx, iy*hy, iz*hz), h = L/n, and has flat
  *    index p = ix + n[0]*(iy + n[1]*iz).  N_d = n[0]*n[1]*n[2].  Every axis
- *    is periodic and must have at least 13 points; n[0] <= 256.
+ *    is periodic and must have at least 13 points (the kernels' stencil
+ *    half-width is 6 whatever fd_half_order is); n[0] <= 256.
  *  - Blocks of orbitals ("X") are column-major N_d x ncol arrays with leading
  *    dimension ldx >= N_d: orbital j occupies X[j*ldx .. j*ldx + N_d).  Their
  *    element type is double for SPARC_FP64 and float for SPARC_FP32.
@@ -177,6 +178,14 @@ sparc_status sparc_gpu_pseudocharge(sparc_gpu_ctx ctx, double* d_b, double* e_se
  * dV sum rho = N_e.  d_rho: N_d doubles. */
 sparc_status sparc_gpu_sad_density(sparc_gpu_ctx ctx, double* d_rho);
 
+/* The same guess split over two spins (eq. (1)-(2) carry a spin index; the
+ * spin-polarised SCF mixes both components, Sec. 2.1) by a starting
+ * polarisation zeta0 in [-1, 1]: d_rho2[0, N_d) = (1 + zeta0) rho / 2 (up),
+ * d_rho2[N_d, 2 N_d) = (1 - zeta0) rho / 2 (down), with rho the output of
+ * sparc_gpu_sad_density.  d_rho2: 2 N_d doubles.  Errors: SPARC_ERR_ARG (null
+ * pointer, zeta0 outside [-1, 1] or not finite). */
+sparc_status sparc_gpu_sad_density_spin(sparc_gpu_ctx ctx, double zeta0, double* d_rho2);
+
 /* Bounds lo <= spec(H) <= hi of the current H (kinetic symbol bound,
  * V_eff extrema, signed projector norms).  Synchronous. */
 sparc_status sparc_gpu_spectrum_bounds(sparc_gpu_ctx ctx, double* lo, double* hi);
@@ -265,7 +274,15 @@ typedef struct {
  * residual, and the mixing step of sparc_gpu_mix with st's mixing fields
  * (plain linear mixing rho_in <- rho_in + beta (rho_out - rho_in) when
  * pulay_history = 0 and kerker_q0 = 0).
- * Synchronises once at the end to fill rep (may be NULL). */
+ * Synchronises once, at the end, to read the device status flags and fill
+ * rep (may be NULL): nothing in the step waits on the host before that.
+ * Errors found on the device are reported then, in this order:
+ * SPARC_ERR_NONFINITE (NaN or Inf in rho_in), SPARC_ERR_NOT_SPD (a Gram
+ * matrix of the block was not positive definite), SPARC_ERR_FERMI,
+ * SPARC_ERR_SINGULAR, SPARC_ERR_NONFINITE (non-finite energy or residual).
+ * After such an error the step has run to its end on the bad values: X,
+ * rho_in, eig and occ hold unspecified values, st->iter and st->bounds are
+ * not advanced, and the context stays usable for a fresh state. */
 sparc_status sparc_gpu_scf_step(sparc_gpu_ctx ctx, sparc_gpu_scf_state* st, sparc_gpu_scf_report* rep);
 
 /* After an SCF run in SPARC_FP32: promote st->d_X into the FP64 block d_X64

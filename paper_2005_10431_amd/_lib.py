@@ -47,6 +47,7 @@ EXPORTED = [
     "sparc_gpu_potential",
     "sparc_gpu_pseudocharge",
     "sparc_gpu_sad_density",
+    "sparc_gpu_sad_density_spin",
     "sparc_gpu_spectrum_bounds",
     "sparc_gpu_mix",
     "sparc_gpu_potential_spin",
@@ -225,6 +226,7 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_potential": ([vp, vp, vp, vp, vp, vp], i),
         "sparc_gpu_pseudocharge": ([vp, vp, C.POINTER(d), C.POINTER(d)], i),
         "sparc_gpu_sad_density": ([vp, vp], i),
+        "sparc_gpu_sad_density_spin": ([vp, C.c_double, vp], i),
         "sparc_gpu_spectrum_bounds": ([vp, C.POINTER(d), C.POINTER(d)], i),
         "sparc_gpu_mix": ([vp, vp, vp, i, d, d, i, i, i, vp, i], i),
         "sparc_gpu_potential_spin": ([vp, vp, vp, vp, vp, vp], i),
@@ -375,6 +377,10 @@ class Context:
 
     def sad_density(self, rho):
         self._check(self.lib.sparc_gpu_sad_density(self.h, _ptr(rho)))
+
+    def sad_density_spin(self, zeta0, rho2):
+        """rho2: (2 N_d,) float64, up then down."""
+        self._check(self.lib.sparc_gpu_sad_density_spin(self.h, float(zeta0), _ptr(rho2)))
 
     def spectrum_bounds(self):
         lo, hi = C.c_double(), C.c_double()

@@ -264,6 +264,17 @@ __global__ void k_projector_norms(const long* sup_off, const double* chi, double
     if (threadIdx.x < 4) norms[4 * a + threadIdx.x] = dV * red[threadIdx.x][0];
 }
 
+// rho[0, n) holds the total guess; on exit rho[0, n) = (1 + z) rho / 2 (up)
+// and rho[n, 2n) = (1 - z) rho / 2 (down).
+__global__ void k_split_spin_guess(double* rho, long n, double z) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double r = rho[i];
+        rho[i] = 0.5 * (1.0 + z) * r;
+        rho[n + i] = 0.5 * (1.0 - z) * r;
+    }
+}
+
 __global__ void k_scale(double* v, long n, const double* num, double target) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) v[i] *= target / *num;
@@ -743,7 +754,11 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     if (!out) return SPARC_ERR_ARG;
     *out = nullptr;
     if (!s) return SPARC_ERR_ARG;
-    const int mino = 2 * s->fd_half_order + 1;
+    // The sweep kernels are instantiated for half-width kMaxHalfOrder (lower
+    // orders only zero their outer coefficients): their x padding, y halo
+    // rows and z ring wrap each index once, which needs 2 kMaxHalfOrder + 1
+    // points on every axis whatever the order.
+    const int mino = 2 * kMaxHalfOrder + 1;
     if (s->fd_half_order < 1 || s->fd_half_order > kMaxHalfOrder) return SPARC_ERR_ARG;
     for (int d = 0; d < 3; ++d) {
         if (s->n[d] < mino || s->n[d] > 4096) return SPARC_ERR_ARG;
@@ -812,6 +827,8 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipGetDeviceProperties(&c->prop, dev);
     for (int i = 0; e == hipSuccess && i < 8; ++i) e = hipEventCreate(&c->ev[i]);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_scal, S_COUNT * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault);
     if (e != hipSuccess) {
         st = hip_err(c, e, "device query");
     } else {
@@ -839,6 +856,9 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
     for (int i = 0; i < 8; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
     for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
+    for (hipEvent_t e : c->step_ev) hipEventDestroy(e);
+    if (c->h_scal) hipHostFree(c->h_scal);
+    if (c->h_flags) hipHostFree(c->h_flags);
     if (c->jac_exec) hipGraphExecDestroy(c->jac_exec);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     if (c->aux_stream) {
@@ -907,6 +927,17 @@ sparc_status sparc_gpu_sad_density(sparc_gpu_ctx c, double* d_rho) {
     k_sum_serial<<<1, 256, 0, c->stream>>>(d_rho, c->nd, c->scal + S_RED0);
     SG_CHECK_LAUNCH(c);
     k_scale<<<div_up(c->nd, 256), 256, 0, c->stream>>>(d_rho, c->nd, c->scal + S_RED0, c->n_electrons / c->dV);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
+
+sparc_status sparc_gpu_sad_density_spin(sparc_gpu_ctx c, double zeta0, double* d_rho2) {
+    if (!c) return SPARC_ERR_ARG;
+    if (!d_rho2) return set_err(c, SPARC_ERR_ARG, "sad_density_spin: null pointer");
+    if (!(zeta0 >= -1.0 && zeta0 <= 1.0)) return set_err(c, SPARC_ERR_ARG, "sad_density_spin: zeta0 outside [-1, 1]");
+    sparc_status st = sparc_gpu_sad_density(c, d_rho2);
+    if (st != SPARC_OK) return st;
+    k_split_spin_guess<<<div_up(c->nd, 256), 256, 0, c->stream>>>(d_rho2, c->nd, zeta0);
     SG_CHECK_LAUNCH(c);
     return SPARC_OK;
 }

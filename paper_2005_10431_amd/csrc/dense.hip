@@ -576,7 +576,9 @@ static sparc_status rr_core(sparc_gpu_ctx c, T* X, int N, long ldx, double* d_ei
     double* Vq = M + 5 * NN;
     double* Rot = M + 6 * NN;
     double* ework = M + 9 * NN;     // eigensolver workspace; Lt lives at 8 NN
-    SG_HIP(c, hipMemsetAsync(c->flags + F_NOT_SPD, 0, sizeof(int), c->stream));
+    // the public call starts from a clear flag; inside an SCF step the flag
+    // was cleared at the step's start and must survive every pass
+    if (check) SG_HIP(c, hipMemsetAsync(c->flags + F_NOT_SPD, 0, sizeof(int), c->stream));
     if ((st = gemm_tn<T>(c, N, N, rows, X, ldx, X, ldx, c->dV, M, N, true)) != SPARC_OK) return st;
     if ((st = dense_cholesky(c, M, N, c->flags + F_NOT_SPD)) != SPARC_OK) return st;
     if (check) {

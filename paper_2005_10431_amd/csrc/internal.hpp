@@ -143,6 +143,9 @@ struct sparc_gpu_ctx_s {
     int n_field = 0;
 
     hipEvent_t ev[8];
+    std::vector<hipEvent_t> step_ev;  // events of one SCF call, read after its single synchronisation
+    double* h_scal = nullptr;   // pinned host mirror of scal (S_COUNT), filled by the SCF calls
+    int* h_flags = nullptr;     // pinned host mirror of flags (F_COUNT)
     std::string err;
 
     // captured Jacobi sweep (see dense.hip)
@@ -213,6 +216,7 @@ enum Scalar {
 };
 enum Flag {
     F_NOT_SPD = 0, F_EIG_NOCONV = 1, F_FERMI = 2, F_NONFINITE = 3, F_JACOBI_DONE = 4, F_PULAY_SINGULAR = 5,
+    F_INPUT_NONFINITE = 6,   // a non-finite value in an SCF call's input density
     F_COUNT = 16
 };
 
@@ -248,7 +252,11 @@ sparc_status dense_eigh_tridiag(sparc_gpu_ctx c, double* A, int N, double* V, do
 constexpr int kEighMaxN = 4096;
 inline size_t eigh_work_doubles(int N) { return 6 * (size_t)N * N + 320 * (size_t)N + 64; }
 
-// RR core shared by the public entry point and the SCF step; eig on device
+// RR core shared by the public entry point and the SCF step; eig on device.
+// check: synchronise after the Cholesky factor and return SPARC_ERR_NOT_SPD
+// with X unchanged on a non-SPD Gram matrix (the public call); without it the
+// flag F_NOT_SPD stays set on the device for the caller's one final read and
+// the rest of the step runs on (bounded loops only).
 template <typename T>
 sparc_status rayleigh_ritz_impl(sparc_gpu_ctx c, T* X, int ncol, long ldx, double* d_eig, bool check);
 

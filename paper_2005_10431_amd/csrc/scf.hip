@@ -675,16 +675,48 @@ __global__ void k_promote(const T* __restrict__ src, double* __restrict__ dst, l
     if (i < nd) dst[i + (long)j * ldd] = (double)src[i + (long)j * lds];
 }
 
-struct Timer {
+// Events of one SCF call: recorded on the context stream while its work is
+// enqueued and read after the call's single synchronisation.  The pool
+// (c->step_ev) is grown by ensure_step_events before the first mark.
+struct StepEvents {
     sparc_gpu_ctx c;
-    explicit Timer(sparc_gpu_ctx cc) : c(cc) {}
-    void mark(int i) { hipEventRecord(c->ev[i], c->stream); }
-    double ms(int a, int b) {
+    int used = 0;
+    explicit StepEvents(sparc_gpu_ctx cc) : c(cc) {}
+    int mark() {
+        if (used >= (int)c->step_ev.size()) return -1;
+        hipEventRecord(c->step_ev[used], c->stream);
+        return used++;
+    }
+    double ms(int a, int b) const {
+        if (a < 0 || b < 0) return 0.0;
         float v = 0.f;
-        hipEventElapsedTime(&v, c->ev[a], c->ev[b]);
+        hipEventElapsedTime(&v, c->step_ev[a], c->step_ev[b]);
         return (double)v;
     }
 };
+
+static sparc_status ensure_step_events(sparc_gpu_ctx c, int n) {
+    while ((int)c->step_ev.size() < n) {
+        hipEvent_t e = nullptr;
+        SG_HIP(c, hipEventCreate(&e));
+        c->step_ev.push_back(e);
+    }
+    return SPARC_OK;
+}
+
+// flags[F_INPUT_NONFINITE] = 1 when a value of v[0, n) is NaN or infinite.
+__global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ v, long n, int* flags) {
+    bool bad = false;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        bad |= !isfinite(v[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) flags[F_INPUT_NONFINITE] = 1;
+}
+
+static sparc_status check_input_density(sparc_gpu_ctx c, const double* rho, long n) {
+    k_check_finite<<<(int)std::min<long>(1024, div_up(n, 256)), 256, 0, c->stream>>>(rho, n, c->flags);
+    SG_CHECK_LAUNCH(c);
+    return SPARC_OK;
+}
 
 // Mixing parameters of one SCF iteration (see sparc_gpu_mix).
 struct MixArgs {
@@ -777,11 +809,12 @@ static sparc_status mix_steps(sparc_gpu_ctx c, double* rho_in, const double* rho
     return SPARC_OK;
 }
 
-// Energy terms and residual at (rho_in, rho_out) into the report, then the
-// mixing step when mix != nullptr.  Fields: phi = f[2], exc = f[3],
-// vxc = f[4]; fields 0, 1 are free.
-static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs* mix,
-                                  sparc_gpu_scf_report* rep, double* hscal, int nspin = 1) {
+// Energy terms and residual at (rho_in, rho_out), then the mixing step when
+// mix != nullptr, then the copies of the device scalars and flags into the
+// context's pinned host mirrors; nothing waits.  Fields: phi = f[2],
+// exc = f[3], vxc = f[4]; fields 0, 1 are free.
+static sparc_status enqueue_energy(sparc_gpu_ctx c, double* rho_in, const double* rho_out, const MixArgs* mix,
+                                   int nspin = 1) {
     const int nblk = std::min(1024, div_up(c->nd, 256));
     sparc_status st = ensure_red(c, std::max((size_t)nblk * kRed, mix ? mix_red_doubles(mix->m) : 0));
     if (st != SPARC_OK) return st;
@@ -800,12 +833,20 @@ static sparc_status finish_energy(sparc_gpu_ctx c, double* rho_in, const double*
     SG_CHECK_LAUNCH(c);
     if (mix && !fused)
         if ((st = mix_impl(c, rho_in, rho_out, *mix)) != SPARC_OK) return st;
-    double hloc[S_COUNT];
-    double* h = hscal ? hscal : hloc;
-    int fl[F_COUNT];
-    SG_HIP(c, hipMemcpyAsync(h, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    SG_HIP(c, hipMemcpyAsync(fl, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    SG_HIP(c, hipStreamSynchronize(c->stream));
+    SG_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP(c, hipMemcpyAsync(c->h_flags, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    return SPARC_OK;
+}
+
+// After the call's synchronisation: the device flags raised during the call
+// (in this order: non-finite input density, non-SPD Gram matrix, Fermi
+// bisection, Pulay normal equations), then the report from the mirrored
+// scalars.
+static sparc_status read_report(sparc_gpu_ctx c, sparc_gpu_scf_report* rep) {
+    const int* fl = c->h_flags;
+    const double* h = c->h_scal;
+    if (fl[F_INPUT_NONFINITE]) return set_err(c, SPARC_ERR_NONFINITE, "non-finite value in the input density");
+    if (fl[F_NOT_SPD]) return set_err(c, SPARC_ERR_NOT_SPD, "Gram matrix of the block is not positive definite");
     if (fl[F_FERMI]) return set_err(c, SPARC_ERR_FERMI, "Fermi level bisection failed");
     if (fl[F_PULAY_SINGULAR]) return set_err(c, SPARC_ERR_SINGULAR, "Pulay normal equations singular");
     const double* r = h + S_RED0;
@@ -833,59 +874,62 @@ static sparc_status scf_step_impl(sparc_gpu_ctx c, sparc_gpu_scf_state* s, sparc
     sparc_status st;
     const int N = c->n_states;
     T* X = (T*)s->d_X;
+    const bool first = s->iter == 0;
+    const int npass = first ? s->n_first : 1;
     if ((st = ensure_fields(c, 6)) != SPARC_OK) return st;
     if ((st = ensure_work(c, ((size_t)(N - 1) * s->ldx + c->nd) * sizeof(T))) != SPARC_OK) return st;
+    if ((st = ensure_step_events(c, 2 * npass + 6)) != SPARC_OK) return st;
     double* phi = c->field + 2 * c->nd;
     double* exc = c->field + 3 * c->nd;
     double* vxc = c->field + 4 * c->nd;
     double* rho_out = s->d_rho_out ? s->d_rho_out : c->field + 5 * c->nd;
     SG_HIP(c, hipMemsetAsync(c->flags, 0, F_COUNT * sizeof(int), c->stream));
-    Timer tm(c);
-    tm.mark(0);
+    StepEvents ev(c);
+    const int e_begin = ev.mark();
+    if ((st = check_input_density(c, s->d_rho_in, c->nd)) != SPARC_OK) return st;
     if ((st = potential_impl(c, s->d_rho_in, phi, exc, vxc, c->veff)) != SPARC_OK) return st;
     if ((st = bounds_impl(c)) != SPARC_OK) return st;
-    tm.mark(1);
-    const bool first = s->iter == 0;
+    const int e_pot = ev.mark();
     if (first) {
-        if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, s->d_eig, true)) != SPARC_OK) return st;
+        if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, s->d_eig, false)) != SPARC_OK) return st;
         k_bounds_from_eig<<<1, 1, 0, c->stream>>>(s->d_eig, N, c->scal, 1);
     } else {
         k_set_ab<<<1, 1, 0, c->stream>>>(c->scal, s->bounds[0], s->bounds[2]);
     }
     SG_CHECK_LAUNCH(c);
-    const int npass = first ? s->n_first : 1;
-    double t_filter = 0.0, t_rr = 0.0;
+    int e_pass[2 * 100 + 1];
+    e_pass[0] = ev.mark();
     for (int pass = 0; pass < npass; ++pass) {
-        tm.mark(2);
         if ((st = filter_impl<T>(c, X, (T*)c->work, N, s->ldx, s->cheb_degree)) != SPARC_OK) return st;
-        tm.mark(3);
-        if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, s->d_eig, true)) != SPARC_OK) return st;
+        e_pass[2 * pass + 1] = ev.mark();
+        if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, s->d_eig, false)) != SPARC_OK) return st;
         k_bounds_from_eig<<<1, 1, 0, c->stream>>>(s->d_eig, N, c->scal, 0);
         SG_CHECK_LAUNCH(c);
-        tm.mark(4);
-        SG_HIP(c, hipEventSynchronize(c->ev[4]));
-        t_filter += tm.ms(2, 3);
-        t_rr += tm.ms(3, 4);
+        e_pass[2 * pass + 2] = ev.mark();
     }
-    tm.mark(5);
     if ((st = occupations_impl(c, s->d_eig, N, s->d_occ, nullptr)) != SPARC_OK) return st;
     if ((st = density_impl<T>(c, X, N, s->ldx, s->d_occ, rho_out)) != SPARC_OK) return st;
-    tm.mark(6);
-    sparc_gpu_scf_report R;
-    double hs[S_COUNT];
+    const int e_dens = ev.mark();
     const MixArgs mix{s->mix_beta, s->kerker_q0, s->pulay_history, s->pulay_period, s->pulay_restart, s->d_pulay,
                       s->iter, 1};
-    if ((st = finish_energy(c, s->d_rho_in, rho_out, &mix, &R, hs)) != SPARC_OK) return st;
-    tm.mark(7);
-    SG_HIP(c, hipEventSynchronize(c->ev[7]));
-    s->bounds[0] = hs[S_A];
-    s->bounds[1] = hs[S_B];
-    s->bounds[2] = hs[S_A0];
-    R.t_potential_ms = tm.ms(0, 1);
+    if ((st = enqueue_energy(c, s->d_rho_in, rho_out, &mix)) != SPARC_OK) return st;
+    const int e_end = ev.mark();
+    SG_HIP(c, hipStreamSynchronize(c->stream));   // the step's one synchronisation
+    sparc_gpu_scf_report R;
+    if ((st = read_report(c, &R)) != SPARC_OK) return st;
+    s->bounds[0] = c->h_scal[S_A];
+    s->bounds[1] = c->h_scal[S_B];
+    s->bounds[2] = c->h_scal[S_A0];
+    double t_filter = 0.0, t_rr = 0.0;
+    for (int pass = 0; pass < npass; ++pass) {
+        t_filter += ev.ms(e_pass[2 * pass], e_pass[2 * pass + 1]);
+        t_rr += ev.ms(e_pass[2 * pass + 1], e_pass[2 * pass + 2]);
+    }
+    R.t_potential_ms = ev.ms(e_begin, e_pot);
     R.t_filter_ms = t_filter;
     R.t_rr_ms = t_rr;
-    R.t_density_ms = tm.ms(5, 6);
-    R.t_total_ms = tm.ms(0, 7);
+    R.t_density_ms = ev.ms(e_pass[2 * npass], e_dens);
+    R.t_total_ms = ev.ms(e_begin, e_end);
     R.n_passes = npass;
     R.iter = s->iter;
     s->iter += 1;
@@ -911,67 +955,72 @@ static sparc_status scf_step_spin_impl(sparc_gpu_ctx c, sparc_gpu_scf_spin_state
     const int N = c->n_states;
     const long nd = c->nd;
     T* Xs[2] = {(T*)s->d_X_up, (T*)s->d_X_dn};
+    const bool first = s->iter == 0;
+    const int npass = first ? s->n_first : 1;
     if ((st = ensure_fields(c, 10)) != SPARC_OK) return st;
     if ((st = ensure_work(c, ((size_t)(N - 1) * s->ldx + nd) * sizeof(T))) != SPARC_OK) return st;
     if ((st = ensure_veff_spin(c)) != SPARC_OK) return st;
+    if ((st = ensure_step_events(c, 2 * (2 * npass + 1) + 6)) != SPARC_OK) return st;
     double* phi = c->field + 2 * nd;
     double* exc = c->field + 3 * nd;
     double* vxc = c->field + 4 * nd;   // 2 N_d
     double* rho_out = s->d_rho_out ? s->d_rho_out : c->field + 6 * nd;
     SG_HIP(c, hipMemsetAsync(c->flags, 0, F_COUNT * sizeof(int), c->stream));
-    Timer tm(c);
-    tm.mark(0);
+    StepEvents ev(c);
+    const int e_begin = ev.mark();
+    if ((st = check_input_density(c, s->d_rho_in, 2 * nd)) != SPARC_OK) return st;
     if ((st = potential_spin_impl(c, s->d_rho_in, phi, exc, vxc, c->veff_spin)) != SPARC_OK) return st;
-    tm.mark(1);
-    const bool first = s->iter == 0;
-    const int npass = first ? s->n_first : 1;
-    double t_filter = 0.0, t_rr = 0.0;
+    const int e_pot = ev.mark();
+    int e_pass[2][2 * 100 + 1];
     for (int sp = 0; sp < 2; ++sp) {
         T* X = Xs[sp];
         double* eig = s->d_eig + (long)sp * N;
         if ((st = set_veff_impl(c, c->veff_spin + sp * nd)) != SPARC_OK) return st;
         if ((st = bounds_impl(c)) != SPARC_OK) return st;
         if (first) {
-            if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, eig, true)) != SPARC_OK) return st;
+            if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, eig, false)) != SPARC_OK) return st;
             k_bounds_from_eig<<<1, 1, 0, c->stream>>>(eig, N, c->scal, 1);
         } else {
             k_set_ab<<<1, 1, 0, c->stream>>>(c->scal, s->bounds[3 * sp], s->bounds[3 * sp + 2]);
         }
         SG_CHECK_LAUNCH(c);
+        e_pass[sp][0] = ev.mark();
         for (int pass = 0; pass < npass; ++pass) {
-            tm.mark(2);
             if ((st = filter_impl<T>(c, X, (T*)c->work, N, s->ldx, s->cheb_degree)) != SPARC_OK) return st;
-            tm.mark(3);
-            if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, eig, true)) != SPARC_OK) return st;
+            e_pass[sp][2 * pass + 1] = ev.mark();
+            if ((st = rayleigh_ritz_impl<T>(c, X, N, s->ldx, eig, false)) != SPARC_OK) return st;
             k_bounds_from_eig<<<1, 1, 0, c->stream>>>(eig, N, c->scal, 0);
             SG_CHECK_LAUNCH(c);
-            tm.mark(4);
-            SG_HIP(c, hipEventSynchronize(c->ev[4]));
-            t_filter += tm.ms(2, 3);
-            t_rr += tm.ms(3, 4);
+            e_pass[sp][2 * pass + 2] = ev.mark();
         }
         k_stash_bounds<<<1, 1, 0, c->stream>>>(c->scal, sp);
         SG_CHECK_LAUNCH(c);
     }
-    tm.mark(5);
+    const int e_dens0 = ev.mark();
     if ((st = occupations_impl(c, s->d_eig, 2 * N, s->d_occ, nullptr, 1.0)) != SPARC_OK) return st;
     for (int sp = 0; sp < 2; ++sp)
         if ((st = density_impl<T>(c, Xs[sp], N, s->ldx, s->d_occ + (long)sp * N, rho_out + sp * nd)) != SPARC_OK)
             return st;
-    tm.mark(6);
-    sparc_gpu_scf_report R;
-    double hs[S_COUNT];
+    const int e_dens = ev.mark();
     const MixArgs mix{s->mix_beta, s->kerker_q0, s->pulay_history, s->pulay_period, s->pulay_restart, s->d_pulay,
                       s->iter, 2};
-    if ((st = finish_energy(c, s->d_rho_in, rho_out, &mix, &R, hs, 2)) != SPARC_OK) return st;
-    tm.mark(7);
-    SG_HIP(c, hipEventSynchronize(c->ev[7]));
-    for (int k = 0; k < 6; ++k) s->bounds[k] = hs[S_SPINB + k];
-    R.t_potential_ms = tm.ms(0, 1);
+    if ((st = enqueue_energy(c, s->d_rho_in, rho_out, &mix, 2)) != SPARC_OK) return st;
+    const int e_end = ev.mark();
+    SG_HIP(c, hipStreamSynchronize(c->stream));   // the step's one synchronisation
+    sparc_gpu_scf_report R;
+    if ((st = read_report(c, &R)) != SPARC_OK) return st;
+    for (int k = 0; k < 6; ++k) s->bounds[k] = c->h_scal[S_SPINB + k];
+    double t_filter = 0.0, t_rr = 0.0;
+    for (int sp = 0; sp < 2; ++sp)
+        for (int pass = 0; pass < npass; ++pass) {
+            t_filter += ev.ms(e_pass[sp][2 * pass], e_pass[sp][2 * pass + 1]);
+            t_rr += ev.ms(e_pass[sp][2 * pass + 1], e_pass[sp][2 * pass + 2]);
+        }
+    R.t_potential_ms = ev.ms(e_begin, e_pot);
     R.t_filter_ms = t_filter;
     R.t_rr_ms = t_rr;
-    R.t_density_ms = tm.ms(5, 6);
-    R.t_total_ms = tm.ms(0, 7);
+    R.t_density_ms = ev.ms(e_dens0, e_dens);
+    R.t_total_ms = ev.ms(e_begin, e_end);
     R.n_passes = 2 * npass;
     R.iter = s->iter;
     s->iter += 1;
@@ -1062,46 +1111,45 @@ static sparc_status scf_step_k_impl(sparc_gpu_ctx c, sparc_gpu_scf_k_state* s, s
             for (int j = 0; j < N2; ++j) w[(size_t)q * N2 + j] = s->kweights[q];
         SG_HIP(c, hipMemcpy(c->kp_wts, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
     }
+    if ((st = ensure_step_events(c, nk * (2 * s->n_first + 1) + 6)) != SPARC_OK) return st;
     double* phi = c->field + 2 * nd;
     double* exc = c->field + 3 * nd;
     double* vxc = c->field + 4 * nd;
     double* rho_out = s->d_rho_out ? s->d_rho_out : c->field + 5 * nd;
     SG_HIP(c, hipMemsetAsync(c->flags, 0, F_COUNT * sizeof(int), c->stream));
-    Timer tm(c);
-    tm.mark(0);
+    StepEvents ev(c);
+    const int e_begin = ev.mark();
+    if ((st = check_input_density(c, s->d_rho_in, nd)) != SPARC_OK) return st;
     if ((st = potential_impl(c, s->d_rho_in, phi, exc, vxc, c->veff)) != SPARC_OK) return st;
-    tm.mark(1);
+    const int e_pot = ev.mark();
     const bool first = s->iter == 0;
     const int npass = first ? s->n_first : 1;
-    double t_filter = 0.0, t_rr = 0.0;
+    std::vector<int> e_pass;   // per k: start, then (filter end, RR end) per pass
     for (int q = 0; q < nk; ++q) {
         for (int d = 0; d < 3; ++d) c->kvec[d] = s->kpts[3 * q + d];
         T* X = (T*)s->d_X[q];
         double* eig = s->d_eig + (long)q * N2;
         if ((st = bloch_bounds_impl(c)) != SPARC_OK) return st;
         if (first) {
-            if ((st = rayleigh_ritz_k_impl<T>(c, X, N2, s->ldx, eig, true)) != SPARC_OK) return st;
+            if ((st = rayleigh_ritz_k_impl<T>(c, X, N2, s->ldx, eig, false)) != SPARC_OK) return st;
             k_bounds_from_eig<<<1, 1, 0, c->stream>>>(eig, N2, c->scal, 1);
         } else {
             k_set_ab<<<1, 1, 0, c->stream>>>(c->scal, s->bounds[3 * q], s->bounds[3 * q + 2]);
         }
         SG_CHECK_LAUNCH(c);
+        e_pass.push_back(ev.mark());
         for (int pass = 0; pass < npass; ++pass) {
-            tm.mark(2);
             if ((st = bloch_filter_impl<T>(c, X, (T*)c->work, N2, s->ldx, s->cheb_degree)) != SPARC_OK) return st;
-            tm.mark(3);
-            if ((st = rayleigh_ritz_k_impl<T>(c, X, N2, s->ldx, eig, true)) != SPARC_OK) return st;
+            e_pass.push_back(ev.mark());
+            if ((st = rayleigh_ritz_k_impl<T>(c, X, N2, s->ldx, eig, false)) != SPARC_OK) return st;
             k_bounds_from_eig<<<1, 1, 0, c->stream>>>(eig, N2, c->scal, 0);
             SG_CHECK_LAUNCH(c);
-            tm.mark(4);
-            SG_HIP(c, hipEventSynchronize(c->ev[4]));
-            t_filter += tm.ms(2, 3);
-            t_rr += tm.ms(3, 4);
+            e_pass.push_back(ev.mark());
         }
         k_stash_kbounds<<<1, 1, 0, c->stream>>>(c->scal, c->kp_bounds, q);
         SG_CHECK_LAUNCH(c);
     }
-    tm.mark(5);
+    const int e_dens0 = ev.mark();
     if ((st = occupations_impl(c, s->d_eig, nk * N2, s->d_occ, nullptr, 1.0, c->kp_wts)) != SPARC_OK) return st;
     for (int q = 0; q < nk; ++q) {
         k_density_k<T><<<div_up(nd, 256), 256, 0, c->stream>>>((const T*)s->d_X[q], N2, s->ldx, nd,
@@ -1109,20 +1157,28 @@ static sparc_status scf_step_k_impl(sparc_gpu_ctx c, sparc_gpu_scf_k_state* s, s
                                                                q > 0 ? 1 : 0);
         SG_CHECK_LAUNCH(c);
     }
-    tm.mark(6);
-    sparc_gpu_scf_report R;
-    double hs[S_COUNT];
+    const int e_dens = ev.mark();
     const MixArgs mix{s->mix_beta, s->kerker_q0, s->pulay_history, s->pulay_period, s->pulay_restart, s->d_pulay,
                       s->iter, 1};
-    if ((st = finish_energy(c, s->d_rho_in, rho_out, &mix, &R, hs)) != SPARC_OK) return st;
-    tm.mark(7);
-    SG_HIP(c, hipEventSynchronize(c->ev[7]));
+    if ((st = enqueue_energy(c, s->d_rho_in, rho_out, &mix)) != SPARC_OK) return st;
+    const int e_end = ev.mark();
+    SG_HIP(c, hipStreamSynchronize(c->stream));
+    sparc_gpu_scf_report R;
+    if ((st = read_report(c, &R)) != SPARC_OK) return st;
     SG_HIP(c, hipMemcpy(s->bounds, c->kp_bounds, 3 * (size_t)nk * sizeof(double), hipMemcpyDeviceToHost));
-    R.t_potential_ms = tm.ms(0, 1);
+    double t_filter = 0.0, t_rr = 0.0;
+    for (int q = 0; q < nk; ++q) {
+        const int* e = e_pass.data() + (size_t)q * (2 * npass + 1);
+        for (int pass = 0; pass < npass; ++pass) {
+            t_filter += ev.ms(e[2 * pass], e[2 * pass + 1]);
+            t_rr += ev.ms(e[2 * pass + 1], e[2 * pass + 2]);
+        }
+    }
+    R.t_potential_ms = ev.ms(e_begin, e_pot);
     R.t_filter_ms = t_filter;
     R.t_rr_ms = t_rr;
-    R.t_density_ms = tm.ms(5, 6);
-    R.t_total_ms = tm.ms(0, 7);
+    R.t_density_ms = ev.ms(e_dens0, e_dens);
+    R.t_total_ms = ev.ms(e_begin, e_end);
     R.n_passes = nk * npass;
     R.iter = s->iter;
     s->iter += 1;
@@ -1209,6 +1265,9 @@ sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx c, sparc_gpu_scf_state* s, do
     if (!d_X64 || ldx64 < c->nd) return set_err(c, SPARC_ERR_ARG, "final_rr_fp64: bad FP64 block");
     const int N = c->n_states;
     if ((st = ensure_fields(c, 6)) != SPARC_OK) return st;
+    if ((st = ensure_step_events(c, 5)) != SPARC_OK) return st;
+    StepEvents ev(c);
+    const int e_begin = ev.mark();   // the promotion of the block is part of the call's time
     dim3 grid(div_up(c->nd, 256), N);
     if (s->prec == SPARC_FP32)
         k_promote<float><<<grid, 256, 0, c->stream>>>((const float*)s->d_X, d_X64, c->nd, N, s->ldx, ldx64);
@@ -1220,23 +1279,23 @@ sparc_status sparc_gpu_final_rr_fp64(sparc_gpu_ctx c, sparc_gpu_scf_state* s, do
     double* exc = c->field + 3 * c->nd;
     double* vxc = c->field + 4 * c->nd;
     double* rho_out = s->d_rho_out ? s->d_rho_out : c->field + 5 * c->nd;
-    Timer tm(c);
-    tm.mark(0);
+    if ((st = check_input_density(c, s->d_rho_in, c->nd)) != SPARC_OK) return st;
     if ((st = potential_impl(c, s->d_rho_in, phi, exc, vxc, c->veff)) != SPARC_OK) return st;
-    tm.mark(1);
-    if ((st = rayleigh_ritz_impl<double>(c, d_X64, N, ldx64, s->d_eig, true)) != SPARC_OK) return st;
-    tm.mark(2);
+    const int e_pot = ev.mark();
+    if ((st = rayleigh_ritz_impl<double>(c, d_X64, N, ldx64, s->d_eig, false)) != SPARC_OK) return st;
+    const int e_rr = ev.mark();
     if ((st = occupations_impl(c, s->d_eig, N, s->d_occ, nullptr)) != SPARC_OK) return st;
     if ((st = density_impl<double>(c, d_X64, N, ldx64, s->d_occ, rho_out)) != SPARC_OK) return st;
-    tm.mark(3);
+    const int e_dens = ev.mark();
+    if ((st = enqueue_energy(c, s->d_rho_in, rho_out, nullptr)) != SPARC_OK) return st;
+    const int e_end = ev.mark();
+    SG_HIP(c, hipStreamSynchronize(c->stream));   // the call's one synchronisation
     sparc_gpu_scf_report R;
-    if ((st = finish_energy(c, s->d_rho_in, rho_out, nullptr, &R, nullptr)) != SPARC_OK) return st;
-    tm.mark(4);
-    SG_HIP(c, hipEventSynchronize(c->ev[4]));
-    R.t_potential_ms = tm.ms(0, 1);
-    R.t_rr_ms = tm.ms(1, 2);
-    R.t_density_ms = tm.ms(2, 3);
-    R.t_total_ms = tm.ms(0, 4);
+    if ((st = read_report(c, &R)) != SPARC_OK) return st;
+    R.t_potential_ms = ev.ms(e_begin, e_pot);
+    R.t_rr_ms = ev.ms(e_pot, e_rr);
+    R.t_density_ms = ev.ms(e_rr, e_dens);
+    R.t_total_ms = ev.ms(e_begin, e_end);
     R.n_passes = 0;
     R.iter = s->iter;
     if (rep) *rep = R;

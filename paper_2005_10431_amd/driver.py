@@ -13,9 +13,12 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
             pulay_history: int = None, pulay_period: int = None, pulay_restart: bool = None):
     """Run the SCF iteration on the GPU.
 
-    X0: (N_s, N_d) numpy array (random block, see ``workloads.initial_orbitals``);
+    X0: (N_s, N_d) numpy array or tensor (random block, see
+    ``workloads.initial_orbitals``; a tensor is copied, never overwritten);
     rho0: (N_d,) numpy array or float64 tensor, or None for the atomic-density
     guess.
+    callback(report) is called after every iteration; a true return value
+    ends the loop there (before the final FP64 Rayleigh-Ritz of the FP32 form).
     Returns a dict with the history of reports and the final device tensors."""
     import torch
     ctx = ctx or Context(system)
@@ -24,7 +27,12 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
     if X0 is None:
         from workloads import initial_orbitals
         X0 = initial_orbitals(nd, ns, system.seed)
-    X = torch.as_tensor(np.asarray(X0), dtype=dt).to(device).contiguous()
+    if isinstance(X0, torch.Tensor):
+        # a private copy: the SCF overwrites its block
+        X = torch.empty((ns, nd), dtype=dt, device=device)
+        X.copy_(X0)
+    else:
+        X = torch.as_tensor(np.asarray(X0), dtype=dt).to(device).contiguous()
     rho_in = torch.empty(nd, dtype=torch.float64, device=device)
     if rho0 is None:
         ctx.sad_density(rho_in)
@@ -49,8 +57,8 @@ def run_scf(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int = 100,
         rep = ctx.scf_step(st)
         rep["eig"] = eig.detach().cpu().numpy().copy()
         hist.append(rep)
-        if callback is not None:
-            callback(rep)
+        if callback is not None and callback(rep):
+            break
         if rep["residual"] < tol:
             break
     out = dict(history=hist, X=X, eig=eig, occ=occ, rho_in=rho_in, rho_out=rho_out, state=st, ctx=ctx,
@@ -86,11 +94,7 @@ def run_scf_spin(system, X0=None, rho0=None, prec: str = "fp64", max_iter: int =
     Xd = torch.as_tensor(np.asarray(X0[1]), dtype=dt).to(device).contiguous()
     rho_in = torch.empty(2 * nd, dtype=torch.float64, device=device)
     if rho0 is None:
-        ctx.sad_density(rho_in[:nd])
-        z = float(getattr(system, "spin_zeta0", 0.0))
-        rho_in[nd:].copy_(rho_in[:nd])
-        rho_in[:nd].mul_(0.5 * (1.0 + z))
-        rho_in[nd:].mul_(0.5 * (1.0 - z))
+        ctx.sad_density_spin(float(getattr(system, "spin_zeta0", 0.0)), rho_in)
     else:
         src = rho0 if isinstance(rho0, torch.Tensor) else torch.as_tensor(np.asarray(rho0), dtype=torch.float64)
         rho_in.copy_(src)

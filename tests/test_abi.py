@@ -74,3 +74,39 @@ def test_null_context_is_rejected_without_a_device(lib):
     lib.sparc_gpu_create.restype = ctypes.c_int
     lib.sparc_gpu_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.sparc_gpu_create(None, None, None) == 1
+
+
+def _system_struct(n, half_order):
+    """A valid one-atom local-only system on an n[0] x n[1] x n[2] grid."""
+    from paper_2005_10431_amd import _lib
+    s = _lib.System()
+    for d in range(3):
+        s.n[d] = n[d]
+        s.L[d] = 0.3 * n[d]
+    s.fd_half_order = half_order
+    keep = [(ctypes.c_double * 3)(0.5, 0.5, 0.5), (ctypes.c_double * 1)(2.0), (ctypes.c_double * 1)(0.8)]
+    s.n_atoms = 1
+    s.pos = ctypes.cast(keep[0], ctypes.POINTER(ctypes.c_double))
+    s.Z = ctypes.cast(keep[1], ctypes.POINTER(ctypes.c_double))
+    s.rc_loc = ctypes.cast(keep[2], ctypes.POINTER(ctypes.c_double))
+    s.nl_lmax = -1
+    s.n_states = 4
+    s.n_electrons = 2.0
+    s.kT = 0.01
+    s.rho_floor = 1e-14
+    s.sad_width = 1.0
+    return s, keep
+
+
+@pytest.mark.parametrize("n, half_order", [((5, 5, 5), 2), ((12, 20, 20), 6), ((20, 12, 20), 3),
+                                           ((20, 20, 12), 1), ((13, 13, 13), 7), ((13, 13, 13), 0)])
+def test_create_rejects_grids_below_the_kernel_half_width(lib, n, half_order):
+    """Every axis needs 13 points (twice the kernels' stencil half-width of 6,
+    plus one) whatever the order; lower orders do not relax it.  Validation
+    runs before any device call, so this needs no GPU."""
+    s, keep = _system_struct(n, half_order)
+    lib.sparc_gpu_create.restype = ctypes.c_int
+    lib.sparc_gpu_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    out = ctypes.c_void_p(7)
+    assert lib.sparc_gpu_create(ctypes.byref(s), None, ctypes.byref(out)) == 1   # SPARC_ERR_ARG
+    assert out.value is None

@@ -3,7 +3,8 @@
 1200-column block is processed in the launch configuration of the library,
 and the oracle recomputes sampled columns one by one (every column of H X
 and of the filter depends on that column alone).  FP64 to 1e-12 (H X) and
-1e-11 (filter) relative; FP32 H X to 2e-6."""
+1e-11 (filter) relative; FP32 H X to 2e-6 and the FP32 filter to
+2 m 2e-6 (each sweep at most one FP32 H X error, adding linearly)."""
 import numpy as np
 import pytest
 
@@ -72,3 +73,32 @@ def test_cfg4_full_block_apply_and_filter():
         err = rel_err(to_np(Y32[j]).astype(np.float64), yref)
         log(f"  FP32 H X column {j}: rel err {err:.2e}")
         assert err <= 2e-6
+
+
+def test_cfg4_full_block_fp32_filter():
+    """Degree-24 FP32 filter with projectors over the full 1200-column block;
+    the oracle filters one FP32-rounded column alone in FP64."""
+    torch = require_gpu()
+    from paper_2005_10431_amd import Context
+    s = W.config4(0)
+    log("cfg4 FP32 filter: 120^3 grid, 500 atoms, 1200 states")
+    ctx = Context(s)
+    projs = atoms.projectors(s)
+    v = np.random.default_rng(32).uniform(-1.0, 1.0, s.nd)
+    ctx.set_veff(to_dev(torch, v))
+    j = 977
+    X, ref_rows = _block(torch, s, 4, (j,))
+    X32 = X.to(torch.float32)
+    del X
+    torch.cuda.empty_cache()
+    lo, hi = hamiltonian.spectrum_bounds(s, v, projs)
+    a, b, a0 = lo + 0.05 * (hi - lo), hi, lo
+    Wk = torch.empty_like(X32)
+    ctx.chebyshev_filter(X32, Wk, s.cheb_degree, a, b, a0)
+    torch.cuda.synchronize()
+    x32 = ref_rows[j].astype(np.float32).astype(np.float64)
+    yref = chefsi.chebyshev_filter(s, v, projs, x32[None], s.cheb_degree, a, b, a0)[0]
+    err = rel_err(to_np(X32[j]).astype(np.float64), yref)
+    bar = 2.0 * s.cheb_degree * 2e-6
+    log(f"  FP32 filter (degree {s.cheb_degree}) column {j}: rel err {err:.2e} (bar {bar:.1e})")
+    assert err <= bar

@@ -140,6 +140,64 @@ def test_chebyshev_filter_cfg2_sampled_columns():
         assert rel_err(to_np(Xd[j]), yref) <= 1e-11, j
 
 
+# FP32 filter bar: each of the m sweeps commits at most the rounding of one
+# FP32 stencil application (the H X bar of 2e-6 relative, test_apply_H_fp32),
+# errors add at worst linearly, and the scaled recurrence keeps every iterate
+# within the norm of its input; a factor 2 covers the recurrence term.
+def fp32_filter_bar(m):
+    return 2.0 * m * 2e-6
+
+
+@pytest.mark.parametrize("make", [ragged_system, small_images_system], ids=["ragged", "images"])
+@pytest.mark.parametrize("degree", [7, 8])
+def test_chebyshev_filter_fp32_nonlocal(make, degree):
+    """FP32 filter with s+p projectors (the nonlocal sweep in its first-step
+    and later-step forms, odd and even degree) against the oracle filtering
+    the same FP32-rounded block in FP64."""
+    torch = require_gpu()
+    s = make()
+    log("filter fp32 nonlocal", s.n, "degree", degree)
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 23)
+    lo, hi = hamiltonian.spectrum_bounds(s, v, projs)
+    a, b, a0 = lo + 0.3 * (hi - lo), hi, lo
+    X = W.initial_orbitals(s.nd, 6, 9).astype(np.float32)
+    Yref = chefsi.chebyshev_filter(s, v, projs, X.astype(np.float64), degree, a, b, a0)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Wd = torch.zeros_like(Xd)
+    ctx.chebyshev_filter(Xd, Wd, degree, a, b, a0)
+    err = rel_err(to_np(Xd).astype(np.float64), Yref)
+    log(f"  rel err {err:.2e} (bar {fp32_filter_bar(degree):.1e})")
+    assert err <= fp32_filter_bar(degree)
+
+
+def test_chebyshev_filter_fp32_cfg2_sampled_columns():
+    """Degree-20 FP32 filter over the full config-2 block with projectors, in
+    the launch configuration of the benchmark; the oracle filters two of the
+    FP32-rounded columns alone in FP64."""
+    torch = require_gpu()
+    s = W.config2(0)
+    log("filter fp32 cfg2 full block")
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 24, 1.0)
+    lo, hi = hamiltonian.spectrum_bounds(s, v, projs)
+    a, b, a0 = lo + 0.05 * (hi - lo), hi, lo
+    X = W.initial_orbitals(s.nd, s.n_states, 3).astype(np.float32)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Wd = torch.empty_like(Xd)
+    ctx.chebyshev_filter(Xd, Wd, s.cheb_degree, a, b, a0)
+    torch.cuda.synchronize()
+    for j in (5, 259):
+        yref = chefsi.chebyshev_filter(s, v, projs, X[j:j + 1].astype(np.float64), s.cheb_degree, a, b, a0)[0]
+        err = rel_err(to_np(Xd[j]).astype(np.float64), yref)
+        log(f"  column {j}: rel err {err:.2e}")
+        assert err <= fp32_filter_bar(s.cheb_degree), j
+
+
 def _projector(X, dV):
     return dV * X.T @ X
 
@@ -211,6 +269,54 @@ def test_rayleigh_ritz_fp32():
     np.testing.assert_allclose(to_np(eig), lam, atol=2e-4 * np.max(np.abs(lam)))
     Xg = to_np(Xd).astype(np.float64)
     assert np.max(np.abs(s.dV * Xg @ Xg.T - np.eye(8))) < 1e-5
+
+
+def _span_sines(s, Xg, Xr, k):
+    """Sines of the principal angles between the spans of the first k rows."""
+    cos = np.linalg.svd(s.dV * Xg[:k] @ Xr[:k].T, compute_uv=False)
+    return np.sqrt(np.maximum(0.0, 1.0 - np.minimum(cos, 1.0) ** 2))
+
+
+@pytest.mark.parametrize("ncol, tile", [(400, "by_size"), (400, "160"), (1200, "by_size")])
+def test_rayleigh_ritz_fp32_wide_block(ncol, tile, monkeypatch):
+    """FP32 Rayleigh-Ritz at the subspace sizes of the benchmark workloads:
+    Gram and projected H on FP32 MFMA tiles (128-wide above N = 320, and the
+    160-wide tiles at 400 columns) with split-K partials reduced in FP64,
+    FP64 Cholesky and eigensolver, FP32 rotation.  Against the oracle's FP64
+    Rayleigh-Ritz of the same FP32-rounded block:
+      - Ritz values within 2e-4 max|lambda| (the 8-column FP32 bar);
+      - dV X^T X = I within 1e-5 (FP32 rounding of the rotated block);
+      - the lowest k states span the oracle's subspace, k at the widest
+        spectral gap between 20 and 60: by the Davis-Kahan bound the sines of
+        the principal angles stay below 2 delta / gap, delta the Ritz bar."""
+    torch = require_gpu()
+    if tile != "by_size":
+        monkeypatch.setenv("SPARC_GPU_GEMM_TILE", tile)
+    s = small_images_system(n_states=ncol) if ncol <= 400 else ragged_system(n_states=ncol)
+    log("rayleigh_ritz fp32", ncol, "columns, tile", tile, "grid", s.n)
+    ctx = _ctx(s)
+    projs = atoms.projectors(s)
+    v = _veff(s, 19)
+    X = W.initial_orbitals(s.nd, ncol, 11).astype(np.float32)
+    Xr, lam = chefsi.rayleigh_ritz(s, v, projs, X.astype(np.float64))
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    eig = torch.zeros(ncol, dtype=torch.float64, device="cuda")
+    ctx.rayleigh_ritz(Xd, eig)
+    Xg = to_np(Xd).astype(np.float64)
+    delta = 2e-4 * float(np.max(np.abs(lam)))
+    dl = np.max(np.abs(to_np(eig) - lam))
+    O = s.dV * Xg @ Xg.T
+    orth = np.max(np.abs(O - np.eye(ncol)))
+    gaps = lam[21:61] - lam[20:60]
+    k = 21 + int(np.argmax(gaps))
+    gap = float(np.max(gaps))
+    sines = _span_sines(s, Xg, Xr, k)
+    log(f"  max|dlam| {dl:.2e} (bar {delta:.2e}), orthonormality {orth:.2e}, span k={k} gap {gap:.3e} "
+        f"max sin {np.max(sines):.2e}")
+    assert dl <= delta
+    assert orth <= 1e-5
+    assert np.max(sines) <= min(1.0, 2.0 * delta / gap)
 
 
 def test_rayleigh_ritz_1200_columns():

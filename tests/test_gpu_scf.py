@@ -156,3 +156,46 @@ def test_scf_cfg2_fixed_point():
     t = scf.energy_terms(s, st_o, rin, phi, exc, vxc, lam, g)
     log(f"  F gpu {rep['free_energy']:.12f} oracle {t['free']:.12f}")
     assert abs(t["free"] - rep["free_energy"]) <= 1e-9 * abs(t["free"])
+
+
+def _state(torch, s, ctx, X0, rho_in=None):
+    from paper_2005_10431_amd import make_state
+    X = torch.as_tensor(X0).cuda()
+    rho = torch.empty(s.nd, dtype=torch.float64, device="cuda")
+    if rho_in is None:
+        ctx.sad_density(rho)
+    else:
+        rho.copy_(torch.as_tensor(rho_in))
+    eig = torch.empty(s.n_states, dtype=torch.float64, device="cuda")
+    occ = torch.empty_like(eig)
+    st = make_state(rho, X, eig, occ, s.cheb_degree, s.n_first, s.mix_beta)
+    return st, (X, rho, eig, occ)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_scf_step_reports_nonfinite_input_density(bad):
+    """A NaN or Inf in rho_in makes sparc_gpu_scf_step return
+    SPARC_ERR_NONFINITE (read with the step's one synchronisation) without
+    advancing the state; the same context then runs a clean state's step to
+    the same result, bit for bit, as a fresh context."""
+    torch = require_gpu()
+    from paper_2005_10431_amd import Context, SparcError
+    s = W.config1(0)
+    X0 = W.initial_orbitals(s.nd, s.n_states, s.seed)
+    ctx = Context(s)
+    rho_bad = np.full(s.nd, 0.01)
+    rho_bad[s.nd // 3] = bad
+    st, keep = _state(torch, s, ctx, X0, rho_bad)
+    with pytest.raises(SparcError) as ei:
+        ctx.scf_step(st)
+    assert ei.value.name == "SPARC_ERR_NONFINITE"
+    assert st.iter == 0
+    st2, keep2 = _state(torch, s, ctx, X0)
+    r1 = ctx.scf_step(st2)
+    fresh = Context(s)
+    st3, keep3 = _state(torch, s, fresh, X0)
+    r2 = fresh.scf_step(st3)
+    assert r1["free_energy"] == r2["free_energy"] and r1["residual"] == r2["residual"]
+    assert torch.equal(keep2[2], keep3[2]) and torch.equal(keep2[1], keep3[1])
+    ctx.close()
+    fresh.close()

@@ -51,6 +51,30 @@ def test_potential_spin_matches_oracle():
         ctx.close()
 
 
+@pytest.mark.parametrize("zeta0", [1.0 / 15.0, -0.4, 1.0])
+def test_sad_density_spin_matches_oracle(zeta0):
+    """The split atomic-density guess is formed in the library (spin up
+    (1 + zeta0) rho / 2, down (1 - zeta0) rho / 2); zeta0 outside [-1, 1]
+    is rejected."""
+    torch = require_gpu()
+    from paper_2005_10431_amd import Context, SparcError
+    s = replace(W.config1_spin(0), spin_zeta0=zeta0)
+    ctx = Context(s)
+    try:
+        up, dn = scf.sad_density_spin(s)
+        rho = torch.full((2 * s.nd,), 7.0, dtype=torch.float64, device="cuda")
+        ctx.sad_density_spin(zeta0, rho)
+        r = to_np(rho)
+        assert np.max(np.abs(r[:s.nd] - up)) <= 1e-13 * np.max(up)
+        assert np.max(np.abs(r[s.nd:] - dn)) <= 1e-13 * max(np.max(up), 1e-300)
+        assert abs(s.dV * r.sum() - s.n_electrons) <= 1e-11 * s.n_electrons
+        for bad in (1.5, -1.01, float("nan")):
+            with pytest.raises(SparcError):
+                ctx.sad_density_spin(bad, rho)
+    finally:
+        ctx.close()
+
+
 def test_occupations_spin_match_oracle():
     torch = require_gpu()
     from paper_2005_10431_amd import Context
