@@ -11,6 +11,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <numeric>
+#include <unordered_map>
 
 #include "internal.hpp"
 
@@ -67,7 +68,6 @@ void prof_end(sparc_gpu_ctx c, int slot, hipStream_t s) {
 static sparc_status prof_flush(sparc_gpu_ctx c) {
     if (c->prof_used == 0) return SPARC_OK;
     SG_HIP(c, hipStreamSynchronize(c->stream));
-    if (c->aux_stream) SG_HIP(c, hipStreamSynchronize(c->aux_stream));
     for (int i = 0; i < c->prof_used; ++i) {
         float ms = 0.f;
         SG_HIP(c, hipEventElapsedTime(&ms, c->prof_pool[2 * i], c->prof_pool[2 * i + 1]));
@@ -280,6 +280,32 @@ __global__ void k_scale(double* v, long n, const double* num, double target) {
     if (i < n) v[i] *= target / *num;
 }
 
+// eyez, dy, dz of every sweep pair: the line (slab row, plane) of pair q
+// against its candidate's image-shifted centre.  The pair's (slab, plane)
+// list is found by binary search in pair_off.
+__global__ void k_pair_geometry(SweepPair* pairs, long n, const int* pair_off, int nlists, const CandInfo* cand,
+                                int kmax, int nz, int ty, const double* pos, double hy, double hz, double Ly,
+                                double Lz, double inv_rc2) {
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    int lo = 0, hi = nlists;   // pair_off[lo] <= q < pair_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (pair_off[mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    const int sl = lo / nz, z = lo - sl * nz;
+    SweepPair& P = pairs[q];
+    const CandInfo ci = cand[(long)sl * kmax + P.k];
+    const double cy = pos[3 * ci.atom + 1] - (double)ci.sy * Ly;
+    const double cz = pos[3 * ci.atom + 2] - (double)ci.sz * Lz;
+    const double dy = (double)(sl * ty + P.row) * hy - cy;
+    const double dz = (double)z * hz - cz;
+    P.dy = dy;
+    P.dz = dz;
+    P.eyez = exp(-(dy * dy + dz * dz) * inv_rc2);
+}
+
 // ------------------------------------------------------------------ host set-up
 
 static long factorial(int n) {
@@ -378,85 +404,163 @@ static double symbol(const double* w, int n_o, double th) {
     return s;
 }
 
-// Per-slab projector tables of the sweep kernel.  The grid is cut into
-// y-slabs of c->nl_ty rows.  A "candidate" of a slab is an (atom, periodic
-// image) pair whose support meets the slab; point p of the slab stores the
-// slab-local indices of its candidates as bytes of pe8[p] (0xFF pads).  For
-// each candidate the unwrapped x and z index ranges touched inside the slab
-// are recorded, so the sweep can tabulate the separable Gaussian factors.
-sparc_status build_slab_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent) {
+// Per-slab tables of the nonlocal sweep.  The grid is cut into y-slabs of
+// ty rows.  A candidate of a slab is an (atom, periodic image) pair whose
+// support meets the slab; the image shift of a support point is the floor of
+// its unwrapped index over the grid size, so every candidate's points lie
+// inside the periodic cell.  The support of a candidate on one grid line
+// (slab row, plane) is a segment of consecutive x (a ball meets a line in a
+// segment); each (plane, candidate, row) segment is a "pair".  Per (slab,
+// plane) the pairs are listed by (candidate, row), and point p stores the
+// byte indices of its pairs in its plane's list in pe8[p] (0xFF pads).
+sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent, int ty) {
     sg::NonlocalTables& T = c->nl;
-    const int ty = c->nl_ty;
-    const int nslab = (c->ny + ty - 1) / ty;
-    std::vector<uint64_t> pe8(c->nd, ~0ull);
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const int nslab = (ny + ty - 1) / ty;
+    // slab-local candidate index of every image entry
+    std::vector<std::vector<uint32_t>> cand_key(nslab);
     std::vector<std::vector<CandInfo>> cands(nslab);
-    int kmax = 0, xw = 0, zw = 0;
-    for (int sidx = 0; sidx < nslab; ++sidx) {
-        const int y0 = sidx * ty, tyn = std::min(ty, c->ny - y0);
-        std::vector<std::pair<uint32_t, int>> keys;  // packed word -> local index
-        auto& cl = cands[sidx];
-        for (int z = 0; z < c->nz; ++z)
-            for (int y = y0; y < y0 + tyn; ++y)
-                for (int x = 0; x < c->nx; ++x) {
-                    const long p = x + (long)c->nx * (y + (long)c->ny * z);
-                    int cnt = 0;
-                    uint64_t word = ~0ull;
-                    for (int e = c->pe_off_host[p]; e < c->pe_off_host[p + 1]; ++e) {
-                        const uint32_t w = ent[e];
-                        int k = -1;
-                        for (auto& kv : keys)
-                            if (kv.first == w) {
-                                k = kv.second;
-                                break;
-                            }
-                        const int sx = (int)((w >> 20) & 15u) - 8, sz = (int)(w >> 28) - 8;
-                        const int ix = x + sx * c->nx, iz = z + sz * c->nz;
-                        if (k < 0) {
-                            k = (int)cl.size();
-                            keys.push_back({w, k});
-                            CandInfo ci;
-                            ci.atom = (int)(w & 0xFFFFFu);
-                            ci.sx = sx;
-                            ci.sy = (int)((w >> 24) & 15u) - 8;
-                            ci.sz = sz;
-                            ci.ixlo = ci.ixhi = ix;
-                            ci.izlo = ci.izhi = iz;
-                            cl.push_back(ci);
-                        }
-                        CandInfo& ci = cl[k];
-                        ci.ixlo = std::min(ci.ixlo, ix);
-                        ci.ixhi = std::max(ci.ixhi, ix);
-                        ci.izlo = std::min(ci.izlo, iz);
-                        ci.izhi = std::max(ci.izhi, iz);
-                        if (k > 254 || cnt >= 7)
-                            return set_err(c, SPARC_ERR_ARG,
-                                           "projector overlap too dense for the sweep tables (> 254 images per slab "
-                                           "or > 7 projectors at one point)");
-                        word &= ~(0xFFull << (8 * cnt));
-                        word |= (uint64_t)k << (8 * cnt);
-                        ++cnt;
-                    }
-                    pe8[p] = word;
-                }
-        kmax = std::max(kmax, (int)cl.size());
-        for (auto& ci : cl) {
-            xw = std::max(xw, ci.ixhi - ci.ixlo + 1);
-            zw = std::max(zw, ci.izhi - ci.izlo + 1);
+    struct Tup {
+        uint64_t key;   // (slab, z, k, row) for sorting
+        int x;
+        long e;         // entry index
+    };
+    std::vector<Tup> tup;
+    tup.reserve(ent.size());
+    std::vector<std::unordered_map<uint32_t, int>> kmap(nslab);
+    for (long p = 0; p < c->nd; ++p) {
+        const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((long)nx * ny));
+        const int sl = y / ty, row = y - sl * ty;
+        for (int e = c->pe_off_host[p]; e < c->pe_off_host[p + 1]; ++e) {
+            const uint32_t w = ent[e];
+            auto& km = kmap[sl];
+            const auto it = km.find(w);
+            int k = it == km.end() ? -1 : it->second;
+            const int sx = (int)((w >> 20) & 15u) - 8, sz = (int)(w >> 28) - 8;
+            const int ix = x + sx * nx, iz = z + sz * nz;
+            if (k < 0) {
+                k = (int)cands[sl].size();
+                km.emplace(w, k);
+                CandInfo ci;
+                ci.atom = (int)(w & 0xFFFFFu);
+                ci.sx = sx;
+                ci.sy = (int)((w >> 24) & 15u) - 8;
+                ci.sz = sz;
+                ci.ixlo = ci.ixhi = ix;
+                ci.izlo = ci.izhi = iz;
+                cands[sl].push_back(ci);
+            }
+            CandInfo& ci = cands[sl][k];
+            ci.ixlo = std::min(ci.ixlo, ix);
+            ci.ixhi = std::max(ci.ixhi, ix);
+            ci.izlo = std::min(ci.izlo, iz);
+            ci.izhi = std::max(ci.izhi, iz);
+            if (k >= 1023 || row >= 63)
+                return set_err(c, SPARC_ERR_ARG, "projector overlap too dense for the sweep tables");
+            tup.push_back({(((uint64_t)sl * nz + z) << 20) | ((uint64_t)k << 6) | (uint64_t)row, x, e});
         }
+    }
+    std::sort(tup.begin(), tup.end(), [](const Tup& A, const Tup& B) {
+        return A.key < B.key || (A.key == B.key && A.x < B.x);
+    });
+    // group into pairs; per (slab, plane) the lists are consecutive
+    std::vector<SweepPair> pairs;
+    std::vector<int> pair_off((size_t)nslab * nz + 1, 0);
+    std::vector<int> ent_pair(ent.size(), -1);   // pair index (within its plane list) of every entry
+    int pmax = 0;
+    size_t i = 0;
+    while (i < tup.size()) {
+        const uint64_t sz_key = tup[i].key >> 20;
+        size_t j = i;
+        int npl = 0;
+        while (j < tup.size() && (tup[j].key >> 20) == sz_key) {
+            size_t q = j;
+            while (q < tup.size() && tup[q].key == tup[j].key) ++q;
+            const int xlo = tup[j].x, n = (int)(q - j);
+            if (tup[q - 1].x != xlo + n - 1)
+                return set_err(c, SPARC_ERR_ARG, "projector support is not a segment on a grid line");
+            if (n > 255 || xlo > 255) return set_err(c, SPARC_ERR_ARG, "projector segment too long for the sweep tables");
+            if (npl >= 255) return set_err(c, SPARC_ERR_ARG, "more than 255 projector segments in one slab plane");
+            SweepPair sp;
+            sp.k = (int)((tup[j].key >> 6) & 1023u);
+            sp.row = (int)(tup[j].key & 63u);
+            sp.xlo = xlo;
+            sp.n = n;
+            sp.run = 0;
+            sp.pad = 0;
+            sp.eyez = sp.dy = sp.dz = 0.0;
+            // run length of the candidate's pairs, held by its first pair
+            if (npl == 0 || pairs.back().k != sp.k) {
+                int r = 0;
+                for (size_t q2 = j; q2 < tup.size() && (tup[q2].key >> 6) == (tup[j].key >> 6); ++q2)
+                    if (q2 == j || (tup[q2].key & 63u) != (tup[q2 - 1].key & 63u)) ++r;
+                sp.run = r;
+            }
+            for (size_t r = j; r < q; ++r) ent_pair[tup[r].e] = npl;
+            pairs.push_back(sp);
+            ++npl;
+            j = q;
+        }
+        pair_off[sz_key + 1] = npl;
+        pmax = std::max(pmax, npl);
+        i = j;
+    }
+    for (size_t q = 0; q < (size_t)nslab * nz; ++q) pair_off[q + 1] += pair_off[q];
+    // per point: its pairs (at most 7)
+    std::vector<uint64_t> pe8(c->nd, ~0ull);
+    for (long p = 0; p < c->nd; ++p) {
+        uint64_t word = ~0ull;
+        int cnt = 0;
+        for (int e = c->pe_off_host[p]; e < c->pe_off_host[p + 1]; ++e) {
+            if (cnt >= 7) return set_err(c, SPARC_ERR_ARG, "more than 7 projector supports meet at one point");
+            word &= ~(0xFFull << (8 * cnt));
+            word |= (uint64_t)ent_pair[e] << (8 * cnt);
+            ++cnt;
+        }
+        pe8[p] = word;
+    }
+    int kmax = 0, xw = 0;
+    for (int sl = 0; sl < nslab; ++sl) {
+        kmax = std::max(kmax, (int)cands[sl].size());
+        for (auto& ci : cands[sl]) xw = std::max(xw, ci.ixhi - ci.ixlo + 1);
     }
     T.slab_kmax = std::max(kmax, 1);
     T.slab_xw = std::max(xw, 1);
-    T.slab_zw = std::max(zw, 1);
+    T.pair_max = std::max(pmax, 1);
     std::vector<CandInfo> flat((size_t)nslab * T.slab_kmax);
     std::vector<int> kcount(nslab);
-    for (int sidx = 0; sidx < nslab; ++sidx) {
-        kcount[sidx] = (int)cands[sidx].size();
-        for (size_t k = 0; k < cands[sidx].size(); ++k) flat[(size_t)sidx * T.slab_kmax + k] = cands[sidx][k];
+    for (int sl = 0; sl < nslab; ++sl) {
+        kcount[sl] = (int)cands[sl].size();
+        for (size_t k = 0; k < cands[sl].size(); ++k) flat[(size_t)sl * T.slab_kmax + k] = cands[sl][k];
+    }
+    // the (slab, candidate) partials of each atom, in (slab, candidate) order
+    std::vector<int> red_off(c->n_atoms + 1, 0), red_idx;
+    {
+        std::vector<std::vector<int>> per_atom(c->n_atoms);
+        for (int sl = 0; sl < nslab; ++sl)
+            for (size_t k = 0; k < cands[sl].size(); ++k)
+                per_atom[cands[sl][k].atom].push_back(sl * T.slab_kmax + (int)k);
+        for (int a = 0; a < c->n_atoms; ++a) {
+            red_off[a + 1] = red_off[a] + (int)per_atom[a].size();
+            red_idx.insert(red_idx.end(), per_atom[a].begin(), per_atom[a].end());
+        }
     }
     sparc_status st;
     if ((st = upload(c, &T.pe8, pe8)) != SPARC_OK) return st;
     if ((st = upload(c, &T.slab_cand, flat)) != SPARC_OK) return st;
     if ((st = upload(c, &T.slab_k, kcount)) != SPARC_OK) return st;
+    if ((st = upload(c, &T.pairs, pairs)) != SPARC_OK) return st;
+    if ((st = upload(c, &T.pair_off, pair_off)) != SPARC_OK) return st;
+    if ((st = upload(c, &T.red_off, red_off)) != SPARC_OK) return st;
+    if ((st = upload(c, &T.red_idx, red_idx)) != SPARC_OK) return st;
+    // geometry of every pair on the device
+    if (!pairs.empty()) {
+        k_pair_geometry<<<div_up((long)pairs.size(), 256), 256, 0, c->stream>>>(
+            T.pairs, (long)pairs.size(), T.pair_off, nslab * nz, T.slab_cand, T.slab_kmax, nz, ty, c->atom_pos,
+            c->hy, c->hz, (double)ny * c->hy, (double)nz * c->hz, 1.0 / (c->rc_nl * c->rc_nl));
+        SG_CHECK_LAUNCH(c);
+    }
+    c->nl_ty = ty;
     return SPARC_OK;
 }
 
@@ -533,6 +637,9 @@ sparc_status build_tables(sparc_gpu_ctx c) {
         hipFree(d_sum);
         hipFree(d_pos);
     }
+
+    // --- atom positions for the on-the-fly projector evaluation
+    if ((st = upload(c, &c->atom_pos, c->pos)) != SPARC_OK) return st;
 
     // --- nonlocal projector tables
     if (c->nl_lmax >= 1) {
@@ -622,21 +729,29 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             std::vector<int> fill(c->pe_off_host.begin(), c->pe_off_host.end() - 1);
             for (auto& q : img_pts) ent[fill[q.first]++] = q.second;
             T.n_pe = (long)ent.size();
-            // slab height: the largest (up to the 512-thread workgroup) whose
-            // FP64 sweep tables fit in LDS
-            for (int ty = c->nl_ty;; --ty) {
-                c->nl_ty = ty;
-                st = build_slab_tables(c, ent);
-                const size_t KM = c->nl.slab_kmax;
-                const size_t lds =
-                    nl_sweep_lds_bytes(ty, c->nx, KM, c->nl.slab_xw, c->nl.slab_zw, sizeof(double));
+            // slab height: from the nonlocal sweep's largest choice down, the
+            // first whose tables fit (at most 255 segments per slab plane, the
+            // FP64 sweep and the 2-orbital FP64 projection within 160 KB of LDS)
+            for (int ty = choose_sweep_ty(c->nx, c->ny, nl_sweep_max_threads());; --ty) {
+                st = build_pair_tables(c, ent, ty);
+                const NonlocalTables& N = c->nl;
+                const size_t lds = st == SPARC_OK
+                                       ? std::max(nl_sweep_lds_bytes(ty, c->nx, c->nz, N.slab_kmax, N.slab_xw, 8),
+                                                  nl_proj_lds_bytes(ty, c->nx, N.slab_kmax, N.slab_xw, N.pair_max,
+                                                                    2, 8))
+                                       : 0;
                 if (st == SPARC_OK && lds <= 160 * 1024) break;
-                if (ty <= 2) return st != SPARC_OK ? st : set_err(c, SPARC_ERR_ARG, "projector tables exceed LDS");
-                for (void* p : {(void*)T.pe8, (void*)T.slab_cand, (void*)T.slab_k})
+                if (ty <= 1) return st != SPARC_OK ? st : set_err(c, SPARC_ERR_ARG, "projector tables exceed LDS");
+                for (void* p : {(void*)T.pe8, (void*)T.slab_cand, (void*)T.slab_k, (void*)T.pairs, (void*)T.pair_off,
+                                (void*)T.red_off, (void*)T.red_idx})
                     if (p) hipFree(p);
                 T.pe8 = nullptr;
                 T.slab_cand = nullptr;
                 T.slab_k = nullptr;
+                T.pairs = nullptr;
+                T.pair_off = nullptr;
+                T.red_off = nullptr;
+                T.red_idx = nullptr;
                 c->err.clear();
             }
         }
@@ -713,8 +828,6 @@ sparc_status build_tables(sparc_gpu_ctx c) {
         SG_HIP(c, hipMalloc((void**)&c->D32, std::max<size_t>(1, 4 * (size_t)c->n_atoms * c->n_states) * sizeof(float)));
     }
 
-    // --- atom positions for the on-the-fly projector evaluation
-    if ((st = upload(c, &c->atom_pos, c->pos)) != SPARC_OK) return st;
 
     // --- Poisson eigenbases
     {
@@ -808,17 +921,13 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     c->sad_width = s->sad_width;
     c->stream = (hipStream_t)hip_stream;
     for (int i = 0; i < 8; ++i) c->ev[i] = nullptr;
-    if (const char* e = std::getenv("SPARC_GPU_SWEEP_SLAB_MAJOR")) c->sweep_slab_major = std::atoi(e) != 0;
-    c->nl_ty = choose_sweep_ty(c->nx, c->ny, 512);
     if (const char* e = std::getenv("SPARC_GPU_DEBUG")) c->debug = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_EIG")) c->eig_jacobi = std::string(e) == "jacobi";
     if (const char* e = std::getenv("SPARC_GPU_TRD_MULTI_MIN")) c->trd_multi_min = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_TRD_TAIL")) c->trd_tail = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("SPARC_GPU_CHOL_MULTI_MIN")) c->chol_multi_min = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_STEIN_LDS_MIN_TPW")) c->stein_lds_min_tpw = std::atoi(e);
-    if (const char* e = std::getenv("SPARC_GPU_SPLIT_FILTER")) c->split_filter = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_PROJ_NB")) c->proj_nb = std::atoi(e);
-    if (const char* e = std::getenv("SPARC_GPU_PROJ_U")) c->proj_u = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_GEMM_TILE")) c->gemm_tile = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_GEMM_NN_COLS")) c->gemm_nn_cols = std::atoi(e);
 
@@ -850,7 +959,8 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
                     c->kp_bounds, c->kp_wts, c->b, c->pois_ux, c->pois_uy, c->pois_uz, c->pois_inv, c->work, c->D,
                     c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,
                     c->nl.sup_chi, c->nl.gamma4, c->nl.atom_order, c->atom_pos, c->nl.pe8, c->nl.slab_cand,
-                    c->nl.slab_k, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo};
+                    c->nl.slab_k, c->nl.pairs, c->nl.pair_off, c->nl.red_off, c->nl.red_idx, c->nl_part,
+                    c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo};
     for (void* p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < 8; ++i)
@@ -861,12 +971,6 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
     if (c->h_flags) hipHostFree(c->h_flags);
     if (c->jac_exec) hipGraphExecDestroy(c->jac_exec);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-    if (c->aux_stream) {
-        hipStreamSynchronize(c->aux_stream);
-        hipStreamDestroy(c->aux_stream);
-    }
-    if (c->fork_ev) hipEventDestroy(c->fork_ev);
-    if (c->join_ev) hipEventDestroy(c->join_ev);
     delete c;
     return SPARC_OK;
 }

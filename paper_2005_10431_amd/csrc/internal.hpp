@@ -31,6 +31,18 @@ struct CandInfo {
     int ixlo, ixhi, izlo, izhi;
 };
 
+// One line segment of a candidate's support in the nonlocal sweep: the
+// points x in [xlo, xlo + n) of slab row `row` at one plane z lie in the
+// support of slab candidate k; eyez = exp(-(dy^2 + dz^2)/rc^2) with dy, dz the
+// line's offsets from the candidate's (image-shifted) centre.  The host
+// fills k, row, xlo, n, run; the device the geometry (k_pair_geometry).
+struct SweepPair {
+    int k, row, xlo, n;
+    int run;   // first pair of a candidate in its plane list: the candidate's pair count; else 0
+    int pad;
+    double eyez, dy, dz;
+};
+
 // Nonlocal projector tables on the device.
 //  - projection: the image points of each atom's ball (ip_*), with the
 //    projector values evaluated from per-axis Gaussian tables;
@@ -47,11 +59,21 @@ struct NonlocalTables {
     // number of image-level (point, atom, image) entries; the sweep's
     // per-slab tables are built from them on the host
     long n_pe = 0;
-    // per-slab candidate tables of the sweep (see build_slab_tables)
+    // per-slab tables of the nonlocal sweep (see build_pair_tables): the
+    // slab's candidate (atom, image) pairs, the line segments (pairs) of each
+    // plane sorted by (candidate, row), and per point the byte indices of its
+    // pairs in its plane's list (0xFF pads)
     uint64_t* pe8 = nullptr;
     CandInfo* slab_cand = nullptr;          // [n_slabs][slab_kmax]
     int* slab_k = nullptr;                  // candidates per slab
-    int slab_kmax = 0, slab_xw = 0, slab_zw = 0;
+    int slab_kmax = 0, slab_xw = 0;
+    SweepPair* pairs = nullptr;             // all segments, plane lists back to back
+    int* pair_off = nullptr;                // n_slabs * nz + 1: list of (slab, plane)
+    int pair_max = 0;                       // longest plane list
+    // the (slab, candidate) partial projections of one atom, in fixed order:
+    // entries slab * slab_kmax + k of red_idx[red_off[a] .. red_off[a + 1])
+    int* red_off = nullptr;
+    int* red_idx = nullptr;
     double nl_hi = 0.0, nl_lo = 0.0;  // signed spectral bound contributions
     int max_per_atom = 0;
     // image points of each atom's ball for the projection, in grid order:
@@ -130,6 +152,8 @@ struct sparc_gpu_ctx_s {
     void* work = nullptr;       // one block of n_states columns (bytes below)
     size_t work_bytes = 0;
     double* D = nullptr;        // projector coefficients: 4 n_atoms x n_states
+    double* nl_part = nullptr;  // projection partials per (z range, slab, candidate)
+    size_t nl_part_elems = 0;
     float* D32 = nullptr;
     double* gemm_part = nullptr; // split-K partials
     size_t gemm_part_elems = 0;
@@ -150,17 +174,12 @@ struct sparc_gpu_ctx_s {
 
     // captured Jacobi sweep (see dense.hip)
     hipStream_t cap_stream = nullptr;
-    hipStream_t aux_stream = nullptr;  // second stream of the split filter
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-    int split_filter = 0;       // SPARC_GPU_SPLIT_FILTER=1: filter halves on two streams
-    int proj_nb = 4;            // SPARC_GPU_PROJ_NB: orbitals per projection workgroup (2, 4, 8)
-    int proj_u = 0;             // SPARC_GPU_PROJ_U: ball points in flight per projection thread (1, 2, 4; 0: 2 in FP64, 1 in FP32)
+    int proj_nb = 4;            // SPARC_GPU_PROJ_NB: orbitals per projection workgroup (2 or 4)
     int gemm_tile = 0;          // SPARC_GPU_GEMM_TILE: Gram/projected-H tile edge (128, 160; 0: by size)
     int gemm_nn_cols = 160;     // SPARC_GPU_GEMM_NN_COLS: rotation tile width (160, 288)
     hipGraphExec_t jac_exec = nullptr;
     int jac_N = 0;
     double *jac_A = nullptr, *jac_A2 = nullptr, *jac_V = nullptr, *jac_V2 = nullptr;
-    int sweep_slab_major = 0;   // block order of the sweep kernel
     int debug = 0;              // SPARC_GPU_DEBUG: diagnostics on stderr
     int eig_jacobi = 0;         // SPARC_GPU_EIG=jacobi: parallel Jacobi instead of tridiagonal
     int trd_multi_min = 320;    // SPARC_GPU_TRD_MULTI_MIN: N from which the reduction uses many workgroups
@@ -222,15 +241,22 @@ enum Flag {
 
 // ---- kernels (launchers) -------------------------------------------------
 // H application / Chebyshev sweeps. mode: 0 out = H x; 1 first filter step;
-// 2 filter step `step` (>= 2) with xprev = X_{k-1} (may alias out).
+// 2 filter step `step` (>= 2) with xprev = X_{k-1} (may alias out).  With
+// projectors the sweep applies the projections held in the context's D,
+// which launch_projection must have formed from x.
 template <typename T>
 sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, int ncol, long ldx,
-                           int mode, int step, int dcol0 = 0, hipStream_t s = nullptr);
-// dcol0: first column of the projection coefficients D that belongs to x;
-// s: stream (null: the context stream)
+                           int mode, int step);
+// D = gamma dV chi^T x, streaming x once over the sweep's slabs
 template <typename T>
-sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, int dcol0 = 0,
-                               hipStream_t s = nullptr);
+sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx);
+// LDS bytes of a nonlocal sweep workgroup (slab height ty, nz planes, K
+// candidates, ex tables xw wide) of element size tsize
+size_t nl_sweep_lds_bytes(int ty, int nx, int nz, int K, int xw, size_t tsize);
+// LDS bytes of a projection workgroup (also PM pairs per plane at most, NB
+// orbitals)
+size_t nl_proj_lds_bytes(int ty, int nx, int K, int xw, int PM, int NB, size_t tsize);
+int nl_sweep_max_threads();   // workgroup size limit of the nonlocal sweep
 
 // C(MxN, col-major, ldc) = alpha * A^T B, A: K x M (lda), B: K x N (ldb),
 // T inputs, double output, deterministic split-K.
@@ -287,7 +313,7 @@ sparc_status rayleigh_ritz_k_impl(sparc_gpu_ctx c, T* X, int ncol, long ldx, dou
 // records its closing event.
 enum ProfKernel {
     PK_SWEEP = 0,    // filter step k >= 2 (reads X_k, X_{k-1}; writes X_{k+1})
-    PK_PROJ = 1,
+    PK_PROJ = 1,     // projections (streaming pass and per-atom sum)
     PK_GEMM_TN = 2,
     PK_GEMM_NN = 3,
     PK_DENSITY = 4,
@@ -313,21 +339,12 @@ enum ProfKernel {
     PK_COUNT = 32    // size of the per-context timing tables
 };
 static_assert(PK_COUNT == sizeof(sparc_gpu_ctx_s::prof_n) / sizeof(long), "timing table size");
-// LDS of one nonlocal sweep workgroup: two padded plane buffers, then the
-// slab's candidate tables (delta, cz; ex, ez over the candidate's x/z range;
-// z-independent factors F (3 per row and candidate); A'/B' for two planes;
-// cxb, czb as ints).
-inline size_t nl_sweep_lds_bytes(int ty, int nx, size_t KM, int xw, int zw, size_t tsize) {
-    return (2 * (size_t)(ty + 2 * kMaxHalfOrder) * (nx + 2 * kMaxHalfOrder) + 2 * KM + KM * (size_t)xw +
-            KM * (size_t)zw + 7 * (size_t)ty * KM) * tsize + 2 * KM * sizeof(int);
-}
-
 int prof_begin(sparc_gpu_ctx c, int kernel, hipStream_t s = nullptr);  // s = null: the context stream
 void prof_end(sparc_gpu_ctx c, int slot, hipStream_t s = nullptr);
 
 // Build geometry tables (ctx.hip)
 sparc_status build_tables(sparc_gpu_ctx c);
-sparc_status build_slab_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent);
+sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent, int ty);
 int choose_sweep_ty(int nx, int ny, int max_threads);
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }

@@ -5,15 +5,21 @@
 // Sec. 2.1).  The scaled three-term Chebyshev recurrence of the CheFSI filter
 // (Sec. 2.1) is fused into the epilogue of the stencil sweep, so one sweep
 // streams X_k (stencil operand), X_{k-1} (recurrence term) and writes X_{k+1}
-// over X_{k-1}: 3 block-sized streams per filter degree.
+// over X_{k-1}: 3 block-sized streams per filter degree.  With projectors the
+// same sweep also forms the projections dV chi^T X_{k+1} of its output, which
+// the next filter step applies, so the block is not read a fourth time.
 //
 // Sweep kernel layout (one workgroup = one orbital x one y-slab x all z):
 //  - the slab is `ty` full x-rows; periodic x wraps inside LDS (padded rows),
 //    so only y needs halo rows, which are read from L2 (the neighbouring slabs
 //    of the same orbital run on the same XCD at the same time, see the block
 //    mapping below);
-//  - z is marched with a register queue of 2*NO+1 planes per thread, so every
-//    point of X_k is fetched from HBM once per sweep (plus 2*NO wrap planes);
+//  - z is marched with a register ring of RING = 13 + PR planes per thread:
+//    planes z-6 .. z+6 in use and PR planes in flight, so every point of X_k
+//    is fetched once per sweep (plus the 12 periodic wrap planes);
+//  - the halo rows, X_{k-1}, V_eff and the nonlocal point words of the
+//    coming planes sit in PQ-deep register queues, so each load has PQ plane
+//    steps to land;
 //  - two LDS plane buffers alternate so one barrier per plane suffices.
 #include <cmath>
 #include <cstdlib>
@@ -30,22 +36,25 @@ struct SweepArgs {
     long ldx;
     int nx, ny, nz;
     int ty, ntiles_y;
-    StencilCoef<T> cf;
+    // -1/2 Delta_h with the y and z coefficients proportional to the x ones
+    // (same weights over h_y^2, h_z^2): ck[q] multiplies
+    // (x-pair + ry y-pair + rz z-pair) at distance q, c0 the point itself
+    T c0, ck[kMaxHalfOrder + 1], ry, rz;
     const T* veff;
-    // nonlocal part (per-slab candidate tables, see build_slab_tables)
+    // nonlocal part (per-slab pair tables, see build_pair_tables)
     const uint64_t* pe8;
     const CandInfo* slab_cand;
     const int* slab_k;
-    int kmax, xw, zw;
+    const SweepPair* pairs;
+    const int* pair_off;
+    int kmax, xw, pmax;
     const double* atom_pos;  // 3 n_atoms
-    T inv_rc2, N0, N1, hx, hy, hz;
-    const T* D;       // gamma-scaled projections, column j at D + j*ldD
+    T inv_rc2, N0, N1, hx;
+    const T* D;       // gamma-scaled projections of x: column j at D + j*ldD, 4 per atom
     int ldD;
     const double* params;  // a, b, a0 on the device
-    int mode;              // 0: H x; 1: first filter step; 2: filter step `step`
     int step;
     int ncol;
-    int slab_major;        // block order: slab-major instead of orbital-major
 };
 
 // Filter coefficients of step k of the scaled recurrence:
@@ -77,449 +86,613 @@ __device__ inline void filter_coefs(const double* params, int mode, int step, do
     beta = -sp * s;
 }
 
-constexpr int RING = 2 * kMaxHalfOrder + 2;  // z-queue slots (one spare for prefetch)
+constexpr int kRing = 16;            // z-ring slots: planes z-6 .. z+6 and 3 in flight
+constexpr int kRingAhead = kRing - 2 * kMaxHalfOrder - 1;
+constexpr int kQueue = 2;            // depth of the halo / X_{k-1} / V_eff / point-word queues
+constexpr int kSlots = 7;            // pair slots of a point word (byte 0xFF: empty)
+constexpr int kPairSlots = 256;      // pair records per plane (index 255: the null pair)
+static_assert(kRing % kQueue == 0, "the unrolled step count must cycle every queue");
+// Workgroups of the nonlocal sweep are capped at 768 threads (3 waves per
+// SIMD) so that the pair tables and the point-word queue fit in registers
+// beside the z-ring without spilling.
+constexpr int kNlThreads = 768;
 
-// Per-thread registers of the sweep: the z-queue ring (plane z lives in slot
-// z mod RING), the prefetched halo values of the next plane, and the next
-// plane's X_{k-1} and V_eff values.  Indices are compile-time after
-// unrolling, so everything stays in VGPRs.
-template <typename T, int HM>
-struct SweepRegs {
-    T q[RING];
-    T h[HM];             // next plane's halo values (this thread's share)
-    T xp[2];
-    T ve[2];
-    uint64_t pe8[2];     // own point's projector candidates (bytes, 0xFF pads)
+// One pair record of a plane in LDS: the pair's contribution at grid x of
+// its segment is ex[x] (A'' + B' x), with ex[x] read at byte address
+// exb + 8 x (or 4 x in FP32) in LDS.
+template <typename T>
+struct alignas(2 * sizeof(T) == 16 ? 32 : 16) PairLds {
+    T A, B;
+    int exb;
 };
 
-template <typename T>
-struct SweepGeom {
-    const void* xc;
-    void* oc;
-    const void* pc;
-    long plane, pxy;
-    int nz, col, hn;
-    bool active;
-    int goff[6], loff[6], poff[6];  // per halo value of this thread (HM <= 6 used)
-    int lrow;  // LDS offset of this thread's own point
-    int W, nx, lx, ly, gy, t, nt;
-    // LDS tables of the slab's projector candidates (K of them):
-    T* delta;               // x offset of the candidate's first ex entry from its centre
-    T* cz;                  // image-shifted z centre
-    int* cxb;               // x index of the candidate's first ex entry (grid row coordinates)
-    T* ex;                  // ex[k*xw + i]: exp(-dx^2/rc^2) over the candidate's x-range
-    T* ez;                  // ez[k*zw + i]: exp(-dz^2/rc^2) over the candidate's z-range
-    int* czb;               // z index offset into the ez table
-    T* F;                   // F[(row*K + k)*3 + {0,1,2}]: z-independent factors (see sweep_ab)
-    T* ab;                  // ab[parity][row][k][2]: A', B' of plane z / z+1
-    int K, y0, tyn, xw, zw;
-    int abk0, abdk;  // candidate of this thread's first sweep_ab pair, and its step per nt pairs
+// LDS of one sweep workgroup, in this order: two padded plane buffers; with
+// projectors: the ex tables (K xw, then nx zeros for the null pair), the
+// input projections (4 K), delta (K), cxb (K, int), the slab's plane list
+// offsets (nz + 1, int), and the pair records of two planes (2 x 256; record
+// 255 is the null pair of empty point slots).
+struct SweepLds {
+    size_t planes, ex, din, delta, cxb, poff, rec, total;
 };
 
-// A'(row, k), B'(row, k) of one plane z.  The candidate's contribution at
-// a point of the row is ex(x) (A + B dx) with
-//   A = ey ez (N0 D_s + N1 (dy D_py + dz D_pz)),  B = ey ez N1 D_px;
-// the z-independent factors F0 = ey (N0 D_s + N1 dy D_py), F1 = ey N1 D_pz,
-// F2 = ey N1 D_px are tabulated once per workgroup, so A = ez (F0 + F1 dz),
-// B = ez F2.  With dx = delta_k + hx i (i the point's index in the ex table)
-// the apply needs A' = A + B delta_k and B' = B hx.
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
 template <typename T>
-__device__ __forceinline__ void sweep_ab(const SweepArgs<T>& a, const SweepGeom<T>& g, int z, T* abz) {
-    const int n = g.tyn * g.K;
-    const T zh = (T)z * a.hz;
-    int k = g.abk0;  // candidate of pair j = row * K + k
-    for (int j = g.t; j < n; j += g.nt) {
-        // planes outside the candidate's z-range never reach a point that
-        // lists it; clamp the table index there
-        const int iz = min(max(z - g.czb[k], 0), g.zw - 1);
-        const T E = g.ez[k * g.zw + iz];
-        const T dz = zh - g.cz[k];
-        const T* F = g.F + 3 * j;
-        const T A = E * (F[0] + F[1] * dz);
-        const T B = E * F[2];
-        abz[2 * j] = A + B * g.delta[k];
-        abz[2 * j + 1] = B * a.hx;
-        k += g.abdk;  // abdk = nt mod K
-        if (k >= g.K) k -= g.K;
+__host__ __device__ inline SweepLds sweep_lds_layout(int ty, int nx, int nz, int K, int xw, bool nl) {
+    SweepLds L{};
+    size_t o = 0;
+    L.planes = o;
+    o += align16(2 * (size_t)(ty + 2 * kMaxHalfOrder) * (nx + 2 * kMaxHalfOrder) * sizeof(T));
+    if (nl) {
+        L.ex = o;
+        o += align16(((size_t)K * xw + nx) * sizeof(T));
+        L.din = o;
+        o += align16(4 * (size_t)K * sizeof(T));
+        L.delta = o;
+        o += align16((size_t)K * sizeof(T));
+        L.cxb = o;
+        o += align16((size_t)K * sizeof(int));
+        L.poff = o;
+        o += align16(((size_t)nz + 1) * sizeof(int));
+        L.rec = o;
+        o += align16(2 * (size_t)kPairSlots * sizeof(PairLds<T>));
     }
+    L.total = o;
+    return L;
 }
 
+size_t nl_sweep_lds_bytes(int ty, int nx, int nz, int K, int xw, size_t tsize) {
+    return tsize == 8 ? sweep_lds_layout<double>(ty, nx, nz, K, xw, true).total
+                      : sweep_lds_layout<float>(ty, nx, nz, K, xw, true).total;
+}
 
+int nl_sweep_max_threads() { return kNlThreads; }
 
-// One z-plane of the sweep at ring phase U (z = z0 + U).  On entry the LDS
-// buffer of parity U holds plane z (own rows with x-wrap padding, halo rows,
-// and the plane's projector entries), written during the previous step.
-//  1. barrier,
-//  2. issue the loads of plane z+1 (halo rows, projector entries, own
-//     X_{k-1}, V_eff and entry range; the plane index wraps so the loads are
-//     unconditional and the step is straight-line code),
-//  3. stencil + potential + nonlocal + recurrence for plane z, store,
-//  4. write plane z+1 into the other LDS buffer (its loads have had the
-//     whole compute phase to land),
-//  5. load plane z + NO + 2 into the ring slot freed by plane z - NO.
+template <typename T>
+struct SweepShared {
+    T* buf0;
+    T* buf1;
+    // nonlocal tables of the slab
+    T* ex;       // ex[k * xw + i] = exp(-(delta_k + i hx)^2 / rc^2); then nx zeros
+    T* din;      // din[4 k + lm]: input projections of candidate k's atom
+    T* delta;    // x offset of candidate k's first ex entry from its centre (Bohr)
+    int* cxb;    // grid x of candidate k's first ex entry
+    int* poff;   // poff[z]: start of plane z's pair list in the pair array (z = 0 .. nz)
+    PairLds<T>* rec;  // rec[par * 256 + j]: pair j of a plane of parity par
+    int exoff;   // byte offset of ex in the workgroup's LDS
+};
+
+// Pair record j of plane z's list (n = 0: no pair).
+struct PairRec {
+    int k, n;
+    double eyez, dy, dz;
+};
+
+__device__ inline PairRec load_pair(const SweepPair* __restrict__ pairs, const int* poff, int z, int j) {
+    PairRec r;
+    const int o0 = poff[z], o1 = poff[z + 1];
+    r.k = 0;
+    r.n = 0;
+    r.eyez = r.dy = r.dz = 0.0;
+    if (j < o1 - o0) {
+        const SweepPair P = pairs[o0 + j];
+        r.k = P.k;
+        r.n = P.n;
+        r.eyez = P.eyez;
+        r.dy = P.dy;
+        r.dz = P.dz;
+    }
+    return r;
+}
+
+// The record of one plane's pair.  A pair's contribution at grid x of its
+// segment is ex(i) (A' + B' i), i = x - cxb_k:
+//   chi_s D_s + chi_p . D_p = ex(i) eyez (N0 D_s + N1 (dx D_px + dy D_py + dz D_pz)),
+//   dx = delta_k + i hx  =>  A' = eyez (N0 D_s + N1 (dy D_py + dz D_pz + delta_k D_px)),
+//                           B' = eyez N1 hx D_px;
+// it is stored as A'' = A' - B' cxb_k, so that the contribution is
+// ex (A'' + B' x), with the LDS byte offset of the pair's row of the ex
+// table shifted by -cxb_k entries, so that x indexes it.
+template <typename T>
+__device__ inline void pair_record(const SweepArgs<T>& a, const SweepShared<T>& sh, const PairRec& r, int j,
+                                   int par) {
+    if (r.n == 0) return;
+    const int k = r.k;
+    const T eyez = (T)r.eyez, dy = (T)r.dy, dz = (T)r.dz;
+    const T fs = eyez * a.N0, fx = eyez * a.N1;
+    const T* D = sh.din + 4 * k;
+    const T A = fs * D[0] + fx * (dy * D[2] + dz * D[3] + sh.delta[k] * D[1]);
+    const T B = fx * a.hx * D[1];
+    const int c0 = sh.cxb[k];
+    PairLds<T>& R = sh.rec[par * kPairSlots + j];
+    R.A = A - B * (T)c0;
+    R.B = B;
+    R.exb = sh.exoff + (k * a.xw - c0) * (int)sizeof(T);
+}
+
+// The sweep.  MODE: 0 out = H x; 1 first filter step; 2 filter step `step`
+// (>= 2) with xprev = X_{k-1} (may alias out).  NL: projectors present (the
+// projections of x are in a.D).  HM: halo values per thread and plane.
+//
+// One z-plane step at ring phase U (z = z0 + U).  On entry the LDS buffer of
+// parity U holds plane z (own rows with x-wrap padding and halo rows) and the
+// pair records of plane z, written during the previous step.
+//  1. barrier;
+//  2. issue the loads of the halo values of plane z + PQ, of ring plane
+//     z + 6 + PR and of the pair records of plane z + 1 (plane indices wrap,
+//     so the loads are unconditional);
+//  3. stencil + potential + nonlocal + recurrence for plane z, store;
+//  4. load X_{k-1}, V_eff and the point word of plane z + PQ into the queue
+//     slot plane z has freed;
+//  5. pair records of plane z + 1; plane z + 1 into the other LDS buffer.
+// The nonlocal term sums every slot of the point word (empty slots name the
+// null pair, whose ex entries are zero), so a step has no loop or branch:
+// a loop inside the unrolled step would keep every value live across it.
 // Threads without a point of the slab (ragged slab, padding to 64) load
 // valid clamped addresses and compute on them, but never store.
-template <int U, typename T, bool NL, int MODE, int HM>
-__device__ __forceinline__ void sweep_step(const SweepArgs<T>& a, SweepRegs<T, HM>& r, const SweepGeom<T>& g,
-                                           T* buf0, T* buf1, int z, T alpha, T cshift, T beta) {
-    constexpr int NO = kMaxHalfOrder;
-    constexpr int P = U & 1, PN = (U + 1) & 1;
-    constexpr int C = U % RING;
-    const T* __restrict__ xc = (const T*)g.xc;
-    __syncthreads();
-    const int z1 = (z + 1 == g.nz) ? 0 : z + 1;
-    const long zoff1 = (long)z1 * g.plane;
-#pragma unroll
-    for (int i = 0; i < HM; ++i) r.h[i] = xc[g.goff[i] + zoff1];
-    if (MODE == 2) r.xp[PN] = ((const T*)g.pc)[g.pxy + zoff1];
-    r.ve[PN] = a.veff[g.pxy + zoff1];
-    if (NL) r.pe8[PN] = a.pe8[g.pxy + zoff1];
-
-    T* buf = P ? buf1 : buf0;
-    const T* rp = buf + g.lrow;
-    const int W = g.W;
-    T lap = a.cf.c0 * r.q[C];
-#pragma unroll
-    for (int k = 1; k <= NO; ++k) lap += a.cf.cz[k] * (r.q[(U + k) % RING] + r.q[(U + RING - k) % RING]);
-#pragma unroll
-    for (int k = 1; k <= NO; ++k) lap += a.cf.cx[k] * (rp[k] + rp[-k]);
-#pragma unroll
-    for (int k = 1; k <= NO; ++k) lap += a.cf.cy[k] * (rp[k * W] + rp[-k * W]);
-    const long p = g.pxy + (long)z * g.plane;
-    T hv = lap + r.ve[P] * r.q[C];
-    if (NL) {
-        // sum over the projectors whose support holds this point of
-        // chi_s D_s + chi_p . D_p = ex(x) (A + B dx)   (see sweep_ab)
-        const T* abr = g.ab + (P * a.ty + (g.active ? g.ly : 0)) * 2 * g.K;
-        uint64_t w = g.active ? r.pe8[P] : ~0ull;
-        T nl = 0;
-        for (int j = 0; j < 7; ++j) {
-            const int k = (int)(w & 0xFFull);
-            if (k == 0xFF) break;
-            w >>= 8;
-            const int i = g.lx - g.cxb[k];
-            nl += g.ex[k * g.xw + i] * (abr[2 * k] + abr[2 * k + 1] * (T)i);
-        }
-        hv += nl;
-    }
-    T o;
-    if (MODE == 0) {
-        o = hv;
-    } else {
-        o = alpha * (hv - cshift * r.q[C]);
-        if (MODE == 2) o += beta * r.xp[P];
-    }
-    if (g.active) ((T*)g.oc)[p] = o;
-
-    // plane z+1 into the other buffer
-    T* nbuf = P ? buf0 : buf1;
-    constexpr int CN = (U + 1) % RING;
-    if (g.active) {
-        nbuf[g.lrow] = r.q[CN];
-        if (g.lx < NO) nbuf[g.lrow + g.nx] = r.q[CN];
-        if (g.lx >= g.nx - NO) nbuf[g.lrow - g.nx] = r.q[CN];
-    }
-#pragma unroll
-    for (int i = 0; i < HM; ++i)
-        if (i < g.hn) {
-            nbuf[g.loff[i]] = r.h[i];
-            if (g.poff[i] >= 0) nbuf[g.poff[i]] = r.h[i];
-        }
-    if (NL) sweep_ab<T>(a, g, z1, g.ab + PN * a.ty * 2 * g.K);  // A/B of the next plane
-    int zn = z + NO + 2;
-    zn = zn >= g.nz ? zn - g.nz : zn;
-    r.q[(U + NO + 2) % RING] = xc[g.pxy + (long)zn * g.plane];
-}
-
-// Workgroups of the nonlocal variant are capped at 512 threads so that its
-// extra live registers (entry prefetch, projector evaluation) fit without
-// spilling.
 template <typename T, bool NL, int MODE, int HM>
-__global__ __attribute__((amdgpu_flat_work_group_size(1, NL ? 512 : 1024))) void k_hsweep(SweepArgs<T> a) {
+__global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> a) {
     constexpr int NO = kMaxHalfOrder;
+    constexpr int RING = kRing, PR = kRingAhead, PQ = kQueue;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* buf0 = reinterpret_cast<T*>(smem_raw);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int W = nx + 2 * NO;
     const int R = a.ty + 2 * NO;
-    T* buf1 = buf0 + R * W;
 
     // Hardware dispatches block b to XCD b % 8.  Give each XCD a contiguous
     // range of logical tiles so that the y-slabs of one orbital (which read
     // each other's rows as halos) share an L2.
     const int nblk = gridDim.x, bid = blockIdx.x;
     const int qn = nblk / 8, rn = nblk % 8;
-    const int xcd = bid % 8, slot = bid / 8;
-    const int logical = xcd * qn + min(xcd, rn) + slot;
-    int col, tile;
-    if (a.slab_major) {
-        // all orbitals of one slab back to back: the slab's projector
-        // entries stay resident in the XCD's L2
-        tile = logical / a.ncol;
-        col = logical - tile * a.ncol;
-    } else {
-        col = logical / a.ntiles_y;
-        tile = logical - col * a.ntiles_y;
-    }
+    const int xcd = bid % 8, bslot = bid / 8;
+    const int logical = xcd * qn + min(xcd, rn) + bslot;
+    const int col = logical / a.ntiles_y;
+    const int tile = logical - col * a.ntiles_y;
     const int y0 = tile * a.ty;
     const int tyn = min(a.ty, ny - y0);
 
     const int t = threadIdx.x;
     const int nt = blockDim.x;
     const int lx = t % nx, ly = t / nx;
+    const bool active = ly < tyn;
+    const long plane = (long)nx * ny;
 
-    SweepGeom<T> g;
-    g.active = ly < tyn;
-    g.plane = (long)nx * ny;
-    g.nz = nz;
-    g.col = col;
-    g.W = W;
-    g.nx = nx;
-    g.lx = lx;
-    g.gy = y0 + (g.active ? ly : 0);
-    g.ly = ly;
-    g.t = t;
-    g.nt = nt;
-    g.y0 = y0;
-    g.tyn = tyn;
+    SweepShared<T> sh;
+    {
+        const SweepLds L = sweep_lds_layout<T>(a.ty, nx, nz, NL ? a.kmax : 0, a.xw, NL);
+        sh.buf0 = reinterpret_cast<T*>(smem_raw + L.planes);
+        sh.buf1 = sh.buf0 + R * W;
+        sh.ex = reinterpret_cast<T*>(smem_raw + L.ex);
+        sh.din = reinterpret_cast<T*>(smem_raw + L.din);
+        sh.delta = reinterpret_cast<T*>(smem_raw + L.delta);
+        sh.cxb = reinterpret_cast<int*>(smem_raw + L.cxb);
+        sh.poff = reinterpret_cast<int*>(smem_raw + L.poff);
+        sh.rec = reinterpret_cast<PairLds<T>*>(smem_raw + L.rec);
+        sh.exoff = (int)L.ex;
+    }
     if (NL) {
-        // LDS after the two plane buffers (layout of nl_sweep_lds_bytes):
-        // delta, cz (K T each), ex (K xw), ez (K zw), F (3 ty K), A'/B'
-        // (2 planes x 2 ty K), cxb, czb (K int each)
-        const int KM = a.kmax;
-        T* tp = buf1 + R * W;
-        g.delta = tp;
-        g.cz = tp + KM;
-        g.ex = tp + 2 * KM;
-        g.ez = g.ex + KM * a.xw;
-        g.F = g.ez + KM * a.zw;
-        g.ab = g.F + 3 * a.ty * KM;
-        g.cxb = reinterpret_cast<int*>(g.ab + 4 * a.ty * KM);
-        g.czb = g.cxb + KM;
-        g.xw = a.xw;
-        g.zw = a.zw;
-        g.K = a.slab_k[tile];
-        g.abk0 = g.K > 0 ? t % g.K : 0;
-        g.abdk = g.K > 0 ? nt % g.K : 0;
-        const CandInfo* ci = a.slab_cand + (long)tile * KM;
+        const int K = a.slab_k[tile];
+        const CandInfo* ci = a.slab_cand + (long)tile * a.kmax;
         const T* Dc = a.D + (long)col * a.ldD;
-        for (int k = t; k < g.K; k += nt) {
+        for (int k = t; k < K; k += nt) {
             const CandInfo c = ci[k];
-            g.delta[k] = (T)((double)c.ixlo * (double)a.hx - a.atom_pos[3 * c.atom]);
-            g.cz[k] = (T)(a.atom_pos[3 * c.atom + 2] - (double)c.sz * (double)nz * (double)a.hz);
-            g.cxb[k] = c.ixlo - c.sx * nx;
-            g.czb[k] = c.izlo - c.sz * nz;
+            sh.delta[k] = (T)((double)c.ixlo * (double)a.hx - a.atom_pos[3 * c.atom]);
+            sh.cxb[k] = c.ixlo - c.sx * nx;
+            for (int lm = 0; lm < 4; ++lm) sh.din[4 * k + lm] = Dc[4 * c.atom + lm];
         }
-        for (int j = t; j < g.K * g.xw; j += nt) {
-            const int k = j / g.xw, i = j - k * g.xw;
-            const T dx = (T)(ci[k].ixlo + i) * a.hx - (T)a.atom_pos[3 * ci[k].atom];
-            g.ex[j] = exp(-dx * dx * a.inv_rc2);
+        for (int j = t; j < K * a.xw + nx; j += nt) {
+            T v = 0;
+            if (j < K * a.xw) {
+                const int k = j / a.xw, i = j - k * a.xw;
+                const T dx = (T)(ci[k].ixlo + i) * a.hx - (T)a.atom_pos[3 * ci[k].atom];
+                v = exp(-dx * dx * a.inv_rc2);
+            }
+            sh.ex[j] = v;
         }
-        for (int j = t; j < g.K * g.zw; j += nt) {
-            const int k = j / g.zw, i = j - k * g.zw;
-            const T dz = (T)(ci[k].izlo + i) * a.hz - (T)a.atom_pos[3 * ci[k].atom + 2];
-            g.ez[j] = exp(-dz * dz * a.inv_rc2);
-        }
-        for (int j = t; j < tyn * g.K; j += nt) {
-            const int row = j / g.K, k = j - row * g.K;
-            const CandInfo c = ci[k];
-            const T cy = (T)(a.atom_pos[3 * c.atom + 1] - (double)c.sy * (double)ny * (double)a.hy);
-            const T dy = (T)(y0 + row) * a.hy - cy;
-            const T ey = exp(-dy * dy * a.inv_rc2);
-            const T* Dk = Dc + 4 * c.atom;
-            g.F[3 * j] = ey * (a.N0 * Dk[0] + a.N1 * dy * Dk[2]);
-            g.F[3 * j + 1] = ey * a.N1 * Dk[3];
-            g.F[3 * j + 2] = ey * a.N1 * Dk[1];
+        for (int z = t; z <= nz; z += nt) sh.poff[z] = a.pair_off[tile * nz + z];
+        // the null pair of both plane parities: ex = 0 over the whole row
+        if (t < 2) {
+            PairLds<T>& N = sh.rec[t * kPairSlots + 255];
+            N.A = 0;
+            N.B = 0;
+            N.exb = sh.exoff + K * a.xw * (int)sizeof(T);
         }
         __syncthreads();
-        sweep_ab<T>(a, g, 0, g.ab);
+        // pair records of plane 0
+        for (int j = t; j < a.pmax; j += nt) pair_record<T>(a, sh, load_pair(a.pairs, sh.poff, 0, j), j, 0);
     }
-    const T* xc = a.x + (long)col * a.ldx;
-    g.xc = xc;
-    g.oc = a.out + (long)col * a.ldx;
-    g.pc = a.xprev ? a.xprev + (long)col * a.ldx : nullptr;
-    g.pxy = lx + (long)nx * (y0 + (g.active ? ly : 0));
-    g.lrow = (ly + NO) * W + NO + lx;
+
+    const T* __restrict__ xc = a.x + (long)col * a.ldx;
+    T* __restrict__ oc = a.out + (long)col * a.ldx;
+    const T* __restrict__ pc = a.xprev ? a.xprev + (long)col * a.ldx : xc;
+    const long pxy = lx + (long)nx * (y0 + (active ? ly : 0));
+    const int lrow = ((active ? ly : 0) + NO) * W + NO + lx;
     // halo rows: 2 NO rows of nx values per plane, spread over the threads
+    int goff[HM], loff[HM], poff[HM];
+    int hn = 0;
     const int nhalo = 2 * NO * nx;
-    g.hn = 0;
 #pragma unroll
     for (int i = 0; i < HM; ++i) {
         const int e = t + i * nt;
-        g.goff[i] = 0;
-        g.loff[i] = 0;
-        g.poff[i] = -1;
+        goff[i] = 0;
+        loff[i] = 0;
+        poff[i] = -1;
         if (e < nhalo) {
-            g.hn = i + 1;
+            hn = i + 1;
             int hr = e / nx, hx = e - hr * nx;
-            int lrow, gy;
+            int lr, gy;
             if (hr < NO) {
-                lrow = hr;
+                lr = hr;
                 gy = y0 - NO + hr;
             } else {
-                lrow = NO + tyn + (hr - NO);
+                lr = NO + tyn + (hr - NO);
                 gy = y0 + tyn + (hr - NO);
             }
             gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-            g.goff[i] = hx + nx * gy;
-            g.loff[i] = lrow * W + NO + hx;
-            if (hx < NO) g.poff[i] = g.loff[i] + nx;
-            if (hx >= nx - NO) g.poff[i] = g.loff[i] - nx;
+            goff[i] = hx + nx * gy;
+            loff[i] = lr * W + NO + hx;
+            if (hx < NO) poff[i] = loff[i] + nx;
+            if (hx >= nx - NO) poff[i] = loff[i] - nx;
         }
     }
 
     double alpha_d, c_d, beta_d;
     filter_coefs(a.params, MODE, a.step, alpha_d, c_d, beta_d);
     const T alpha = (T)alpha_d, cshift = (T)c_d, beta = (T)beta_d;
+    auto wz = [nz](int z) { return z >= nz ? z - nz : (z < 0 ? z + nz : z); };
+    const T lxd = (T)lx;
+    const int lxb = lx * (int)sizeof(T);
 
-    SweepRegs<T, HM> r;
-    // ring: planes -NO .. NO+1 (slot = plane mod RING), plane 0 prefetches
+    T q[RING];
+    T hq[PQ][HM];
+    T xp[PQ], ve[PQ];
+    uint64_t w8[PQ];
+    // ring: planes -6 .. 5 + PR (slot = plane mod RING); queues: planes 0 .. PQ-1
 #pragma unroll
-    for (int j = -NO; j <= NO + 1; ++j) {
-        int zz = j < 0 ? j + nz : j;
-        r.q[(j + RING) % RING] = xc[g.pxy + (long)zz * g.plane];
+    for (int j = -NO; j <= NO - 1 + PR; ++j) q[(j + 2 * RING) % RING] = xc[pxy + (long)wz(j) * plane];
+#pragma unroll
+    for (int j = 0; j < PQ; ++j) {
+        const long zo = (long)wz(j) * plane;
+        xp[j] = MODE == 2 ? __builtin_nontemporal_load(&pc[pxy + zo]) : (T)0;
+        ve[j] = a.veff[pxy + zo];
+        w8[j] = NL ? a.pe8[pxy + zo] : ~0ull;
     }
-    r.xp[0] = (MODE == 2) ? ((const T*)g.pc)[g.pxy] : (T)0;
-    r.ve[0] = a.veff[g.pxy];
+#pragma unroll
+    for (int j = 1; j < PQ; ++j)
+#pragma unroll
+        for (int i = 0; i < HM; ++i) hq[j][i] = (i < hn) ? xc[goff[i] + (long)wz(j) * plane] : (T)0;
     // plane 0 into LDS buffer 0
-    if (g.active) {
-        buf0[g.lrow] = r.q[0];
-        if (lx < NO) buf0[g.lrow + nx] = r.q[0];
-        if (lx >= nx - NO) buf0[g.lrow - nx] = r.q[0];
+    if (active) {
+        sh.buf0[lrow] = q[0];
+        if (lx < NO) sh.buf0[lrow + nx] = q[0];
+        if (lx >= nx - NO) sh.buf0[lrow - nx] = q[0];
     }
 #pragma unroll
     for (int i = 0; i < HM; ++i)
-        if (i < g.hn) {
-            T v = xc[g.goff[i]];
-            buf0[g.loff[i]] = v;
-            if (g.poff[i] >= 0) buf0[g.poff[i]] = v;
+        if (i < hn) {
+            const T v = xc[goff[i]];
+            sh.buf0[loff[i]] = v;
+            if (poff[i] >= 0) sh.buf0[poff[i]] = v;
         }
-    if (NL) r.pe8[0] = a.pe8[g.pxy];
 
-#define SG_STEP(U)                                                                     \
-    if (z0 + U >= nz) break;                                                           \
-    sweep_step<U, T, NL, MODE, HM>(a, r, g, buf0, buf1, z0 + U, alpha, cshift, beta);
     for (int z0 = 0; z0 < nz; z0 += RING) {
-        SG_STEP(0) SG_STEP(1) SG_STEP(2) SG_STEP(3) SG_STEP(4) SG_STEP(5) SG_STEP(6)
-        SG_STEP(7) SG_STEP(8) SG_STEP(9) SG_STEP(10) SG_STEP(11) SG_STEP(12) SG_STEP(13)
+#pragma unroll
+        for (int U = 0; U < RING; ++U) {
+            const int z = z0 + U;
+            if (z >= nz) break;
+            const int P = U & 1, PN = (U + 1) & 1, QS = U % PQ, QN = (U + 1) % PQ;
+            __syncthreads();
+            // 2. loads of later planes
+            {
+                const long zo = (long)wz(z + PQ) * plane;
+#pragma unroll
+                for (int i = 0; i < HM; ++i) hq[QS][i] = (i < hn) ? xc[goff[i] + zo] : (T)0;
+                q[(U + NO + PR + RING) % RING] = xc[pxy + (long)wz(z + NO + PR) * plane];
+            }
+            PairRec rec;
+            if (NL && z + 1 < nz && t < a.pmax) rec = load_pair(a.pairs, sh.poff, z + 1, t);
+            // 3. plane z
+            const T* rp = (P ? sh.buf1 : sh.buf0) + lrow;
+            const int C = U % RING;
+            T lap = a.c0 * q[C];
+#pragma unroll
+            for (int k = 1; k <= NO; ++k) {
+                T s = (rp[k] + rp[-k]) + a.ry * (rp[k * W] + rp[-k * W]);
+                s += a.rz * (q[(U + k) % RING] + q[(U + RING - k) % RING]);
+                lap += a.ck[k] * s;
+            }
+            T hv = lap + ve[QS] * q[C];
+            if (NL) {
+                // sum over the pairs whose segment holds this point of
+                // chi_s D_s + chi_p . D_p = ex (A'' + B' x)
+                const uint64_t w = active ? w8[QS] : ~0ull;
+                const PairLds<T>* rb = sh.rec + P * kPairSlots;
+                T nl = 0;
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    const PairLds<T>& R8 = rb[(int)((w >> (8 * sl)) & 0xFFull)];
+                    const T e = *reinterpret_cast<const T*>(smem_raw + (R8.exb + lxb));
+                    nl += e * (R8.A + R8.B * lxd);
+                }
+                hv += nl;
+            }
+            T o;
+            if (MODE == 0) {
+                o = hv;
+            } else {
+                o = alpha * (hv - cshift * q[C]);
+                if (MODE == 2) o += beta * xp[QS];
+            }
+            if (active) __builtin_nontemporal_store(o, &oc[pxy + (long)z * plane]);
+            // 4. queue loads of plane z + PQ
+            {
+                const long zo = (long)wz(z + PQ) * plane;
+                if (MODE == 2) xp[QS] = __builtin_nontemporal_load(&pc[pxy + zo]);
+                ve[QS] = a.veff[pxy + zo];
+                if (NL) w8[QS] = a.pe8[pxy + zo];
+            }
+            // 5. pair records and LDS plane of z + 1
+            if (NL && z + 1 < nz && t < a.pmax) pair_record<T>(a, sh, rec, t, PN);
+            T* nbuf = P ? sh.buf0 : sh.buf1;
+            const int CN = (U + 1) % RING;
+            if (active) {
+                nbuf[lrow] = q[CN];
+                if (lx < NO) nbuf[lrow + nx] = q[CN];
+                if (lx >= nx - NO) nbuf[lrow - nx] = q[CN];
+            }
+#pragma unroll
+            for (int i = 0; i < HM; ++i)
+                if (i < hn) {
+                    nbuf[loff[i]] = hq[QN][i];
+                    if (poff[i] >= 0) nbuf[poff[i]] = hq[QN][i];
+                }
+        }
     }
-#undef SG_STEP
 }
 
-// D(4a+lm, j) = gamma_lm * dV * sum over the image points p of atom a's
-// ball of chi_lm(p) X(idx(p), j), accumulated in double in a fixed order
-// (deterministic).  chi_s = N0 e, chi_p = N1 {dx, dy, dz} e with
-// e = ex(x) ey(y) ez(z) from per-axis tables of the atom's bounding box,
-// evaluated in LDS (no per-point projector table is read).
-template <typename T, int NB, int U>
-__global__ __launch_bounds__(256) void k_projection(const T* __restrict__ x, long ldx, int ncol,
-                                                    const long* __restrict__ ip_off, const int* __restrict__ ip_idx,
-                                                    const uint32_t* __restrict__ ip_box, const int* __restrict__ box_lo,
-                                                    int ext, const double* __restrict__ pos, double hx, double hy,
-                                                    double hz, double inv_rc2, double N0, double N1,
-                                                    const double* __restrict__ g4, double dV, T* __restrict__ D,
-                                                    int ldD, const int* __restrict__ atom_order, int n_atoms) {
-    // Block b runs on XCD b % 8.  Atoms are visited in a space-filling order
-    // and each XCD takes a contiguous range of it for one orbital chunk at a
-    // time, so overlapping supports of neighbouring atoms hit in that XCD's L2.
-    extern __shared__ double ptab[];  // e and d tables: ex, ey, ez, dx, dy, dz (ext each)
-    const int bid = blockIdx.x;
-    const int xcd = bid % 8, slot = bid / 8;
-    const int per = (n_atoms + 7) / 8;
-    const int rank = xcd * per + slot % per;
-    const int chunk = slot / per;
-    if (rank >= n_atoms || chunk * NB >= ncol) return;
-    const int a = atom_order[rank];
-    for (int q = threadIdx.x; q < 3 * ext; q += blockDim.x) {
-        const int d = q / ext, i = q - d * ext;
-        const double h = d == 0 ? hx : (d == 1 ? hy : hz);
-        const double dv = (double)(box_lo[3 * a + d] + i) * h - pos[3 * a + d];
-        ptab[q] = exp(-dv * dv * inv_rc2);
-        ptab[3 * ext + q] = dv;
+// Projections by streaming the block once.  D(4a+lm, j) = gamma_lm dV
+// sum_p chi_lm(p) X(p, j) over the image points of atom a's support.  One
+// workgroup takes one y-slab of the nonlocal sweep (the same slabs and pair
+// tables), NB orbitals and a range of z-planes; it reads each plane of the
+// slab once (coalesced rows), and for each pair (candidate k, row, segment)
+// of the plane forms
+//   S0 = sum_i ex_k(i) X(i),  S1 = sum_i i ex_k(i) X(i)   (i: ex index),
+// whose contributions to candidate k are, with f_s = eyez N0, f_p = eyez N1,
+//   s: f_s S0,  p_x: f_p (delta_k S0 + hx S1),  p_y: f_p dy S0,  p_z: f_p dz S0.
+// The first pair of each candidate's run in a plane adds the run's
+// contributions, in row order, to the candidate's accumulators; planes are
+// taken in order.  Every sum is in double and in a fixed order, so the
+// result is bitwise reproducible.  The accumulators of the (slab, z range,
+// candidate) are written as partials, which k_proj_reduce sums per atom.
+constexpr int kProjThreads = 512;
+constexpr int kProjLoads = 6;   // plane values per thread and plane: NB ty nx <= 6 x 512
+
+struct ProjRecLds {
+    int k, row, xlo, n;  // segment: grid x in [xlo, xlo + n) of slab row `row`
+    int xo, run, pad0, pad1;  // xo: ex index of the segment's first point
+    double fs, fp, fpdy, fpdz;
+};
+
+struct ProjLds {
+    size_t ex, delta, planes, rec, psum, acc, total;
+};
+
+__host__ __device__ inline ProjLds proj_lds_layout(int ty, int nx, int K, int xw, int PM, int NB, size_t ts) {
+    ProjLds L{};
+    size_t o = 0;
+    L.ex = o;
+    o += align16((size_t)K * xw * sizeof(double));
+    L.delta = o;
+    o += align16((size_t)K * sizeof(double));
+    L.planes = o;
+    o += align16(2 * (size_t)NB * ty * nx * ts);
+    L.rec = o;
+    o += align16(2 * (size_t)PM * sizeof(ProjRecLds));
+    L.psum = o;
+    o += align16((size_t)PM * NB * 4 * sizeof(double));
+    L.acc = o;
+    o += align16((size_t)K * NB * 4 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+size_t nl_proj_lds_bytes(int ty, int nx, int K, int xw, int PM, int NB, size_t tsize) {
+    return proj_lds_layout(ty, nx, K, xw, PM, NB, tsize).total;
+}
+
+struct ProjArgs {
+    long ldx;
+    int nx, ny, nz, ty, ntiles_y, ncol;
+    int zsplit, zlen;          // z ranges per slab and planes per range
+    const CandInfo* slab_cand;
+    const int* slab_k;
+    const SweepPair* pairs;
+    const int* pair_off;
+    int kmax, xw, pmax;
+    const double* atom_pos;
+    double inv_rc2, N0, N1, hx;
+    double* part;              // [((zr * ntiles_y + slab) * kmax + k) * ncol + col] * 4
+};
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kProjThreads) void k_proj_stream(const T* __restrict__ x, ProjArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nx = a.nx, ny = a.ny;
+    const long plane = (long)nx * ny;
+    const int nchunk = (a.ncol + NB - 1) / NB;
+    // block -> (column chunk, z range, slab), slabs fastest
+    int bid = blockIdx.x;
+    const int tile = bid % a.ntiles_y;
+    bid /= a.ntiles_y;
+    const int zr = bid % a.zsplit;
+    const int chunk = bid / a.zsplit;
+    if (chunk >= nchunk) return;
+    const int n0 = chunk * NB, nb = min(NB, a.ncol - n0);
+    const int y0 = tile * a.ty, tyn = min(a.ty, ny - y0);
+    const int zb = zr * a.zlen, ze = min(a.nz, zb + a.zlen);
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int K = a.slab_k[tile];
+    const CandInfo* ci = a.slab_cand + (long)tile * a.kmax;
+    const int* poffg = a.pair_off + (long)tile * a.nz;
+
+    const ProjLds L = proj_lds_layout(a.ty, nx, a.kmax, a.xw, a.pmax, NB, sizeof(T));
+    double* ex = reinterpret_cast<double*>(smem_raw + L.ex);
+    double* delta = reinterpret_cast<double*>(smem_raw + L.delta);
+    T* buf = reinterpret_cast<T*>(smem_raw + L.planes);
+    ProjRecLds* prec = reinterpret_cast<ProjRecLds*>(smem_raw + L.rec);
+    double* psum = reinterpret_cast<double*>(smem_raw + L.psum);
+    double* acc = reinterpret_cast<double*>(smem_raw + L.acc);
+    const int pl = NB * a.ty * nx;  // values of one plane buffer
+
+    for (int j = t; j < K * a.xw; j += nt) {
+        const int k = j / a.xw, i = j - k * a.xw;
+        const double dx = (double)(ci[k].ixlo + i) * a.hx - a.atom_pos[3 * ci[k].atom];
+        ex[j] = exp(-dx * dx * a.inv_rc2);
+    }
+    for (int k = t; k < K; k += nt) delta[k] = (double)ci[k].ixlo * a.hx - a.atom_pos[3 * ci[k].atom];
+    for (int j = t; j < K * NB * 4; j += nt) acc[j] = 0.0;
+
+    // this thread's plane values: element e = t + i nt of (n, row, x)
+    long goff[kProjLoads];
+    int loff[kProjLoads];
+    const int nvals = nb * tyn * nx;
+#pragma unroll
+    for (int i = 0; i < kProjLoads; ++i) {
+        const int e = t + i * nt;
+        goff[i] = -1;
+        loff[i] = 0;
+        if (e < nvals) {
+            const int n = e / (tyn * nx), r = e - n * tyn * nx;
+            const int row = r / nx, xx = r - row * nx;
+            goff[i] = (long)(n0 + n) * a.ldx + xx + (long)nx * (y0 + row);
+            loff[i] = (n * a.ty + row) * nx + xx;
+        }
+    }
+    // one pair of plane z as an LDS record
+    auto load_rec = [&](int z, int j, ProjRecLds& R) -> bool {
+        const int o0 = poffg[z], o1 = poffg[z + 1];
+        if (j >= o1 - o0) return false;
+        const SweepPair P = a.pairs[o0 + j];
+        R.k = P.k;
+        R.row = P.row;
+        R.xo = P.xlo - (ci[P.k].ixlo - ci[P.k].sx * nx);
+        R.xlo = P.xlo;
+        R.n = P.n;
+        R.run = P.run;
+        R.pad0 = R.pad1 = 0;
+        R.fs = P.eyez * a.N0;
+        R.fp = P.eyez * a.N1;
+        R.fpdy = R.fp * P.dy;
+        R.fpdz = R.fp * P.dz;
+        return true;
+    };
+    // plane zb into buffer 0, its pairs into record set 0
+    if (zb < ze) {
+#pragma unroll
+        for (int i = 0; i < kProjLoads; ++i)
+            if (goff[i] >= 0) buf[loff[i]] = x[goff[i] + (long)zb * plane];
+        for (int j = t; j < a.pmax; j += nt) {
+            ProjRecLds R;
+            if (load_rec(zb, j, R)) prec[j] = R;
+        }
     }
     __syncthreads();
-    const double* ex = ptab;
-    const double* ey = ptab + ext;
-    const double* ez = ptab + 2 * ext;
-    const double* dxt = ptab + 3 * ext;
-    const double* dyt = ptab + 4 * ext;
-    const double* dzt = ptab + 5 * ext;
-    const int n0 = chunk * NB;
-    const int nb = min(NB, ncol - n0);
-    double acc[NB][4];
+    for (int z = zb; z < ze; ++z) {
+        const int P = (z - zb) & 1;
+        const bool more = z + 1 < ze;
+        // loads of plane z + 1 and its pair records
+        T v[kProjLoads];
 #pragma unroll
-    for (int n = 0; n < NB; ++n)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[n][k] = 0.0;
-    // U points per thread are in flight at once: their indices, then their
-    // X values, are loaded before any is accumulated (each thread still
-    // accumulates its points s0 + t, s0 + t + nt, ... in increasing order).
-    const long s0 = ip_off[a], s1 = ip_off[a + 1];
-    const int nt = blockDim.x;
-    for (long s = s0 + threadIdx.x; s < s1; s += (long)U * nt) {
-        long idx[U];
-        uint32_t bb[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long su = s + (long)u * nt;
-            const bool ok = su < s1;
-            idx[u] = ok ? ip_idx[su] : 0;
-            bb[u] = ok ? ip_box[su] : 0xFFFFFFFFu;
-        }
-        double v[U][NB];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int n = 0; n < NB; ++n)
-                v[u][n] = (bb[u] != 0xFFFFFFFFu && n < nb) ? (double)x[idx[u] + (long)(n0 + n) * ldx] : 0.0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (bb[u] == 0xFFFFFFFFu) break;
-            const uint32_t b = bb[u];
-            const int bx = b & 0xFF, by = (b >> 8) & 0xFF, bz = (b >> 16) & 0xFF;
-            const double e = ex[bx] * ey[by] * ez[bz];
-            const double c0 = N0 * e, c1 = N1 * dxt[bx] * e, c2 = N1 * dyt[by] * e, c3 = N1 * dzt[bz] * e;
-#pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                if (n < nb) {
-                    acc[n][0] += c0 * v[u][n];
-                    acc[n][1] += c1 * v[u][n];
-                    acc[n][2] += c2 * v[u][n];
-                    acc[n][3] += c3 * v[u][n];
-                }
+        for (int i = 0; i < kProjLoads; ++i)
+            v[i] = (more && goff[i] >= 0) ? x[goff[i] + (long)(z + 1) * plane] : (T)0;
+        ProjRecLds Rn;
+        const bool hasr = more && t < a.pmax && load_rec(z + 1, t, Rn);
+        // pair sums of plane z
+        const int np = poffg[z + 1] - poffg[z];
+        const T* bp = buf + P * pl;
+        const ProjRecLds* rp = prec + P * a.pmax;
+        for (int task = t; task < np * NB; task += nt) {
+            const int j = task / NB, n = task - j * NB;
+            if (n >= nb) continue;
+            const ProjRecLds& R = rp[j];
+            const T* xr = bp + (n * a.ty + R.row) * nx + R.xlo;
+            const double* er = ex + R.k * a.xw + R.xo;
+            double s0 = 0.0, s1 = 0.0, ii = (double)R.xo;
+            for (int i = 0; i < R.n; ++i) {
+                const double ev = er[i] * (double)xr[i];
+                s0 += ev;
+                s1 += ev * ii;
+                ii += 1.0;
             }
+            double* ps = psum + (j * NB + n) * 4;
+            ps[0] = R.fs * s0;
+            ps[1] = R.fp * (delta[R.k] * s0 + a.hx * s1);
+            ps[2] = R.fpdy * s0;
+            ps[3] = R.fpdz * s0;
         }
-    }
-    // wave reduction then across the 4 waves
-    __shared__ double part[4][NB * 4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        __syncthreads();
+        // each candidate's run adds to its accumulators, rows in order
+        for (int task = t; task < np * NB; task += nt) {
+            const int j = task / NB, n = task - j * NB;
+            const ProjRecLds& R = rp[j];
+            if (n >= nb || R.run == 0) continue;
+            double* ac = acc + (R.k * NB + n) * 4;
+            double c0 = ac[0], c1 = ac[1], c2 = ac[2], c3 = ac[3];
+            for (int r = 0; r < R.run; ++r) {
+                const double* ps = psum + ((j + r) * NB + n) * 4;
+                c0 += ps[0];
+                c1 += ps[1];
+                c2 += ps[2];
+                c3 += ps[3];
+            }
+            ac[0] = c0;
+            ac[1] = c1;
+            ac[2] = c2;
+            ac[3] = c3;
+        }
+        if (more) {
+            T* bq = buf + (1 - P) * pl;
 #pragma unroll
-    for (int n = 0; n < NB; ++n)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            double v = acc[n][k];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-            if (lane == 0) part[wv][n * 4 + k] = v;
+            for (int i = 0; i < kProjLoads; ++i)
+                if (goff[i] >= 0) bq[loff[i]] = v[i];
+            if (hasr) prec[(1 - P) * a.pmax + t] = Rn;
         }
-    __syncthreads();
-    if (threadIdx.x < NB * 4) {
-        int n = threadIdx.x / 4, k = threadIdx.x % 4;
-        if (n < nb) {
-            double v = ((part[0][threadIdx.x] + part[1][threadIdx.x]) + part[2][threadIdx.x]) + part[3][threadIdx.x];
-            D[(long)(n0 + n) * ldD + 4 * a + k] = (T)(g4[4 * a + k] * dV * v);
-        }
+        __syncthreads();
     }
+    const long row0 = ((long)zr * a.ntiles_y + tile) * a.kmax;
+    for (int j = t; j < K * NB * 4; j += nt) {
+        const int k = j / (NB * 4), r = j - k * NB * 4, n = r / 4, lm = r - n * 4;
+        if (n < nb) a.part[((row0 + k) * a.ncol + n0 + n) * 4 + lm] = acc[j];
+    }
+}
+
+// D(4a+lm, col) = gamma_lm dV sum of atom a's partials: its (slab,
+// candidate) entries in table order, and within each the z ranges in order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_proj_reduce(const double* __restrict__ part, int ncol, int zsplit,
+                                                     long zstride, const int* __restrict__ red_off,
+                                                     const int* __restrict__ red_idx,
+                                                     const double* __restrict__ g4, double dV, T* __restrict__ D,
+                                                     int ldD) {
+    const int a = blockIdx.x;
+    const long q = (long)blockIdx.y * blockDim.x + threadIdx.x;
+    if (q >= 4L * ncol) return;
+    const int col = (int)(q / 4), lm = (int)(q % 4);
+    double s = 0.0;
+    for (int e = red_off[a]; e < red_off[a + 1]; ++e)
+        for (int zr = 0; zr < zsplit; ++zr) s += part[(zr * zstride + red_idx[e]) * ncol * 4 + q];
+    D[(long)col * ldD + 4 * a + lm] = (T)(g4[4 * a + lm] * dV * s);
 }
 
 int choose_sweep_ty(int nx, int ny, int max_threads) {
     // tuning override: rows per y-slab
     if (const char* e = std::getenv("SPARC_GPU_SWEEP_TY")) {
         int v = std::atoi(e);
-        if (v >= 2 && v <= ny && ((v * nx + 63) / 64) * 64 <= max_threads) return v;
+        if (v >= 1 && v <= ny && ((v * nx + 63) / 64) * 64 <= max_threads) return v;
     }
     int maxty = std::max(1, std::min(16, max_threads / nx));
     maxty = std::min(maxty, ny);
-    // prefer the largest divisor of ny not above maxty, unless it is small
+    // the largest divisor of ny not above maxty, unless it is small
     int best = 1;
     for (int t = maxty; t >= 1; --t)
         if (ny % t == 0) {
@@ -563,10 +736,17 @@ float* D_of<float>(sparc_gpu_ctx c) {
     return c->D32;
 }
 
+// Slab height of the local sweep: the largest divisor of n_y with at most
+// 1024 threads in FP64 and 512 in FP32 (whose lighter threads prefer more
+// workgroups per CU), measured best on MI355X at 72 and 120 points per row.
+static int local_ty(sparc_gpu_ctx c, size_t tsize) {
+    return choose_sweep_ty(c->nx, c->ny, tsize == 8 ? 1024 : 512);
+}
+
 template <typename T>
 sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, int ncol, long ldx, int mode,
-                           int step, int dcol0, hipStream_t s) {
-    hipStream_t stream = s ? s : c->stream;
+                           int step) {
+    hipStream_t stream = c->stream;
     SweepArgs<T> a;
     a.x = x;
     a.out = out;
@@ -575,21 +755,25 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     a.nx = c->nx;
     a.ny = c->ny;
     a.nz = c->nz;
-    a.ty = choose_sweep_ty(c->nx, c->ny, 1024);
-    a.ntiles_y = div_up(c->ny, a.ty);
-    a.cf = coef<T>(c);
-    a.veff = veff_of<T>(c);
     const bool nl = !c->sweep_local_only && c->nl_lmax >= 1 && c->nl.n_pe > 0;
-    if (nl) {
-        a.ty = c->nl_ty;
-        a.ntiles_y = div_up(c->ny, a.ty);
+    a.ty = nl ? c->nl_ty : local_ty(c, sizeof(T));
+    a.ntiles_y = div_up(c->ny, a.ty);
+    {
+        const StencilCoef<T>& cf = coef<T>(c);
+        a.c0 = cf.c0;
+        for (int k = 0; k <= kMaxHalfOrder; ++k) a.ck[k] = cf.cx[k];
+        a.ry = (T)((c->hx * c->hx) / (c->hy * c->hy));
+        a.rz = (T)((c->hx * c->hx) / (c->hz * c->hz));
     }
+    a.veff = veff_of<T>(c);
     a.pe8 = c->nl.pe8;
     a.slab_cand = c->nl.slab_cand;
     a.slab_k = c->nl.slab_k;
+    a.pairs = c->nl.pairs;
+    a.pair_off = c->nl.pair_off;
     a.kmax = c->nl.slab_kmax;
     a.xw = c->nl.slab_xw;
-    a.zw = c->nl.slab_zw;
+    a.pmax = c->nl.pair_max;
     a.atom_pos = c->atom_pos;
     {
         const double pi = 3.14159265358979323846;
@@ -599,53 +783,45 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
         a.N0 = (T)N0;
         a.N1 = (T)((2.0 / rc) * N0);
         a.hx = (T)c->hx;
-        a.hy = (T)c->hy;
-        a.hz = (T)c->hz;
     }
-    a.D = D_of<T>(c) + (long)dcol0 * 4 * c->n_atoms;
+    a.D = D_of<T>(c);
     a.ldD = 4 * c->n_atoms;
     a.params = c->scal + S_A;
-    a.mode = mode;
     a.step = step;
     a.ncol = ncol;
-    a.slab_major = c->sweep_slab_major;
-    const int threads = div_up((long)c->nx * a.ty, 64) * 64;
-    size_t shmem = 2 * (size_t)(a.ty + 2 * kMaxHalfOrder) * (c->nx + 2 * kMaxHalfOrder) * sizeof(T);
-    if (nl) shmem = nl_sweep_lds_bytes(a.ty, c->nx, a.kmax, a.xw, a.zw, sizeof(T));
+    int threads = div_up((long)c->nx * a.ty, 64) * 64;
+    if (nl) threads = std::max(threads, div_up(a.pmax, 64) * 64);
+    const size_t shmem = sweep_lds_layout<T>(a.ty, c->nx, c->nz, nl ? a.kmax : 0, a.xw, nl).total;
     if (shmem > 160 * 1024) return set_err(c, SPARC_ERR_ARG, "sweep workgroup needs more than 160 KB of LDS");
-    if (threads > (nl ? 512 : 1024)) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
+    if (threads > (nl ? kNlThreads : 1024)) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
     const long nblocks = (long)ncol * a.ntiles_y;
     if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "too many blocks");
     const int hm = div_up(2L * kMaxHalfOrder * c->nx, threads);
-    if (hm > (nl ? 6 : 3)) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
+    if (hm > 6) return set_err(c, SPARC_ERR_ARG, "grid x-extent too large for the sweep kernel");
+    if (nblocks == 0) return SPARC_OK;
     const int slot = prof_begin(c, mode == 2 ? PK_SWEEP : (mode == 1 ? PK_SWEEP1 : PK_APPLY), stream);
     const dim3 g((unsigned)nblocks), b(threads);
 #define SG_LAUNCH_SWEEP(NLV, MV, HMV) k_hsweep<T, NLV, MV, HMV><<<g, b, shmem, stream>>>(a)
-#define SG_SWEEP_HM(NLV, MV)          \
-    do {                              \
-        if (hm == 1) SG_LAUNCH_SWEEP(NLV, MV, 1); \
-        else if (hm == 2) SG_LAUNCH_SWEEP(NLV, MV, 2); \
-        else SG_LAUNCH_SWEEP(NLV, MV, 3); \
-    } while (0)
-    // the nonlocal variant's slab can be as low as 2 rows on wide grids
-    // (its candidate tables share the LDS), hence up to 6 halo values
-#define SG_SWEEP_HM_NL(MV)            \
-    do {                              \
-        if (hm <= 3) SG_SWEEP_HM(true, MV); \
-        else if (hm == 4) SG_LAUNCH_SWEEP(true, MV, 4); \
-        else if (hm == 5) SG_LAUNCH_SWEEP(true, MV, 5); \
-        else SG_LAUNCH_SWEEP(true, MV, 6); \
+#define SG_SWEEP_HM(NLV, MV)                          \
+    do {                                              \
+        switch (hm) {                                 \
+            case 1: SG_LAUNCH_SWEEP(NLV, MV, 1); break; \
+            case 2: SG_LAUNCH_SWEEP(NLV, MV, 2); break; \
+            case 3: SG_LAUNCH_SWEEP(NLV, MV, 3); break; \
+            case 4: SG_LAUNCH_SWEEP(NLV, MV, 4); break; \
+            case 5: SG_LAUNCH_SWEEP(NLV, MV, 5); break; \
+            default: SG_LAUNCH_SWEEP(NLV, MV, 6); break; \
+        }                                             \
     } while (0)
     if (nl) {
-        if (mode == 0) SG_SWEEP_HM_NL(0);
-        else if (mode == 1) SG_SWEEP_HM_NL(1);
-        else SG_SWEEP_HM_NL(2);
+        if (mode == 0) SG_SWEEP_HM(true, 0);
+        else if (mode == 1) SG_SWEEP_HM(true, 1);
+        else SG_SWEEP_HM(true, 2);
     } else {
         if (mode == 0) SG_SWEEP_HM(false, 0);
         else if (mode == 1) SG_SWEEP_HM(false, 1);
         else SG_SWEEP_HM(false, 2);
     }
-#undef SG_SWEEP_HM_NL
 #undef SG_SWEEP_HM
 #undef SG_LAUNCH_SWEEP
     SG_CHECK_LAUNCH(c);
@@ -653,48 +829,88 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     return SPARC_OK;
 }
 
+// Orbitals per projection workgroup: 4, or 2 (SPARC_GPU_PROJ_NB = 2) where
+// that is asked for or the 4-orbital tables exceed LDS.
+static int proj_nb(sparc_gpu_ctx c, size_t tsize) {
+    const NonlocalTables& T = c->nl;
+    const size_t l4 = nl_proj_lds_bytes(c->nl_ty, c->nx, T.slab_kmax, T.slab_xw, T.pair_max, 4, tsize);
+    return (c->proj_nb == 2 || l4 > 160 * 1024) ? 2 : 4;
+}
+
 template <typename T>
-sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, int dcol0, hipStream_t s) {
-    if (c->nl_lmax < 1 || c->nl.n_sup == 0) return SPARC_OK;
-    hipStream_t stream = s ? s : c->stream;
-    const int per = (c->n_atoms + 7) / 8;
+sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) {
+    if (c->nl_lmax < 1 || c->nl.n_pe == 0 || ncol == 0) return SPARC_OK;
+    hipStream_t stream = c->stream;
+    const NonlocalTables& NT = c->nl;
+    ProjArgs a;
+    a.ldx = ldx;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.nz = c->nz;
+    a.ty = c->nl_ty;
+    a.ntiles_y = div_up(c->ny, a.ty);
+    a.ncol = ncol;
+    a.slab_cand = NT.slab_cand;
+    a.slab_k = NT.slab_k;
+    a.pairs = NT.pairs;
+    a.pair_off = NT.pair_off;
+    a.kmax = NT.slab_kmax;
+    a.xw = NT.slab_xw;
+    a.pmax = NT.pair_max;
+    a.atom_pos = c->atom_pos;
+    {
+        const double pi = 3.14159265358979323846;
+        const double rc = c->rc_nl;
+        const double N0 = std::pow(2.0 / (pi * rc * rc), 0.75);
+        a.inv_rc2 = 1.0 / (rc * rc);
+        a.N0 = N0;
+        a.N1 = (2.0 / rc) * N0;
+        a.hx = c->hx;
+    }
+    const int NB = proj_nb(c, sizeof(T));
+    const size_t shmem = nl_proj_lds_bytes(a.ty, a.nx, a.kmax, a.xw, a.pmax, NB, sizeof(T));
+    if (shmem > 160 * 1024) return set_err(c, SPARC_ERR_ARG, "projection workgroup needs more than 160 KB of LDS");
+    if ((long)NB * a.ty * a.nx > (long)kProjLoads * kProjThreads)
+        return set_err(c, SPARC_ERR_ARG, "slab too large for the projection kernel");
+    // z ranges per slab: enough workgroups for four per compute unit, each
+    // range at least 8 planes
+    const long base = (long)a.ntiles_y * div_up(ncol, NB);
+    a.zsplit = (int)std::max(1L, std::min((long)std::max(1, a.nz / 8), (long)div_up(1024L, base)));
+    a.zlen = div_up(a.nz, a.zsplit);
+    a.zsplit = div_up(a.nz, a.zlen);
+    const size_t need = (size_t)a.zsplit * a.ntiles_y * a.kmax * ncol * 4;
+    if (c->nl_part_elems < need) {
+        if (c->nl_part) {
+            SG_HIP(c, hipStreamSynchronize(stream));
+            SG_HIP(c, hipFree(c->nl_part));
+            c->nl_part = nullptr;
+            c->nl_part_elems = 0;
+        }
+        SG_HIP(c, hipMalloc((void**)&c->nl_part, need * sizeof(double)));
+        c->nl_part_elems = need;
+    }
+    a.part = c->nl_part;
+    const long nblocks = base * a.zsplit;
+    if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "too many blocks");
     const int slot = prof_begin(c, PK_PROJ, stream);
-    const double pi = 3.14159265358979323846;
-    const double rc = c->rc_nl;
-    const double N0 = std::pow(2.0 / (pi * rc * rc), 0.75), N1 = (2.0 / rc) * N0;
-    const int ext = c->nl.box_ext;
-    T* Dd = D_of<T>(c) + (long)dcol0 * 4 * c->n_atoms;
-#define SG_PROJ(NBV, UV)                                                                                           \
-    k_projection<T, NBV, UV><<<dim3(8 * per * div_up(ncol, NBV)), 256, 6 * ext * sizeof(double), stream>>>(            \
-        x, ldx, ncol, c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo, ext, c->atom_pos, c->hx, c->hy, c->hz, \
-        1.0 / (rc * rc), N0, N1, c->nl.gamma4, c->dV, Dd, 4 * c->n_atoms, c->nl.atom_order, c->n_atoms)
-    // columns per workgroup (tuning override SPARC_GPU_PROJ_NB = 2, 4 or 8):
-    // fewer accumulators per thread keep more waves in flight for the gather
-    // and points in flight per thread (SPARC_GPU_PROJ_U = 1, 2 or 4; by
-    // default 2 in FP64 and 1 in FP32, the faster of each on cfg2)
-    const int pu = c->proj_u > 0 ? c->proj_u : (sizeof(T) == 8 ? 2 : 1);
-    if (c->proj_nb == 2)
-        SG_PROJ(2, 4);
-    else if (c->proj_nb == 8)
-        SG_PROJ(8, 2);
-    else if (pu == 1)
-        SG_PROJ(4, 1);
-    else if (pu == 4)
-        SG_PROJ(4, 4);
+    if (NB == 4)
+        k_proj_stream<T, 4><<<dim3((unsigned)nblocks), kProjThreads, shmem, stream>>>(x, a);
     else
-        SG_PROJ(4, 2);
-#undef SG_PROJ
+        k_proj_stream<T, 2><<<dim3((unsigned)nblocks), kProjThreads, shmem, stream>>>(x, a);
+    SG_CHECK_LAUNCH(c);
+    k_proj_reduce<T><<<dim3(c->n_atoms, div_up(4L * ncol, 256)), 256, 0, stream>>>(
+        c->nl_part, ncol, a.zsplit, (long)a.ntiles_y * a.kmax, NT.red_off, NT.red_idx, NT.gamma4, c->dV, D_of<T>(c),
+        4 * c->n_atoms);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot, stream);
     return SPARC_OK;
 }
 
 template sparc_status launch_hsweep<double>(sparc_gpu_ctx, const double*, double*, const double*, int, long, int,
-                                            int, int, hipStream_t);
-template sparc_status launch_hsweep<float>(sparc_gpu_ctx, const float*, float*, const float*, int, long, int, int,
-                                           int, hipStream_t);
-template sparc_status launch_projection<double>(sparc_gpu_ctx, const double*, int, long, int, hipStream_t);
-template sparc_status launch_projection<float>(sparc_gpu_ctx, const float*, int, long, int, hipStream_t);
+                                            int);
+template sparc_status launch_hsweep<float>(sparc_gpu_ctx, const float*, float*, const float*, int, long, int, int);
+template sparc_status launch_projection<double>(sparc_gpu_ctx, const double*, int, long);
+template sparc_status launch_projection<float>(sparc_gpu_ctx, const float*, int, long);
 
 template <typename T>
 static sparc_status apply_impl(sparc_gpu_ctx c, const T* X, T* Y, int ncol, long ldx) {
@@ -711,68 +927,28 @@ __global__ void k_copy_block(const T* __restrict__ src, T* __restrict__ dst, lon
 }
 
 // Filter with bounds already in c->scal[S_A..S_A0].  Y_k lives in X when k is
-// even and in W when k is odd; the result ends in X.
-//
-// One chain of the filter over columns [col0, col0 + ncol) on stream s.
+// even and in W when k is odd; the result ends in X.  The projections of
+// Y_0 come from the gather kernel; every later sweep forms the projections
+// of its own output for the next one (not needed after the last).
 template <typename T>
-static sparc_status filter_chain(sparc_gpu_ctx c, T* X, T* Wk, int col0, int ncol, long ldx, int m, hipStream_t s) {
+sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m) {
     sparc_status st;
-    X += (long)col0 * ldx;
-    Wk += (long)col0 * ldx;
-    if ((st = launch_projection<T>(c, X, ncol, ldx, col0, s)) != SPARC_OK) return st;
-    if ((st = launch_hsweep<T>(c, X, Wk, nullptr, ncol, ldx, 1, 1, col0, s)) != SPARC_OK) return st;
+    // every sweep needs the projections of its operand
+    if ((st = launch_projection<T>(c, X, ncol, ldx)) != SPARC_OK) return st;
+    if ((st = launch_hsweep<T>(c, X, Wk, nullptr, ncol, ldx, 1, 1)) != SPARC_OK) return st;
     for (int k = 2; k <= m; ++k) {
         T* cur = (k % 2 == 0) ? Wk : X;   // Y_{k-1}
         T* dst = (k % 2 == 0) ? X : Wk;   // Y_{k-2}, overwritten with Y_k
-        if ((st = launch_projection<T>(c, cur, ncol, ldx, col0, s)) != SPARC_OK) return st;
-        if ((st = launch_hsweep<T>(c, cur, dst, dst, ncol, ldx, 2, k, col0, s)) != SPARC_OK) return st;
+        if ((st = launch_projection<T>(c, cur, ncol, ldx)) != SPARC_OK) return st;
+        if ((st = launch_hsweep<T>(c, cur, dst, dst, ncol, ldx, 2, k)) != SPARC_OK) return st;
     }
     if (m % 2 == 1) {
         dim3 grid(div_up(c->nd, 256), ncol);
-        k_copy_block<T><<<grid, 256, 0, s>>>(Wk, X, c->nd, ncol, ldx);
+        const int slot = prof_begin(c, PK_COPY);
+        k_copy_block<T><<<grid, 256, 0, c->stream>>>(Wk, X, c->nd, ncol, ldx);
         SG_CHECK_LAUNCH(c);
+        prof_end(c, slot);
     }
-    return SPARC_OK;
-}
-
-// The filter acts on every column independently.  Optionally (context flag
-// split_filter, off by default) a block of at least 64 columns with
-// projectors is split in two halves filtered on two streams, the second
-// started one projection later, so that kernels of the two halves overlap.
-// The default is one stream: concurrent halves make the per-launch times
-// of the sweep overlap each other.
-template <typename T>
-sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m) {
-    const bool nl = c->nl_lmax >= 1 && c->nl.n_sup > 0;
-    if (!nl || ncol < 64 || !c->split_filter) return filter_chain<T>(c, X, Wk, 0, ncol, ldx, m, c->stream);
-    if (!c->aux_stream) {
-        SG_HIP(c, hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
-        SG_HIP(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-        SG_HIP(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
-    }
-    const int na = ncol / 2, nb = ncol - na;
-    sparc_status st;
-    // second half: starts after the first half's first projection (and after
-    // everything queued before this call on the context stream)
-    if ((st = launch_projection<T>(c, X, na, ldx, 0, c->stream)) != SPARC_OK) return st;
-    SG_HIP(c, hipEventRecord(c->fork_ev, c->stream));
-    SG_HIP(c, hipStreamWaitEvent(c->aux_stream, c->fork_ev, 0));
-    if ((st = filter_chain<T>(c, X, Wk, na, nb, ldx, m, c->aux_stream)) != SPARC_OK) return st;
-    // first half (its first projection is already queued)
-    if ((st = launch_hsweep<T>(c, X, Wk, nullptr, na, ldx, 1, 1, 0, c->stream)) != SPARC_OK) return st;
-    for (int k = 2; k <= m; ++k) {
-        T* cur = (k % 2 == 0) ? Wk : X;
-        T* dst = (k % 2 == 0) ? X : Wk;
-        if ((st = launch_projection<T>(c, cur, na, ldx, 0, c->stream)) != SPARC_OK) return st;
-        if ((st = launch_hsweep<T>(c, cur, dst, dst, na, ldx, 2, k, 0, c->stream)) != SPARC_OK) return st;
-    }
-    if (m % 2 == 1) {
-        dim3 grid(div_up(c->nd, 256), na);
-        k_copy_block<T><<<grid, 256, 0, c->stream>>>(Wk, X, c->nd, na, ldx);
-        SG_CHECK_LAUNCH(c);
-    }
-    SG_HIP(c, hipEventRecord(c->join_ev, c->aux_stream));
-    SG_HIP(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
     return SPARC_OK;
 }
 
