@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <cstdlib>
 #include <numeric>
@@ -296,6 +297,10 @@ __global__ void k_pair_geometry(SweepPair* pairs, long n, const int* pair_off, i
     }
     const int sl = lo / nz, z = lo - sl * nz;
     SweepPair& P = pairs[q];
+    if (P.n == 0) {
+        P.eyez = P.dy = P.dz = 0.0;
+        return;
+    }
     const CandInfo ci = cand[(long)sl * kmax + P.k];
     const double cy = pos[3 * ci.atom + 1] - (double)ci.sy * Ly;
     const double cz = pos[3 * ci.atom + 2] - (double)ci.sz * Lz;
@@ -304,6 +309,19 @@ __global__ void k_pair_geometry(SweepPair* pairs, long n, const int* pair_off, i
     P.dy = dy;
     P.dz = dz;
     P.eyez = exp(-(dy * dy + dz * dz) * inv_rc2);
+}
+
+__global__ void k_pack_proj_pairs(const SweepPair* pairs, long n, ProjPair* out) {
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const SweepPair P = pairs[q];
+    ProjPair R;
+    R.kw = (uint32_t)P.k | ((uint32_t)P.xo << 10) | ((uint32_t)P.run << 18);
+    R.rw = (uint32_t)P.row | ((uint32_t)P.xlo << 8) | ((uint32_t)P.n << 16);
+    R.eyez = P.eyez;
+    R.dy = P.dy;
+    R.dz = P.dz;
+    out[q] = R;
 }
 
 // ------------------------------------------------------------------ host set-up
@@ -480,22 +498,33 @@ sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent
             if (tup[q - 1].x != xlo + n - 1)
                 return set_err(c, SPARC_ERR_ARG, "projector support is not a segment on a grid line");
             if (n > 255 || xlo > 255) return set_err(c, SPARC_ERR_ARG, "projector segment too long for the sweep tables");
-            if (npl >= 255) return set_err(c, SPARC_ERR_ARG, "more than 255 projector segments in one slab plane");
+            const int sl = (int)(sz_key / nz);
             SweepPair sp;
             sp.k = (int)((tup[j].key >> 6) & 1023u);
             sp.row = (int)(tup[j].key & 63u);
             sp.xlo = xlo;
             sp.n = n;
             sp.run = 0;
-            sp.pad = 0;
+            sp.xo = xlo - (cands[sl][sp.k].ixlo - cands[sl][sp.k].sx * nx);
             sp.eyez = sp.dy = sp.dz = 0.0;
-            // run length of the candidate's pairs, held by its first pair
+            // run length of the candidate's pairs, held by its first pair; a
+            // run never crosses a multiple of 64 in the plane list (empty
+            // pairs pad it), so that one wave holds every run it starts
             if (npl == 0 || pairs.back().k != sp.k) {
                 int r = 0;
                 for (size_t q2 = j; q2 < tup.size() && (tup[q2].key >> 6) == (tup[j].key >> 6); ++q2)
                     if (q2 == j || (tup[q2].key & 63u) != (tup[q2 - 1].key & 63u)) ++r;
                 sp.run = r;
+                if (npl % 64 + r > 64) {
+                    SweepPair pad{};
+                    while (npl % 64 != 0) {
+                        pairs.push_back(pad);
+                        ++npl;
+                    }
+                }
             }
+            if (npl >= 255) return set_err(c, SPARC_ERR_ARG, "more than 255 projector segments in one slab plane");
+            if (sp.xo < 0 || sp.xo > 255) return set_err(c, SPARC_ERR_ARG, "projector support wider than 256 points");
             for (size_t r = j; r < q; ++r) ent_pair[tup[r].e] = npl;
             pairs.push_back(sp);
             ++npl;
@@ -559,8 +588,15 @@ sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent
             T.pairs, (long)pairs.size(), T.pair_off, nslab * nz, T.slab_cand, T.slab_kmax, nz, ty, c->atom_pos,
             c->hy, c->hz, (double)ny * c->hy, (double)nz * c->hz, 1.0 / (c->rc_nl * c->rc_nl));
         SG_CHECK_LAUNCH(c);
+        SG_HIP(c, hipMalloc((void**)&T.ppairs, pairs.size() * sizeof(ProjPair)));
+        k_pack_proj_pairs<<<div_up((long)pairs.size(), 256), 256, 0, c->stream>>>(T.pairs, (long)pairs.size(),
+                                                                                  T.ppairs);
+        SG_CHECK_LAUNCH(c);
     }
     c->nl_ty = ty;
+    if (c->debug)
+        fprintf(stderr, "[sparc_gpu] pair tables: ty %d, %zu pairs, at most %d per plane, %d candidates, ex width %d\n",
+                ty, pairs.size(), T.pair_max, T.slab_kmax, T.slab_xw);
     return SPARC_OK;
 }
 
@@ -731,20 +767,20 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             T.n_pe = (long)ent.size();
             // slab height: from the nonlocal sweep's largest choice down, the
             // first whose tables fit (at most 255 segments per slab plane, the
-            // FP64 sweep and the 2-orbital FP64 projection within 160 KB of LDS)
+            // FP64 sweep and the two-wave FP64 projection within 160 KB of LDS)
             for (int ty = choose_sweep_ty(c->nx, c->ny, nl_sweep_max_threads());; --ty) {
                 st = build_pair_tables(c, ent, ty);
                 const NonlocalTables& N = c->nl;
                 const size_t lds = st == SPARC_OK
                                        ? std::max(nl_sweep_lds_bytes(ty, c->nx, c->nz, N.slab_kmax, N.slab_xw, 8),
-                                                  nl_proj_lds_bytes(ty, c->nx, N.slab_kmax, N.slab_xw, N.pair_max,
-                                                                    2, 8))
+                                                  nl_proj_lds_bytes(ty, c->nx, c->nz, N.slab_kmax, N.slab_xw, 2, 8))
                                        : 0;
                 if (st == SPARC_OK && lds <= 160 * 1024) break;
                 if (ty <= 1) return st != SPARC_OK ? st : set_err(c, SPARC_ERR_ARG, "projector tables exceed LDS");
                 for (void* p : {(void*)T.pe8, (void*)T.slab_cand, (void*)T.slab_k, (void*)T.pairs, (void*)T.pair_off,
-                                (void*)T.red_off, (void*)T.red_idx})
+                                (void*)T.red_off, (void*)T.red_idx, (void*)T.ppairs})
                     if (p) hipFree(p);
+                T.ppairs = nullptr;
                 T.pe8 = nullptr;
                 T.slab_cand = nullptr;
                 T.slab_k = nullptr;
@@ -959,7 +995,7 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
                     c->kp_bounds, c->kp_wts, c->b, c->pois_ux, c->pois_uy, c->pois_uz, c->pois_inv, c->work, c->D,
                     c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,
                     c->nl.sup_chi, c->nl.gamma4, c->nl.atom_order, c->atom_pos, c->nl.pe8, c->nl.slab_cand,
-                    c->nl.slab_k, c->nl.pairs, c->nl.pair_off, c->nl.red_off, c->nl.red_idx, c->nl_part,
+                    c->nl.slab_k, c->nl.pairs, c->nl.ppairs, c->nl.pair_off, c->nl.red_off, c->nl.red_idx, c->nl_part,
                     c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo};
     for (void* p : ptrs)
         if (p) hipFree(p);

@@ -35,11 +35,19 @@ struct CandInfo {
 // points x in [xlo, xlo + n) of slab row `row` at one plane z lie in the
 // support of slab candidate k; eyez = exp(-(dy^2 + dz^2)/rc^2) with dy, dz the
 // line's offsets from the candidate's (image-shifted) centre.  The host
-// fills k, row, xlo, n, run; the device the geometry (k_pair_geometry).
+// fills k, row, xlo, n, run, xo; the device the geometry (k_pair_geometry).
+// A plane list may hold empty pairs (n = 0), which contribute nothing.
 struct SweepPair {
     int k, row, xlo, n;
     int run;   // first pair of a candidate in its plane list: the candidate's pair count; else 0
-    int pad;
+    int xo;    // index of the segment's first point in the candidate's ex table
+    double eyez, dy, dz;
+};
+
+// The same pair packed for the projection pass (32 bytes):
+// kw = k | xo << 10 | run << 18, rw = row | xlo << 8 | n << 16.
+struct ProjPair {
+    uint32_t kw, rw;
     double eyez, dy, dz;
 };
 
@@ -68,6 +76,7 @@ struct NonlocalTables {
     int* slab_k = nullptr;                  // candidates per slab
     int slab_kmax = 0, slab_xw = 0;
     SweepPair* pairs = nullptr;             // all segments, plane lists back to back
+    ProjPair* ppairs = nullptr;             // the same, packed for the projection pass
     int* pair_off = nullptr;                // n_slabs * nz + 1: list of (slab, plane)
     int pair_max = 0;                       // longest plane list
     // the (slab, candidate) partial projections of one atom, in fixed order:
@@ -174,7 +183,7 @@ struct sparc_gpu_ctx_s {
 
     // captured Jacobi sweep (see dense.hip)
     hipStream_t cap_stream = nullptr;
-    int proj_nb = 4;            // SPARC_GPU_PROJ_NB: orbitals per projection workgroup (2 or 4)
+    int proj_nb = 8;            // SPARC_GPU_PROJ_NB: at most this many orbitals per projection workgroup (2, 4, 8)
     int gemm_tile = 0;          // SPARC_GPU_GEMM_TILE: Gram/projected-H tile edge (128, 160; 0: by size)
     int gemm_nn_cols = 160;     // SPARC_GPU_GEMM_NN_COLS: rotation tile width (160, 288)
     hipGraphExec_t jac_exec = nullptr;
@@ -253,9 +262,8 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx);
 // LDS bytes of a nonlocal sweep workgroup (slab height ty, nz planes, K
 // candidates, ex tables xw wide) of element size tsize
 size_t nl_sweep_lds_bytes(int ty, int nx, int nz, int K, int xw, size_t tsize);
-// LDS bytes of a projection workgroup (also PM pairs per plane at most, NB
-// orbitals)
-size_t nl_proj_lds_bytes(int ty, int nx, int K, int xw, int PM, int NB, size_t tsize);
+// LDS bytes of a projection workgroup of NW waves (one orbital each)
+size_t nl_proj_lds_bytes(int ty, int nx, int nz, int K, int xw, int NW, size_t tsize);
 int nl_sweep_max_threads();   // workgroup size limit of the nonlocal sweep
 
 // C(MxN, col-major, ldc) = alpha * A^T B, A: K x M (lda), B: K x N (ldb),

@@ -382,6 +382,28 @@ __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> 
             if (z >= nz) break;
             const int P = U & 1, PN = (U + 1) & 1, QS = U % PQ, QN = (U + 1) % PQ;
             __syncthreads();
+            // nonlocal term of plane z: the sum over the pairs whose
+            // segment holds this point of chi_s D_s + chi_p . D_p =
+            // ex (A'' + B' x)
+            T nl = 0;
+            if (NL) {
+                const uint64_t w = active ? w8[QS] : ~0ull;
+                const PairLds<T>* rb = sh.rec + P * kPairSlots;
+                auto slot = [&](int sl) {
+                    const PairLds<T>& R8 = rb[(int)((w >> (8 * sl)) & 0xFFull)];
+                    const T e = *reinterpret_cast<const T*>(smem_raw + (R8.exb + lxb));
+                    nl += e * (R8.A + R8.B * lxd);
+                };
+                // four slots for every point; the other three only where a
+                // point of the wave lies in more than four supports (about
+                // one point in a hundred)
+#pragma unroll
+                for (int sl = 0; sl < 4; ++sl) slot(sl);
+                if (((uint32_t)(w >> 32) | 0xFF000000u) != 0xFFFFFFFFu) {
+#pragma unroll
+                    for (int sl = 4; sl < kSlots; ++sl) slot(sl);
+                }
+            }
             // 2. loads of later planes
             {
                 const long zo = (long)wz(z + PQ) * plane;
@@ -401,21 +423,7 @@ __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> 
                 s += a.rz * (q[(U + k) % RING] + q[(U + RING - k) % RING]);
                 lap += a.ck[k] * s;
             }
-            T hv = lap + ve[QS] * q[C];
-            if (NL) {
-                // sum over the pairs whose segment holds this point of
-                // chi_s D_s + chi_p . D_p = ex (A'' + B' x)
-                const uint64_t w = active ? w8[QS] : ~0ull;
-                const PairLds<T>* rb = sh.rec + P * kPairSlots;
-                T nl = 0;
-#pragma unroll
-                for (int sl = 0; sl < kSlots; ++sl) {
-                    const PairLds<T>& R8 = rb[(int)((w >> (8 * sl)) & 0xFFull)];
-                    const T e = *reinterpret_cast<const T*>(smem_raw + (R8.exb + lxb));
-                    nl += e * (R8.A + R8.B * lxd);
-                }
-                hv += nl;
-            }
+            T hv = lap + ve[QS] * q[C] + nl;
             T o;
             if (MODE == 0) {
                 o = hv;
@@ -451,75 +459,79 @@ __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> 
 }
 
 // Projections by streaming the block once.  D(4a+lm, j) = gamma_lm dV
-// sum_p chi_lm(p) X(p, j) over the image points of atom a's support.  One
+// sum_p chi_lm(p) X(p, j) over the image points of atom a's support.  A
 // workgroup takes one y-slab of the nonlocal sweep (the same slabs and pair
-// tables), NB orbitals and a range of z-planes; it reads each plane of the
-// slab once (coalesced rows), and for each pair (candidate k, row, segment)
-// of the plane forms
+// tables), a range of z-planes and NW orbitals, one per wave; the waves
+// share the slab's ex tables and otherwise run independently (no workgroup
+// barrier after set-up).  A wave copies each plane of its orbital's slab
+// into its own LDS (coalesced rows, two planes in flight ahead) and, 64
+// pairs (candidate k, row, segment) at a time, one per lane, forms
 //   S0 = sum_i ex_k(i) X(i),  S1 = sum_i i ex_k(i) X(i)   (i: ex index),
 // whose contributions to candidate k are, with f_s = eyez N0, f_p = eyez N1,
 //   s: f_s S0,  p_x: f_p (delta_k S0 + hx S1),  p_y: f_p dy S0,  p_z: f_p dz S0.
-// The first pair of each candidate's run in a plane adds the run's
-// contributions, in row order, to the candidate's accumulators; planes are
-// taken in order.  Every sum is in double and in a fixed order, so the
-// result is bitwise reproducible.  The accumulators of the (slab, z range,
-// candidate) are written as partials, which k_proj_reduce sums per atom.
-constexpr int kProjThreads = 512;
-constexpr int kProjLoads = 6;   // plane values per thread and plane: NB ty nx <= 6 x 512
-
-struct ProjRecLds {
-    int k, row, xlo, n;  // segment: grid x in [xlo, xlo + n) of slab row `row`
-    int xo, run, pad0, pad1;  // xo: ex index of the segment's first point
-    double fs, fp, fpdy, fpdz;
-};
+// The lane of the first pair of each candidate's run (never split over two
+// groups of 64) adds the run's contributions, in row order, to the
+// candidate's accumulators; planes are taken in order.  Every sum is in
+// double and in a fixed order, so the result is bitwise reproducible.  The
+// accumulators of the (z range, slab, candidate) are written as partials,
+// which k_proj_reduce sums per atom.
+constexpr int kProjWaveVals = 12;   // plane values per lane: ty nx <= 768
 
 struct ProjLds {
-    size_t ex, delta, planes, rec, psum, acc, total;
+    size_t ex, delta, poff, wave, wave_bytes, total;
 };
 
-__host__ __device__ inline ProjLds proj_lds_layout(int ty, int nx, int K, int xw, int PM, int NB, size_t ts) {
+__host__ __device__ inline ProjLds proj_lds_layout(int ty, int nx, int nz, int K, int xw, int NW, size_t ts) {
     ProjLds L{};
     size_t o = 0;
     L.ex = o;
     o += align16((size_t)K * xw * sizeof(double));
     L.delta = o;
     o += align16((size_t)K * sizeof(double));
-    L.planes = o;
-    o += align16(2 * (size_t)NB * ty * nx * ts);
-    L.rec = o;
-    o += align16(2 * (size_t)PM * sizeof(ProjRecLds));
-    L.psum = o;
-    o += align16((size_t)PM * NB * 4 * sizeof(double));
-    L.acc = o;
-    o += align16((size_t)K * NB * 4 * sizeof(double));
+    L.poff = o;
+    o += align16(((size_t)nz + 1) * sizeof(int));
+    // per wave: its plane (64 x kProjWaveVals values, of which ty nx are
+    // used), 64 x 4 pair contributions, K x 4 accumulators
+    L.wave_bytes = align16((size_t)64 * kProjWaveVals * ts) + 64 * 4 * sizeof(double) +
+                   align16((size_t)K * 4 * sizeof(double));
+    L.wave = o;
+    o += (size_t)NW * L.wave_bytes;
     L.total = o;
     return L;
 }
 
-size_t nl_proj_lds_bytes(int ty, int nx, int K, int xw, int PM, int NB, size_t tsize) {
-    return proj_lds_layout(ty, nx, K, xw, PM, NB, tsize).total;
+size_t nl_proj_lds_bytes(int ty, int nx, int nz, int K, int xw, int NW, size_t tsize) {
+    return proj_lds_layout(ty, nx, nz, K, xw, NW, tsize).total;
 }
 
 struct ProjArgs {
     long ldx;
-    int nx, ny, nz, ty, ntiles_y, ncol;
+    int nx, ny, nz, ty, ntiles_y, ncol, nw;
     int zsplit, zlen;          // z ranges per slab and planes per range
     const CandInfo* slab_cand;
     const int* slab_k;
-    const SweepPair* pairs;
+    const ProjPair* ppairs;
     const int* pair_off;
-    int kmax, xw, pmax;
+    int kmax, xw;
     const double* atom_pos;
     double inv_rc2, N0, N1, hx;
     double* part;              // [((zr * ntiles_y + slab) * kmax + k) * ncol + col] * 4
 };
 
-template <typename T, int NB>
-__global__ __launch_bounds__(kProjThreads) void k_proj_stream(const T* __restrict__ x, ProjArgs a) {
+// LDS writes of one lane made visible to the other lanes of its wave
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, ProjArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int nx = a.nx, ny = a.ny;
     const long plane = (long)nx * ny;
-    const int nchunk = (a.ncol + NB - 1) / NB;
+    const int NW = a.nw;
+    const int nchunk = (a.ncol + NW - 1) / NW;
     // block -> (column chunk, z range, slab), slabs fastest
     int bid = blockIdx.x;
     const int tile = bid % a.ntiles_y;
@@ -527,7 +539,6 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_stream(const T* __restric
     const int zr = bid % a.zsplit;
     const int chunk = bid / a.zsplit;
     if (chunk >= nchunk) return;
-    const int n0 = chunk * NB, nb = min(NB, a.ncol - n0);
     const int y0 = tile * a.ty, tyn = min(a.ty, ny - y0);
     const int zb = zr * a.zlen, ze = min(a.nz, zb + a.zlen);
     const int t = threadIdx.x, nt = blockDim.x;
@@ -535,134 +546,151 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_stream(const T* __restric
     const CandInfo* ci = a.slab_cand + (long)tile * a.kmax;
     const int* poffg = a.pair_off + (long)tile * a.nz;
 
-    const ProjLds L = proj_lds_layout(a.ty, nx, a.kmax, a.xw, a.pmax, NB, sizeof(T));
+    const ProjLds L = proj_lds_layout(a.ty, nx, a.nz, a.kmax, a.xw, NW, sizeof(T));
     double* ex = reinterpret_cast<double*>(smem_raw + L.ex);
     double* delta = reinterpret_cast<double*>(smem_raw + L.delta);
-    T* buf = reinterpret_cast<T*>(smem_raw + L.planes);
-    ProjRecLds* prec = reinterpret_cast<ProjRecLds*>(smem_raw + L.rec);
-    double* psum = reinterpret_cast<double*>(smem_raw + L.psum);
-    double* acc = reinterpret_cast<double*>(smem_raw + L.acc);
-    const int pl = NB * a.ty * nx;  // values of one plane buffer
-
+    int* poff = reinterpret_cast<int*>(smem_raw + L.poff);   // plane lists of z in [zb, ze]
     for (int j = t; j < K * a.xw; j += nt) {
         const int k = j / a.xw, i = j - k * a.xw;
         const double dx = (double)(ci[k].ixlo + i) * a.hx - a.atom_pos[3 * ci[k].atom];
         ex[j] = exp(-dx * dx * a.inv_rc2);
     }
     for (int k = t; k < K; k += nt) delta[k] = (double)ci[k].ixlo * a.hx - a.atom_pos[3 * ci[k].atom];
-    for (int j = t; j < K * NB * 4; j += nt) acc[j] = 0.0;
-
-    // this thread's plane values: element e = t + i nt of (n, row, x)
-    long goff[kProjLoads];
-    int loff[kProjLoads];
-    const int nvals = nb * tyn * nx;
-#pragma unroll
-    for (int i = 0; i < kProjLoads; ++i) {
-        const int e = t + i * nt;
-        goff[i] = -1;
-        loff[i] = 0;
-        if (e < nvals) {
-            const int n = e / (tyn * nx), r = e - n * tyn * nx;
-            const int row = r / nx, xx = r - row * nx;
-            goff[i] = (long)(n0 + n) * a.ldx + xx + (long)nx * (y0 + row);
-            loff[i] = (n * a.ty + row) * nx + xx;
-        }
-    }
-    // one pair of plane z as an LDS record
-    auto load_rec = [&](int z, int j, ProjRecLds& R) -> bool {
-        const int o0 = poffg[z], o1 = poffg[z + 1];
-        if (j >= o1 - o0) return false;
-        const SweepPair P = a.pairs[o0 + j];
-        R.k = P.k;
-        R.row = P.row;
-        R.xo = P.xlo - (ci[P.k].ixlo - ci[P.k].sx * nx);
-        R.xlo = P.xlo;
-        R.n = P.n;
-        R.run = P.run;
-        R.pad0 = R.pad1 = 0;
-        R.fs = P.eyez * a.N0;
-        R.fp = P.eyez * a.N1;
-        R.fpdy = R.fp * P.dy;
-        R.fpdz = R.fp * P.dz;
-        return true;
-    };
-    // plane zb into buffer 0, its pairs into record set 0
-    if (zb < ze) {
-#pragma unroll
-        for (int i = 0; i < kProjLoads; ++i)
-            if (goff[i] >= 0) buf[loff[i]] = x[goff[i] + (long)zb * plane];
-        for (int j = t; j < a.pmax; j += nt) {
-            ProjRecLds R;
-            if (load_rec(zb, j, R)) prec[j] = R;
-        }
-    }
+    for (int z = zb + t; z <= ze; z += nt) poff[z - zb] = poffg[z];
     __syncthreads();
-    for (int z = zb; z < ze; ++z) {
-        const int P = (z - zb) & 1;
-        const bool more = z + 1 < ze;
-        // loads of plane z + 1 and its pair records
-        T v[kProjLoads];
+
+    const int w = t >> 6, lane = t & 63;
+    const int col = chunk * NW + w;
+    if (col >= a.ncol) return;
+    unsigned char* wb = smem_raw + L.wave + (size_t)w * L.wave_bytes;
+    T* buf = reinterpret_cast<T*>(wb);
+    double* psum = reinterpret_cast<double*>(wb + align16((size_t)64 * kProjWaveVals * sizeof(T)));
+    double* acc = psum + 64 * 4;
+    for (int j = lane; j < K * 4; j += 64) acc[j] = 0.0;
+
+    // The slab's rows of one plane are contiguous: value e of the plane is
+    // global offset base + e and LDS offset e.  Loads and stores take no
+    // branch (values past the plane and planes past the range read clamped
+    // valid addresses and land in unused LDS), so that the loads of later
+    // planes stay in flight while a plane is processed.
+    const int nvals = tyn * nx;
+    const T* xs = x + (long)col * a.ldx + (long)nx * y0;
+    long eoff[kProjWaveVals];
 #pragma unroll
-        for (int i = 0; i < kProjLoads; ++i)
-            v[i] = (more && goff[i] >= 0) ? x[goff[i] + (long)(z + 1) * plane] : (T)0;
-        ProjRecLds Rn;
-        const bool hasr = more && t < a.pmax && load_rec(z + 1, t, Rn);
-        // pair sums of plane z
-        const int np = poffg[z + 1] - poffg[z];
-        const T* bp = buf + P * pl;
-        const ProjRecLds* rp = prec + P * a.pmax;
-        for (int task = t; task < np * NB; task += nt) {
-            const int j = task / NB, n = task - j * NB;
-            if (n >= nb) continue;
-            const ProjRecLds& R = rp[j];
-            const T* xr = bp + (n * a.ty + R.row) * nx + R.xlo;
-            const double* er = ex + R.k * a.xw + R.xo;
-            double s0 = 0.0, s1 = 0.0, ii = (double)R.xo;
-            for (int i = 0; i < R.n; ++i) {
-                const double ev = er[i] * (double)xr[i];
-                s0 += ev;
-                s1 += ev * ii;
-                ii += 1.0;
-            }
-            double* ps = psum + (j * NB + n) * 4;
-            ps[0] = R.fs * s0;
-            ps[1] = R.fp * (delta[R.k] * s0 + a.hx * s1);
-            ps[2] = R.fpdy * s0;
-            ps[3] = R.fpdz * s0;
-        }
-        __syncthreads();
-        // each candidate's run adds to its accumulators, rows in order
-        for (int task = t; task < np * NB; task += nt) {
-            const int j = task / NB, n = task - j * NB;
-            const ProjRecLds& R = rp[j];
-            if (n >= nb || R.run == 0) continue;
-            double* ac = acc + (R.k * NB + n) * 4;
-            double c0 = ac[0], c1 = ac[1], c2 = ac[2], c3 = ac[3];
-            for (int r = 0; r < R.run; ++r) {
-                const double* ps = psum + ((j + r) * NB + n) * 4;
-                c0 += ps[0];
-                c1 += ps[1];
-                c2 += ps[2];
-                c3 += ps[3];
-            }
-            ac[0] = c0;
-            ac[1] = c1;
-            ac[2] = c2;
-            ac[3] = c3;
-        }
-        if (more) {
-            T* bq = buf + (1 - P) * pl;
+    for (int i = 0; i < kProjWaveVals; ++i) eoff[i] = min(lane + 64 * i, nvals - 1);
+    T va[kProjWaveVals], vb[kProjWaveVals];
+    auto load_plane = [&](T* v, int z) {
+        const long zo = (long)min(z, ze - 1) * plane;
 #pragma unroll
-            for (int i = 0; i < kProjLoads; ++i)
-                if (goff[i] >= 0) bq[loff[i]] = v[i];
-            if (hasr) prec[(1 - P) * a.pmax + t] = Rn;
+        for (int i = 0; i < kProjWaveVals; ++i) v[i] = xs[zo + eoff[i]];
+    };
+    auto store_plane = [&](const T* v) {
+#pragma unroll
+        for (int i = 0; i < kProjWaveVals; ++i) buf[lane + 64 * i] = v[i];
+    };
+    // The pairs of a plane, 64 per group (lane = pair); the first three
+    // groups are loaded a plane ahead.  Lanes past the list load a clamped
+    // valid record and ignore it (the record is not touched before use, so
+    // that its load stays in flight).
+    constexpr int kGroups = 3;
+    auto load_recs = [&](ProjPair* R, int z) {
+        const int zc = min(z, ze - 1) - zb;
+        const int o0 = poff[zc], np = poff[zc + 1] - o0;
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) {
+            const int j = 64 * g + lane;
+            R[g] = a.ppairs[max(0, o0 + min(j, np - 1))];
         }
-        __syncthreads();
+    };
+    auto do_group = [&](const ProjPair& Q, bool ok) {
+        const int k = Q.kw & 1023, xo = (Q.kw >> 10) & 255, run = Q.kw >> 18;
+        const int row = Q.rw & 255, xlo = (Q.rw >> 8) & 255, n = ok ? (int)(Q.rw >> 16) : 0;
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+        if (n > 0) {
+            const T* xr = buf + row * nx + xlo;
+            const double* er = ex + k * a.xw + xo;
+            // four points at a time: with e_u = ex(i+u) X(i+u),
+            //   S0 += sum_u e_u,  S1 += (xo+i) sum_u e_u + (e_1 + 2 e_2 + 3 e_3)
+            double s0 = 0.0, s1 = 0.0, ii = (double)xo;
+            int i = 0;
+            for (; i + 4 <= n; i += 4) {
+                const double e0 = er[i] * (double)xr[i], e1 = er[i + 1] * (double)xr[i + 1];
+                const double e2 = er[i + 2] * (double)xr[i + 2], e3 = er[i + 3] * (double)xr[i + 3];
+                const double sum = (e0 + e1) + (e2 + e3);
+                s0 += sum;
+                s1 += ii * sum + fma(3.0, e3, fma(2.0, e2, e1));
+                ii += 4.0;
+            }
+            if (i < n) {
+                // the last one to three points
+                const double e0 = er[i] * (double)xr[i];
+                const double e1 = i + 1 < n ? er[i + 1] * (double)xr[i + 1] : 0.0;
+                const double e2 = i + 2 < n ? er[i + 2] * (double)xr[i + 2] : 0.0;
+                const double sum = (e0 + e1) + e2;
+                s0 += sum;
+                s1 += ii * sum + fma(2.0, e2, e1);
+            }
+            const double fs = Q.eyez * a.N0, fp = Q.eyez * a.N1;
+            c0 = fs * s0;
+            c1 = fp * (delta[k] * s0 + a.hx * s1);
+            c2 = fp * Q.dy * s0;
+            c3 = fp * Q.dz * s0;
+        }
+        double* ps = psum + lane * 4;
+        ps[0] = c0;
+        ps[1] = c1;
+        ps[2] = c2;
+        ps[3] = c3;
+        wave_sync();
+        if (n > 0 && run > 0) {
+            double* ac = acc + k * 4;
+            double d0 = ac[0], d1 = ac[1], d2 = ac[2], d3 = ac[3];
+            for (int r = 0; r < run; ++r) {
+                const double* q = psum + (lane + r) * 4;
+                d0 += q[0];
+                d1 += q[1];
+                d2 += q[2];
+                d3 += q[3];
+            }
+            ac[0] = d0;
+            ac[1] = d1;
+            ac[2] = d2;
+            ac[3] = d3;
+        }
+        wave_sync();
+    };
+    auto do_plane = [&](const ProjPair* R, int z) {
+        const int o0 = poff[z - zb], np = poff[z - zb + 1] - o0;
+        if (np > 0) do_group(R[0], lane < np);
+        if (np > 64) do_group(R[1], 64 + lane < np);
+        if (np > 128) do_group(R[2], 128 + lane < np);
+        for (int g = kGroups; 64 * g < np; ++g) {
+            const int j = 64 * g + lane;
+            do_group(a.ppairs[o0 + min(j, np - 1)], j < np);
+        }
+    };
+    ProjPair ra[kGroups], rb[kGroups];
+    load_plane(va, zb);
+    load_plane(vb, zb + 1);
+    load_recs(ra, zb);
+    load_recs(rb, zb + 1);
+    for (int z = zb; z < ze; z += 2) {
+        store_plane(va);
+        load_plane(va, z + 2);
+        wave_sync();
+        do_plane(ra, z);
+        load_recs(ra, z + 2);
+        if (z + 1 >= ze) break;
+        store_plane(vb);
+        load_plane(vb, z + 3);
+        wave_sync();
+        do_plane(rb, z + 1);
+        load_recs(rb, z + 3);
     }
     const long row0 = ((long)zr * a.ntiles_y + tile) * a.kmax;
-    for (int j = t; j < K * NB * 4; j += nt) {
-        const int k = j / (NB * 4), r = j - k * NB * 4, n = r / 4, lm = r - n * 4;
-        if (n < nb) a.part[((row0 + k) * a.ncol + n0 + n) * 4 + lm] = acc[j];
+    for (int j = lane; j < K * 4; j += 64) {
+        const int k = j >> 2, lm = j & 3;
+        a.part[((row0 + k) * a.ncol + col) * 4 + lm] = acc[j];
     }
 }
 
@@ -829,12 +857,14 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     return SPARC_OK;
 }
 
-// Orbitals per projection workgroup: 4, or 2 (SPARC_GPU_PROJ_NB = 2) where
-// that is asked for or the 4-orbital tables exceed LDS.
-static int proj_nb(sparc_gpu_ctx c, size_t tsize) {
-    const NonlocalTables& T = c->nl;
-    const size_t l4 = nl_proj_lds_bytes(c->nl_ty, c->nx, T.slab_kmax, T.slab_xw, T.pair_max, 4, tsize);
-    return (c->proj_nb == 2 || l4 > 160 * 1024) ? 2 : 4;
+// Orbitals (waves) per projection workgroup: the most of 8, 4, 2 whose
+// LDS fits (SPARC_GPU_PROJ_NB caps it).
+static int proj_nw(sparc_gpu_ctx c, size_t tsize) {
+    const NonlocalTables& NT = c->nl;
+    int nw = (c->proj_nb == 2 || c->proj_nb == 4) ? c->proj_nb : 8;
+    while (nw > 1 && nl_proj_lds_bytes(c->nl_ty, c->nx, c->nz, NT.slab_kmax, NT.slab_xw, nw, tsize) > 160 * 1024)
+        nw /= 2;
+    return nw;
 }
 
 template <typename T>
@@ -852,11 +882,10 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) 
     a.ncol = ncol;
     a.slab_cand = NT.slab_cand;
     a.slab_k = NT.slab_k;
-    a.pairs = NT.pairs;
+    a.ppairs = NT.ppairs;
     a.pair_off = NT.pair_off;
     a.kmax = NT.slab_kmax;
     a.xw = NT.slab_xw;
-    a.pmax = NT.pair_max;
     a.atom_pos = c->atom_pos;
     {
         const double pi = 3.14159265358979323846;
@@ -867,15 +896,15 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) 
         a.N1 = (2.0 / rc) * N0;
         a.hx = c->hx;
     }
-    const int NB = proj_nb(c, sizeof(T));
-    const size_t shmem = nl_proj_lds_bytes(a.ty, a.nx, a.kmax, a.xw, a.pmax, NB, sizeof(T));
+    a.nw = proj_nw(c, sizeof(T));
+    const size_t shmem = nl_proj_lds_bytes(a.ty, a.nx, a.nz, a.kmax, a.xw, a.nw, sizeof(T));
     if (shmem > 160 * 1024) return set_err(c, SPARC_ERR_ARG, "projection workgroup needs more than 160 KB of LDS");
-    if ((long)NB * a.ty * a.nx > (long)kProjLoads * kProjThreads)
+    if ((long)a.ty * a.nx > 64L * kProjWaveVals)
         return set_err(c, SPARC_ERR_ARG, "slab too large for the projection kernel");
-    // z ranges per slab: enough workgroups for four per compute unit, each
-    // range at least 8 planes
-    const long base = (long)a.ntiles_y * div_up(ncol, NB);
-    a.zsplit = (int)std::max(1L, std::min((long)std::max(1, a.nz / 8), (long)div_up(1024L, base)));
+    // z ranges per slab: enough waves for 32 per compute unit, each range
+    // at least 8 planes
+    const long base = (long)a.ntiles_y * div_up(ncol, a.nw);
+    a.zsplit = (int)std::max(1L, std::min((long)std::max(1, a.nz / 8), (long)div_up(8192L, base * a.nw)));
     a.zlen = div_up(a.nz, a.zsplit);
     a.zsplit = div_up(a.nz, a.zlen);
     const size_t need = (size_t)a.zsplit * a.ntiles_y * a.kmax * ncol * 4;
@@ -893,10 +922,7 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) 
     const long nblocks = base * a.zsplit;
     if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "too many blocks");
     const int slot = prof_begin(c, PK_PROJ, stream);
-    if (NB == 4)
-        k_proj_stream<T, 4><<<dim3((unsigned)nblocks), kProjThreads, shmem, stream>>>(x, a);
-    else
-        k_proj_stream<T, 2><<<dim3((unsigned)nblocks), kProjThreads, shmem, stream>>>(x, a);
+    k_proj_stream<T><<<dim3((unsigned)nblocks), 64 * a.nw, shmem, stream>>>(x, a);
     SG_CHECK_LAUNCH(c);
     k_proj_reduce<T><<<dim3(c->n_atoms, div_up(4L * ncol, 256)), 256, 0, stream>>>(
         c->nl_part, ncol, a.zsplit, (long)a.ntiles_y * a.kmax, NT.red_off, NT.red_idx, NT.gamma4, c->dV, D_of<T>(c),
