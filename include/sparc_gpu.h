@@ -129,6 +129,22 @@ sparc_status sparc_gpu_apply_H(sparc_gpu_ctx ctx, sparc_prec prec, const void* d
 sparc_status sparc_gpu_chebyshev_filter(sparc_gpu_ctx ctx, sparc_prec prec, void* d_X, void* d_work,
                                         int ncol, long ldx, int degree, double a, double b, double a0);
 
+/* The Chebyshev filter above for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): same arguments, results and errors as
+ * sparc_gpu_chebyshev_filter, bitwise equal to it, and it calls no hipMalloc,
+ * hipFree or other allocating routine (nor records timing events).  Its
+ * projection partials live in a fixed 32 MiB device array of the library
+ * (one copy per GPU, held until the process ends, its address looked up at
+ * sparc_gpu_create); columns are processed in as many groups as that needs.
+ * Returns SPARC_ERR_ARG when the partials of one column alone exceed the
+ * array (4 x (z ranges) x (y-slabs) x (candidates per slab) doubles).  Every
+ * entry it reads is written by the same call first, so nothing needs
+ * clearing; calls that overlap on one GPU (other streams, other contexts)
+ * share the array and race. */
+sparc_status sparc_gpu_chebyshev_filter_noalloc(sparc_gpu_ctx ctx, sparc_prec prec, void* d_X, void* d_work,
+                                                int ncol, long ldx, int degree, double a, double b, double a0);
+
 /* Orthonormalise and Rayleigh-Ritz (the subspace step of CheFSI, Sec. 2.1):
  *   M = dV Y^T Y = R^T R (Cholesky, FP64), Hs = R^-T (dV Y^T H Y) R^-1,
  *   Hs = Q diag(lam) Q^T (FP64 eigensolver, ascending), X <- Y R^-1 Q.

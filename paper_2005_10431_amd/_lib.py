@@ -40,6 +40,7 @@ EXPORTED = [
     "sparc_gpu_set_veff",
     "sparc_gpu_apply_H",
     "sparc_gpu_chebyshev_filter",
+    "sparc_gpu_chebyshev_filter_noalloc",
     "sparc_gpu_rayleigh_ritz",
     "sparc_gpu_subspace_eigh",
     "sparc_gpu_density",
@@ -219,6 +220,7 @@ def load(path: str = LIB_PATH):
         "sparc_gpu_set_veff": ([vp, vp], i),
         "sparc_gpu_apply_H": ([vp, i, vp, vp, i, l], i),
         "sparc_gpu_chebyshev_filter": ([vp, i, vp, vp, i, l, i, d, d, d], i),
+        "sparc_gpu_chebyshev_filter_noalloc": ([vp, i, vp, vp, i, l, i, d, d, d], i),
         "sparc_gpu_rayleigh_ritz": ([vp, i, vp, i, l, vp], i),
         "sparc_gpu_subspace_eigh": ([vp, vp, i, vp, vp], i),
         "sparc_gpu_density": ([vp, i, vp, i, l, vp, vp], i),
@@ -350,6 +352,12 @@ class Context:
         ncol, ld = _block(X)
         self._check(self.lib.sparc_gpu_chebyshev_filter(self.h, _prec_of(X), _ptr(X), _ptr(work), ncol, ld,
                                                         int(degree), float(a), float(b), float(a0)))
+
+    def chebyshev_filter_noalloc(self, X, work, degree, a, b, a0):
+        """The filter with its scratch in the library's fixed device array."""
+        ncol, ld = _block(X)
+        self._check(self.lib.sparc_gpu_chebyshev_filter_noalloc(self.h, _prec_of(X), _ptr(X), _ptr(work), ncol,
+                                                                ld, int(degree), float(a), float(b), float(a0)))
 
     def rayleigh_ritz(self, X, eig):
         ncol, ld = _block(X)

@@ -977,7 +977,8 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     if (e != hipSuccess) {
         st = hip_err(c, e, "device query");
     } else {
-        st = build_tables(c);
+        st = scratch_init(c, dev);
+        if (st == SPARC_OK) st = build_tables(c);
     }
     if (st != SPARC_OK) {
         sparc_gpu_destroy(c);

@@ -162,6 +162,8 @@ struct sparc_gpu_ctx_s {
     size_t work_bytes = 0;
     double* D = nullptr;        // projector coefficients: 4 n_atoms x n_states
     double* nl_part = nullptr;  // projection partials per (z range, slab, candidate)
+    double* scratch = nullptr;  // this device's fixed scratch array (allocation-free filter)
+    size_t scratch_elems = 0;
     size_t nl_part_elems = 0;
     float* D32 = nullptr;
     double* gemm_part = nullptr; // split-K partials
@@ -256,9 +258,17 @@ enum Flag {
 template <typename T>
 sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, int ncol, long ldx,
                            int mode, int step);
-// D = gamma dV chi^T x, streaming x once over the sweep's slabs
+// D = gamma dV chi^T x, streaming x once over the sweep's slabs.  The
+// partial sums go to `part` (part_elems doubles, as many columns at a time
+// as fit) when given, else to context memory sized for the whole block.
 template <typename T>
-sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx);
+sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, double* part = nullptr,
+                               size_t part_elems = 0);
+// Chebyshev filter of degree m on X (Wk: scratch block); projection partials
+// as in launch_projection.
+template <typename T>
+sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m, double* part = nullptr,
+                         size_t part_elems = 0);
 // LDS bytes of a nonlocal sweep workgroup (slab height ty, nz planes, K
 // candidates, ex tables xw wide) of element size tsize
 size_t nl_sweep_lds_bytes(int ty, int nx, int nz, int K, int xw, size_t tsize);
@@ -353,6 +363,9 @@ void prof_end(sparc_gpu_ctx c, int slot, hipStream_t s = nullptr);
 // Build geometry tables (ctx.hip)
 sparc_status build_tables(sparc_gpu_ctx c);
 sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent, int ty);
+// Device address of the fixed scratch array on device `dev` (current),
+// looked up once per device and kept in the context.
+sparc_status scratch_init(sparc_gpu_ctx c, int dev);
 int choose_sweep_ty(int nx, int ny, int max_threads);
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }

@@ -17,9 +17,6 @@
 
 namespace sg {
 
-template <typename T>
-sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m);
-
 // out = (I x M x I) in along `axis`, M = U^T (fwd) or U (bwd); U is n x n
 // column-major (column k = mode k).
 __global__ void k_axis_transform(const double* __restrict__ in, double* __restrict__ out,

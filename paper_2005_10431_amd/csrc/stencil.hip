@@ -22,6 +22,8 @@
 //    steps to land;
 //  - two LDS plane buffers alternate so one barrier per plane suffices.
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdlib>
 
 #include "internal.hpp"
@@ -868,7 +870,7 @@ static int proj_nw(sparc_gpu_ctx c, size_t tsize) {
 }
 
 template <typename T>
-sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) {
+sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, double* part, size_t part_elems) {
     if (c->nl_lmax < 1 || c->nl.n_pe == 0 || ncol == 0) return SPARC_OK;
     hipStream_t stream = c->stream;
     const NonlocalTables& NT = c->nl;
@@ -879,7 +881,6 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) 
     a.nz = c->nz;
     a.ty = c->nl_ty;
     a.ntiles_y = div_up(c->ny, a.ty);
-    a.ncol = ncol;
     a.slab_cand = NT.slab_cand;
     a.slab_k = NT.slab_k;
     a.ppairs = NT.ppairs;
@@ -901,33 +902,48 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) 
     if (shmem > 160 * 1024) return set_err(c, SPARC_ERR_ARG, "projection workgroup needs more than 160 KB of LDS");
     if ((long)a.ty * a.nx > 64L * kProjWaveVals)
         return set_err(c, SPARC_ERR_ARG, "slab too large for the projection kernel");
-    // z ranges per slab: enough waves for 32 per compute unit, each range
-    // at least 8 planes
+    // z ranges per slab, from the whole block: enough waves for 32 per
+    // compute unit, each range at least 8 planes (the ranges fix the order of
+    // the sums, so a block gives the same result however its columns are
+    // launched)
     const long base = (long)a.ntiles_y * div_up(ncol, a.nw);
     a.zsplit = (int)std::max(1L, std::min((long)std::max(1, a.nz / 8), (long)div_up(8192L, base * a.nw)));
     a.zlen = div_up(a.nz, a.zsplit);
     a.zsplit = div_up(a.nz, a.zlen);
-    const size_t need = (size_t)a.zsplit * a.ntiles_y * a.kmax * ncol * 4;
-    if (c->nl_part_elems < need) {
-        if (c->nl_part) {
-            SG_HIP(c, hipStreamSynchronize(stream));
-            SG_HIP(c, hipFree(c->nl_part));
-            c->nl_part = nullptr;
-            c->nl_part_elems = 0;
+    const size_t per_col = (size_t)a.zsplit * a.ntiles_y * a.kmax * 4;
+    int chunk = ncol;
+    if (part) {
+        // caller memory: as many columns at a time as it holds
+        if (per_col > part_elems)
+            return set_err(c, SPARC_ERR_ARG, "projection partials of one column exceed the fixed scratch array");
+        chunk = (int)std::min<size_t>((size_t)ncol, part_elems / per_col);
+    } else {
+        const size_t need = per_col * ncol;
+        if (c->nl_part_elems < need) {
+            if (c->nl_part) {
+                SG_HIP(c, hipStreamSynchronize(stream));
+                SG_HIP(c, hipFree(c->nl_part));
+                c->nl_part = nullptr;
+                c->nl_part_elems = 0;
+            }
+            SG_HIP(c, hipMalloc((void**)&c->nl_part, need * sizeof(double)));
+            c->nl_part_elems = need;
         }
-        SG_HIP(c, hipMalloc((void**)&c->nl_part, need * sizeof(double)));
-        c->nl_part_elems = need;
+        part = c->nl_part;
     }
-    a.part = c->nl_part;
-    const long nblocks = base * a.zsplit;
-    if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "too many blocks");
+    a.part = part;
     const int slot = prof_begin(c, PK_PROJ, stream);
-    k_proj_stream<T><<<dim3((unsigned)nblocks), 64 * a.nw, shmem, stream>>>(x, a);
-    SG_CHECK_LAUNCH(c);
-    k_proj_reduce<T><<<dim3(c->n_atoms, div_up(4L * ncol, 256)), 256, 0, stream>>>(
-        c->nl_part, ncol, a.zsplit, (long)a.ntiles_y * a.kmax, NT.red_off, NT.red_idx, NT.gamma4, c->dV, D_of<T>(c),
-        4 * c->n_atoms);
-    SG_CHECK_LAUNCH(c);
+    for (int c0 = 0; c0 < ncol; c0 += chunk) {
+        a.ncol = std::min(chunk, ncol - c0);
+        const long nblocks = (long)a.ntiles_y * div_up(a.ncol, a.nw) * a.zsplit;
+        if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "too many blocks");
+        k_proj_stream<T><<<dim3((unsigned)nblocks), 64 * a.nw, shmem, stream>>>(x + (long)c0 * ldx, a);
+        SG_CHECK_LAUNCH(c);
+        k_proj_reduce<T><<<dim3(c->n_atoms, div_up(4L * a.ncol, 256)), 256, 0, stream>>>(
+            part, a.ncol, a.zsplit, (long)a.ntiles_y * a.kmax, NT.red_off, NT.red_idx, NT.gamma4, c->dV,
+            D_of<T>(c) + (long)c0 * 4 * c->n_atoms, 4 * c->n_atoms);
+        SG_CHECK_LAUNCH(c);
+    }
     prof_end(c, slot, stream);
     return SPARC_OK;
 }
@@ -935,8 +951,33 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx) 
 template sparc_status launch_hsweep<double>(sparc_gpu_ctx, const double*, double*, const double*, int, long, int,
                                             int);
 template sparc_status launch_hsweep<float>(sparc_gpu_ctx, const float*, float*, const float*, int, long, int, int);
-template sparc_status launch_projection<double>(sparc_gpu_ctx, const double*, int, long);
-template sparc_status launch_projection<float>(sparc_gpu_ctx, const float*, int, long);
+template sparc_status launch_projection<double>(sparc_gpu_ctx, const double*, int, long, double*, size_t);
+template sparc_status launch_projection<float>(sparc_gpu_ctx, const float*, int, long, double*, size_t);
+
+// ---- allocation-free filter -----------------------------------------------
+// The projection partials of sparc_gpu_chebyshev_filter_noalloc live in this
+// fixed array (32 MiB; each GPU the library runs on holds its own copy until
+// the process ends) instead of memory the library allocates.  Host code never
+// names the array: it uses the device address looked up once per device by
+// scratch_init.  Calls that overlap on one GPU share it and race.
+constexpr size_t kScratchDoubles = (size_t)4 << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+sparc_status scratch_init(sparc_gpu_ctx c, int dev) {
+    static std::mutex mu;
+    static std::map<int, double*> addr;   // device -> address of its copy of the array
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_err(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+        it = addr.emplace(dev, static_cast<double*>(ptr)).first;
+    }
+    c->scratch = it->second;
+    c->scratch_elems = kScratchDoubles;
+    return SPARC_OK;
+}
 
 template <typename T>
 static sparc_status apply_impl(sparc_gpu_ctx c, const T* X, T* Y, int ncol, long ldx) {
@@ -957,15 +998,15 @@ __global__ void k_copy_block(const T* __restrict__ src, T* __restrict__ dst, lon
 // Y_0 come from the gather kernel; every later sweep forms the projections
 // of its own output for the next one (not needed after the last).
 template <typename T>
-sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m) {
+sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m, double* part, size_t part_elems) {
     sparc_status st;
     // every sweep needs the projections of its operand
-    if ((st = launch_projection<T>(c, X, ncol, ldx)) != SPARC_OK) return st;
+    if ((st = launch_projection<T>(c, X, ncol, ldx, part, part_elems)) != SPARC_OK) return st;
     if ((st = launch_hsweep<T>(c, X, Wk, nullptr, ncol, ldx, 1, 1)) != SPARC_OK) return st;
     for (int k = 2; k <= m; ++k) {
         T* cur = (k % 2 == 0) ? Wk : X;   // Y_{k-1}
         T* dst = (k % 2 == 0) ? X : Wk;   // Y_{k-2}, overwritten with Y_k
-        if ((st = launch_projection<T>(c, cur, ncol, ldx)) != SPARC_OK) return st;
+        if ((st = launch_projection<T>(c, cur, ncol, ldx, part, part_elems)) != SPARC_OK) return st;
         if ((st = launch_hsweep<T>(c, cur, dst, dst, ncol, ldx, 2, k)) != SPARC_OK) return st;
     }
     if (m % 2 == 1) {
@@ -978,8 +1019,8 @@ sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m
     return SPARC_OK;
 }
 
-template sparc_status filter_impl<double>(sparc_gpu_ctx, double*, double*, int, long, int);
-template sparc_status filter_impl<float>(sparc_gpu_ctx, float*, float*, int, long, int);
+template sparc_status filter_impl<double>(sparc_gpu_ctx, double*, double*, int, long, int, double*, size_t);
+template sparc_status filter_impl<float>(sparc_gpu_ctx, float*, float*, int, long, int, double*, size_t);
 
 __global__ void k_set3(double* dst, double a, double b, double c) {
     dst[0] = a;
@@ -1118,6 +1159,33 @@ sparc_status sparc_gpu_chebyshev_filter(sparc_gpu_ctx c, sparc_prec prec, void* 
     SG_CHECK_LAUNCH(c);
     if (prec == SPARC_FP64) return filter_impl<double>(c, (double*)d_X, (double*)d_work, ncol, ldx, degree);
     return filter_impl<float>(c, (float*)d_X, (float*)d_work, ncol, ldx, degree);
+}
+
+sparc_status sparc_gpu_chebyshev_filter_noalloc(sparc_gpu_ctx c, sparc_prec prec, void* d_X, void* d_work, int ncol,
+                                                long ldx, int degree, double a, double b, double a0) {
+    if (!c) return SPARC_ERR_ARG;
+    c->err.clear();
+    sparc_status st = check_block(c, prec, d_X, ncol, ldx, "chebyshev_filter_noalloc");
+    if (st != SPARC_OK) return st;
+    if (!d_work) return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_noalloc: null work block");
+    if (degree < 1 || degree > 10000) return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_noalloc: degree out of range");
+    if (!(a0 < a && a < b) || !std::isfinite(a0) || !std::isfinite(b))
+        return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_noalloc: need a0 < a < b");
+    size_t es = prec == SPARC_FP64 ? 8 : 4;
+    size_t bytes = ((size_t)(ncol - 1) * ldx + c->nd) * es;
+    if (overlaps(d_X, d_work, bytes)) return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_noalloc: X and work overlap");
+    if (!c->scratch) return set_err(c, SPARC_ERR_ARG, "chebyshev_filter_noalloc: no scratch array on this device");
+    k_set3<<<1, 1, 0, c->stream>>>(c->scal + S_A, a, b, a0);
+    SG_CHECK_LAUNCH(c);
+    // no timing events either (creating them could allocate)
+    const bool prof = c->prof;
+    c->prof = false;
+    const sparc_status r =
+        prec == SPARC_FP64
+            ? filter_impl<double>(c, (double*)d_X, (double*)d_work, ncol, ldx, degree, c->scratch, c->scratch_elems)
+            : filter_impl<float>(c, (float*)d_X, (float*)d_work, ncol, ldx, degree, c->scratch, c->scratch_elems);
+    c->prof = prof;
+    return r;
 }
 
 }  // extern "C"
