@@ -431,8 +431,22 @@ static double symbol(const double* w, int n_o, double th) {
 // segment); each (plane, candidate, row) segment is a "pair".  Per (slab,
 // plane) the pairs are listed by (candidate, row), and point p stores the
 // byte indices of its pairs in its plane's list in pe8[p] (0xFF pads).
-sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent, int ty) {
-    sg::NonlocalTables& T = c->nl;
+void free_slab_tables(NonlocalTables& T) {
+    for (void* p : {(void*)T.pe8, (void*)T.slab_cand, (void*)T.slab_k, (void*)T.pairs, (void*)T.pair_off,
+                    (void*)T.red_off, (void*)T.red_idx, (void*)T.ppairs})
+        if (p) hipFree(p);
+    T.ppairs = nullptr;
+    T.pe8 = nullptr;
+    T.slab_cand = nullptr;
+    T.slab_k = nullptr;
+    T.pairs = nullptr;
+    T.pair_off = nullptr;
+    T.red_off = nullptr;
+    T.red_idx = nullptr;
+    T.slab_ty = 0;
+}
+
+sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent, int ty, NonlocalTables& T) {
     const int nx = c->nx, ny = c->ny, nz = c->nz;
     const int nslab = (ny + ty - 1) / ty;
     // slab-local candidate index of every image entry
@@ -593,7 +607,7 @@ sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent
                                                                                   T.ppairs);
         SG_CHECK_LAUNCH(c);
     }
-    c->nl_ty = ty;
+    T.slab_ty = ty;
     if (c->debug)
         fprintf(stderr, "[sparc_gpu] pair tables: ty %d, %zu pairs, at most %d per plane, %d candidates, ex width %d\n",
                 ty, pairs.size(), T.pair_max, T.slab_kmax, T.slab_xw);
@@ -769,7 +783,7 @@ sparc_status build_tables(sparc_gpu_ctx c) {
             // first whose tables fit (at most 255 segments per slab plane, the
             // FP64 sweep and the two-wave FP64 projection within 160 KB of LDS)
             for (int ty = choose_sweep_ty(c->nx, c->ny, nl_sweep_max_threads());; --ty) {
-                st = build_pair_tables(c, ent, ty);
+                st = build_pair_tables(c, ent, ty, c->nl);
                 const NonlocalTables& N = c->nl;
                 const size_t lds = st == SPARC_OK
                                        ? std::max(nl_sweep_lds_bytes(ty, c->nx, c->nz, N.slab_kmax, N.slab_xw, 8),
@@ -777,18 +791,24 @@ sparc_status build_tables(sparc_gpu_ctx c) {
                                        : 0;
                 if (st == SPARC_OK && lds <= 160 * 1024) break;
                 if (ty <= 1) return st != SPARC_OK ? st : set_err(c, SPARC_ERR_ARG, "projector tables exceed LDS");
-                for (void* p : {(void*)T.pe8, (void*)T.slab_cand, (void*)T.slab_k, (void*)T.pairs, (void*)T.pair_off,
-                                (void*)T.red_off, (void*)T.red_idx, (void*)T.ppairs})
-                    if (p) hipFree(p);
-                T.ppairs = nullptr;
-                T.pe8 = nullptr;
-                T.slab_cand = nullptr;
-                T.slab_k = nullptr;
-                T.pairs = nullptr;
-                T.pair_off = nullptr;
-                T.red_off = nullptr;
-                T.red_idx = nullptr;
+                free_slab_tables(c->nl);
                 c->err.clear();
+            }
+            c->nl_ty = c->nl.slab_ty;
+            // The FP32 sweep takes slabs of at most 512 threads, like the
+            // local FP32 sweep (measured faster than the FP64 slabs: 13.8
+            // against 15.8 ms at 120^3, 0.80 against 0.92 ms at 72^3); the
+            // projection pass keeps the FP64 tables in both precisions.  If no
+            // such slab fits, the FP32 sweep uses the FP64 tables.
+            for (int ty = choose_sweep_ty(c->nx, c->ny, 512); ty >= 1 && ty != c->nl_ty; --ty) {
+                st = build_pair_tables(c, ent, ty, c->nl32);
+                const NonlocalTables& N = c->nl32;
+                if (st == SPARC_OK &&
+                    nl_sweep_lds_bytes(ty, c->nx, c->nz, N.slab_kmax, N.slab_xw, 4) <= 160 * 1024)
+                    break;
+                free_slab_tables(c->nl32);
+                c->err.clear();
+                st = SPARC_OK;
             }
         }
         // Morton order of the atoms (10 bits per axis of the fractional position)
@@ -997,6 +1017,8 @@ sparc_status sparc_gpu_destroy(sparc_gpu_ctx c) {
                     c->D32, c->gemm_part, c->small, c->red, c->scal, c->flags, c->field, c->nl.sup_off,
                     c->nl.sup_chi, c->nl.gamma4, c->nl.atom_order, c->atom_pos, c->nl.pe8, c->nl.slab_cand,
                     c->nl.slab_k, c->nl.pairs, c->nl.ppairs, c->nl.pair_off, c->nl.red_off, c->nl.red_idx, c->nl_part,
+                    c->nl32.pe8, c->nl32.slab_cand, c->nl32.slab_k, c->nl32.pairs, c->nl32.ppairs, c->nl32.pair_off,
+                    c->nl32.red_off, c->nl32.red_idx,
                     c->nl.ip_off, c->nl.ip_idx, c->nl.ip_box, c->nl.box_lo};
     for (void* p : ptrs)
         if (p) hipFree(p);

@@ -83,6 +83,7 @@ struct NonlocalTables {
     // entries slab * slab_kmax + k of red_idx[red_off[a] .. red_off[a + 1])
     int* red_off = nullptr;
     int* red_idx = nullptr;
+    int slab_ty = 0;                        // rows per slab of these tables (0: none built)
     double nl_hi = 0.0, nl_lo = 0.0;  // signed spectral bound contributions
     int max_per_atom = 0;
     // image points of each atom's ball for the projection, in grid order:
@@ -149,6 +150,9 @@ struct sparc_gpu_ctx_s {
     double* b = nullptr;        // pseudocharge, N_d
     double e_self = 0, e_c = 0;
     sg::NonlocalTables nl;
+    // per-slab tables of the FP32 sweep when its slab height differs (only
+    // the per-slab fields are filled; slab_ty 0: it uses nl's)
+    sg::NonlocalTables nl32;
 
     // Poisson: real orthonormal Fourier bases per axis and the operator's
     // eigenvalues on the product basis
@@ -362,7 +366,8 @@ void prof_end(sparc_gpu_ctx c, int slot, hipStream_t s = nullptr);
 
 // Build geometry tables (ctx.hip)
 sparc_status build_tables(sparc_gpu_ctx c);
-sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent, int ty);
+sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent, int ty, NonlocalTables& T);
+void free_slab_tables(NonlocalTables& T);
 // Device address of the fixed scratch array on device `dev` (current),
 // looked up once per device and kept in the context.
 sparc_status scratch_init(sparc_gpu_ctx c, int dev);

@@ -786,7 +786,9 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     a.ny = c->ny;
     a.nz = c->nz;
     const bool nl = !c->sweep_local_only && c->nl_lmax >= 1 && c->nl.n_pe > 0;
-    a.ty = nl ? c->nl_ty : local_ty(c, sizeof(T));
+    // the FP32 sweep's own slab tables where it has them
+    const NonlocalTables& NT = (sizeof(T) == 4 && c->nl32.slab_ty > 0) ? c->nl32 : c->nl;
+    a.ty = nl ? NT.slab_ty : local_ty(c, sizeof(T));
     a.ntiles_y = div_up(c->ny, a.ty);
     {
         const StencilCoef<T>& cf = coef<T>(c);
@@ -796,14 +798,14 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
         a.rz = (T)((c->hx * c->hx) / (c->hz * c->hz));
     }
     a.veff = veff_of<T>(c);
-    a.pe8 = c->nl.pe8;
-    a.slab_cand = c->nl.slab_cand;
-    a.slab_k = c->nl.slab_k;
-    a.pairs = c->nl.pairs;
-    a.pair_off = c->nl.pair_off;
-    a.kmax = c->nl.slab_kmax;
-    a.xw = c->nl.slab_xw;
-    a.pmax = c->nl.pair_max;
+    a.pe8 = NT.pe8;
+    a.slab_cand = NT.slab_cand;
+    a.slab_k = NT.slab_k;
+    a.pairs = NT.pairs;
+    a.pair_off = NT.pair_off;
+    a.kmax = NT.slab_kmax;
+    a.xw = NT.slab_xw;
+    a.pmax = NT.pair_max;
     a.atom_pos = c->atom_pos;
     {
         const double pi = 3.14159265358979323846;
