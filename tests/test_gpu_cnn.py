@@ -150,3 +150,36 @@ def test_training_reduces_loss_on_snapshots():
     log(f"loss curve: first {curve[0]:.3e} last {curve[-1]:.3e}")
     assert np.all(np.isfinite(curve))
     assert curve[-1] < 0.5 * curve[0]
+
+
+def test_warm_start_gains_on_held_out_snapshots():
+    """What the trained network gains over the atomic-density start
+    (Sec. 2.1), on the config-1 cell at 24^3 (h = 1/3 Bohr): trained for 40
+    epochs on the converged densities of 24 displaced-atom snapshots, it
+    starts 8 held-out snapshots (seeds 100..107) closer to their converged
+    densities and reaches |F - F_conv| <= 1e-6 Ha/atom in fewer SCF
+    iterations, with 4 first-iteration passes, at degree 12 and at degree
+    40.  Everything is seeded and the kernels are deterministic, so the
+    counts are fixed: at degree 12 the mean measured 9.62 against 10.88
+    iterations, at degree 40 7.50 against 12.00.  On the 72^3 grid with
+    degree 12 the subspace, not the density, sets the count and the two
+    starts need the same number of iterations."""
+    require_gpu()
+    from paper_2005_10431_amd import warmstart
+    data = warmstart.make_dataset(range(24), n=24, log=log)
+    w, curve, _ = warmstart.train(data, epochs=40, lr=3e-3, log=lambda *a: None)
+    log(f"training loss {curve[0]:.3e} -> {curve[-1]:.3e}")
+    test = warmstart.make_dataset(range(100, 108), n=24, log=log)
+    for degree, min_gain in ((12, 0.5), (40, 2.0)):
+        rows = warmstart.evaluate(w, test, n_first=4, degree=degree, log=log)
+        k_sad = np.array([r["iters_sad"] for r in rows], float)
+        k_cnn = np.array([r["iters_cnn"] for r in rows], float)
+        l1_sad = np.array([r["l1_sad"] for r in rows])
+        l1_cnn = np.array([r["l1_cnn"] for r in rows])
+        log(f"degree {degree}: iterations atomic guess {k_sad.mean():.2f}, network {k_cnn.mean():.2f}; "
+            f"L1 {l1_sad.mean():.4f} -> {l1_cnn.mean():.4f}")
+        assert all(r["used_cnn"] for r in rows)
+        assert np.all(l1_cnn < 0.25 * l1_sad)
+        assert np.all(k_cnn <= k_sad)
+        assert k_sad.mean() - k_cnn.mean() >= min_gain
+        assert max(r["f_diff"] for r in rows) <= 1e-6
