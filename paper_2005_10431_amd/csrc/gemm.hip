@@ -65,19 +65,45 @@ __device__ __forceinline__ void mfma_stage(const T* sa, int lda_s, const T* sb, 
 
 // Partial[split][n][m] = sum_{k in chunk} A[k, m] B[k, n] for one tile of
 // (32 MT) x (32 NT) outputs.  A, B are K x M / K x N column-major.
+//
+// One workgroup per (active tile, split); only the upper tiles tn >= tm are
+// active when `symmetric`.  Hardware dispatches block b to XCD b % 8.  When
+// nsplit is a multiple of 8, every tile of one split runs on one XCD, and
+// its tiles are dispatched together, so that the panels of that K-chunk,
+// which a tile row or column shares, come from HBM about once and then from
+// the XCD's L2 (wholly so while one split's tiles fit the XCD's workgroup
+// slots: up to 64 tiles of 128 x 128).
 template <typename T, int MT, int NT>
 __global__ __launch_bounds__(256) void k_gemm_tn_split(int M, int N, long K, long kchunk, const T* __restrict__ A,
                                                        long lda, const T* __restrict__ B, long ldb,
-                                                       double* __restrict__ part, int tiles_m, bool symmetric) {
+                                                       double* __restrict__ part, int tiles_m, bool symmetric,
+                                                       int active, int nsplit) {
     using acc_t = typename Mfma<T>::acc_t;
     constexpr int TM = 32 * MT, TN = 32 * NT;
     constexpr int LA = TM + PAD, LB = TN + PAD;
     __shared__ T sA[2][BK * LA];
     __shared__ T sB[2][BK * LB];
-    const int tile = blockIdx.x;
-    const int tm = tile % tiles_m, tn = tile / tiles_m;
-    if (symmetric && tn < tm) return;
-    const long k0 = (long)blockIdx.y * kchunk;
+    const int bid = blockIdx.x;
+    int split, tidx;
+    if (nsplit % 8 == 0) {
+        const int slot = bid / 8;
+        split = bid % 8 + 8 * (slot / active);
+        tidx = slot % active;
+    } else {
+        split = bid / active;
+        tidx = bid % active;
+    }
+    int tm, tn;
+    if (symmetric) {
+        // tidx-th upper tile, column by column: (0,0), (0,1), (1,1), (0,2), ...
+        tn = 0;
+        while ((tn + 1) * (tn + 2) / 2 <= tidx) ++tn;
+        tm = tidx - tn * (tn + 1) / 2;
+    } else {
+        tm = tidx % tiles_m;
+        tn = tidx / tiles_m;
+    }
+    const long k0 = (long)split * kchunk;
     const long k1 = min(K, k0 + kchunk);
     const int m0 = tm * TM, n0 = tn * TN;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -133,7 +159,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn_split(int M, int N, long K, lon
         if (s + 1 < nst) store(buf ^ 1);
         __syncthreads();
     }
-    double* P = part + (long)blockIdx.y * M * N;
+    double* P = part + (long)split * M * N;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -170,17 +196,20 @@ static sparc_status gemm_tn_launch(sparc_gpu_ctx c, int M, int N, long K, const 
     const int tiles_m = div_up(M, TT), tiles_n = div_up(N, TT);
     const int tiles = tiles_m * tiles_n;
     const int active = symmetric ? tiles_m * (tiles_m + 1) / 2 : tiles;
-    // about two workgroups per CU, chunks of >= 1024 rows
-    long want = std::max<long>(1, 512 / active);
-    long kchunk = std::max<long>(1024, (K + want - 1) / want);
+    // about two workgroups per CU, in a multiple of 8 splits (one XCD per
+    // split at a time), chunks of >= 1024 rows
+    const long want = std::max<long>(1, 512 / active);
+    int nsplit = 8 * (int)std::max<long>(1, (want + 4) / 8);
+    if ((long)nsplit * 1024 > K) nsplit = (int)std::max<long>(1, K / 1024);
+    long kchunk = (K + nsplit - 1) / nsplit;
     kchunk = (kchunk + BK - 1) / BK * BK;
-    int nsplit = (int)((K + kchunk - 1) / kchunk);
     sparc_status st = ensure_gemm_part(c, (size_t)nsplit * M * N);
     if (st != SPARC_OK) return st;
-    dim3 grid(tiles, nsplit);
+    const long nblocks = (long)active * nsplit;
+    if (nblocks > 0x7fffffffL) return set_err(c, SPARC_ERR_ARG, "gemm_tn: too many blocks");
     const int slot = prof_begin(c, PK_GEMM_TN);
-    k_gemm_tn_split<T, MT, MT><<<grid, 256, 0, c->stream>>>(M, N, K, kchunk, A, lda, B, ldb, c->gemm_part, tiles_m,
-                                                          symmetric);
+    k_gemm_tn_split<T, MT, MT><<<dim3((unsigned)nblocks), 256, 0, c->stream>>>(
+        M, N, K, kchunk, A, lda, B, ldb, c->gemm_part, tiles_m, symmetric, active, nsplit);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
     k_gemm_reduce<<<div_up((long)M * N, 256), 256, 0, c->stream>>>(M, N, nsplit, c->gemm_part, alpha, C, ldc,
