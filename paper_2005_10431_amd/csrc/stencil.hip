@@ -303,6 +303,16 @@ __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> 
         // pair records of plane 0
         for (int j = t; j < a.pmax; j += nt) pair_record<T>(a, sh, load_pair(a.pairs, sh.poff, 0, j), j, 0);
     }
+    // pair records in flight: rec[p] holds the record of the next plane of
+    // parity p (plane 1 to start with; plane 2 is loaded by the first step)
+    PairRec rec[2];
+    rec[0].k = rec[0].n = 0;
+    rec[0].eyez = rec[0].dy = rec[0].dz = 0.0;
+    if (NL && t < a.pmax) {
+        rec[1] = load_pair(a.pairs, sh.poff, 1 < nz ? 1 : 0, t);
+    } else {
+        rec[1] = rec[0];
+    }
 
     const T* __restrict__ xc = a.x + (long)col * a.ldx;
     T* __restrict__ oc = a.out + (long)col * a.ldx;
@@ -413,8 +423,8 @@ __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> 
                 for (int i = 0; i < HM; ++i) hq[QS][i] = (i < hn) ? xc[goff[i] + zo] : (T)0;
                 q[(U + NO + PR + RING) % RING] = xc[pxy + (long)wz(z + NO + PR) * plane];
             }
-            PairRec rec;
-            if (NL && z + 1 < nz && t < a.pmax) rec = load_pair(a.pairs, sh.poff, z + 1, t);
+            // the record of plane z + 2, two steps ahead of its use
+            if (NL && t < a.pmax) rec[P] = load_pair(a.pairs, sh.poff, z + 2 < nz ? z + 2 : 0, t);
             // 3. plane z
             const T* rp = (P ? sh.buf1 : sh.buf0) + lrow;
             const int C = U % RING;
@@ -442,7 +452,7 @@ __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> 
                 if (NL) w8[QS] = a.pe8[pxy + zo];
             }
             // 5. pair records and LDS plane of z + 1
-            if (NL && z + 1 < nz && t < a.pmax) pair_record<T>(a, sh, rec, t, PN);
+            if (NL && z + 1 < nz && t < a.pmax) pair_record<T>(a, sh, rec[PN], t, PN);
             T* nbuf = P ? sh.buf0 : sh.buf1;
             const int CN = (U + 1) % RING;
             if (active) {
