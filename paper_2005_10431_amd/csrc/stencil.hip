@@ -527,6 +527,7 @@ struct ProjArgs {
     int kmax, xw;
     const double* atom_pos;
     double inv_rc2, N0, N1, hx;
+    double cq;                 // exp(-2 hx^2 / rc^2)
     double* part;              // [((zr * ntiles_y + slab) * kmax + k) * ncol + col] * 4
 };
 
@@ -621,13 +622,26 @@ __global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, Pr
         if (n > 0) {
             const T* xr = buf + row * nx + xlo;
             const double* er = ex + k * a.xw + xo;
+            // The Gaussian along the segment by its recurrence: with
+            // ex(i) = exp(-(delta + i hx)^2 / rc^2) and g(i) = ex(i+1)/ex(i),
+            // g(i+1) = g(i) exp(-2 hx^2 / rc^2); two multiplies per point in
+            // place of an LDS read (ex >= exp(-rcut^2/rc^2) > 0 on a support).
+            double ev = er[0];
+            double gq = n > 1 ? er[1] / er[0] : 0.0;
+            auto next = [&](double x) {
+                const double v = ev * x;
+                ev *= gq;
+                gq *= a.cq;
+                return v;
+            };
             // four points at a time: with e_u = ex(i+u) X(i+u),
             //   S0 += sum_u e_u,  S1 += (xo+i) sum_u e_u + (e_1 + 2 e_2 + 3 e_3)
             double s0 = 0.0, s1 = 0.0, ii = (double)xo;
             int i = 0;
             for (; i + 4 <= n; i += 4) {
-                const double e0 = er[i] * (double)xr[i], e1 = er[i + 1] * (double)xr[i + 1];
-                const double e2 = er[i + 2] * (double)xr[i + 2], e3 = er[i + 3] * (double)xr[i + 3];
+                const double x0 = (double)xr[i], x1 = (double)xr[i + 1];
+                const double x2 = (double)xr[i + 2], x3 = (double)xr[i + 3];
+                const double e0 = next(x0), e1 = next(x1), e2 = next(x2), e3 = next(x3);
                 const double sum = (e0 + e1) + (e2 + e3);
                 s0 += sum;
                 s1 += ii * sum + fma(3.0, e3, fma(2.0, e2, e1));
@@ -635,9 +649,9 @@ __global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, Pr
             }
             if (i < n) {
                 // the last one to three points
-                const double e0 = er[i] * (double)xr[i];
-                const double e1 = i + 1 < n ? er[i + 1] * (double)xr[i + 1] : 0.0;
-                const double e2 = i + 2 < n ? er[i + 2] * (double)xr[i + 2] : 0.0;
+                const double e0 = next((double)xr[i]);
+                const double e1 = i + 1 < n ? next((double)xr[i + 1]) : 0.0;
+                const double e2 = i + 2 < n ? next((double)xr[i + 2]) : 0.0;
                 const double sum = (e0 + e1) + e2;
                 s0 += sum;
                 s1 += ii * sum + fma(2.0, e2, e1);
@@ -908,6 +922,7 @@ sparc_status launch_projection(sparc_gpu_ctx c, const T* x, int ncol, long ldx, 
         a.N0 = N0;
         a.N1 = (2.0 / rc) * N0;
         a.hx = c->hx;
+        a.cq = std::exp(-2.0 * c->hx * c->hx / (rc * rc));
     }
     a.nw = proj_nw(c, sizeof(T));
     const size_t shmem = nl_proj_lds_bytes(a.ty, a.nx, a.nz, a.kmax, a.xw, a.nw, sizeof(T));
