@@ -551,6 +551,7 @@ sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent
     for (size_t q = 0; q < (size_t)nslab * nz; ++q) pair_off[q + 1] += pair_off[q];
     // per point: its pairs (at most 7)
     std::vector<uint64_t> pe8(c->nd, ~0ull);
+    int max_entries = 0;
     for (long p = 0; p < c->nd; ++p) {
         uint64_t word = ~0ull;
         int cnt = 0;
@@ -561,7 +562,9 @@ sparc_status build_pair_tables(sparc_gpu_ctx c, const std::vector<uint32_t>& ent
             ++cnt;
         }
         pe8[p] = word;
+        max_entries = std::max(max_entries, cnt);
     }
+    T.max_entries = max_entries;
     int kmax = 0, xw = 0;
     for (int sl = 0; sl < nslab; ++sl) {
         kmax = std::max(kmax, (int)cands[sl].size());
@@ -984,6 +987,7 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     if (const char* e = std::getenv("SPARC_GPU_CHOL_MULTI_MIN")) c->chol_multi_min = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_STEIN_LDS_MIN_TPW")) c->stein_lds_min_tpw = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_PROJ_NB")) c->proj_nb = std::atoi(e);
+    if (const char* e = std::getenv("SPARC_GPU_NL_SLOTS")) c->nl_slots = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_GEMM_TILE")) c->gemm_tile = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_GEMM_NN_COLS")) c->gemm_nn_cols = std::atoi(e);
 

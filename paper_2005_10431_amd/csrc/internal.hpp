@@ -84,6 +84,7 @@ struct NonlocalTables {
     int* red_off = nullptr;
     int* red_idx = nullptr;
     int slab_ty = 0;                        // rows per slab of these tables (0: none built)
+    int max_entries = 0;                    // most pairs meeting at one point (at most 7)
     double nl_hi = 0.0, nl_lo = 0.0;  // signed spectral bound contributions
     int max_per_atom = 0;
     // image points of each atom's ball for the projection, in grid order:
@@ -190,6 +191,7 @@ struct sparc_gpu_ctx_s {
     // captured Jacobi sweep (see dense.hip)
     hipStream_t cap_stream = nullptr;
     int proj_nb = 8;            // SPARC_GPU_PROJ_NB: at most this many orbitals per projection workgroup (2, 4, 8)
+    int nl_slots = 0;           // SPARC_GPU_NL_SLOTS=7: FP64 sweep takes 7 nonlocal slots per point (0: by the tables)
     int gemm_tile = 0;          // SPARC_GPU_GEMM_TILE: Gram/projected-H tile edge (128, 160; 0: by size)
     int gemm_nn_cols = 160;     // SPARC_GPU_GEMM_NN_COLS: rotation tile width (160, 288)
     hipGraphExec_t jac_exec = nullptr;

@@ -232,7 +232,7 @@ __device__ inline void pair_record(const SweepArgs<T>& a, const SweepShared<T>& 
 // a loop inside the unrolled step would keep every value live across it.
 // Threads without a point of the slab (ragged slab, padding to 64) load
 // valid clamped addresses and compute on them, but never store.
-template <typename T, bool NL, int MODE, int HM>
+template <typename T, bool NL, int MODE, int HM, int NSL = 4>
 __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> a) {
     constexpr int NO = kMaxHalfOrder;
     constexpr int RING = kRing, PR = kRingAhead, PQ = kQueue;
@@ -406,14 +406,21 @@ __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> 
                     const T e = *reinterpret_cast<const T*>(smem_raw + (R8.exb + lxb));
                     nl += e * (R8.A + R8.B * lxd);
                 };
-                // four slots for every point; the other three only where a
-                // point of the wave lies in more than four supports (about
-                // one point in a hundred)
+                if constexpr (NSL == 4) {
+                    // four slots for every point; the other three only where
+                    // a point of the wave lies in more than four supports
+                    // (about one point in a hundred)
 #pragma unroll
-                for (int sl = 0; sl < 4; ++sl) slot(sl);
-                if (((uint32_t)(w >> 32) | 0xFF000000u) != 0xFFFFFFFFu) {
+                    for (int sl = 0; sl < 4; ++sl) slot(sl);
+                    if (((uint32_t)(w >> 32) | 0xFF000000u) != 0xFFFFFFFFu) {
 #pragma unroll
-                    for (int sl = 4; sl < kSlots; ++sl) slot(sl);
+                        for (int sl = 4; sl < kSlots; ++sl) slot(sl);
+                    }
+                } else {
+                    // NSL slots for every point, no branch (the tables hold
+                    // at most NSL pairs per point)
+#pragma unroll
+                    for (int sl = 0; sl < NSL; ++sl) slot(sl);
                 }
             }
             // 2. loads of later planes
@@ -857,27 +864,44 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     if (nblocks == 0) return SPARC_OK;
     const int slot = prof_begin(c, mode == 2 ? PK_SWEEP : (mode == 1 ? PK_SWEEP1 : PK_APPLY), stream);
     const dim3 g((unsigned)nblocks), b(threads);
-#define SG_LAUNCH_SWEEP(NLV, MV, HMV) k_hsweep<T, NLV, MV, HMV><<<g, b, shmem, stream>>>(a)
-#define SG_SWEEP_HM(NLV, MV)                          \
-    do {                                              \
-        switch (hm) {                                 \
-            case 1: SG_LAUNCH_SWEEP(NLV, MV, 1); break; \
-            case 2: SG_LAUNCH_SWEEP(NLV, MV, 2); break; \
-            case 3: SG_LAUNCH_SWEEP(NLV, MV, 3); break; \
-            case 4: SG_LAUNCH_SWEEP(NLV, MV, 4); break; \
-            case 5: SG_LAUNCH_SWEEP(NLV, MV, 5); break; \
-            default: SG_LAUNCH_SWEEP(NLV, MV, 6); break; \
-        }                                             \
+    // Nonlocal slots per point: FP64 takes them all without a branch (6 when
+    // no point of the tables lies in more than 6 supports, else 7); FP32,
+    // whose 4-row slabs need 128 VGPRs or fewer for two workgroups per CU,
+    // takes 4 and the rest in a branch.  Measured at 120^3 FP64: 18.3 (6),
+    // 18.7 (7) against 18.8 ms (4 + branch); FP32: 12.7 (4 + branch)
+    // against 19.6 ms (7).
+    const int nsl = sizeof(T) == 8 ? (NT.max_entries <= 6 && c->nl_slots != 7 ? 6 : 7) : 4;
+#define SG_LAUNCH_SWEEP(NLV, MV, HMV, NSV) k_hsweep<T, NLV, MV, HMV, NSV><<<g, b, shmem, stream>>>(a)
+#define SG_SWEEP_HM(NLV, MV, NSV)                          \
+    do {                                                   \
+        switch (hm) {                                      \
+            case 1: SG_LAUNCH_SWEEP(NLV, MV, 1, NSV); break; \
+            case 2: SG_LAUNCH_SWEEP(NLV, MV, 2, NSV); break; \
+            case 3: SG_LAUNCH_SWEEP(NLV, MV, 3, NSV); break; \
+            case 4: SG_LAUNCH_SWEEP(NLV, MV, 4, NSV); break; \
+            case 5: SG_LAUNCH_SWEEP(NLV, MV, 5, NSV); break; \
+            default: SG_LAUNCH_SWEEP(NLV, MV, 6, NSV); break; \
+        }                                                  \
+    } while (0)
+#define SG_SWEEP_NL(MV)                                          \
+    do {                                                         \
+        if constexpr (sizeof(T) == 8) {                          \
+            if (nsl == 6) SG_SWEEP_HM(true, MV, 6);              \
+            else SG_SWEEP_HM(true, MV, 7);                       \
+        } else {                                                 \
+            SG_SWEEP_HM(true, MV, 4);                            \
+        }                                                        \
     } while (0)
     if (nl) {
-        if (mode == 0) SG_SWEEP_HM(true, 0);
-        else if (mode == 1) SG_SWEEP_HM(true, 1);
-        else SG_SWEEP_HM(true, 2);
+        if (mode == 0) SG_SWEEP_NL(0);
+        else if (mode == 1) SG_SWEEP_NL(1);
+        else SG_SWEEP_NL(2);
     } else {
-        if (mode == 0) SG_SWEEP_HM(false, 0);
-        else if (mode == 1) SG_SWEEP_HM(false, 1);
-        else SG_SWEEP_HM(false, 2);
+        if (mode == 0) SG_SWEEP_HM(false, 0, 4);
+        else if (mode == 1) SG_SWEEP_HM(false, 1, 4);
+        else SG_SWEEP_HM(false, 2, 4);
     }
+#undef SG_SWEEP_NL
 #undef SG_SWEEP_HM
 #undef SG_LAUNCH_SWEEP
     SG_CHECK_LAUNCH(c);

@@ -496,11 +496,11 @@ def test_argument_errors():
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_filter_is_bitwise_reproducible(prec):
-    """Every reduction of the filter has a fixed order (the projections the
-    sweep forms of its own output: segment sums combined over a fixed lane
-    pattern, candidate sums in list order, slab partials in a fixed order),
-    so two filters of the same block agree bit for bit, on one context and
-    across contexts."""
+    """Every reduction of the filter has a fixed order (the projection pass:
+    pair sums in segment order, each candidate's pairs in row order, planes
+    in order, per-atom partials in (slab, candidate, z range) order), so two
+    filters of the same block agree bit for bit, on one context and across
+    contexts."""
     torch = require_gpu()
     s = ragged_system(n_states=70)
     v = _veff(s, 21)
@@ -519,6 +519,37 @@ def test_filter_is_bitwise_reproducible(prec):
         float(np.max(np.abs(outs[0] - outs[2]))))
     assert np.array_equal(outs[0], outs[1])
     assert np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("system", ["ragged", "images"])
+def test_fp64_nonlocal_slot_counts_agree_bitwise(system, monkeypatch):
+    """The FP64 sweep adds 6 nonlocal slots per point when no point of its
+    tables lies in more than 6 supports, else 7; forced to 7
+    (SPARC_GPU_NL_SLOTS=7, read at context creation), the extra slot names
+    the empty pair, adds an exact zero, and H X and the filter are bitwise
+    the same."""
+    torch = require_gpu()
+    s = ragged_system(n_states=6) if system == "ragged" else small_images_system(n_states=6)
+    v = _veff(s, 23)
+    X = W.initial_orbitals(s.nd, s.n_states, 5)
+    outs = []
+    for force in (None, "7"):
+        if force:
+            monkeypatch.setenv("SPARC_GPU_NL_SLOTS", force)
+        else:
+            monkeypatch.delenv("SPARC_GPU_NL_SLOTS", raising=False)
+        ctx = _ctx(s)
+        ctx.set_veff(to_dev(torch, v))
+        lo, hi = ctx.spectrum_bounds()
+        Xd = to_dev(torch, X)
+        Yd = torch.empty_like(Xd)
+        ctx.apply_H(Xd, Yd)
+        Wd = torch.empty_like(Xd)
+        ctx.chebyshev_filter(Xd, Wd, 8, 0.5 * (lo + hi), hi, lo)
+        outs.append((to_np(Yd), to_np(Xd)))
+    monkeypatch.delenv("SPARC_GPU_NL_SLOTS", raising=False)
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
 
 
 def test_apply_H_wide_grid_many_halo_values():
