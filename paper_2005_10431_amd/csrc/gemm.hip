@@ -308,10 +308,9 @@ __global__ __launch_bounds__(256) void k_gemm_nn(long K, int N, int M, const T* 
             }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int MT = 2>
 static sparc_status gemm_nn_launch(sparc_gpu_ctx c, long K, int N, int M, const T* A, long lda, const double* Bm,
                                    int ldb, T* Out, long ldo) {
-    constexpr int MT = 2;
     dim3 grid(div_up(K, 32 * MT), div_up(N, 32 * NT));
     const int slot = prof_begin(c, PK_GEMM_NN);
     k_gemm_nn<T, MT, NT><<<grid, 256, 0, c->stream>>>(K, N, M, A, lda, Bm, ldb, Out, ldo);
@@ -326,8 +325,13 @@ sparc_status gemm_nn(sparc_gpu_ctx c, long K, int N, int M, const T* A, long lda
     if (N <= 32) return gemm_nn_launch<T, 1>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
     if (N <= 96) return gemm_nn_launch<T, 3>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
     // 160-column tiles (two waves per SIMD) or 288-column (one per SIMD,
-    // fewer passes over A); tuning override SPARC_GPU_GEMM_NN_COLS = 160 | 288
+    // fewer passes over A); tuning override SPARC_GPU_GEMM_NN_COLS = 160 | 288.
+    // Rows per tile: 128 for FP64 (twice the MFMAs per barrier: 92.6 against
+    // 102.1 ms at 1.73M x 1200 x 1200), 64 for FP32 (71.1 against 73.5 ms);
+    // override SPARC_GPU_GEMM_NN_ROWS = 64 | 128
     if (c->gemm_nn_cols == 288) return gemm_nn_launch<T, 9>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
+    const int rows = c->gemm_nn_rows > 0 ? c->gemm_nn_rows : (sizeof(T) == 8 ? 128 : 64);
+    if (rows == 128) return gemm_nn_launch<T, 5, 4>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
     return gemm_nn_launch<T, 5>(c, K, N, M, A, lda, Bm, ldb, Out, ldo);
 }
 

@@ -194,6 +194,7 @@ struct sparc_gpu_ctx_s {
     int nl_slots = 0;           // SPARC_GPU_NL_SLOTS=7: FP64 sweep takes 7 nonlocal slots per point (0: by the tables)
     int gemm_tile = 0;          // SPARC_GPU_GEMM_TILE: Gram/projected-H tile edge (128, 160; 0: by size)
     int gemm_nn_cols = 160;     // SPARC_GPU_GEMM_NN_COLS: rotation tile width (160, 288)
+    int gemm_nn_rows = 0;       // SPARC_GPU_GEMM_NN_ROWS: rotation tile height (64, 128; 0: 128 FP64, 64 FP32)
     hipGraphExec_t jac_exec = nullptr;
     int jac_N = 0;
     double *jac_A = nullptr, *jac_A2 = nullptr, *jac_V = nullptr, *jac_V2 = nullptr;
