@@ -451,7 +451,8 @@ sparc_status sparc_gpu_forces(sparc_gpu_ctx ctx, const double* d_phi, sparc_prec
  * kernels is bracketed by HIP events on the context's stream.
  * sparc_gpu_profile_read() synchronises, returns the summed device time (ms)
  * and launch count since the last read for one kernel, and resets it.
- * Kernel ids: 0 filter sweep of degree >= 2, 1 nonlocal projection,
+ * Kernel ids: 0 filter sweep of degree >= 2, 1 nonlocal projection (its
+ * streaming pass and per-atom sum),
  * 2 Gram/projected-H GEMM, 3 rotation GEMM, 4 density, 5 first filter
  * sweep, 6 plain H application, 7 Cholesky, 8 triangular inverse,
  * 9 subspace eigensolver (all its launches, host waits included),

@@ -5,21 +5,22 @@
 // Sec. 2.1).  The scaled three-term Chebyshev recurrence of the CheFSI filter
 // (Sec. 2.1) is fused into the epilogue of the stencil sweep, so one sweep
 // streams X_k (stencil operand), X_{k-1} (recurrence term) and writes X_{k+1}
-// over X_{k-1}: 3 block-sized streams per filter degree.  With projectors the
-// same sweep also forms the projections dV chi^T X_{k+1} of its output, which
-// the next filter step applies, so the block is not read a fourth time.
+// over X_{k-1}: 3 block-sized streams per filter degree.  With projectors a
+// separate pass before each sweep forms the projections D = gamma dV chi^T X_k
+// by reading the block once (k_proj_stream), and the sweep adds chi D point
+// by point.
 //
 // Sweep kernel layout (one workgroup = one orbital x one y-slab x all z):
 //  - the slab is `ty` full x-rows; periodic x wraps inside LDS (padded rows),
-//    so only y needs halo rows, which are read from L2 (the neighbouring slabs
-//    of the same orbital run on the same XCD at the same time, see the block
-//    mapping below);
+//    so only y needs halo rows, read from L2 where a neighbouring slab of the
+//    same orbital (mapped to the same XCD, see the block mapping below)
+//    loaded them recently enough, else from the last-level cache or HBM;
 //  - z is marched with a register ring of RING = 13 + PR planes per thread:
 //    planes z-6 .. z+6 in use and PR planes in flight, so every point of X_k
 //    is fetched once per sweep (plus the 12 periodic wrap planes);
 //  - the halo rows, X_{k-1}, V_eff and the nonlocal point words of the
 //    coming planes sit in PQ-deep register queues, so each load has PQ plane
-//    steps to land;
+//    steps to land; the nonlocal pair records are loaded two planes ahead;
 //  - two LDS plane buffers alternate so one barrier per plane suffices.
 #include <cmath>
 #include <map>
@@ -219,19 +220,22 @@ __device__ inline void pair_record(const SweepArgs<T>& a, const SweepShared<T>& 
 // One z-plane step at ring phase U (z = z0 + U).  On entry the LDS buffer of
 // parity U holds plane z (own rows with x-wrap padding and halo rows) and the
 // pair records of plane z, written during the previous step.
-//  1. barrier;
+//  1. barrier, then the nonlocal term of plane z from the pair records (right
+//     after the barrier, where the fewest values are live);
 //  2. issue the loads of the halo values of plane z + PQ, of ring plane
-//     z + 6 + PR and of the pair records of plane z + 1 (plane indices wrap,
-//     so the loads are unconditional);
-//  3. stencil + potential + nonlocal + recurrence for plane z, store;
+//     z + 6 + PR (plane indices wrap, so the loads are unconditional) and of
+//     the pair records of plane z + 2;
+//  3. stencil + potential + recurrence for plane z, store;
 //  4. load X_{k-1}, V_eff and the point word of plane z + PQ into the queue
 //     slot plane z has freed;
-//  5. pair records of plane z + 1; plane z + 1 into the other LDS buffer.
-// The nonlocal term sums every slot of the point word (empty slots name the
-// null pair, whose ex entries are zero), so a step has no loop or branch:
-// a loop inside the unrolled step would keep every value live across it.
-// Threads without a point of the slab (ragged slab, padding to 64) load
-// valid clamped addresses and compute on them, but never store.
+//  5. pair records of plane z + 1 (loaded during the previous step) into the
+//     other record buffer; plane z + 1 into the other LDS buffer.
+// The nonlocal term takes NSL slots of the point word without a branch (empty
+// slots name the null pair, whose ex entries are zero), or with NSL = 4 four
+// slots and the other three in a branch; a loop inside the unrolled step
+// would keep every value live across it.  Threads without a point of the slab
+// (ragged slab, padding to 64) load valid clamped addresses and compute on
+// them, but never store.
 template <typename T, bool NL, int MODE, int HM, int NSL = 4>
 __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> a) {
     constexpr int NO = kMaxHalfOrder;
@@ -1045,9 +1049,8 @@ __global__ void k_copy_block(const T* __restrict__ src, T* __restrict__ dst, lon
 }
 
 // Filter with bounds already in c->scal[S_A..S_A0].  Y_k lives in X when k is
-// even and in W when k is odd; the result ends in X.  The projections of
-// Y_0 come from the gather kernel; every later sweep forms the projections
-// of its own output for the next one (not needed after the last).
+// even and in W when k is odd; the result ends in X.  Before each sweep the
+// projection pass forms the projections of its operand Y_{k-1}.
 template <typename T>
 sparc_status filter_impl(sparc_gpu_ctx c, T* X, T* Wk, int ncol, long ldx, int m, double* part, size_t part_elems) {
     sparc_status st;
