@@ -552,6 +552,53 @@ def test_fp64_nonlocal_slot_counts_agree_bitwise(system, monkeypatch):
     assert np.array_equal(outs[0][1], outs[1][1])
 
 
+def test_projection_over_ragged_z_ranges():
+    """14 x 16 x 37 grid, 4 atoms, 4 columns: the projection pass splits the
+    37 planes of each slab into 4 z ranges of 10, 10, 10 and 7 planes, whose
+    partials the per-atom sum adds in order.  H X and a degree-7 filter
+    against the oracle, and the allocation-free filter bitwise equal to the
+    filter."""
+    torch = require_gpu()
+    s = W.tiny_system(n=(14, 16, 37), L=(7.0, 7.5, 11.1), n_atoms=4, seed=13, n_states=4)
+    v = _veff(s, 29)
+    projs = atoms.projectors(s)
+    X = W.initial_orbitals(s.nd, s.n_states, 6)
+    ctx = _ctx(s)
+    ctx.set_veff(to_dev(torch, v))
+    Xd = to_dev(torch, X)
+    Yd = torch.empty_like(Xd)
+    ctx.apply_H(Xd, Yd)
+    torch.cuda.synchronize()
+    err = rel_err(to_np(Yd), hamiltonian.apply_H(s, v, projs, X))
+    log(f"ragged z ranges: H X rel err {err:.2e}")
+    assert err <= 1e-12
+    lo, hi = hamiltonian.spectrum_bounds(s, v, projs)
+    a, b, a0 = lo + 0.3 * (hi - lo), hi, lo
+    Wd = torch.empty_like(Xd)
+    ctx.chebyshev_filter(Xd, Wd, 7, a, b, a0)
+    X2 = to_dev(torch, X)
+    W2 = torch.empty_like(X2)
+    ctx.chebyshev_filter_noalloc(X2, W2, 7, a, b, a0)
+    torch.cuda.synchronize()
+    ref = chefsi.chebyshev_filter(s, v, projs, X, 7, a, b, a0)
+    err = rel_err(to_np(Xd), ref)
+    log(f"ragged z ranges: filter rel err {err:.2e}")
+    assert err <= 1e-11
+    assert torch.equal(Xd, X2)
+
+
+def test_create_rejects_more_than_seven_supports_at_a_point():
+    """4 atoms in a 4.2 x 4.5 Bohr cross-section with 3 Bohr projector
+    supports: with their periodic images, 8 supports meet at some grid point
+    (counted on the CPU), more than the sweep's point words hold; creation
+    fails with SPARC_ERR_ARG instead of dropping a term."""
+    require_gpu()
+    from paper_2005_10431_amd import Context, SparcError
+    s = W.tiny_system(n=(14, 16, 37), L=(4.2, 4.5, 11.1), n_atoms=4, seed=13, n_states=4)
+    with pytest.raises(SparcError, match="SPARC_ERR_ARG"):
+        Context(s)
+
+
 def test_apply_H_wide_grid_many_halo_values():
     """200 x 14 x 13 grid: the nonlocal sweep's slab shrinks to 2 rows and
     each thread carries 6 halo values per plane."""
