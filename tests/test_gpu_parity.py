@@ -587,6 +587,37 @@ def test_projection_over_ragged_z_ranges():
     assert torch.equal(Xd, X2)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_projection_workgroup_size_does_not_change_results(prec, monkeypatch):
+    """The projection pass gives each orbital its own wave, so the number of
+    orbitals per workgroup (SPARC_GPU_PROJ_NB=2 against the default 8, read at
+    context creation) changes no sum: with one z range per slab (13 planes)
+    H X and the filter are bitwise the same."""
+    torch = require_gpu()
+    s = ragged_system(n_states=11)
+    v = _veff(s, 31)
+    X = W.initial_orbitals(s.nd, s.n_states, 8)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    outs = []
+    for nb in (None, "2"):
+        if nb:
+            monkeypatch.setenv("SPARC_GPU_PROJ_NB", nb)
+        else:
+            monkeypatch.delenv("SPARC_GPU_PROJ_NB", raising=False)
+        ctx = _ctx(s)
+        ctx.set_veff(to_dev(torch, v))
+        lo, hi = ctx.spectrum_bounds()
+        Xd = to_dev(torch, X, dt)
+        Yd = torch.empty_like(Xd)
+        ctx.apply_H(Xd, Yd)
+        Wd = torch.empty_like(Xd)
+        ctx.chebyshev_filter(Xd, Wd, 6, 0.5 * (lo + hi), hi, lo)
+        outs.append((to_np(Yd), to_np(Xd)))
+    monkeypatch.delenv("SPARC_GPU_PROJ_NB", raising=False)
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_create_rejects_more_than_seven_supports_at_a_point():
     """4 atoms in a 4.2 x 4.5 Bohr cross-section with 3 Bohr projector
     supports: with their periodic images, 8 supports meet at some grid point
