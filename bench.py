@@ -274,9 +274,10 @@ def time_to_accuracy(system, X0, eps=1e-5, tol_ref=1e-6, max_iter=120, deadline=
 
 
 def cnn_measure(steps: int = 10):
-    """Forward pass of the warm-start network on the 72^3 snapshot grid:
-    average time per forward and of its 16 -> 16 convolution, against the
-    FP32 vector peak (the convolutions are plain FMA work)."""
+    """Forward and gradient of the warm-start network on the 72^3 snapshot
+    grid: average time per forward, per gradient and of the forward's
+    16 -> 16 convolution (the matrix-core kernel) against the FP32 MFMA
+    peak."""
     import torch
 
     import workloads as W
@@ -314,7 +315,7 @@ def cnn_measure(steps: int = 10):
         "forward_ms": fwd_ms / n,
         "backward_ms": bwd_ms / n3,
         "forward_gflop": flop_fwd / 1e9,
-        "roofline": {"kernel": "k_conv<16, 16, forward, relu>", "bound": "alu",
+        "roofline": {"kernel": "k_conv16_mfma<8, forward, relu>", "bound": "mfma",
                      "achieved": flop_c2 / (c2 * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": flop_c2 / (c2 * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, "avg_launch_ms": c2,
                      "algorithmic_flop_per_launch": flop_c2},
@@ -344,6 +345,9 @@ def main():
                     help="columns in the CPU oracle sample (0: skip; default 2 at cfg4, 40 at cfg2, 12 at cfg1)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-filter companion measurement")
     ap.add_argument("--no-cnn", action="store_true", help="skip the warm-start network measurement")
+    ap.add_argument("--cnn-only", action="store_true",
+                    help="run only the warm-start network measurement and print it (the program profiled for "
+                         "the convolution kernels)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the time-to-1e-5-Ha/atom comparison of the FP64 and FP32 forms")
     ap.add_argument("--budget-s", type=float, default=420.0,
@@ -364,6 +368,9 @@ def main():
 
     if args.oracle_timing:
         print(json.dumps(oracle_timing()))
+        return
+    if args.cnn_only:
+        print(json.dumps({"warm_start_cnn": cnn_measure()}), flush=True)
         return
 
     import numpy as np

@@ -109,6 +109,187 @@ __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ in, cons
     }
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// The 16 -> 16 layer (either MODE of k_conv) as an implicit GEMM on the FP32
+// matrix cores: D[o][p] = sum over (tap, i) of A[o][tap, i] B[tap, i][p], A
+// the weights (M = 16 output channels), B channel i at p + d(tap) (N = 16
+// points), K = 27 taps x 16 channels in steps of four channels of one tap
+// (MFMA 16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]; register
+// r of lane l receives D[4 (l/16) + r][l%16]).  K-step (tap, g) takes the
+// channels i = 4 g + l/16.
+//
+// Output tiles are 8 x 8 x TZ made of 16-point blocks, an x-row at two
+// consecutive z; wave w owns the four blocks at y = 4 (w % 2) + j (j < 4)
+// and z = 2 (w / 2) + {0, 1}.  LDS holds the halo tile as float4 of the
+// channels i % 4 + {0, 4, 8, 12} per point (one plane of channel quad
+// i % 4 after another) and the weights as wq[tap][lane] = float4 over g, so
+// that one 16-byte read at a per-lane base plus a compile-time offset gives
+// a lane its operands for the four K-steps of a tap.
+//
+// The workgroups are persistent: the weights are staged once; while a tile
+// is computed, the previous tile's results are stored and this tile's mask
+// read (first taps) and the next tile's halo is loaded into registers (last
+// taps), two accesses per tap, so that no wait on memory stands between the
+// tiles' MFMAs; operands are read two taps ahead of their MFMAs, the taps
+// kept apart by scheduling barriers.
+template <int TZ>
+struct Conv16Shape {
+    static constexpr int NT = 64 * TZ;                 // threads
+    static constexpr int PQ = kH * kH;                 // plane pitch (float4)
+    static constexpr int NH = (TZ + 2) * kH * kH;      // halo points (= channel-quad stride)
+    static constexpr int NQ = (NH + NT - 1) / NT;      // halo points per thread
+    static constexpr int NL = NQ * 16;                 // halo loads per thread
+    static_assert(TZ % 2 == 0 && NL <= 2 * 27 && NL % 2 == 0, "two halo loads per tap");
+};
+
+template <int TZ, int MODE, bool RELU>
+__global__ __launch_bounds__(64 * TZ) void k_conv16_mfma(const float* __restrict__ in, const float* __restrict__ W,
+                                                         const float* __restrict__ bias,
+                                                         const float* __restrict__ mask, float* __restrict__ out,
+                                                         Grid3 g, int ntile) {
+    using S = Conv16Shape<TZ>;
+    __shared__ float4 tile4[4 * S::NH];
+    __shared__ float4 wq[27 * 64];
+    const long nd = (long)g.nx * g.ny * g.nz;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, pl = lane & 15;
+    float bo[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bo[r] = MODE == 0 ? bias[4 * (lane >> 4) + r] : 0.0f;
+    // grid offsets of this thread's halo points in a tile
+    auto halo_offsets = [&](int tile, long (&gp)[S::NQ]) {
+        const int x0 = (tile % g.tx) * kT;
+        const int y0 = ((tile / g.tx) % g.ty) * kT;
+        const int z0 = (tile / (g.tx * g.ty)) * TZ;
+#pragma unroll
+        for (int i = 0; i < S::NQ; ++i) {
+            // threads past the halo re-read its last point (the value is unused)
+            const int q = min((int)threadIdx.x + i * S::NT, S::NH - 1);
+            const int lz = q / (kH * kH), ly = (q / kH) % kH, lx = q % kH;
+            gp[i] = wrap(x0 + lx - 1, g.nx) +
+                    (long)g.nx * (wrap(y0 + ly - 1, g.ny) + (long)g.ny * wrap(z0 + lz - 1, g.nz));
+        }
+    };
+    float hr[S::NQ][16];
+    long gp[S::NQ];
+    // results of the previous tile (block j, register r) and their grid
+    // points, stored during the next tile's first taps
+    float res[4][4];
+    long pp[4];
+    int vp = 0;   // bit j: block j of the previous tile lies in the grid
+    {
+        // destination order: consecutive threads write consecutive floats
+        float* wf = reinterpret_cast<float*>(wq);
+        for (int d = threadIdx.x; d < 27 * 64 * 4; d += S::NT) {
+            const int gq = d & 3, ln = (d >> 2) & 63, tap = d >> 8;
+            const int o = ln & 15, ci = 4 * gq + (ln >> 4);
+            wf[d] = MODE == 0 ? W[(o * 16 + ci) * 27 + tap] : W[(ci * 16 + o) * 27 + 26 - tap];
+        }
+    }
+    int t = blockIdx.x;
+    if (t < ntile) {
+        halo_offsets(t, gp);
+#pragma unroll
+        for (int i = 0; i < S::NQ; ++i)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) hr[i][c] = in[c * nd + gp[i]];
+    }
+    for (; t < ntile; t += gridDim.x) {
+        __syncthreads();   // the previous tile's reads of the halo are done
+#pragma unroll
+        for (int i = 0; i < S::NQ; ++i) {
+            const int q = threadIdx.x + i * S::NT;
+            if (i * S::NT + S::NT <= S::NH || q < S::NH) {
+#pragma unroll
+                for (int cq = 0; cq < 4; ++cq)
+                    tile4[cq * S::NH + q] = make_float4(hr[i][cq], hr[i][cq + 4], hr[i][cq + 8], hr[i][cq + 12]);
+            }
+        }
+        __syncthreads();
+        // the last tile re-reads its own halo (branch-free; values unused)
+        halo_offsets(t + (int)gridDim.x < ntile ? t + (int)gridDim.x : t, gp);
+        const float4* bp =
+            tile4 + (lane >> 4) * S::NH + (2 * (wv >> 1) + (pl >> 3)) * S::PQ + 4 * (wv & 1) * kH + (pl & 7);
+        const float4* wp = wq + lane;
+        long pc[4];
+        int vc = 0;
+        {
+            const int x = (t % g.tx) * kT + (pl & 7);
+            const int y0 = ((t / g.tx) % g.ty) * kT + 4 * (wv & 1);
+            const int z = (t / (g.tx * g.ty)) * TZ + 2 * (wv >> 1) + (pl >> 3);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool in_grid = x < g.nx && y0 + j < g.ny && z < g.nz;
+                pc[j] = in_grid ? x + (long)g.nx * (y0 + j + (long)g.ny * z) : 0;
+                vc |= (int)in_grid << j;
+            }
+        }
+        float mk[4][4];
+        f32x4 acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[j][r] = bo[r];
+        constexpr int kPipe = 2;
+        float4 oa[kPipe + 1], ob[kPipe + 1][4];
+        auto operands = [&](int tap, float4& a, float4 (&v)[4]) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+            a = wp[tap * 64];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = bp[j * kH + dz * S::PQ + dy * kH + dx];
+        };
+#pragma unroll
+        for (int tap = 0; tap < kPipe; ++tap) operands(tap, oa[tap], ob[tap]);
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) {
+            if (tap + kPipe < 27)
+                operands(tap + kPipe, oa[(tap + kPipe) % (kPipe + 1)], ob[(tap + kPipe) % (kPipe + 1)]);
+            if (tap < 8) {
+                // the previous tile's results, then this tile's mask
+#pragma unroll
+                for (int e = 2 * tap; e < 2 * tap + 2; ++e) {
+                    const int j = e >> 2, r = e & 3;
+                    if (vp >> j & 1) out[(long)(4 * (lane >> 4) + r) * nd + pp[j]] = res[j][r];
+                    if (MODE == 1) mk[j][r] = mask[(long)(4 * (lane >> 4) + r) * nd + pc[j]];
+                }
+            }
+            if (tap >= 27 - S::NL / 2) {
+#pragma unroll
+                for (int h = 2 * (tap - (27 - S::NL / 2)); h < 2 * (tap - (27 - S::NL / 2)) + 2; ++h)
+                    hr[h >> 4][h & 15] = in[(h & 15) * nd + gp[h >> 4]];
+            }
+            const float4 a = oa[tap % (kPipe + 1)];
+            const float av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float4 v = ob[tap % (kPipe + 1)][j];
+                    const float bv = gq == 0 ? v.x : gq == 1 ? v.y : gq == 2 ? v.z : v.w;
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[gq], bv, acc[j], 0, 0, 0);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[j][r];
+                if (MODE == 0 && RELU) v = fmaxf(v, 0.0f);
+                if (MODE == 1) v = mk[j][r] > 0.0f ? v : 0.0f;
+                res[j][r] = v;
+            }
+            pp[j] = pc[j];
+        }
+        vp = vc;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (vp >> j & 1) out[(long)(4 * (lane >> 4) + r) * nd + pp[j]] = res[j][r];
+}
+
 // Per-tile partial gradients of one layer: thread j < CI*27 owns the taps
 // (i = j / 27, k = j % 27) for every output channel, thread CI*27 + o owns
 // the bias of channel o.  part[tile][CO*CI*27 + CO] in the parameter order.
@@ -157,13 +338,116 @@ __global__ __launch_bounds__(512) void k_wgrad(const float* __restrict__ u, cons
     }
 }
 
-// grad[off + j] = sum over tiles of part[tile][j] (FP64, fixed order).
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int ntiles, int np, float* __restrict__ grad) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= np) return;
+// Per-tile partial gradient of the 16 -> 16 layer on the FP32 matrix cores:
+// dW[o][i][k] = sum over the tile's points p of gr[o][p] u[i][p + d(k)], a
+// GEMM per tap k with M = 16 (o), N = 16 (i) and K = the 512 points in steps
+// of four (lane l supplies A[o = l%16][p = 4s + l/16] and
+// B[p = 4s + l/16][i = l%16]; register r of lane l receives D[4 (l/16) + r]
+// [l%16]).  LDS holds the input halo and the tile of gr point-major (the 16
+// channels of a point contiguous), so that both operand reads of a step are
+// 64 consecutive floats.  Wave w owns the taps w, w+8, w+16 and, for w < 3,
+// w+24; wave 3 adds the bias sum sum_p gr[o][p] as a fourth GEMM against
+// ones, so that each SIMD (waves w and w+4) issues seven GEMMs.  Each step's
+// gr read serves all of the wave's GEMMs.  part[tile][(o*16 + i)*27 + k],
+// bias at part[tile][16*16*27 + o], as k_wgrad<16, 16>.
+template <int NSL, bool BIAS>
+__device__ inline void wgrad16_gemms(const float* gt, const float* uh, int w, int lane, float* pp) {
+    f32x4 acc[NSL];
+#pragma unroll
+    for (int k = 0; k < NSL; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const float* bt[NSL];
+#pragma unroll
+    for (int k = 0; k < NSL; ++k) {
+        const int tap = w + 8 * k, dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+        bt[k] = uh + (dz * kH * kH + dy * kH + dx) * 16 + lane;
+    }
+    const float* at = gt + lane;
+#pragma unroll
+    for (int s = 0; s < kTile / 4; ++s) {
+        // the four points 4s .. 4s+3: x = 4 (s % 2) + l/16, y = (s / 2) % 8, z = s / 16
+        const int hp = (s / 16) * kH * kH + ((s / 2) % 8) * kH + 4 * (s % 2);
+        const float a = at[64 * s];
+#pragma unroll
+        for (int k = 0; k < NSL; ++k) {
+            const float b = (BIAS && k == NSL - 1) ? 1.0f : bt[k][hp * 16];
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[k], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NSL; ++k) {
+        const int i = lane & 15;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * (lane >> 4) + r;
+            if (BIAS && k == NSL - 1) {
+                if (i == 0) pp[16 * 16 * 27 + o] = acc[k][r];
+            } else {
+                pp[(o * 16 + i) * 27 + w + 8 * k] = acc[k][r];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(512) void k_wgrad16_mfma(const float* __restrict__ u, const float* __restrict__ gr,
+                                                      float* __restrict__ part, Grid3 g) {
+    __shared__ float uh[kHalo * 16];
+    __shared__ float gt[kTile * 16];
+    const long nd = (long)g.nx * g.ny * g.nz;
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    for (int q = threadIdx.x; q < kHalo; q += blockDim.x) {
+        const int lz = q / (kH * kH), ly = (q / kH) % kH, lx = q % kH;
+        const long gp = wrap(x0 + lx - 1, g.nx) +
+                        (long)g.nx * (wrap(y0 + ly - 1, g.ny) + (long)g.ny * wrap(z0 + lz - 1, g.nz));
+        float v[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = u[c * nd + gp];
+#pragma unroll
+        for (int c = 0; c < 16; c += 4)
+            *reinterpret_cast<float4*>(uh + q * 16 + c) = make_float4(v[c], v[c + 1], v[c + 2], v[c + 3]);
+    }
+    {
+        const int r = threadIdx.x;   // one tile point per thread
+        const int x = x0 + r % kT, y = y0 + (r / kT) % kT, z = z0 + r / (kT * kT);
+        const bool in_grid = x < g.nx && y < g.ny && z < g.nz;
+        const long p = in_grid ? x + (long)g.nx * (y + (long)g.ny * z) : 0;
+        float v[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = in_grid ? gr[c * nd + p] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < 16; c += 4)
+            *reinterpret_cast<float4*>(gt + r * 16 + c) = make_float4(v[c], v[c + 1], v[c + 2], v[c + 3]);
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* pp = part + (long)blockIdx.x * (16 * 16 * 27 + 16);
+    if (w < 3)
+        wgrad16_gemms<4, false>(gt, uh, w, lane, pp);
+    else if (w == 3)
+        wgrad16_gemms<4, true>(gt, uh, w, lane, pp);
+    else
+        wgrad16_gemms<3, false>(gt, uh, w, lane, pp);
+}
+
+// grad[off + j] = sum over tiles of part[tile][j] in FP64 and a fixed
+// order: thread (j, q) of a 64 x 16 workgroup sums the tiles b = q (mod 16)
+// in increasing b, then the 16 partial sums of j are added in increasing q.
+constexpr int kRedJ = 64, kRedQ = 16;
+__global__ __launch_bounds__(kRedJ* kRedQ) void k_wgrad_reduce(const float* __restrict__ part, int ntiles, int np,
+                                                               float* __restrict__ grad) {
+    __shared__ double ps[kRedQ][kRedJ];
+    const int jl = threadIdx.x % kRedJ, q = threadIdx.x / kRedJ;
+    const int j = blockIdx.x * kRedJ + jl;
     double s = 0.0;
-    for (int b = 0; b < ntiles; ++b) s += (double)part[(long)b * np + j];
-    grad[j] = (float)s;
+    if (j < np)
+        for (int b = q; b < ntiles; b += kRedQ) s += (double)part[(long)b * np + j];
+    ps[q][jl] = s;
+    __syncthreads();
+    if (q == 0 && j < np) {
+        double t = 0.0;
+        for (int k = 0; k < kRedQ; ++k) t += ps[k][jl];
+        grad[j] = (float)t;
+    }
 }
 
 __device__ inline double softplus_d(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
@@ -192,12 +476,15 @@ __device__ inline void block_reduce3(double a, double b, double c, double* out) 
     }
 }
 
-__global__ void k_reduce3_final(const double* part, int nblk, double* out) {
-    const int q = threadIdx.x;
-    if (q >= 3) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b * 3 + q];
-    out[q] = s;
+// out[q] = sum over blocks of part[block * 3 + q]: one workgroup of 256,
+// thread t summing the blocks t (mod 256) in increasing order, then the
+// fixed tree of block_reduce3.
+__global__ __launch_bounds__(256) void k_reduce3_final(const double* part, int nblk, double* out) {
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s[q] += part[b * 3 + q];
+    block_reduce3(s[0], s[1], s[2], out);
 }
 
 // sum of softplus(z)
@@ -339,6 +626,34 @@ static size_t wgrad_lds() {
     return (size_t)(CI * kHalo + CO * kTile) * sizeof(float);
 }
 
+// One persistent workgroup per resident slot (LDS sets how many fit on a
+// CU; the count is taken once per context), never more than there are tiles.
+template <int TZ, int MODE, bool RELU>
+static void conv16_launch(sparc_gpu_ctx c, const Grid3& g, const float* in, const float* W, const float* bias,
+                          const float* mask, float* out) {
+    int& per_cu = c->cnn_per_cu[TZ == 8][MODE];
+    if (per_cu == 0 && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv16_mfma<TZ, MODE, RELU>,
+                                                                      64 * TZ, 0) != hipSuccess ||
+                        per_cu < 1))
+        per_cu = 1;
+    const int ntile = g.tx * g.ty * div_up(g.nz, TZ);
+    const int nb = std::min(ntile, per_cu * c->prop.multiProcessorCount);
+    k_conv16_mfma<TZ, MODE, RELU><<<nb, 64 * TZ, 0, c->stream>>>(in, W, bias, mask, out, g, ntile);
+}
+
+// The 16 -> 16 layer: the matrix-core kernel on 8 x 8 x cnn_tz tiles, or
+// the vector kernel when cnn_tz is 0.
+template <int MODE, bool RELU>
+static void conv16(sparc_gpu_ctx c, const Grid3& g, const float* in, const float* W, const float* bias,
+                   const float* mask, float* out) {
+    if (c->cnn_tz == 0)
+        k_conv<16, 16, MODE, RELU><<<ntiles(g), 512, 0, c->stream>>>(in, W, bias, mask, out, g);
+    else if (c->cnn_tz == 4)
+        conv16_launch<4, MODE, RELU>(c, g, in, W, bias, mask, out);
+    else
+        conv16_launch<8, MODE, RELU>(c, g, in, W, bias, mask, out);
+}
+
 // head scalars live in scal[S_CNN .. S_CNN+5]: S, -, -, loss, G, -
 static sparc_status forward_impl(sparc_gpu_ctx c, const float* w, const float* feat, float* act, double* rho) {
     const Grid3 g = grid3(c);
@@ -350,7 +665,7 @@ static sparc_status forward_impl(sparc_gpu_ctx c, const float* w, const float* f
     const int slot = prof_begin(c, PK_CNN_FWD);
     k_conv<3, 16, 0, true><<<nt, 512, 0, c->stream>>>(feat, w, w + kOff1, nullptr, a1, g);
     const int slot2 = prof_begin(c, PK_CNN_CONV2);
-    k_conv<16, 16, 0, true><<<nt, 512, 0, c->stream>>>(a1, w + kOff2, w + kOff3, nullptr, a2, g);
+    conv16<0, true>(c, g, a1, w + kOff2, w + kOff3, nullptr, a2);
     prof_end(c, slot2);
     k_conv<16, 1, 0, false><<<nt, 512, 0, c->stream>>>(a2, w + kOff4, w + kOff5, nullptr, z, g);
     SG_CHECK_LAUNCH(c);
@@ -358,7 +673,7 @@ static sparc_status forward_impl(sparc_gpu_ctx c, const float* w, const float* f
     sparc_status st = ensure_red(c, 3 * (size_t)nblk);
     if (st != SPARC_OK) return st;
     k_head_sum<<<nblk, 256, 0, c->stream>>>(z, nd, c->red);
-    k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
+    k_reduce3_final<<<1, 256, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
     k_head_rho<<<div_up(nd, 256), 256, 0, c->stream>>>(z, nd, c->scal + S_CNN, c->n_electrons / c->dV, rho);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
@@ -392,23 +707,26 @@ static sparc_status backward_impl(sparc_gpu_ctx c, const float* w, const float* 
     // the forward's softplus sum is recomputed so that backward depends only
     // on its arguments
     k_head_sum<<<nblk, 256, 0, c->stream>>>(z, nd, c->red);
-    k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
+    k_reduce3_final<<<1, 256, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
     k_head_loss<<<nblk, 256, 0, c->stream>>>(z, rho, tgt, nd, c->red);
-    k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN + 3);
+    k_reduce3_final<<<1, 256, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN + 3);
     k_head_dz<<<div_up(nd, 256), 256, 0, c->stream>>>(z, rho, tgt, nd, c->scal + S_CNN, c->scal + S_CNN + 3,
                                                       c->n_electrons / c->dV, dz);
     SG_CHECK_LAUNCH(c);
     // layer 3
     k_wgrad<16, 1><<<nt, 512, wgrad_lds<16, 1>(), c->stream>>>(a2, dz, part, g);
-    k_wgrad_reduce<<<div_up(np3, 256), 256, 0, c->stream>>>(part, nt, np3, grad + kOff4);
+    k_wgrad_reduce<<<div_up(np3, kRedJ), kRedJ * kRedQ, 0, c->stream>>>(part, nt, np3, grad + kOff4);
     k_conv<1, 16, 1, false><<<nt, 512, 0, c->stream>>>(dz, w + kOff4, nullptr, a2, d2, g);
     // layer 2
-    k_wgrad<16, 16><<<nt, 512, wgrad_lds<16, 16>(), c->stream>>>(a1, d2, part, g);
-    k_wgrad_reduce<<<div_up(np2, 256), 256, 0, c->stream>>>(part, nt, np2, grad + kOff2);
-    k_conv<16, 16, 1, false><<<nt, 512, 0, c->stream>>>(d2, w + kOff2, nullptr, a1, d1, g);
+    if (c->cnn_tz == 0)
+        k_wgrad<16, 16><<<nt, 512, wgrad_lds<16, 16>(), c->stream>>>(a1, d2, part, g);
+    else
+        k_wgrad16_mfma<<<nt, 512, 0, c->stream>>>(a1, d2, part, g);
+    k_wgrad_reduce<<<div_up(np2, kRedJ), kRedJ * kRedQ, 0, c->stream>>>(part, nt, np2, grad + kOff2);
+    conv16<1, false>(c, g, d2, w + kOff2, nullptr, a1, d1);
     // layer 1
     k_wgrad<3, 16><<<nt, 512, wgrad_lds<3, 16>(), c->stream>>>(feat, d1, part, g);
-    k_wgrad_reduce<<<div_up(np1, 256), 256, 0, c->stream>>>(part, nt, np1, grad);
+    k_wgrad_reduce<<<div_up(np1, kRedJ), kRedJ * kRedQ, 0, c->stream>>>(part, nt, np1, grad);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
     if (loss)
@@ -480,7 +798,7 @@ sparc_status sparc_gpu_warm_start(sparc_gpu_ctx c, const float* d_w, double max_
     const int nblk = (int)std::min<long>(1024, div_up(nd, 256));
     if ((st = ensure_red(c, 3 * (size_t)nblk)) != SPARC_OK) return st;
     k_l1<<<nblk, 256, 0, c->stream>>>(d_rho, sad, nd, c->red);
-    k_reduce3_final<<<1, 64, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
+    k_reduce3_final<<<1, 256, 0, c->stream>>>(c->red, nblk, c->scal + S_CNN);
     SG_CHECK_LAUNCH(c);
     double h[3];
     SG_HIP(c, hipMemcpyAsync(h, c->scal + S_CNN, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));

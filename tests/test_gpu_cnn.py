@@ -103,6 +103,56 @@ def test_forward_full_grid_snapshot():
     assert err <= 1e-5
 
 
+def _conv16_case(name, tz, monkeypatch, torch):
+    """Forward and gradient with the 16 -> 16 layer on the path tz (0: the
+    vector kernel; 4, 8: the matrix-core kernel with 8 x 8 x tz tiles)."""
+    monkeypatch.setenv("SPARC_GPU_CNN_TZ", tz)
+    s = W.config5_snapshot(201) if name == "snapshot72" else _systems()[name]
+    ctx = _ctx(s)
+    w = _weights(4)
+    fdev = torch.empty((3, s.nd), dtype=torch.float32, device="cuda")
+    ctx.features(fdev)
+    act = torch.empty((33, s.nd), dtype=torch.float32, device="cuda")
+    rho = torch.empty(s.nd, dtype=torch.float64, device="cuda")
+    ctx.cnn_forward(to_dev(torch, w), fdev, act, rho)
+    tgt = atoms.sad_density(s) * np.random.default_rng(11).uniform(0.8, 1.2, s.nd)
+    grad = torch.empty(w.size, dtype=torch.float32, device="cuda")
+    ctx.cnn_backward(to_dev(torch, w), fdev, act, rho, to_dev(torch, tgt), grad, None)
+    return s, w, to_np(fdev), to_np(act), to_np(grad), tgt
+
+
+@pytest.mark.parametrize("name", ["odd_tiles", "snapshot72"])
+@pytest.mark.parametrize("tz", ["0", "4", "8"])
+def test_conv16_layer_matches_oracle_on_every_path(name, tz, monkeypatch):
+    """The 16 -> 16 layer's output (layer-2 activations) element by element
+    and the full gradient, whose backward pass runs the layer transposed and
+    masked, against the oracle on the same inputs: a ragged 17 x 13 x 21
+    grid (partial tiles in every direction, one tile per workgroup) and the
+    72^3 snapshot grid (several tiles per persistent workgroup)."""
+    torch = require_gpu()
+    s, w, f, act, g, tgt = _conv16_case(name, tz, monkeypatch, torch)
+    rho_ref, cache = cnn.forward(s, w.astype(np.float64), f.astype(np.float64).reshape(3, s.n[2], s.n[1], s.n[0]))
+    a2 = act[16:32].reshape(cache["a2"].shape)
+    aerr = np.max(np.abs(a2 - cache["a2"])) / np.max(np.abs(cache["a2"]))
+    shp = (s.n[2], s.n[1], s.n[0])
+    g_ref = cnn.backward(s, w.astype(np.float64), rho_ref.reshape(shp), tgt.reshape(shp), cache)
+    gerr = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    log(f"conv16 {name} tz={tz}: layer-2 max rel err {aerr:.2e}, grad rel err {gerr:.2e}")
+    assert aerr <= 1e-5
+    assert gerr <= 1e-4
+
+
+def test_conv16_tile_depths_agree_bitwise(monkeypatch):
+    """Each output of the matrix-core layer is one fixed sequence of MFMA
+    steps whatever the tile depth or the number of tiles a workgroup owns,
+    so 8 x 8 x 4 and 8 x 8 x 8 tiles give the same bits (72^3 grid)."""
+    torch = require_gpu()
+    r4 = _conv16_case("snapshot72", "4", monkeypatch, torch)
+    r8 = _conv16_case("snapshot72", "8", monkeypatch, torch)
+    assert np.array_equal(r4[3], r8[3])
+    assert np.array_equal(r4[4], r8[4])
+
+
 def test_adam_steps():
     torch = require_gpu()
     s = _systems()["odd_tiles"]
