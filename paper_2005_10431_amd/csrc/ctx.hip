@@ -991,6 +991,7 @@ sparc_status sparc_gpu_create(const sparc_gpu_system* s, void* hip_stream, sparc
     if (const char* e = std::getenv("SPARC_GPU_GEMM_TILE")) c->gemm_tile = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_GEMM_NN_COLS")) c->gemm_nn_cols = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_GEMM_NN_ROWS")) c->gemm_nn_rows = std::atoi(e);
+    if (const char* e = std::getenv("SPARC_GPU_SWEEP_GROUP")) c->sweep_group = std::atoi(e);
     if (const char* e = std::getenv("SPARC_GPU_CNN_TZ")) {
         const int tz = std::atoi(e);
         if (tz == 0 || tz == 4 || tz == 8) c->cnn_tz = tz;

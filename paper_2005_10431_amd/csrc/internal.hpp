@@ -195,6 +195,7 @@ struct sparc_gpu_ctx_s {
     int gemm_tile = 0;          // SPARC_GPU_GEMM_TILE: Gram/projected-H tile edge (128, 160; 0: by size)
     int gemm_nn_cols = 160;     // SPARC_GPU_GEMM_NN_COLS: rotation tile width (160, 288)
     int gemm_nn_rows = 0;       // SPARC_GPU_GEMM_NN_ROWS: rotation tile height (64, 128; 0: 128 FP64, 64 FP32)
+    int sweep_group = 4;        // SPARC_GPU_SWEEP_GROUP: orbitals whose copies of a slab the sweep dispatches side by side
     int cnn_tz = 8;             // SPARC_GPU_CNN_TZ: depth of the matrix-core 16 -> 16 convolution tile (4, 8; 0: vector kernel)
     int cnn_per_cu[2][2] = {};  // resident convolution workgroups per CU, by (tile depth 8, MODE)
     hipGraphExec_t jac_exec = nullptr;

@@ -39,6 +39,7 @@ struct SweepArgs {
     long ldx;
     int nx, ny, nz;
     int ty, ntiles_y;
+    int grp;          // orbitals whose copies of a slab are dispatched side by side
     // -1/2 Delta_h with the y and z coefficients proportional to the x ones
     // (same weights over h_y^2, h_z^2): ck[q] multiplies
     // (x-pair + ry y-pair + rz z-pair) at distance q, c0 the point itself
@@ -247,13 +248,18 @@ __global__ __launch_bounds__(NL ? kNlThreads : 1024) void k_hsweep(SweepArgs<T> 
 
     // Hardware dispatches block b to XCD b % 8.  Give each XCD a contiguous
     // range of logical tiles so that the y-slabs of one orbital (which read
-    // each other's rows as halos) share an L2.
+    // each other's rows as halos) share an L2.  Within a group of grp
+    // orbitals the logical order is slab-major, so that the grp copies of a
+    // slab (which read the same V_eff rows and point words) run side by side.
     const int nblk = gridDim.x, bid = blockIdx.x;
     const int qn = nblk / 8, rn = nblk % 8;
     const int xcd = bid % 8, bslot = bid / 8;
     const int logical = xcd * qn + min(xcd, rn) + bslot;
-    const int col = logical / a.ntiles_y;
-    const int tile = logical - col * a.ntiles_y;
+    const int gsz = a.grp * a.ntiles_y;
+    const int gi = logical / gsz, gr = logical - gi * gsz;
+    const int gcols = min(a.grp, a.ncol - gi * a.grp);   // the last group may be short
+    const int tile = gr / gcols;
+    const int col = gi * a.grp + (gr - tile * gcols);
     const int y0 = tile * a.ty;
     const int tyn = min(a.ty, ny - y0);
 
@@ -825,6 +831,7 @@ sparc_status launch_hsweep(sparc_gpu_ctx c, const T* x, T* out, const T* xprev, 
     const NonlocalTables& NT = (sizeof(T) == 4 && c->nl32.slab_ty > 0) ? c->nl32 : c->nl;
     a.ty = nl ? NT.slab_ty : local_ty(c, sizeof(T));
     a.ntiles_y = div_up(c->ny, a.ty);
+    a.grp = std::max(1, std::min(c->sweep_group, ncol));
     {
         const StencilCoef<T>& cf = coef<T>(c);
         a.c0 = cf.c0;

@@ -618,6 +618,39 @@ def test_projection_workgroup_size_does_not_change_results(prec, monkeypatch):
     assert np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sweep_block_order_does_not_change_results(prec, monkeypatch):
+    """The sweep's workgroups each write their own slab of one orbital, so
+    the order in which they are dispatched (SPARC_GPU_SWEEP_GROUP orbitals'
+    copies of a slab side by side: 1, the default 4, and 3, which leaves a
+    short last group of the 11 orbitals) changes no result: H X and the
+    filter are bitwise the same."""
+    torch = require_gpu()
+    s = ragged_system(n_states=11)
+    v = _veff(s, 33)
+    X = W.initial_orbitals(s.nd, s.n_states, 9)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    outs = []
+    for grp in ("1", None, "3"):
+        if grp:
+            monkeypatch.setenv("SPARC_GPU_SWEEP_GROUP", grp)
+        else:
+            monkeypatch.delenv("SPARC_GPU_SWEEP_GROUP", raising=False)
+        ctx = _ctx(s)
+        ctx.set_veff(to_dev(torch, v))
+        lo, hi = ctx.spectrum_bounds()
+        Xd = to_dev(torch, X, dt)
+        Yd = torch.empty_like(Xd)
+        ctx.apply_H(Xd, Yd)
+        Wd = torch.empty_like(Xd)
+        ctx.chebyshev_filter(Xd, Wd, 6, 0.5 * (lo + hi), hi, lo)
+        outs.append((to_np(Yd), to_np(Xd)))
+    monkeypatch.delenv("SPARC_GPU_SWEEP_GROUP", raising=False)
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0])
+        assert np.array_equal(outs[0][1], o[1])
+
+
 def test_create_rejects_more_than_seven_supports_at_a_point():
     """4 atoms in a 4.2 x 4.5 Bohr cross-section with 3 Bohr projector
     supports: with their periodic images, 8 supports meet at some grid point
