@@ -290,15 +290,19 @@ __global__ __launch_bounds__(64 * TZ) void k_conv16_mfma(const float* __restrict
             if (vp >> j & 1) out[(long)(4 * (lane >> 4) + r) * nd + pp[j]] = res[j][r];
 }
 
-// Per-tile partial gradients of one layer: thread j < CI*27 owns the taps
-// (i = j / 27, k = j % 27) for every output channel, thread CI*27 + o owns
-// the bias of channel o.  part[tile][CO*CI*27 + CO] in the parameter order.
-template <int CI, int CO>
-__global__ __launch_bounds__(512) void k_wgrad(const float* __restrict__ u, const float* __restrict__ gr,
-                                               float* __restrict__ part, Grid3 g) {
+// Per-tile partial gradients of one layer.  Work item j < CI*27 owns the
+// taps (i = j / 27, k = j % 27) for every output channel, item CI*27 + o the
+// bias of channel o; S threads share an item, thread s summing the tile
+// points [s 512/S, (s+1) 512/S) in order, and the S partial sums are then
+// added in increasing s.  part[tile][CO*CI*27 + CO] in the parameter order.
+template <int CI, int CO, int S>
+__global__ __launch_bounds__(1024) void k_wgrad(const float* __restrict__ u, const float* __restrict__ gr,
+                                                float* __restrict__ part, Grid3 g) {
+    constexpr int NI = CI * 27 + CO;   // work items
     extern __shared__ float lds_wg[];
     float* ut = lds_wg;                 // CI * kHalo
-    float* gt = lds_wg + CI * kHalo;    // CO * kTile
+    float* gt = lds_wg + CI * kHalo;    // kTile x CO, point-major
+    float* red = gt + CO * kTile;       // S * NI * CO partial sums
     const long nd = (long)g.nx * g.ny * g.nz;
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
@@ -306,35 +310,62 @@ __global__ __launch_bounds__(512) void k_wgrad(const float* __restrict__ u, cons
     for (int q = threadIdx.x; q < CO * kTile; q += blockDim.x) {
         const int o = q / kTile, r = q - o * kTile;
         const int x = x0 + r % kT, y = y0 + (r / kT) % kT, z = z0 + r / (kT * kT);
-        gt[q] = (x < g.nx && y < g.ny && z < g.nz) ? gr[(long)o * nd + x + (long)g.nx * (y + (long)g.ny * z)] : 0.0f;
+        gt[r * CO + o] =
+            (x < g.nx && y < g.ny && z < g.nz) ? gr[(long)o * nd + x + (long)g.nx * (y + (long)g.ny * z)] : 0.0f;
     }
     __syncthreads();
     const int t = threadIdx.x;
-    const int np = CO * CI * 27 + CO;
-    float* pp = part + (long)blockIdx.x * np;
-    if (t < CI * 27) {
-        const int i = t / 27, k = t % 27;
-        const int dz = k / 9, dy = (k / 3) % 3, dx = k % 3;
-        const float* ui = ut + i * kHalo;
+    const int item = t % NI, sg = t / NI;
+    if (sg < S) {
+        const int r0 = sg * kTile / S, r1 = (sg + 1) * kTile / S;
         float acc[CO];
 #pragma unroll
         for (int o = 0; o < CO; ++o) acc[o] = 0.0f;
-        for (int lz = 0; lz < kT; ++lz)
-            for (int ly = 0; ly < kT; ++ly)
-#pragma unroll 4
-                for (int lx = 0; lx < kT; ++lx) {
-                    const float v = ui[(lz + dz) * kH * kH + (ly + dy) * kH + (lx + dx)];
-                    const int r = (lz * kT + ly) * kT + lx;
+        if (item < CI * 27) {
+            const int i = item / 27, k = item % 27;
+            const int dz = k / 9, dy = (k / 3) % 3, dx = k % 3;
+            const float* ui = ut + i * kHalo + dz * kH * kH + dy * kH + dx;
+            for (int r = r0; r < r1; ++r) {
+                const float v = ui[(r >> 6) * kH * kH + ((r >> 3) & 7) * kH + (r & 7)];
+                if constexpr (CO % 4 == 0) {
+                    // the point's CO channels as 16-byte reads (gt and r CO are
+                    // 16-byte aligned)
+                    const float4* g4 = reinterpret_cast<const float4*>(gt + r * CO);
 #pragma unroll
-                    for (int o = 0; o < CO; ++o) acc[o] = fmaf(gt[o * kTile + r], v, acc[o]);
+                    for (int o4 = 0; o4 < CO / 4; ++o4) {
+                        const float4 gv = g4[o4];
+                        acc[4 * o4] = fmaf(gv.x, v, acc[4 * o4]);
+                        acc[4 * o4 + 1] = fmaf(gv.y, v, acc[4 * o4 + 1]);
+                        acc[4 * o4 + 2] = fmaf(gv.z, v, acc[4 * o4 + 2]);
+                        acc[4 * o4 + 3] = fmaf(gv.w, v, acc[4 * o4 + 3]);
+                    }
+                } else {
+#pragma unroll
+                    for (int o = 0; o < CO; ++o) acc[o] = fmaf(gt[r * CO + o], v, acc[o]);
                 }
+            }
+        } else {
+            const int o = item - CI * 27;
+            float sum = 0.0f;
+            for (int r = r0; r < r1; ++r) sum += gt[r * CO + o];
+            acc[0] = sum;
+        }
 #pragma unroll
-        for (int o = 0; o < CO; ++o) pp[(o * CI + i) * 27 + k] = acc[o];
-    } else if (t < CI * 27 + CO) {
-        const int o = t - CI * 27;
-        float acc = 0.0f;
-        for (int r = 0; r < kTile; ++r) acc += gt[o * kTile + r];
-        pp[CO * CI * 27 + o] = acc;
+        for (int o = 0; o < CO; ++o) red[(sg * NI + item) * CO + o] = acc[o];
+    }
+    __syncthreads();
+    float* pp = part + (long)blockIdx.x * (CO * CI * 27 + CO);
+    for (int q = t; q < CI * 27 * CO; q += blockDim.x) {
+        // q = item * CO + o; parameter (o, i, k) = (o * CI + i) * 27 + k
+        const int it = q / CO, o = q - it * CO;
+        float sum = 0.0f;
+        for (int s2 = 0; s2 < S; ++s2) sum += red[(s2 * NI + it) * CO + o];
+        pp[o * CI * 27 + it] = sum;
+    }
+    for (int o = t; o < CO; o += blockDim.x) {
+        float sum = 0.0f;
+        for (int s2 = 0; s2 < S; ++s2) sum += red[(s2 * NI + CI * 27 + o) * CO];
+        pp[CO * CI * 27 + o] = sum;
     }
 }
 
@@ -621,9 +652,18 @@ static sparc_status features_impl(sparc_gpu_ctx c, const double w[3], float* fea
     return SPARC_OK;
 }
 
+// Threads sharing a work item of k_wgrad<CI, CO, S>, and its launch.
 template <int CI, int CO>
-static size_t wgrad_lds() {
-    return (size_t)(CI * kHalo + CO * kTile) * sizeof(float);
+constexpr int wgrad_split() {
+    return CI == 3 ? 5 : 1;
+}
+
+template <int CI, int CO>
+static void wgrad_launch(sparc_gpu_ctx c, const Grid3& g, const float* u, const float* gr, float* part) {
+    constexpr int S = wgrad_split<CI, CO>(), NI = CI * 27 + CO;
+    const size_t lds = (size_t)(CI * kHalo + CO * kTile + S * NI * CO) * sizeof(float);
+    const int threads = div_up(S * NI, 64) * 64;
+    k_wgrad<CI, CO, S><<<ntiles(g), threads, lds, c->stream>>>(u, gr, part, g);
 }
 
 // One persistent workgroup per resident slot (LDS sets how many fit on a
@@ -714,18 +754,18 @@ static sparc_status backward_impl(sparc_gpu_ctx c, const float* w, const float* 
                                                       c->n_electrons / c->dV, dz);
     SG_CHECK_LAUNCH(c);
     // layer 3
-    k_wgrad<16, 1><<<nt, 512, wgrad_lds<16, 1>(), c->stream>>>(a2, dz, part, g);
+    wgrad_launch<16, 1>(c, g, a2, dz, part);
     k_wgrad_reduce<<<div_up(np3, kRedJ), kRedJ * kRedQ, 0, c->stream>>>(part, nt, np3, grad + kOff4);
     k_conv<1, 16, 1, false><<<nt, 512, 0, c->stream>>>(dz, w + kOff4, nullptr, a2, d2, g);
     // layer 2
     if (c->cnn_tz == 0)
-        k_wgrad<16, 16><<<nt, 512, wgrad_lds<16, 16>(), c->stream>>>(a1, d2, part, g);
+        wgrad_launch<16, 16>(c, g, a1, d2, part);
     else
         k_wgrad16_mfma<<<nt, 512, 0, c->stream>>>(a1, d2, part, g);
     k_wgrad_reduce<<<div_up(np2, kRedJ), kRedJ * kRedQ, 0, c->stream>>>(part, nt, np2, grad + kOff2);
     conv16<1, false>(c, g, d2, w + kOff2, nullptr, a1, d1);
     // layer 1
-    k_wgrad<3, 16><<<nt, 512, wgrad_lds<3, 16>(), c->stream>>>(feat, d1, part, g);
+    wgrad_launch<3, 16>(c, g, feat, d1, part);
     k_wgrad_reduce<<<div_up(np1, kRedJ), kRedJ * kRedQ, 0, c->stream>>>(part, nt, np1, grad);
     SG_CHECK_LAUNCH(c);
     prof_end(c, slot);
