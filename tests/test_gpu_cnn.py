@@ -107,7 +107,12 @@ def _conv16_case(name, tz, monkeypatch, torch):
     """Forward and gradient with the 16 -> 16 layer on the path tz (0: the
     vector kernel; 4, 8: the matrix-core kernel with 8 x 8 x tz tiles)."""
     monkeypatch.setenv("SPARC_GPU_CNN_TZ", tz)
-    s = W.config5_snapshot(201) if name == "snapshot72" else _systems()[name]
+    if name == "snapshot72":
+        s = W.config5_snapshot(201)
+    elif name == "ragged_many_tiles":
+        s = W.tiny_system(n=(60, 68, 76), L=(18.0, 20.4, 22.8), n_atoms=8, with_nonlocal=False, seed=21)
+    else:
+        s = _systems()[name]
     ctx = _ctx(s)
     w = _weights(4)
     fdev = torch.empty((3, s.nd), dtype=torch.float32, device="cuda")
@@ -121,14 +126,15 @@ def _conv16_case(name, tz, monkeypatch, torch):
     return s, w, to_np(fdev), to_np(act), to_np(grad), tgt
 
 
-@pytest.mark.parametrize("name", ["odd_tiles", "snapshot72"])
+@pytest.mark.parametrize("name", ["odd_tiles", "snapshot72", "ragged_many_tiles"])
 @pytest.mark.parametrize("tz", ["0", "4", "8"])
 def test_conv16_layer_matches_oracle_on_every_path(name, tz, monkeypatch):
     """The 16 -> 16 layer's output (layer-2 activations) element by element
     and the full gradient, whose backward pass runs the layer transposed and
     masked, against the oracle on the same inputs: a ragged 17 x 13 x 21
-    grid (partial tiles in every direction, one tile per workgroup) and the
-    72^3 snapshot grid (several tiles per persistent workgroup)."""
+    grid (partial tiles in every direction, one tile per workgroup), the
+    72^3 snapshot grid (several tiles per persistent workgroup) and a
+    60 x 68 x 76 grid (both: 720 tiles of 8^3, partial in x, y and z)."""
     torch = require_gpu()
     s, w, f, act, g, tgt = _conv16_case(name, tz, monkeypatch, torch)
     rho_ref, cache = cnn.forward(s, w.astype(np.float64), f.astype(np.float64).reshape(3, s.n[2], s.n[1], s.n[0]))
