@@ -637,41 +637,43 @@ __global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, Pr
         const int row = Q.rw & 255, xlo = (Q.rw >> 8) & 255, n = ok ? (int)(Q.rw >> 16) : 0;
         double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
         if (n > 0) {
+            // a segment's arithmetic runs in the block's precision (the
+            // per-atom sums below stay in FP64)
+            using R = T;
             const T* xr = buf + row * nx + xlo;
             const double* er = ex + k * a.xw + xo;
             // The Gaussian along the segment by its recurrence: with
             // ex(i) = exp(-(delta + i hx)^2 / rc^2) and g(i) = ex(i+1)/ex(i),
             // g(i+1) = g(i) exp(-2 hx^2 / rc^2); two multiplies per point in
             // place of an LDS read (ex >= exp(-rcut^2/rc^2) > 0 on a support).
-            double ev = er[0];
-            double gq = n > 1 ? er[1] / er[0] : 0.0;
-            auto next = [&](double x) {
-                const double v = ev * x;
+            R ev = (R)er[0];
+            R gq = n > 1 ? (R)(er[1] / er[0]) : (R)0;
+            const R cq = (R)a.cq;
+            auto next = [&](R x) {
+                const R v = ev * x;
                 ev *= gq;
-                gq *= a.cq;
+                gq *= cq;
                 return v;
             };
             // four points at a time: with e_u = ex(i+u) X(i+u),
             //   S0 += sum_u e_u,  S1 += (xo+i) sum_u e_u + (e_1 + 2 e_2 + 3 e_3)
-            double s0 = 0.0, s1 = 0.0, ii = (double)xo;
+            R s0 = 0, s1 = 0, ii = (R)xo;
             int i = 0;
             for (; i + 4 <= n; i += 4) {
-                const double x0 = (double)xr[i], x1 = (double)xr[i + 1];
-                const double x2 = (double)xr[i + 2], x3 = (double)xr[i + 3];
-                const double e0 = next(x0), e1 = next(x1), e2 = next(x2), e3 = next(x3);
-                const double sum = (e0 + e1) + (e2 + e3);
+                const R e0 = next(xr[i]), e1 = next(xr[i + 1]), e2 = next(xr[i + 2]), e3 = next(xr[i + 3]);
+                const R sum = (e0 + e1) + (e2 + e3);
                 s0 += sum;
-                s1 += ii * sum + fma(3.0, e3, fma(2.0, e2, e1));
-                ii += 4.0;
+                s1 += ii * sum + fma((R)3, e3, fma((R)2, e2, e1));
+                ii += (R)4;
             }
             if (i < n) {
                 // the last one to three points
-                const double e0 = next((double)xr[i]);
-                const double e1 = i + 1 < n ? next((double)xr[i + 1]) : 0.0;
-                const double e2 = i + 2 < n ? next((double)xr[i + 2]) : 0.0;
-                const double sum = (e0 + e1) + e2;
+                const R e0 = next(xr[i]);
+                const R e1 = i + 1 < n ? next(xr[i + 1]) : (R)0;
+                const R e2 = i + 2 < n ? next(xr[i + 2]) : (R)0;
+                const R sum = (e0 + e1) + e2;
                 s0 += sum;
-                s1 += ii * sum + fma(2.0, e2, e1);
+                s1 += ii * sum + fma((R)2, e2, e1);
             }
             const double fs = Q.eyez * a.N0, fp = Q.eyez * a.N1;
             c0 = fs * s0;
