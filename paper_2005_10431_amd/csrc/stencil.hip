@@ -514,14 +514,15 @@ __host__ __device__ inline ProjLds proj_lds_layout(int ty, int nx, int nz, int K
     ProjLds L{};
     size_t o = 0;
     L.ex = o;
-    o += align16((size_t)K * xw * sizeof(double));
+    o += align16((size_t)K * xw * ts);
     L.delta = o;
     o += align16((size_t)K * sizeof(double));
     L.poff = o;
     o += align16(((size_t)nz + 1) * sizeof(int));
     // per wave: its plane (64 x kProjWaveVals values, of which ty nx are
-    // used), 64 x 4 pair contributions, K x 4 accumulators
-    L.wave_bytes = align16((size_t)64 * kProjWaveVals * ts) + 64 * 4 * sizeof(double) +
+    // used), 64 x 4 pair contributions, K x 4 FP64 accumulators (the ex
+    // table, the plane and the contributions in the block's precision)
+    L.wave_bytes = align16((size_t)64 * kProjWaveVals * ts) + align16(64 * 4 * ts) +
                    align16((size_t)K * 4 * sizeof(double));
     L.wave = o;
     o += (size_t)NW * L.wave_bytes;
@@ -577,13 +578,13 @@ __global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, Pr
     const int* poffg = a.pair_off + (long)tile * a.nz;
 
     const ProjLds L = proj_lds_layout(a.ty, nx, a.nz, a.kmax, a.xw, NW, sizeof(T));
-    double* ex = reinterpret_cast<double*>(smem_raw + L.ex);
+    T* ex = reinterpret_cast<T*>(smem_raw + L.ex);
     double* delta = reinterpret_cast<double*>(smem_raw + L.delta);
     int* poff = reinterpret_cast<int*>(smem_raw + L.poff);   // plane lists of z in [zb, ze]
     for (int j = t; j < K * a.xw; j += nt) {
         const int k = j / a.xw, i = j - k * a.xw;
         const double dx = (double)(ci[k].ixlo + i) * a.hx - a.atom_pos[3 * ci[k].atom];
-        ex[j] = exp(-dx * dx * a.inv_rc2);
+        ex[j] = (T)exp(-dx * dx * a.inv_rc2);
     }
     for (int k = t; k < K; k += nt) delta[k] = (double)ci[k].ixlo * a.hx - a.atom_pos[3 * ci[k].atom];
     for (int z = zb + t; z <= ze; z += nt) poff[z - zb] = poffg[z];
@@ -594,8 +595,8 @@ __global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, Pr
     if (col >= a.ncol) return;
     unsigned char* wb = smem_raw + L.wave + (size_t)w * L.wave_bytes;
     T* buf = reinterpret_cast<T*>(wb);
-    double* psum = reinterpret_cast<double*>(wb + align16((size_t)64 * kProjWaveVals * sizeof(T)));
-    double* acc = psum + 64 * 4;
+    T* psum = reinterpret_cast<T*>(wb + align16((size_t)64 * kProjWaveVals * sizeof(T)));
+    double* acc = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(psum) + align16(64 * 4 * sizeof(T)));
     for (int j = lane; j < K * 4; j += 64) acc[j] = 0.0;
 
     // The slab's rows of one plane are contiguous: value e of the plane is
@@ -641,7 +642,7 @@ __global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, Pr
             // per-atom sums below stay in FP64)
             using R = T;
             const T* xr = buf + row * nx + xlo;
-            const double* er = ex + k * a.xw + xo;
+            const T* er = ex + k * a.xw + xo;
             // The Gaussian along the segment by its recurrence: with
             // ex(i) = exp(-(delta + i hx)^2 / rc^2) and g(i) = ex(i+1)/ex(i),
             // g(i+1) = g(i) exp(-2 hx^2 / rc^2); two multiplies per point in
@@ -681,7 +682,7 @@ __global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, Pr
             c2 = fp * Q.dy * s0;
             c3 = fp * Q.dz * s0;
         }
-        double* ps = psum + lane * 4;
+        T* ps = psum + lane * 4;
         ps[0] = c0;
         ps[1] = c1;
         ps[2] = c2;
@@ -691,7 +692,7 @@ __global__ __launch_bounds__(512) void k_proj_stream(const T* __restrict__ x, Pr
             double* ac = acc + k * 4;
             double d0 = ac[0], d1 = ac[1], d2 = ac[2], d3 = ac[3];
             for (int r = 0; r < run; ++r) {
-                const double* q = psum + (lane + r) * 4;
+                const T* q = psum + (lane + r) * 4;
                 d0 += q[0];
                 d1 += q[1];
                 d2 += q[2];
